@@ -1,0 +1,495 @@
+"""Pins for the FP64 oracle, each independent of the oracle's own code.
+
+Every check below compares the oracle with something fixed by the paper or by
+mathematics: the dense matrices that Eq. (2) and Eq. (7) define, closed-form
+TV values and prox solutions, hand-derived worked examples, an independent
+bound-constrained solve of the denoising dual with scipy, optimality
+certificates computed with dense matrices, fixed points and normal equations.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+from oracle import oracle as orc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fgp_worked_examples.json")
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------------------
+# Dense reference matrices, written straight from the definitions.
+# ---------------------------------------------------------------------------
+
+def dense_phi(C):
+    """Phi = [D_1, ..., D_B], D_k = diag(vec(C_k)) (Eq. (2), (5)); vec stacks columns."""
+    B = C.shape[0]
+    return np.hstack([np.diag(C[k].ravel(order="F")) for k in range(B)])
+
+
+def vec_video(X):
+    return np.concatenate([X[k].ravel(order="F") for k in range(X.shape[0])])
+
+
+def unvec_video(x, B, nx, ny):
+    n = nx * ny
+    return np.stack([x[k * n:(k + 1) * n].reshape((nx, ny), order="F") for k in range(B)])
+
+
+def diff_matrix(n):
+    """(n-1) x n forward-difference matrix: row r = e_{r+1} - e_r (Eq. (7) sizes)."""
+    D = np.zeros((max(n - 1, 0), n))
+    for r in range(n - 1):
+        D[r, r] = -1.0
+        D[r, r + 1] = 1.0
+    return D
+
+
+def dense_grad(X):
+    """D_h x_k = X_k D_h^T, D_v x_k = D_v X_k (Eq. (7)), zero-padded to full size."""
+    B, nx, ny = X.shape
+    Dh, Dv = diff_matrix(ny), diff_matrix(nx)
+    gh = np.zeros_like(X)
+    gv = np.zeros_like(X)
+    for k in range(B):
+        gh[k, :, :ny - 1] = X[k] @ Dh.T
+        gv[k, :nx - 1, :] = Dv @ X[k]
+    return np.stack([gh, gv])
+
+
+def dense_grad_adj(p):
+    _, B, nx, ny = p.shape
+    Dh, Dv = diff_matrix(ny), diff_matrix(nx)
+    out = np.zeros((B, nx, ny))
+    for k in range(B):
+        out[k] += p[0, k, :, :ny - 1] @ Dh
+        out[k] += Dv.T @ p[1, k, :nx - 1, :]
+    return out
+
+
+def dense_tv(theta, tv):
+    g = dense_grad(theta)
+    if tv == "atv":
+        return np.abs(g).sum()
+    if tv == "itv2d":
+        return np.sqrt(g[0] ** 2 + g[1] ** 2).sum()
+    return np.sqrt((g[0] ** 2 + g[1] ** 2).sum(axis=0)).sum()
+
+
+def dual_norm_max(p, tv):
+    if tv == "atv":
+        return np.abs(p).max()
+    if tv == "itv2d":
+        return np.sqrt(p[0] ** 2 + p[1] ** 2).max()
+    return np.sqrt((p[0] ** 2 + p[1] ** 2).sum(axis=0)).max()
+
+
+def certificate_gap(x, p, lam, tv):
+    """Primal minus dual objective with dense operators: an optimality
+    certificate of theta = x - lam D^T p that does not use the oracle's code."""
+    th = x - lam * dense_grad_adj(p)
+    primal = 0.5 * ((th - x) ** 2).sum() + lam * dense_tv(th, tv)
+    dual = 0.5 * (x ** 2).sum() - 0.5 * ((x - lam * dense_grad_adj(p)) ** 2).sum()
+    return primal - dual, primal
+
+
+# ---------------------------------------------------------------------------
+# Sensing operator Phi, Phi^T (Eq. (2)-(5)).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("B,nx,ny", [(1, 3, 4), (3, 5, 2), (4, 6, 7)])
+def test_forward_adjoint_match_dense_phi(B, nx, ny):
+    r = rng(1)
+    C = r.uniform(size=(B, nx, ny))
+    X = r.normal(size=(B, nx, ny))
+    Yv = r.normal(size=(nx, ny))
+    Phi = dense_phi(C)
+    y = Phi @ vec_video(X)
+    np.testing.assert_allclose(orc.forward(C, X).ravel(order="F"), y, rtol=1e-13, atol=1e-13)
+    xa = Phi.T @ Yv.ravel(order="F")
+    np.testing.assert_allclose(vec_video(orc.adjoint(C, Yv)), xa, rtol=1e-13, atol=1e-13)
+    # adjoint identity <Phi x, y> = <x, Phi^T y>
+    lhs = (orc.forward(C, X) * Yv).sum()
+    rhs = (X * orc.adjoint(C, Yv)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_forward_special_masks():
+    r = rng(2)
+    X = r.normal(size=(5, 4, 6))
+    np.testing.assert_allclose(orc.forward(np.ones_like(X), X), X.sum(axis=0), rtol=1e-14)
+    C = np.zeros_like(X)
+    C[3] = 1.0
+    np.testing.assert_array_equal(orc.forward(C, X), X[3])
+
+
+def test_weights_diag_phiphit():
+    r = rng(3)
+    C = (r.uniform(size=(4, 5, 6)) < 0.5).astype(float)
+    C[:, 0, 0] = 0.0  # a pixel no frame sees
+    Phi = dense_phi(C)
+    S = np.diag(Phi @ Phi.T).reshape((5, 6), order="F")
+    W = orc.weights(C)
+    expect = np.where(S > 0, 1.0 / np.where(S > 0, S, 1.0), 0.0)
+    np.testing.assert_allclose(W, expect, rtol=1e-15)
+    assert W[0, 0] == 0.0
+    np.testing.assert_allclose(orc.weights(C, 0.5), 1.0 / (S + 0.5), rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Finite differences (Eq. (7)).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (1, 1, 5), (2, 4, 1), (2, 5, 7), (3, 8, 3)])
+def test_grad_matches_dense_difference_matrices(B, nx, ny):
+    r = rng(4)
+    X = r.normal(size=(B, nx, ny))
+    p = r.normal(size=(2, B, nx, ny))
+    np.testing.assert_allclose(orc.grad(X), dense_grad(X), rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(orc.grad_adj(p), dense_grad_adj(p), rtol=1e-13, atol=1e-13)
+    lhs = (orc.grad(X) * p).sum()
+    rhs = (X * orc.grad_adj(p)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_grad_of_constant_is_zero():
+    assert np.abs(orc.grad(np.full((3, 6, 5), 2.5))).max() == 0.0
+
+
+def test_dtd_norm_below_eight():
+    """||D^T D|| approaches 8 from below (the 1/(8 lambda) step of Algorithm 1)."""
+    r = rng(5)
+    v = r.normal(size=(1, 48, 48))
+    for _ in range(600):
+        v = orc.grad_adj(orc.grad(v))
+        nrm = np.sqrt((v ** 2).sum())
+        v /= nrm
+    assert 7.9 < nrm < 8.0
+
+
+# ---------------------------------------------------------------------------
+# TV values (Eq. (8)-(10), per-pixel reading).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_tv_closed_forms(tv):
+    nx, ny, B, h, m = 7, 9, 4, 0.35, 4
+    assert orc.tv_value(np.full((B, nx, ny), 0.3), tv) == 0.0
+    step = np.zeros((B, nx, ny))
+    step[:, :, m:] = h  # identical frames, a jump of height h across every row
+    expect = {"atv": B * nx * h, "itv2d": B * nx * h, "vtv": math.sqrt(B) * nx * h}[tv]
+    assert abs(orc.tv_value(step, tv) - expect) < 1e-12
+    X = rng(6).normal(size=(B, nx, ny))
+    assert abs(orc.tv_value(X, tv) - dense_tv(X, tv)) < 1e-10 * dense_tv(X, tv)
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_project_dual_is_ball_projection(tv):
+    r = rng(7)
+    q = r.normal(size=(2, 3, 4, 5)) * 2.0
+    p = orc.project_dual(q, tv)
+    assert dual_norm_max(p, tv) <= 1.0 + 1e-15
+    # the projection onto a convex set is firmly non-expansive and idempotent
+    np.testing.assert_allclose(orc.project_dual(p, tv), p, rtol=0, atol=1e-15)
+    if tv == "atv":
+        np.testing.assert_allclose(p, np.clip(q, -1, 1), rtol=0, atol=1e-15)
+    else:
+        axes = (0,) if tv == "itv2d" else (0, 1)
+        nq = np.sqrt((q ** 2).sum(axis=axes, keepdims=True))
+        np.testing.assert_allclose(p, q / np.maximum(1.0, nq), rtol=1e-15)
+
+
+def test_fgp_beta_recursion():
+    b = orc.fgp_beta(4)
+    nu1 = (1 + math.sqrt(5)) / 2
+    nu2 = (1 + math.sqrt(1 + 4 * nu1 * nu1)) / 2
+    assert b[0] == 0.0
+    assert abs(b[1] - (nu1 - 1) / nu2) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# TV denoiser (Algorithm 1 FGP / Cham boxes, Eq. (27)-(32)).
+# ---------------------------------------------------------------------------
+
+def test_golden_worked_example_2x2():
+    g = json.load(open(GOLDEN))["cases"][0]
+    x = np.array(g["x"], dtype=float)
+    for n in (1, 2, 7):
+        th, p = orc.tv_denoise(x, g["lam"], n, g["tv"], return_dual=True)
+        np.testing.assert_allclose(th, np.array(g["theta"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(p[0], np.array(g["p_h"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(p[1], np.array(g["p_v"]), rtol=0, atol=1e-15)
+        gap, _ = orc.dual_gap(x, p, g["lam"], g["tv"])
+        assert abs(gap - g["gap"]) < 1e-15
+
+
+@pytest.mark.parametrize("case", [1, 2])
+def test_golden_step_closed_form(case):
+    g = json.load(open(GOLDEN))["cases"][case]
+    B = g.get("B", 1)
+    nx = 3
+    x = np.full((B, nx, g["n"]), g["a"])
+    x[:, :, g["m"]:] = g["b"]
+    tvs = g["tv"] if isinstance(g["tv"], list) else [g["tv"]]
+    for tv in tvs:
+        th = orc.tv_denoise(x, g["lam"], 3000, tv)
+        np.testing.assert_allclose(th[:, :, :g["m"]], g["left"], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(th[:, :, g["m"]:], g["right"], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoiser_identities(tv):
+    r = rng(8)
+    B, nx, ny = 3, 9, 11
+    x = r.uniform(size=(B, nx, ny))
+    lam = 0.07
+    # lambda = 0 and N = 0 return the input
+    np.testing.assert_array_equal(orc.tv_denoise(x, 0.0, 5, tv), x)
+    np.testing.assert_array_equal(orc.tv_denoise(x, lam, 0, tv), x)
+    # constant input is a fixed point
+    c = np.full((B, nx, ny), 0.4)
+    np.testing.assert_allclose(orc.tv_denoise(c, lam, 6, tv), c, rtol=0, atol=1e-15)
+    base = orc.tv_denoise(x, lam, 6, tv)
+    # per-frame constant shifts pass through (D kills constants)
+    shift = np.array([0.5, -1.25, 3.0])[:, None, None]
+    np.testing.assert_allclose(orc.tv_denoise(x + shift, lam, 6, tv), base + shift, rtol=0, atol=1e-12)
+    # positive homogeneity: TVD_{a lam}(a x) = a TVD_lam(x)
+    a = 2.5
+    np.testing.assert_allclose(orc.tv_denoise(a * x, a * lam, 6, tv), a * base, rtol=0, atol=1e-12)
+
+
+def test_vtv_single_frame_equals_itv2d():
+    x = rng(9).uniform(size=(1, 10, 8))
+    np.testing.assert_allclose(orc.tv_denoise(x, 0.1, 9, "vtv"), orc.tv_denoise(x, 0.1, 9, "itv2d"),
+                               rtol=0, atol=0)
+
+
+def test_identical_rows_atv_equals_itv2d():
+    row = rng(10).uniform(size=(2, 1, 13))
+    x = np.repeat(row, 6, axis=1)
+    np.testing.assert_allclose(orc.tv_denoise(x, 0.1, 9, "atv"), orc.tv_denoise(x, 0.1, 9, "itv2d"),
+                               rtol=0, atol=1e-15)
+
+
+def scipy_atv_prox(x, lam):
+    """Independent ATV prox: minimise 1/2 ||x - lam D^T p||^2 over the box
+    |p| <= 1 (entries without a difference fixed to 0) with L-BFGS-B on the
+    dense difference matrices."""
+    B, nx, ny = x.shape
+    mask = np.zeros((2, B, nx, ny), bool)
+    mask[0, :, :, :ny - 1] = True
+    mask[1, :, :nx - 1, :] = True
+    idx = np.flatnonzero(mask)
+
+    def unpack(z):
+        p = np.zeros(mask.size)
+        p[idx] = z
+        return p.reshape(mask.shape)
+
+    def f(z):
+        p = unpack(z)
+        res = x - lam * dense_grad_adj(p)
+        g = -lam * dense_grad(res)
+        return 0.5 * (res ** 2).sum(), g.ravel()[idx]
+
+    z0 = np.zeros(idx.size)
+    out = scipy.optimize.minimize(f, z0, jac=True, method="L-BFGS-B", bounds=[(-1, 1)] * idx.size,
+                                  options=dict(maxiter=20000, ftol=1e-15, gtol=1e-12))
+    return x - lam * dense_grad_adj(unpack(out.x))
+
+
+def test_atv_fgp_converges_to_independent_prox():
+    x = rng(11).uniform(size=(2, 6, 7))
+    lam = 0.08
+    ref = scipy_atv_prox(x, lam)
+    th = orc.tv_denoise(x, lam, 4000, "atv")
+    np.testing.assert_allclose(th, ref, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoiser_gap_certificate_and_convergence(tv):
+    """The oracle's dual is feasible and its dense-matrix duality gap, which
+    bounds the distance to the unique prox, goes to zero; the oracle's own
+    gap routine agrees with the dense certificate."""
+    x = rng(12).uniform(size=(4, 16, 16))
+    lam = 0.1
+    prev = np.inf
+    for n in (5, 20, 80, 400):
+        th, p = orc.tv_denoise(x, lam, n, tv, return_dual=True)
+        assert dual_norm_max(p, tv) <= 1.0 + 1e-12
+        cg, prim = certificate_gap(x, p, lam, tv)
+        og, oprim = orc.dual_gap(x, p, lam, tv)
+        assert cg >= -1e-12
+        assert abs(cg - og) <= 1e-9 * max(1.0, prim)
+        assert abs(prim - oprim) <= 1e-10 * prim
+        np.testing.assert_allclose(th, x - lam * dense_grad_adj(p), rtol=0, atol=1e-13)
+        assert cg <= prev * 1.05 + 1e-14
+        prev = cg
+    assert prev / prim < 1e-6
+    # the long-run Chambolle projected gradient reaches the same prox
+    th_pg = orc.tv_denoise(x, lam, 20000, tv, accel=False)
+    th_fgp = orc.tv_denoise(x, lam, 3000, tv)
+    assert np.sqrt(((th_pg - th_fgp) ** 2).sum() / (th_fgp ** 2).sum()) < 1e-5
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoiser_variants_reach_same_prox(tv):
+    """Chambolle-2004 denominator and the literal FGP output converge to the same prox."""
+    x = rng(13).uniform(size=(2, 8, 9))
+    lam = 0.1
+    ref = orc.tv_denoise(x, lam, 3000, tv)
+    lit = orc.tv_denoise(x, lam, 3000, tv, literal_out=True)
+    ch = orc.tv_denoise(x, lam, 20000, tv, accel=False, chambolle04=True)
+    assert np.abs(lit - ref).max() < 1e-6
+    assert np.abs(ch - ref).max() < 1e-4
+
+
+def test_large_lambda_gives_frame_means():
+    x = rng(14).uniform(size=(3, 6, 6))
+    th = orc.tv_denoise(x, 50.0, 3000, "itv2d")
+    np.testing.assert_allclose(th, np.broadcast_to(x.mean(axis=(1, 2), keepdims=True), x.shape),
+                               rtol=0, atol=1e-6)
+
+
+def test_warm_start_from_converged_dual_is_fixed():
+    x = rng(15).uniform(size=(2, 7, 7))
+    th, p = orc.tv_denoise(x, 0.1, 3000, "vtv", return_dual=True)
+    th2 = orc.tv_denoise(x, 0.1, 1, "vtv", p_init=p)
+    assert np.abs(th2 - th).max() < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# GAP (Eq. (21)-(22)) and ADMM (Eq. (24)-(26)).
+# ---------------------------------------------------------------------------
+
+def small_problem(seed=16, B=3, nx=5, ny=6, p=0.5):
+    r = rng(seed)
+    C = (r.uniform(size=(B, nx, ny)) < p).astype(float)
+    X = r.uniform(size=(B, nx, ny))
+    return C, X, orc.forward(C, X)
+
+
+def test_gap_projection_matches_dense_pseudo_inverse():
+    C, X, Y = small_problem()
+    C[:, 1, 2] = 0.0  # pixel with S = 0
+    Y = orc.forward(C, X)
+    th0 = rng(17).normal(size=X.shape)
+    x, th = orc.gap_tv(Y, C, 0.1, 1, 0, x_init=th0)  # N = 0: denoiser is the identity
+    Phi = dense_phi(C)
+    y = Y.ravel(order="F")
+    ref = vec_video(th0) + Phi.T @ np.linalg.pinv(Phi @ Phi.T) @ (y - Phi @ vec_video(th0))
+    np.testing.assert_allclose(vec_video(x), ref, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(th, x)
+
+
+def test_gap_iterates_satisfy_measurement():
+    C, X, Y = small_problem(18, B=4, nx=12, ny=10)
+    S = (C ** 2).sum(axis=0)
+    for T in (1, 3):
+        x, _ = orc.gap_tv(Y, C, 0.1, T, 5, tv="itv2d")
+        fx = orc.forward(C, x)
+        np.testing.assert_allclose(fx[S > 0], Y[S > 0], rtol=0, atol=1e-12)
+
+
+def test_gap_single_frame_full_mask_returns_measurement():
+    Y = rng(19).uniform(size=(6, 7))
+    C = np.ones((1, 6, 7))
+    x, _ = orc.gap_tv(Y, C, 0.2, 2, 4, tv="atv")
+    np.testing.assert_allclose(x[0], Y, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_constant_frames_are_fixed_points(solver, tv):
+    B, nx, ny = 4, 9, 8
+    truth = np.broadcast_to(np.array([0.2, 0.5, 0.9, 0.1])[:, None, None], (B, nx, ny)).copy()
+    C = (rng(20).uniform(size=(B, nx, ny)) < 0.5).astype(float)
+    Y = orc.forward(C, truth)
+    if solver == "gap":
+        x, th = orc.gap_tv(Y, C, 0.1, 5, 5, tv=tv, x_init=truth)
+    else:
+        x, th = orc.admm_tv(Y, C, 0.1, 0.01, 5, 5, tv=tv, x_init=truth)
+    np.testing.assert_allclose(x, truth, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(th, truth, rtol=0, atol=1e-13)
+
+
+def test_admm_x_update_solves_normal_equations():
+    C, X, Y = small_problem(21)
+    rho = 0.3
+    v = rng(22).normal(size=X.shape)
+    x, th = orc.admm_tv(Y, C, 0.1, rho, 1, 0, x_init=v)  # u0 = 0 -> v = theta0
+    Phi = dense_phi(C)
+    A = Phi.T @ Phi + rho * np.eye(Phi.shape[1])
+    ref = np.linalg.solve(A, Phi.T @ Y.ravel(order="F") + rho * vec_video(v))
+    np.testing.assert_allclose(vec_video(x), ref, rtol=0, atol=1e-12)
+
+
+def test_admm_rho_zero_first_step_is_gap():
+    C, X, Y = small_problem(23, B=4, nx=10, ny=9)
+    xg, tg = orc.gap_tv(Y, C, 0.1, 1, 6, tv="vtv")
+    xa, ta = orc.admm_tv(Y, C, 0.1, 0.0, 1, 6, tv="vtv")
+    np.testing.assert_array_equal(xg, xa)
+    np.testing.assert_array_equal(tg, ta)
+
+
+def test_gap_improves_reconstruction():
+    """Sanity of the whole loop on a small scene: PSNR rises well above the
+    back-projection's."""
+    from paper_2005_08028_amd import synth
+    pr = synth.make_problem(64, 64, 8, seed=24)
+    Y = orc.measurement(pr.masks, pr.truth)
+    x0 = orc.adjoint(pr.masks, Y) * orc.weights(pr.masks)[None] * 8 / 8
+    x, _ = orc.gap_tv(Y, pr.masks, 0.1, 30, 5, tv="atv")
+    assert orc.psnr(x, pr.truth) > orc.psnr(x0, pr.truth) + 8.0
+
+
+# ---------------------------------------------------------------------------
+# Metrics.
+# ---------------------------------------------------------------------------
+
+def test_psnr_closed_form():
+    ref = rng(25).uniform(size=(3, 4, 5))
+    assert abs(orc.psnr(ref + 0.01, ref) - 40.0) < 1e-9
+    assert abs(orc.psnr(ref - 0.1, ref, peak=2.0) - 20 * math.log10(20.0)) < 1e-9
+
+
+def test_residual_sq():
+    C, X, Y = small_problem(26)
+    assert orc.residual_sq(C, X, Y) < 1e-28
+    assert abs(orc.residual_sq(C, X, Y + 0.5) - 0.25 * Y.size) < 1e-12
+
+
+def test_golden_three_iterations_pin_momentum():
+    g = json.load(open(GOLDEN))["cases"][3]
+    x = np.array(g["x"], dtype=float)
+    for n, ref in g["by_n"].items():
+        th, p = orc.tv_denoise(x, g["lam"], int(n), g["tv"], return_dual=True)
+        np.testing.assert_allclose(th[0, 0], ref["theta"], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(p[0, 0, 0], ref["p_h"], rtol=0, atol=1e-15)
+    th = orc.tv_denoise(x, g["lam"], 500, g["tv"])
+    np.testing.assert_allclose(th[0, 0], g["converged_theta"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_fgp_and_pg_rate_bounds(tv):
+    """Beck-Teboulle bounds on the dual objective h(p) = 1/2 ||x - lam D^T p||^2
+    (gradient Lipschitz constant L = 8 lam^2, step 1/L): FGP
+    h(p_N) - h* <= 2 L ||p0 - p*||^2 / (N+1)^2, projected gradient
+    h(p_N) - h* <= L ||p0 - p*||^2 / (2N), from p0 = 0."""
+    x = rng(27).uniform(size=(3, 12, 12))
+    lam = 0.1
+    L = 8 * lam * lam
+    th_star, p_star = orc.tv_denoise(x, lam, 20000, tv, return_dual=True)
+    h_star = 0.5 * (th_star ** 2).sum()
+    R2 = (p_star ** 2).sum()
+    for n in (1, 2, 3, 5, 10, 30, 100):
+        th = orc.tv_denoise(x, lam, n, tv)
+        assert 0.5 * (th ** 2).sum() - h_star <= 2 * L * R2 / (n + 1) ** 2 + 1e-12
+        th = orc.tv_denoise(x, lam, n, tv, accel=False)
+        assert 0.5 * (th ** 2).sum() - h_star <= L * R2 / (2 * n) + 1e-12
