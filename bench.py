@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of GAP-TV video SCI reconstruction on one MI355X.
+
+One step = one whole reconstruction of a synthetic CACTI-style measurement
+(1024 x 1024 pixels, B = 24 frames, shifted Bernoulli(0.5) masks, moving
+shapes on a gradient background plus N(0, 0.02) texture): GAP with isotropic
+(ITV2D) TV, 200 outer x 10 FGP inner iterations, lambda = 0.1, float32, plus
+the FP64 PSNR and residual reductions on the result. Inputs are resident in
+HBM before the timed region starts.
+
+Prints ONE JSON line: the throughput in voxel-iterations per second
+(voxels x inner iterations / s), the roofline position of the dominant kernel
+(timed live with HIP events inside the library), the HBM traffic measured by
+rocprofv3 counters when the committed counter summary still matches the
+kernel source, and the FP64 oracle timed on the host cores on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GAP-TV voxel-iter/s, % HBM roofline; time-to-PSNR learned/batched vs plain"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic_fgp_cacti_1024x24.txt")
+
+
+def fgp_stream_bytes_per_voxel(n_inner: int, elem: int) -> float:
+    """Algorithmic HBM bytes per voxel summed over the n_inner streaming FGP
+    passes of one denoiser call: every pass reads x (4 B) and writes p^(s+1)
+    (2 elem); pass s >= 1 also reads p^(s) (2 elem); pass s >= 2 also reads
+    p^(s-1) (2 elem) for the momentum term (the first momentum coefficient is
+    zero)."""
+    total = 0.0
+    for s in range(n_inner):
+        b = 4 + 2 * elem
+        if s >= 1:
+            b += 2 * elem
+        if s >= 2:
+            b += 2 * elem
+        total += b
+    return total
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_fgp.hip", "sci_math.h"):
+        with open(os.path.join(ROOT, "paper_2005_08028_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(family: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_family") != family or kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--outer", type=int, default=200, help="outer iterations per step (default: the full 200)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "stream", "fused"])
+    ap.add_argument("--dual-dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations of the oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run plain 1 GiB device copies (reference for HBM counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this implementation runs on a single GPU; --gpus must be 1 "
+              "(multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    from paper_2005_08028_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build()
+    from paper_2005_08028_amd import scitv, synth
+
+    wl = "cacti_1024x24"
+    cfg = synth.CONFIGS[wl]
+    nx, ny, B = cfg["nx"], cfg["ny"], cfg["B"]
+    T, N, lam = args.outer, cfg["N"], cfg["lam"]
+    V = nx * ny * B
+    dev = torch.device("cuda:0")
+    pr = synth.problem_from_config(wl)
+    ctx = scitv.Context(0)
+    h = ctx.handle
+    C = torch.from_numpy(pr.masks).to(dev)
+    X_true = torch.from_numpy(pr.truth).to(dev)
+    Y = scitv.sci_forward(h, C, X_true) + torch.from_numpy(pr.noise).to(dev)
+    X_out = torch.empty_like(C)
+    Th_out = torch.empty_like(C)
+    prm = scitv.solver_params(outer_iters=T, tv=cfg["tv"], lam=lam, n_inner=N, schedule=args.schedule,
+                              dual_dtype=args.dual_dtype)
+
+    def step():
+        scitv.sci_gap_tv(h, Y, C, prm, X_out=X_out, Theta_out=Th_out)
+        psnr = scitv.sci_psnr(h, X_out, X_true)
+        resid = scitv.sci_residual_sq(h, C, X_out, Y)
+        return psnr, resid
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    scitv.sci_profile_enable(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        psnr, resid = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    scitv.sci_profile_enable(h, False)
+
+    fams = {}
+    for fam in ("fgp_stream", "fgp_fused", "tv_theta", "project", "setup"):
+        n, ms = scitv.sci_profile_read(h, fam)
+        if n:
+            fams[fam] = (n, ms)
+    dom = max(fams, key=lambda f: fams[f][1])
+    n_dom, ms_dom = fams[dom]
+    avg_s = ms_dom / n_dom / 1e3
+    elem = 4 if args.dual_dtype == "f32" else 2
+    if dom == "fgp_stream":
+        bytes_per_launch = V * fgp_stream_bytes_per_voxel(N, elem) / N
+    elif dom == "fgp_fused":
+        bytes_per_launch = V * 8.0  # read x, write theta; the dual never leaves the chip
+    else:
+        bytes_per_launch = None
+    achieved = bytes_per_launch / avg_s / 1e9 if bytes_per_launch else None
+    traffic = read_traffic(dom)
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": traffic, "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_dom,
+        "bytes_per_launch": bytes_per_launch,
+    }
+
+    steps = args.steps
+    value = V * T * N * steps / elapsed
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxel-iter/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{wl}: GAP-ITV2D {nx}x{ny}x{B}, {T} outer x {N} inner FGP, lambda={lam}, "
+                               f"shifted Bernoulli(0.5) masks, textured moving-shape scene",
+                   "nx": nx, "ny": ny, "B": B, "outer_iters": T, "inner_iters": N, "tv": cfg["tv"],
+                   "schedule": args.schedule, "dual_dtype": args.dual_dtype, "graph": False},
+        "roofline": roofline,
+        "kernel_ms_per_step": {f: round(ms / steps, 3) for f, (n, ms) in fams.items()},
+        "psnr_db": round(psnr, 4), "residual_sq": resid,
+    }
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 4
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        Ts = args.cpu_outer
+        Yh = Y.cpu().numpy()
+        t0 = time.perf_counter()
+        xr, _ = orc.gap_tv(Yh, pr.masks, float(np.float32(lam)), Ts, N, tv=cfg["tv"])
+        tc = time.perf_counter() - t0
+        prs = scitv.solver_params(outer_iters=Ts, tv=cfg["tv"], lam=lam, n_inner=N, schedule=args.schedule,
+                                  dual_dtype=args.dual_dtype)
+        xs, _ = scitv.sci_gap_tv(h, Y, C, prs)
+        xg = xs.cpu().numpy().astype(np.float64)
+        rel = float(np.linalg.norm(xg - xr) / np.linalg.norm(xr))
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            cores = os.cpu_count()
+        cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+        out["cpu_baseline"] = {
+            "value": V * Ts * N / tc, "unit": "voxel-iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"same {nx}x{ny}x{B} inputs, GAP-ITV2D {Ts} outer x {N} inner (of {T}), FP64, {tc:.1f} s",
+            "gpu_rel_l2_vs_oracle_on_sample": rel,
+        }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

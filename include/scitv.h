@@ -1,0 +1,197 @@
+/*
+ * libscitv — GAP-TV / ADMM-TV reconstruction for snapshot video compressive
+ * imaging (SCI) on AMD Instinct MI355X (gfx950).
+ *
+ * Method: X. Yuan, "Various Total Variation for Snapshot Video Compressive
+ * Imaging", arXiv:2005.08028. Equation numbers below count the paper's
+ * numbered displays in order of appearance.
+ *
+ * Measurement model (Eq. (1)-(5)): B frames X_k in R^{nx x ny} are coded by
+ * masks C_k and summed into one image, Y = sum_k C_k .* X_k + G. Phi is never
+ * formed: the caller passes the B mask images.
+ *
+ * Conventions for every entry point
+ *   - Arrays are caller-owned DEVICE pointers (memory of the device the
+ *     context was created on), contiguous, row-major, column index fastest:
+ *       video  [B][nx][ny] float32          (frame k, row i, column j)
+ *       image  [nx][ny]    float32
+ *       dual   [2][B][nx][ny] in the dual storage type of the call
+ *              (channel 0 = horizontal differences along j, 1 = vertical
+ *              along i). Entries with no difference behind them (j = ny-1
+ *              in channel 0, i = nx-1 in channel 1) are written as 0 and
+ *              ignored on input.
+ *   - The library never frees or retains caller memory. Scratch buffers,
+ *     graphs and tables belong to the context.
+ *   - Work is enqueued on `stream` (0 = the legacy default stream) and is
+ *     asynchronous unless a host output is requested (then the call
+ *     synchronises `stream` before returning).
+ *   - Every call validates its arguments before launching anything and
+ *     returns a status code; no C++ exception crosses this interface.
+ *     Outputs must not overlap inputs (SCI_ERR_ALIAS).
+ *   - Sizes: nx, ny, B >= 1 and B*nx*ny < 2^31.
+ *   - A context may be used from one host thread at a time. Calls that
+ *     share a context and overlap on different streams race on its scratch.
+ */
+#ifndef SCITV_H
+#define SCITV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SCI_OK 0
+#define SCI_NOT_CONVERGED 1     /* outputs written; the duality-gap tolerance was not met at the cap */
+#define SCI_ERR_INVALID_ARG (-1)/* null pointer, size out of range, lambda/rho < 0 or non-finite, bad enum */
+#define SCI_ERR_ALIAS (-2)      /* an output overlaps an input */
+#define SCI_ERR_NOMEM (-3)      /* device scratch allocation failed */
+#define SCI_ERR_HIP (-4)        /* a HIP runtime call failed; sci_last_error() has the text */
+#define SCI_ERR_UNSUPPORTED (-5)/* valid request this build does not implement (message in sci_last_error) */
+
+typedef struct sci_ctx sci_ctx;
+
+typedef struct {
+    int32_t nx; /* rows i    */
+    int32_t ny; /* columns j */
+    int32_t B;  /* frames k  */
+} sci_dims;
+
+/* TV regulariser (Sec. 2.1). ITV2D and ITV3D are per-pixel isotropic norms:
+ * ITV2D over (h, v) of one voxel (Eq. (9), dual projection Eq. (29)-(30));
+ * SCI_TV_VTV is the paper's ITV3D, a norm over (h, v) of all B frames at one
+ * pixel (Eq. (10), dual projection Eq. (31)-(32)). */
+typedef enum { SCI_TV_ATV = 0, SCI_TV_ITV2D = 1, SCI_TV_VTV = 2 } sci_tv_kind;
+
+/* Storage type of the dual fields kept in device memory between denoiser
+ * passes; arithmetic is always float32. */
+typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_dtype;
+
+/* How the inner denoiser iterations are scheduled on the GPU:
+ *   STREAM: one pass over HBM per inner iteration (dual fields in memory);
+ *   FUSED : all inner iterations of one denoiser call in one on-chip pass
+ *           per tile (dual fields never leave the chip; cold start and
+ *           float32 duals only);
+ *   AUTO  : FUSED where it applies, else STREAM.
+ * Both schedules evaluate the same per-voxel expressions. */
+typedef enum { SCI_SCHED_AUTO = 0, SCI_SCHED_STREAM = 1, SCI_SCHED_FUSED = 2 } sci_schedule;
+
+/* TV denoiser parameters: theta = argmin 1/2 ||theta - x||^2 + lambda TV(theta)
+ * solved on the dual with step 1/(8 lambda) (Algorithm 1, FGP box). */
+typedef struct {
+    int32_t tv;              /* sci_tv_kind */
+    float lambda;            /* TV weight >= 0; 0 returns the input unchanged */
+    int32_t n_inner;         /* inner iterations (In-Iter) >= 0; 0 returns the input */
+    int32_t accel;           /* 1 = FGP (Beck-Teboulle momentum), 0 = Chambolle projected gradient */
+    int32_t dual_dtype;      /* sci_dual_dtype */
+    int32_t schedule;        /* sci_schedule */
+    double gap_tol;          /* sci_tv_denoise only: > 0 iterates until the relative duality
+                                gap <= gap_tol (checked every gap_check_every iterations,
+                                at most n_inner_max iterations); <= 0 runs exactly n_inner */
+    int32_t n_inner_max;
+    int32_t gap_check_every;
+} sci_tv_params;
+
+/* Outer framework parameters (Algorithm 1; ADMM of Eq. (24)-(26)). */
+typedef struct {
+    sci_tv_params tv;        /* denoiser used once per outer iteration (fixed n_inner) */
+    int32_t outer_iters;     /* MaxIter >= 0 */
+    float rho;               /* ADMM penalty >= 0 (ignored by GAP) */
+    int32_t warm_dual;       /* 1 = carry the denoiser's dual from one outer iteration to
+                                the next (momentum restarted), 0 = cold start every call */
+    int32_t use_graph;       /* 1 = capture the outer loop once in a HIP graph and replay it */
+} sci_solver_params;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device` (it becomes current on the
+ * calling thread). *out receives the handle. */
+int sci_create(sci_ctx **out, int device);
+/* Free the context's scratch and graphs (synchronises the device first). NULL is a no-op. */
+void sci_destroy(sci_ctx *ctx);
+/* Static text for a status code. */
+const char *sci_status_string(int status);
+/* Text of the last failure recorded in the context (empty if none). */
+const char *sci_last_error(const sci_ctx *ctx);
+
+/* ---- sensing operator, Eq. (3)-(4) ------------------------------------- */
+
+/* Y_ij = sum_k C_kij X_kij. C, X: video; Y: image (output). The noise term G
+ * of Eq. (3) is not added. */
+int sci_forward(sci_ctx *ctx, sci_dims d, const float *C, const float *X, float *Y, hipStream_t stream);
+
+/* Transpose of Phi = [D_1 ... D_B] (Eq. (2)): X_kij = C_kij Y_ij. C: video;
+ * Y: image; X: video (output). */
+int sci_adjoint(sci_ctx *ctx, sci_dims d, const float *C, const float *Y, float *X, hipStream_t stream);
+
+/* ---- TV denoiser (Sec. 2.3, Algorithm 1 FGP/Cham boxes) ------------------ */
+
+/* Theta_out = TVdenoise(X_in) with the dual started from dual_init (NULL =
+ * zero). dual_init / dual_out are dual-shaped in p->dual_dtype; dual_out
+ * (nullable) receives the final projected dual p^(N); Theta_out is
+ * X_in - lambda D^T p^(N). rel_gap_out (nullable, HOST pointer) receives
+ * the relative duality gap lambda (TV(theta) - <D theta, p>) / P(theta)
+ * computed in FP64; iters_out (nullable, HOST) the iterations run.
+ * Returns SCI_NOT_CONVERGED when gap_tol > 0 was not met at n_inner_max. */
+int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *X_in, float *Theta_out,
+                   const void *dual_init, void *dual_out, double *rel_gap_out, int32_t *iters_out,
+                   hipStream_t stream);
+
+/* ---- outer frameworks ---------------------------------------------------- */
+
+/* GAP (Eq. (21)-(22), Algorithm 1): theta^(0) = Phi^T Y (or X_init);
+ *   x^(t+1) = theta^(t) + Phi^T (Phi Phi^T)^+ (Y - Phi theta^(t)),
+ *   theta^(t+1) = TVdenoise(x^(t+1)),
+ * for exactly outer_iters iterations. (Phi Phi^T)^+ is 1/sum_k C_k^2 where
+ * that sum is positive and 0 elsewhere. Y: image; C: video; X_out: video
+ * receiving x^(T) (theta^(0) if T = 0); Theta_out (nullable): theta^(T);
+ * X_init (nullable): theta^(0). */
+int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
+               float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
+
+/* ADMM (Eq. (24)-(26)): theta^(0) = Phi^T Y (or X_init), u^(0) = 0;
+ *   x^(t+1) = v + Phi^T (Phi Phi^T + rho I)^{-1} (Y - Phi v), v = theta^(t) - u^(t)
+ *   theta^(t+1) = TVdenoise(u^(t) + x^(t+1))   (weight lambda)
+ *   u^(t+1) = u^(t) + x^(t+1) - theta^(t+1).
+ * Arguments as sci_gap_tv; rho from p->rho (rho = 0 reduces to GAP). */
+int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
+                float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
+
+/* ---- FP64 reductions on the GPU (results to HOST pointers) ---------------- */
+
+/* 10 log10(peak^2 / MSE), MSE over `count` floats of a against ref. */
+int sci_psnr(sci_ctx *ctx, int64_t count, const float *a, const float *ref, double peak, double *out_host,
+             hipStream_t stream);
+
+/* ||Y - Phi X||^2 (Eq. (6) data term times 2). */
+int sci_residual_sq(sci_ctx *ctx, sci_dims d, const float *C, const float *X, const float *Y, double *out_host,
+                    hipStream_t stream);
+
+/* Duality gap of the denoising problem at the dual p (dual-shaped, storage
+ * type dual_dtype): gap = lambda (TV(theta) - <D theta, p>) and primal
+ * P(theta) = 1/2 ||theta - x||^2 + lambda TV(theta) with
+ * theta = x - lambda D^T p, all in FP64. Either host output may be NULL. */
+int sci_dual_gap(sci_ctx *ctx, sci_dims d, int32_t tv, int32_t dual_dtype, float lambda, const float *X,
+                 const void *p, double *gap_host, double *primal_host, hipStream_t stream);
+
+/* ---- kernel timing (the library's own tracing) -------------------------- */
+
+/* enable != 0: from now on record a HIP event pair on the launch stream
+ * around every kernel the solver entry points launch outside graph capture
+ * (earlier records are cleared); enable == 0 stops recording. */
+int sci_profile_enable(sci_ctx *ctx, int enable);
+
+/* Number of recorded launches and their summed duration (milliseconds, from
+ * hipEventElapsedTime) for one kernel family: "fgp_stream" (one inner
+ * iteration over HBM), "fgp_fused" (all inner iterations on chip),
+ * "tv_theta" (theta = x - lambda D^T p), "project" (GAP / ADMM projection),
+ * "setup" (weights, Phi^T y, copies). Synchronises on the recorded events.
+ * Unknown family: SCI_ERR_INVALID_ARG. */
+int sci_profile_read(sci_ctx *ctx, const char *family, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCITV_H */

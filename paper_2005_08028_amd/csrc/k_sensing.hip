@@ -1,0 +1,175 @@
+// Sensing-operator kernels: Phi (Eq. (3)-(4)), Phi^T, the diagonal of
+// Phi Phi^T, and the element-wise GAP / ADMM projections (Eq. (21), Eq. (24)).
+//
+// All of them are HBM streams over [B][nx][ny] volumes: one thread per pixel
+// (i, j), consecutive threads on consecutive columns (coalesced), looping
+// over the B frames. The per-pixel sum over frames stays in a register.
+#include <hip/hip_runtime.h>
+
+#include "sci_internal.h"
+
+namespace sci {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(size_t n)
+{
+    size_t g = (n + kBlock - 1) / kBlock;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_forward(uint32_t npix, int B, const float *__restrict__ C,
+                                                    const float *__restrict__ X, float *__restrict__ Y)
+{
+    uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= npix) return;
+    float acc = 0.0f;
+    for (int k = 0; k < B; ++k) {
+        uint32_t o = (uint32_t)k * npix + pix;
+        acc = fmaf(C[o], X[o], acc);
+    }
+    Y[pix] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint(uint32_t npix, int B, const float *__restrict__ C,
+                                                    const float *__restrict__ Y, float *__restrict__ X)
+{
+    uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= npix) return;
+    float y = Y[pix];
+    for (int k = 0; k < B; ++k) {
+        uint32_t o = (uint32_t)k * npix + pix;
+        X[o] = C[o] * y;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_weights(uint32_t npix, int B, const float *__restrict__ C, float rho,
+                                                    float *__restrict__ Sinv)
+{
+    uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= npix) return;
+    float s = 0.0f;
+    for (int k = 0; k < B; ++k) {
+        float c = C[(uint32_t)k * npix + pix];
+        s = fmaf(c, c, s);
+    }
+    s = s + rho;
+    Sinv[pix] = s > 0.0f ? 1.0f / s : 0.0f;
+}
+
+// x_k = v_k + C_k r with r = (Y - sum_k C_k v_k) Sinv, v = theta (GAP) or
+// theta - u (ADMM); ADMM also writes the denoiser input s = u + x.
+template <bool ADMM>
+__global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, const float *__restrict__ theta,
+                                                    const float *__restrict__ u, const float *__restrict__ C,
+                                                    const float *__restrict__ Y, const float *__restrict__ Sinv,
+                                                    float *__restrict__ x, float *__restrict__ svol)
+{
+    uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= npix) return;
+    float acc = 0.0f;
+    for (int k = 0; k < B; ++k) {
+        uint32_t o = (uint32_t)k * npix + pix;
+        float v = ADMM ? theta[o] - u[o] : theta[o];
+        acc = fmaf(C[o], v, acc);
+    }
+    float r = (Y[pix] - acc) * Sinv[pix];
+    for (int k = 0; k < B; ++k) {
+        uint32_t o = (uint32_t)k * npix + pix;
+        float v = ADMM ? theta[o] - u[o] : theta[o];
+        float xv = fmaf(C[o], r, v);
+        x[o] = xv;
+        if (ADMM) svol[o] = u[o] + xv;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy4(uint32_t n4, const uint32_t *__restrict__ src,
+                                                  uint32_t *__restrict__ dst)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n4) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy1(uint32_t n, const uint8_t *__restrict__ src,
+                                                  uint8_t *__restrict__ dst)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero4(uint32_t n4, uint32_t *__restrict__ dst)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n4) dst[i] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero1(uint32_t n, uint8_t *__restrict__ dst)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = 0;
+}
+
+} // namespace
+
+void launch_forward(int nx, int ny, int B, const float *C, const float *X, float *Y, hipStream_t s)
+{
+    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
+    hipLaunchKernelGGL(k_forward, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, C, X, Y);
+}
+
+void launch_adjoint(int nx, int ny, int B, const float *C, const float *Y, float *X, hipStream_t s)
+{
+    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
+    hipLaunchKernelGGL(k_adjoint, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, C, Y, X);
+}
+
+void launch_weights(int nx, int ny, int B, const float *C, float rho, float *Sinv, hipStream_t s)
+{
+    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
+    hipLaunchKernelGGL(k_weights, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, C, rho, Sinv);
+}
+
+void launch_gap_project(int nx, int ny, int B, const float *theta, const float *C, const float *Y,
+                        const float *Sinv, float *x, hipStream_t s)
+{
+    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
+    hipLaunchKernelGGL(k_project<false>, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, theta,
+                       (const float *)nullptr, C, Y, Sinv, x, (float *)nullptr);
+}
+
+void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
+                         const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s)
+{
+    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
+    hipLaunchKernelGGL(k_project<true>, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, theta, u, C, Y, Sinv,
+                       x, svol);
+}
+
+// Device-to-device copy and zero fill as plain kernels, so that they can be
+// captured into HIP graphs (no memset / memcpy nodes).
+void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return;
+    if ((bytes & 3) == 0 && ((uintptr_t)src & 3) == 0 && ((uintptr_t)dst & 3) == 0) {
+        uint32_t n4 = (uint32_t)(bytes / 4);
+        hipLaunchKernelGGL(k_copy4, dim3(grid_for(n4)), dim3(kBlock), 0, s, n4, (const uint32_t *)src,
+                           (uint32_t *)dst);
+    } else {
+        hipLaunchKernelGGL(k_copy1, dim3(grid_for(bytes)), dim3(kBlock), 0, s, (uint32_t)bytes,
+                           (const uint8_t *)src, (uint8_t *)dst);
+    }
+}
+
+void launch_zero(void *dst, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return;
+    if ((bytes & 3) == 0 && ((uintptr_t)dst & 3) == 0) {
+        uint32_t n4 = (uint32_t)(bytes / 4);
+        hipLaunchKernelGGL(k_zero4, dim3(grid_for(n4)), dim3(kBlock), 0, s, n4, (uint32_t *)dst);
+    } else {
+        hipLaunchKernelGGL(k_zero1, dim3(grid_for(bytes)), dim3(kBlock), 0, s, (uint32_t)bytes, (uint8_t *)dst);
+    }
+}
+
+} // namespace sci

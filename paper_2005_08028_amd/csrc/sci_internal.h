@@ -1,0 +1,125 @@
+// Internal host-side declarations of libscitv: the context, its scratch
+// buffers, and the kernel launchers implemented in the .hip files.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/scitv.h"
+
+namespace sci {
+
+// Growable device scratch buffer owned by a context.
+struct Buf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+enum BufSlot {
+    WS_DUAL0 = 0, WS_DUAL1, WS_DUAL2, // rotating dual fields p^(s-1), p^(s), p^(s+1)
+    WS_THETA,                         // theta volume when the caller does not want it
+    WS_SVOL,                          // ADMM denoiser input s = u + x
+    WS_UVOL,                          // ADMM multiplier u
+    WS_SINV,                          // 1 / (sum_k C_k^2 + rho) image
+    WS_PARTIAL,                       // FP64 block partials of the reductions
+    WS_XTMP,                          // denoiser input copy when X_in aliases the output
+    WS_COUNT
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+// Kernel families timed by the profiler.
+enum ProfFamily { PF_FGP_STREAM = 0, PF_FGP_FUSED, PF_TV_THETA, PF_PROJECT, PF_SETUP, PF_COUNT };
+
+struct ProfRec {
+    int family;
+    hipEvent_t a, b;
+};
+
+} // namespace sci
+
+struct sci_ctx {
+    int device = 0;
+    int num_cus = 0;
+    std::string last_error;
+    sci::Buf ws[sci::WS_COUNT];
+    double *host_scalars = nullptr; // pinned, 8 doubles
+    hipStream_t capture_stream = nullptr;
+    std::map<std::string, sci::GraphEntry> graphs;
+    // profiler: event pairs around launches (not recorded while capturing)
+    bool prof_on = false;
+    bool capturing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<sci::ProfRec> prof;
+};
+
+namespace sci {
+
+// ---- context helpers (ctx.cpp) ---------------------------------------------
+int fail_hip(sci_ctx *ctx, hipError_t e, const char *what);
+int fail(sci_ctx *ctx, int status, const std::string &msg);
+int ensure_ws(sci_ctx *ctx, BufSlot slot, size_t bytes, hipStream_t stream);
+int check_launch(sci_ctx *ctx, const char *what);
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes);
+size_t dual_elem_bytes(int dual_dtype);
+
+// Scoped timing of the launches enqueued during its lifetime.
+class ProfScope {
+  public:
+    ProfScope(sci_ctx *ctx, int family, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    sci_ctx *ctx_;
+    int family_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr;
+};
+
+// ---- launchers (k_sensing.hip) ------------------------------------------------
+void launch_forward(int nx, int ny, int B, const float *C, const float *X, float *Y, hipStream_t s);
+void launch_adjoint(int nx, int ny, int B, const float *C, const float *Y, float *X, hipStream_t s);
+void launch_weights(int nx, int ny, int B, const float *C, float rho, float *Sinv, hipStream_t s);
+// x = theta + C .* ((Y - sum_k C_k theta_k) .* Sinv)
+void launch_gap_project(int nx, int ny, int B, const float *theta, const float *C, const float *Y,
+                        const float *Sinv, float *x, hipStream_t s);
+// v = theta - u; x = v + C .* ((Y - sum_k C_k v_k) .* Sinv); s = u + x
+void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
+                         const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s);
+void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+void launch_zero(void *dst, size_t bytes, hipStream_t s);
+
+// ---- launchers (k_fgp.hip) ----------------------------------------------------
+// One FGP iteration over HBM: p_next = P(w + D(x - lambda D^T w) / (8 lambda)),
+// w = 0 (mode 0), w = p_cur (mode 1), w = p_cur + beta (p_cur - p_prev) (mode 2).
+int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
+                      const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
+// theta = x - lambda D^T p; when u_out is non-null also u_out = x - theta.
+int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const void *p, float lam,
+                    float *theta, float *u_out, hipStream_t s);
+// All n inner iterations from a zero dual in one on-chip pass per tile, then
+// theta = x - lambda D^T p^(n) (and u_out = x - theta when non-null).
+// Returns false when the fused schedule does not cover the request.
+bool fused_supported(int tv, int nx, int ny, int B, int n);
+int launch_fgp_fused(int tv, int nx, int ny, int B, int n, const float *beta_tab, const float *x, float lam,
+                     float *theta, float *u_out, hipStream_t s);
+
+// ---- launchers (k_reduce.hip) -------------------------------------------------
+// Deterministic two-stage FP64 reductions into out_dev (device doubles).
+int reduce_partial_blocks();
+void launch_sqdiff(int64_t n, const float *a, const float *b, double *partials, double *out_dev, hipStream_t s);
+void launch_residual_sq(int nx, int ny, int B, const float *C, const float *X, const float *Y, double *partials,
+                        double *out_dev, hipStream_t s);
+// out_dev[0] = TV(theta), out_dev[1] = <D theta, p>, out_dev[2] = ||theta - x||^2
+int launch_gap_terms(int tv, int dual_dtype, int nx, int ny, int B, float lam, const float *x, const void *p,
+                     double *partials, double *out_dev, hipStream_t s);
+
+} // namespace sci

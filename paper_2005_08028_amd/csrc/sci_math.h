@@ -1,0 +1,74 @@
+// Per-voxel arithmetic of the TV denoiser, shared by every HIP kernel of the
+// library so that the streaming and the fused schedules evaluate identical
+// expressions (the build disables floating-point contraction; every fused
+// multiply-add below is explicit).
+//
+// Notation follows Algorithm 1 (FGP box) of the paper: w is the extrapolated
+// dual, theta = x - lambda D^T w, z = D theta, q = w + z / (8 lambda),
+// p = projection of q onto the unit ball of the TV's dual norm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sci {
+
+enum { TV_ATV = 0, TV_ITV2D = 1, TV_VTV = 2 };
+enum { DT_F32 = 0, DT_BF16 = 1, DT_F16 = 2 };
+
+// ---- dual storage types ---------------------------------------------------
+
+template <int DT> struct Dual;
+
+template <> struct Dual<DT_F32> {
+    using T = float;
+    __device__ static inline float ld(const T *p, uint32_t i) { return p[i]; }
+    __device__ static inline void st(T *p, uint32_t i, float v) { p[i] = v; }
+};
+
+// bfloat16: upper half of a float32; stores round to nearest even.
+template <> struct Dual<DT_BF16> {
+    using T = uint16_t;
+    __device__ static inline float ld(const T *p, uint32_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
+    __device__ static inline void st(T *p, uint32_t i, float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+        if ((u & 0x7fffffffu) > 0x7f800000u) r = (u >> 16) | 0x40u; // keep NaN a NaN
+        p[i] = (uint16_t)r;
+    }
+};
+
+// IEEE binary16: hardware conversion (round to nearest even).
+template <> struct Dual<DT_F16> {
+    using T = _Float16;
+    __device__ static inline float ld(const T *p, uint32_t i) { return (float)p[i]; }
+    __device__ static inline void st(T *p, uint32_t i, float v) { p[i] = (_Float16)v; }
+};
+
+// ---- the FGP step ---------------------------------------------------------
+
+// Extrapolated dual w = p + beta (p - p_prev).
+__device__ inline float extrapolate(float p, float pp, float beta) { return fmaf(beta, p - pp, p); }
+
+// theta = x - lambda (D^T w) with
+// (D^T w)(i,j) = (w_h(i,j-1) - w_h(i,j)) + (w_v(i-1,j) - w_v(i,j));
+// missing neighbours enter as 0.
+__device__ inline float theta_of(float x, float wh_left, float wh, float wv_up, float wv, float lam)
+{
+    return fmaf(-lam, (wh_left - wh) + (wv_up - wv), x);
+}
+
+// q = w + step * z.
+__device__ inline float ascend(float w, float z, float step) { return fmaf(step, z, w); }
+
+// ATV projection q / max(1, |q|): equal to clamping q to [-1, 1].
+__device__ inline float proj_atv(float q) { return fminf(fmaxf(q, -1.0f), 1.0f); }
+
+// Isotropic scale 1 / max(1, sqrt(n2)) for a squared norm n2.
+__device__ inline float iso_scale(float n2) { return n2 > 1.0f ? __builtin_amdgcn_rsqf(n2) : 1.0f; }
+
+// Squared-norm accumulation (h^2 + v^2 added to acc).
+__device__ inline float norm2_add(float acc, float h, float v) { return fmaf(v, v, fmaf(h, h, acc)); }
+
+} // namespace sci

@@ -1,0 +1,512 @@
+// Host drivers of libscitv: the TV denoiser loop (Algorithm 1, FGP / Cham
+// boxes), GAP (Eq. (21)-(22)) and ADMM (Eq. (24)-(26)) outer loops, HIP-graph
+// capture of the outer loop, and the FP64 metric entry points.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "sci_internal.h"
+
+namespace sci {
+namespace {
+
+inline size_t vol_elems(const sci_dims &d) { return (size_t)d.nx * d.ny * d.B; }
+inline size_t img_elems(const sci_dims &d) { return (size_t)d.nx * d.ny; }
+
+int use_device(sci_ctx *ctx)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) return fail_hip(ctx, e, "hipSetDevice");
+    }
+    return SCI_OK;
+}
+
+int check_dims(sci_ctx *ctx, const sci_dims &d)
+{
+    if (d.nx < 1 || d.ny < 1 || d.B < 1) return fail(ctx, SCI_ERR_INVALID_ARG, "nx, ny and B must be >= 1");
+    if ((int64_t)d.nx * d.ny * d.B >= ((int64_t)1 << 31))
+        return fail(ctx, SCI_ERR_INVALID_ARG, "B*nx*ny must be < 2^31");
+    return SCI_OK;
+}
+
+int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
+{
+    if (p.tv < SCI_TV_ATV || p.tv > SCI_TV_VTV) return fail(ctx, SCI_ERR_INVALID_ARG, "unknown tv kind");
+    if (!std::isfinite(p.lambda) || p.lambda < 0.0f) return fail(ctx, SCI_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    if (p.n_inner < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "n_inner must be >= 0");
+    if (p.accel != 0 && p.accel != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "accel must be 0 or 1");
+    if (p.dual_dtype < SCI_DUAL_F32 || p.dual_dtype > SCI_DUAL_F16)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "unknown dual dtype");
+    if (p.schedule < SCI_SCHED_AUTO || p.schedule > SCI_SCHED_FUSED)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "unknown schedule");
+    if (p.tv == SCI_TV_VTV && d.B > 32)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "VTV denoiser supports B <= 32 frames");
+    return SCI_OK;
+}
+
+// FGP momentum nu^(s+1) = (1 + sqrt(1 + 4 nu^(s)^2)) / 2, nu^(0) = 1
+// (Algorithm 1, FGP box); beta_s = (nu^(s) - 1) / nu^(s+1).
+struct Momentum {
+    double nu = 1.0;
+    double step() // returns beta_s and advances s
+    {
+        const double nu1 = (1.0 + std::sqrt(1.0 + 4.0 * nu * nu)) / 2.0;
+        const double b = (nu - 1.0) / nu1;
+        nu = nu1;
+        return b;
+    }
+};
+
+// Dual-field bookkeeping of one denoiser call: three rotating scratch
+// buffers hold p^(s-1), p^(s), p^(s+1) so no pass reads what it writes.
+struct FgpRun {
+    void *buf[3] = {nullptr, nullptr, nullptr};
+    const void *cur = nullptr;  // p^(s) (nullptr = zero)
+    const void *prev = nullptr; // p^(s-1)
+    int iters = 0;
+    double beta_prev = 0.0; // beta_(s-1), used to form w^(s)
+    Momentum mom;
+    void *next_buffer() const
+    {
+        for (void *b : buf)
+            if (b != cur && b != prev) return b;
+        return nullptr;
+    }
+};
+
+// Enqueue `n` more inner iterations.
+int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
+                hipStream_t s)
+{
+    for (int it = 0; it < n; ++it) {
+        int mode;
+        if (!r.cur) mode = 0;                                         // w = 0
+        else if (p.accel && r.iters > 0 && r.beta_prev != 0.0) mode = 2; // momentum
+        else mode = 1;                                                // w = p^(s)
+        void *out = r.next_buffer();
+        ProfScope prof(ctx, PF_FGP_STREAM, s);
+        int st = launch_fgp_stream(p.tv, p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, r.prev ? r.prev : r.cur, out,
+                                   mode, (float)r.beta_prev, p.lambda, s);
+        if (st != SCI_OK) return fail(ctx, st, "FGP pass not available for this request");
+        st = check_launch(ctx, "k_fgp_stream");
+        if (st != SCI_OK) return st;
+        const double b = r.mom.step();
+        r.beta_prev = p.accel ? b : 0.0;
+        r.prev = r.cur;
+        r.cur = out;
+        ++r.iters;
+    }
+    return SCI_OK;
+}
+
+int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s)
+{
+    const size_t bytes = 2 * vol_elems(d) * dual_elem_bytes(dual_dtype);
+    for (int k = 0; k < 3; ++k) {
+        int st = ensure_ws(ctx, (BufSlot)(WS_DUAL0 + k), bytes, s);
+        if (st != SCI_OK) return st;
+    }
+    return SCI_OK;
+}
+
+void bind_duals(sci_ctx *ctx, FgpRun &r)
+{
+    for (int k = 0; k < 3; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
+}
+
+// One denoiser call with a fixed iteration count, as used inside the outer
+// loops: theta = x - lambda D^T p^(N), and u_out = x - theta when non-null.
+// `warm` (nullable) is a scratch dual buffer holding the starting dual; the
+// final dual is left in r.cur.
+int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, float *theta,
+                  float *u_out, const void *warm, FgpRun &r, hipStream_t s)
+{
+    const size_t vb = vol_elems(d) * sizeof(float);
+    if (p.lambda == 0.0f || p.n_inner == 0) {
+        launch_copy(x, theta, vb, s);
+        if (u_out) launch_zero(u_out, vb, s);
+        r.cur = warm;
+        return check_launch(ctx, "copy");
+    }
+    const bool fused = p.schedule != SCI_SCHED_STREAM && !warm && p.dual_dtype == SCI_DUAL_F32 &&
+                       fused_supported(p.tv, d.nx, d.ny, d.B, p.n_inner);
+    if (p.schedule == SCI_SCHED_FUSED && !fused)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "fused schedule needs a cold start, float32 duals and a supported shape");
+    if (fused) {
+        float beta[256];
+        Momentum m;
+        for (int k = 0; k < p.n_inner && k < 256; ++k) beta[k] = p.accel ? (float)m.step() : 0.0f;
+        ProfScope prof(ctx, PF_FGP_FUSED, s);
+        int st = launch_fgp_fused(p.tv, d.nx, d.ny, d.B, p.n_inner, beta, x, p.lambda, theta, u_out, s);
+        if (st != SCI_OK) return fail(ctx, st, "fused FGP launch");
+        r.cur = nullptr;
+        return check_launch(ctx, "k_fgp_fused");
+    }
+    r.cur = warm;
+    r.prev = nullptr;
+    r.iters = 0;
+    r.beta_prev = 0.0;
+    r.mom = Momentum();
+    int st = fgp_iterate(ctx, d, p, x, r, p.n_inner, s);
+    if (st != SCI_OK) return st;
+    ProfScope prof(ctx, PF_TV_THETA, s);
+    st = launch_tv_theta(p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, p.lambda, theta, u_out, s);
+    if (st != SCI_OK) return fail(ctx, st, "theta pass");
+    return check_launch(ctx, "k_tv_theta");
+}
+
+// Relative duality gap lambda (TV - <D theta, p>) / P(theta) of the dual p,
+// computed in FP64 on the GPU and read back (synchronises the stream).
+int rel_gap(sci_ctx *ctx, const sci_dims &d, int tv, int dual_dtype, float lam, const float *x, const void *p,
+            double *gap, double *primal, hipStream_t s)
+{
+    const int nb = reduce_partial_blocks();
+    int st = ensure_ws(ctx, WS_PARTIAL, (3 * (size_t)nb + 8) * sizeof(double), s);
+    if (st != SCI_OK) return st;
+    double *part = (double *)ctx->ws[WS_PARTIAL].ptr;
+    double *outd = part + 3 * nb;
+    if (!p) {
+        st = ensure_ws(ctx, WS_DUAL2, 2 * vol_elems(d) * dual_elem_bytes(dual_dtype), s);
+        if (st != SCI_OK) return st;
+        launch_zero(ctx->ws[WS_DUAL2].ptr, 2 * vol_elems(d) * dual_elem_bytes(dual_dtype), s);
+        p = ctx->ws[WS_DUAL2].ptr;
+    }
+    launch_gap_terms(tv, dual_dtype, d.nx, d.ny, d.B, lam, x, p, part, outd, s);
+    st = check_launch(ctx, "k_gap_part");
+    if (st != SCI_OK) return st;
+    hipError_t e = hipMemcpyAsync(ctx->host_scalars, outd, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamSynchronize");
+    const double tvv = ctx->host_scalars[0], inner = ctx->host_scalars[1], fid = ctx->host_scalars[2];
+    *gap = (double)lam * (tvv - inner);
+    *primal = 0.5 * fid + (double)lam * tvv;
+    return SCI_OK;
+}
+
+// ---- outer loops ---------------------------------------------------------------
+
+struct OuterArgs {
+    sci_dims d;
+    sci_solver_params p;
+    const float *Y, *C, *X_init;
+    float *X_out, *theta;
+    bool admm;
+};
+
+int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
+{
+    const sci_dims &d = a.d;
+    const size_t vb = vol_elems(d) * sizeof(float);
+    float *Sinv = (float *)ctx->ws[WS_SINV].ptr;
+    float *theta = a.theta;
+    float *svol = a.admm ? (float *)ctx->ws[WS_SVOL].ptr : nullptr;
+    float *u = a.admm ? (float *)ctx->ws[WS_UVOL].ptr : nullptr;
+
+    {
+        ProfScope prof(ctx, PF_SETUP, s);
+        launch_weights(d.nx, d.ny, d.B, a.C, a.admm ? a.p.rho : 0.0f, Sinv, s);
+        if (a.X_init) launch_copy(a.X_init, theta, vb, s);     // theta^(0) = X_init
+        else launch_adjoint(d.nx, d.ny, d.B, a.C, a.Y, theta, s); // theta^(0) = Phi^T y
+        if (a.admm) launch_zero(u, vb, s);                     // u^(0) = 0
+    }
+    int st = check_launch(ctx, "outer setup");
+    if (st != SCI_OK) return st;
+    if (a.p.outer_iters == 0) {
+        launch_copy(theta, a.X_out, vb, s);
+        return check_launch(ctx, "copy");
+    }
+    FgpRun r;
+    bind_duals(ctx, r);
+    const void *warm = nullptr;
+    for (int t = 0; t < a.p.outer_iters; ++t) {
+        if (!a.admm) {
+            {
+                ProfScope prof(ctx, PF_PROJECT, s);
+                launch_gap_project(d.nx, d.ny, d.B, theta, a.C, a.Y, Sinv, a.X_out, s);
+            }
+            st = check_launch(ctx, "k_project");
+            if (st != SCI_OK) return st;
+            st = denoise_fixed(ctx, d, a.p.tv, a.X_out, theta, nullptr, warm, r, s);
+        } else {
+            {
+                ProfScope prof(ctx, PF_PROJECT, s);
+                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, a.X_out, svol, s);
+            }
+            st = check_launch(ctx, "k_project");
+            if (st != SCI_OK) return st;
+            // theta = TVdenoise(s); u = s - theta  (= u + x - theta)
+            st = denoise_fixed(ctx, d, a.p.tv, svol, theta, u, warm, r, s);
+        }
+        if (st != SCI_OK) return st;
+        if (a.p.warm_dual) warm = r.cur;
+    }
+    return SCI_OK;
+}
+
+std::string graph_key(const OuterArgs &a)
+{
+    char buf[512];
+    const sci_tv_params &t = a.p.tv;
+    snprintf(buf, sizeof buf, "%d|%d,%d,%d|%d,%.9g,%d,%d,%d,%d|%d,%.9g,%d|%p,%p,%p,%p,%p", a.admm ? 1 : 0, a.d.nx,
+             a.d.ny, a.d.B, t.tv, (double)t.lambda, t.n_inner, t.accel, t.dual_dtype, t.schedule, a.p.outer_iters,
+             (double)a.p.rho, a.p.warm_dual, (const void *)a.Y, (const void *)a.C, (const void *)a.X_init,
+             (void *)a.X_out, (void *)a.theta);
+    return buf;
+}
+
+int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const float *Y, const float *C,
+              float *X_out, float *Theta_out, const float *X_init, bool admm, hipStream_t s)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!p || !Y || !C || !X_out) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    st = check_tv(ctx, p->tv, d);
+    if (st != SCI_OK) return st;
+    if (p->outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "outer_iters must be >= 0");
+    if (!std::isfinite(p->rho) || p->rho < 0.0f) return fail(ctx, SCI_ERR_INVALID_ARG, "rho must be finite and >= 0");
+    if (p->warm_dual != 0 && p->warm_dual != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "warm_dual must be 0 or 1");
+    const size_t vb = vol_elems(d) * sizeof(float), ib = img_elems(d) * sizeof(float);
+    const void *ins[3] = {Y, C, X_init};
+    const size_t inb[3] = {ib, vb, vb};
+    for (int k = 0; k < 3; ++k)
+        if (overlaps(X_out, vb, ins[k], inb[k]) || overlaps(Theta_out, vb, ins[k], inb[k]))
+            return fail(ctx, SCI_ERR_ALIAS, "outputs must not overlap Y, C or X_init");
+    if (overlaps(X_out, vb, Theta_out, vb)) return fail(ctx, SCI_ERR_ALIAS, "X_out and Theta_out overlap");
+    st = use_device(ctx);
+    if (st != SCI_OK) return st;
+
+    // scratch first: a graph must never see a buffer that later grows
+    if ((st = ensure_ws(ctx, WS_SINV, ib, s)) != SCI_OK) return st;
+    if (!Theta_out && (st = ensure_ws(ctx, WS_THETA, vb, s)) != SCI_OK) return st;
+    if (admm && ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK || (st = ensure_ws(ctx, WS_UVOL, vb, s)) != SCI_OK))
+        return st;
+    if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
+
+    OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm};
+    if (!p->use_graph) return enqueue_outer(ctx, a, s);
+
+    const std::string key = graph_key(a);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamBeginCapture");
+        ctx->capturing = true;
+        st = enqueue_outer(ctx, a, ctx->capture_stream);
+        ctx->capturing = false;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->capture_stream, &g);
+        if (st != SCI_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail_hip(ctx, e, "hipGraphInstantiate");
+        it = ctx->graphs.emplace(key, GraphEntry{exec}).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second.exec, s);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipGraphLaunch");
+    return SCI_OK;
+}
+
+int read_scalars(sci_ctx *ctx, const double *dev, int n, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(ctx->host_scalars, dev, n * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamSynchronize");
+    return SCI_OK;
+}
+
+} // namespace
+} // namespace sci
+
+using namespace sci;
+
+extern "C" {
+
+int sci_forward(sci_ctx *ctx, sci_dims d, const float *C, const float *X, float *Y, hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!C || !X || !Y) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    const size_t vb = vol_elems(d) * sizeof(float), ib = img_elems(d) * sizeof(float);
+    if (overlaps(Y, ib, C, vb) || overlaps(Y, ib, X, vb)) return fail(ctx, SCI_ERR_ALIAS, "Y overlaps C or X");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    launch_forward(d.nx, d.ny, d.B, C, X, Y, stream);
+    return check_launch(ctx, "k_forward");
+}
+
+int sci_adjoint(sci_ctx *ctx, sci_dims d, const float *C, const float *Y, float *X, hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!C || !X || !Y) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    const size_t vb = vol_elems(d) * sizeof(float), ib = img_elems(d) * sizeof(float);
+    if (overlaps(X, vb, C, vb) || overlaps(X, vb, Y, ib)) return fail(ctx, SCI_ERR_ALIAS, "X overlaps C or Y");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    launch_adjoint(d.nx, d.ny, d.B, C, Y, X, stream);
+    return check_launch(ctx, "k_adjoint");
+}
+
+int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *X_in, float *Theta_out,
+                   const void *dual_init, void *dual_out, double *rel_gap_out, int32_t *iters_out,
+                   hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!p || !X_in || !Theta_out) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    if ((st = check_tv(ctx, *p, d)) != SCI_OK) return st;
+    const bool adaptive = p->gap_tol > 0.0;
+    if (adaptive && (p->n_inner_max < 1 || !std::isfinite(p->gap_tol)))
+        return fail(ctx, SCI_ERR_INVALID_ARG, "gap_tol > 0 needs n_inner_max >= 1");
+    const size_t vb = vol_elems(d) * sizeof(float);
+    const size_t db = 2 * vol_elems(d) * dual_elem_bytes(p->dual_dtype);
+    if (overlaps(Theta_out, vb, X_in, vb) || overlaps(Theta_out, vb, dual_init, db) ||
+        overlaps(dual_out, db, X_in, vb) || overlaps(dual_out, db, dual_init, db) ||
+        overlaps(dual_out, db, Theta_out, vb))
+        return fail(ctx, SCI_ERR_ALIAS, "outputs must not overlap the inputs or each other");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, p->dual_dtype, stream)) != SCI_OK) return st;
+
+    sci_tv_params q = *p;
+    const bool want_dual = dual_out || rel_gap_out || adaptive;
+    if (want_dual && q.schedule == SCI_SCHED_FUSED)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule does not return the dual field");
+    if (want_dual) q.schedule = SCI_SCHED_STREAM;
+    FgpRun r;
+    bind_duals(ctx, r);
+
+    if (q.lambda == 0.0f) {
+        launch_copy(X_in, Theta_out, vb, stream);
+        if (dual_out) {
+            if (dual_init) launch_copy(dual_init, dual_out, db, stream);
+            else launch_zero(dual_out, db, stream);
+        }
+        if ((st = check_launch(ctx, "copy")) != SCI_OK) return st;
+        if (rel_gap_out) *rel_gap_out = 0.0;
+        if (iters_out) *iters_out = 0;
+        if (rel_gap_out) {
+            hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamSynchronize");
+        }
+        return SCI_OK;
+    }
+
+    int status = SCI_OK;
+    double gap = 0.0, primal = 0.0;
+    if (!adaptive) {
+        if ((st = denoise_fixed(ctx, d, q, X_in, Theta_out, nullptr, dual_init, r, stream)) != SCI_OK) return st;
+        if (rel_gap_out) {
+            if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_in, r.cur, &gap, &primal, stream)) != SCI_OK)
+                return st;
+        }
+    } else {
+        const int every = q.gap_check_every > 0 ? q.gap_check_every : 10;
+        r.cur = dual_init;
+        status = SCI_NOT_CONVERGED;
+        while (r.iters < q.n_inner_max) {
+            const int n = std::min(every, q.n_inner_max - r.iters);
+            if ((st = fgp_iterate(ctx, d, q, X_in, r, n, stream)) != SCI_OK) return st;
+            if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_in, r.cur, &gap, &primal, stream)) != SCI_OK)
+                return st;
+            const double rel = primal > 0.0 ? gap / primal : 0.0;
+            if (rel <= q.gap_tol) {
+                status = SCI_OK;
+                break;
+            }
+        }
+        st = launch_tv_theta(q.dual_dtype, d.nx, d.ny, d.B, X_in, r.cur, q.lambda, Theta_out, nullptr, stream);
+        if (st == SCI_OK) st = check_launch(ctx, "k_tv_theta");
+        if (st != SCI_OK) return st;
+    }
+    if (dual_out) {
+        if (r.cur) launch_copy(r.cur, dual_out, db, stream);
+        else launch_zero(dual_out, db, stream);
+        if ((st = check_launch(ctx, "copy")) != SCI_OK) return st;
+    }
+    if (rel_gap_out) *rel_gap_out = primal > 0.0 ? gap / primal : 0.0;
+    if (iters_out) *iters_out = (q.n_inner == 0 && !adaptive) ? 0 : (adaptive ? r.iters : q.n_inner);
+    return status;
+}
+
+int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
+               float *Theta_out, const float *X_init, hipStream_t stream)
+{
+    return run_outer(ctx, d, p, Y, C, X_out, Theta_out, X_init, false, stream);
+}
+
+int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
+                float *Theta_out, const float *X_init, hipStream_t stream)
+{
+    return run_outer(ctx, d, p, Y, C, X_out, Theta_out, X_init, true, stream);
+}
+
+int sci_psnr(sci_ctx *ctx, int64_t count, const float *a, const float *ref, double peak, double *out_host,
+             hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    if (count < 1 || !a || !ref || !out_host || !std::isfinite(peak) || peak <= 0.0)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "psnr: bad arguments");
+    int st = use_device(ctx);
+    if (st != SCI_OK) return st;
+    const int nb = reduce_partial_blocks();
+    if ((st = ensure_ws(ctx, WS_PARTIAL, (3 * (size_t)nb + 8) * sizeof(double), stream)) != SCI_OK) return st;
+    double *part = (double *)ctx->ws[WS_PARTIAL].ptr;
+    launch_sqdiff(count, a, ref, part, part + 3 * nb, stream);
+    if ((st = check_launch(ctx, "k_sqdiff")) != SCI_OK) return st;
+    if ((st = read_scalars(ctx, part + 3 * nb, 1, stream)) != SCI_OK) return st;
+    const double mse = ctx->host_scalars[0] / (double)count;
+    *out_host = 10.0 * std::log10(peak * peak / mse);
+    return SCI_OK;
+}
+
+int sci_residual_sq(sci_ctx *ctx, sci_dims d, const float *C, const float *X, const float *Y, double *out_host,
+                    hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!C || !X || !Y || !out_host) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    const int nb = reduce_partial_blocks();
+    if ((st = ensure_ws(ctx, WS_PARTIAL, (3 * (size_t)nb + 8) * sizeof(double), stream)) != SCI_OK) return st;
+    double *part = (double *)ctx->ws[WS_PARTIAL].ptr;
+    launch_residual_sq(d.nx, d.ny, d.B, C, X, Y, part, part + 3 * nb, stream);
+    if ((st = check_launch(ctx, "k_resid")) != SCI_OK) return st;
+    if ((st = read_scalars(ctx, part + 3 * nb, 1, stream)) != SCI_OK) return st;
+    *out_host = ctx->host_scalars[0];
+    return SCI_OK;
+}
+
+int sci_dual_gap(sci_ctx *ctx, sci_dims d, int32_t tv, int32_t dual_dtype, float lambda, const float *X,
+                 const void *p, double *gap_host, double *primal_host, hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!X || !p) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    if (tv < SCI_TV_ATV || tv > SCI_TV_VTV || dual_dtype < SCI_DUAL_F32 || dual_dtype > SCI_DUAL_F16 ||
+        !std::isfinite(lambda) || lambda < 0.0f)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "dual_gap: bad tv, dtype or lambda");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    double gap = 0.0, primal = 0.0;
+    if ((st = rel_gap(ctx, d, tv, dual_dtype, lambda, X, p, &gap, &primal, stream)) != SCI_OK) return st;
+    if (gap_host) *gap_host = gap;
+    if (primal_host) *primal_host = primal;
+    return SCI_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,373 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle.
+
+Inputs come from the seeded generator (scene, masks, noise); the measurement
+Y is formed by the oracle in FP64 and rounded once to float32, and both sides
+consume exactly those float32 arrays. Floating-point results are compared by
+relative L2 error (bar 1e-4) and PSNR difference (bar 0.01 dB); results that
+the oracle cannot produce at full size are checked through properties that
+hold at any size.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2005_08028_amd import synth  # noqa: E402
+
+REL_TOL = 1e-4
+PSNR_TOL = 0.01
+
+
+def f32(v):
+    """The C ABI takes lambda and rho as float32; the oracle gets the same values."""
+    return float(np.float32(v))
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_08028_amd import scitv
+    return scitv
+
+
+@pytest.fixture(scope="module")
+def ctx(sc):
+    c = sc.Context(0)
+    yield c.handle
+    c.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, ref):
+    n = np.linalg.norm(ref)
+    return np.linalg.norm(a - ref) / (n if n > 0 else 1.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Sensing operator.
+# ---------------------------------------------------------------------------
+
+SHAPES = [(1, 1, 1), (2, 3, 70), (8, 17, 255), (3, 130, 129), (8, 256, 256)]
+
+
+@pytest.mark.parametrize("B,nx,ny", SHAPES)
+def test_forward_adjoint(sc, ctx, B, nx, ny):
+    r = np.random.default_rng(nx * 1000 + ny)
+    C = synth.masks_bernoulli(r, nx, ny, B)
+    X = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    Yv = r.uniform(size=(nx, ny)).astype(np.float32)
+    Y = host(sc.sci_forward(ctx, dev(C), dev(X)))
+    assert rel_l2(Y, orc.forward(C, X)) < 1e-6
+    Xa = host(sc.sci_adjoint(ctx, dev(C), dev(Yv)))
+    np.testing.assert_array_equal(Xa, orc.adjoint(C, Yv).astype(np.float32))
+    lhs = (Y * Yv).sum()
+    rhs = (X.astype(np.float64) * Xa).sum()
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs) + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# TV denoiser.
+# ---------------------------------------------------------------------------
+
+DEN_SHAPES = [(1, 1, 1), (1, 2, 2), (2, 5, 3), (3, 17, 63), (2, 33, 125), (4, 130, 64), (9, 20, 70), (24, 16, 64)]
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+@pytest.mark.parametrize("B,nx,ny", DEN_SHAPES)
+def test_denoise_matches_oracle(sc, ctx, tv, B, nx, ny):
+    r = np.random.default_rng(B * 7 + nx * 13 + ny)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    for n, accel in ((1, True), (2, True), (7, True), (5, False)):
+        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, schedule="stream")
+        dual = torch.empty((2, B, nx, ny), device="cuda")
+        th, _, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, dual_out=dual)
+        ref, pref = orc.tv_denoise(x, f32(0.1), n, tv, accel=accel, return_dual=True)
+        e = rel_l2(host(th), ref)
+        ep = np.abs(host(dual) - pref).max()
+        say(f"denoise {tv} B={B} {nx}x{ny} N={n} accel={accel}: rel-L2 {e:.2e}, dual max-abs {ep:.2e}")
+        assert its == n
+        assert e <= REL_TOL
+        assert ep <= 1e-4
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoise_default_schedule_matches_oracle(sc, ctx, tv):
+    x = np.random.default_rng(3).uniform(size=(6, 70, 150)).astype(np.float32)
+    prm = sc.tv_params(tv=tv, lam=0.07, n_inner=10)
+    th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm)
+    ref = orc.tv_denoise(x, f32(0.07), 10, tv)
+    assert rel_l2(host(th), ref) <= REL_TOL
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoise_warm_start(sc, ctx, tv):
+    r = np.random.default_rng(4)
+    x = r.uniform(size=(3, 40, 90)).astype(np.float32)
+    p0 = orc.project_dual(r.normal(size=(2, 3, 40, 90)), tv)
+    p0[0, :, :, -1] = 0.0
+    p0[1, :, -1, :] = 0.0
+    p0 = p0.astype(np.float32)
+    prm = sc.tv_params(tv=tv, lam=0.1, n_inner=6)
+    th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=dev(p0))
+    ref = orc.tv_denoise(x, f32(0.1), 6, tv, p_init=p0)
+    assert rel_l2(host(th), ref) <= REL_TOL
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoise_special_cases(sc, ctx, tv):
+    x = np.random.default_rng(5).uniform(size=(4, 31, 77)).astype(np.float32)
+    for prm in (sc.tv_params(tv=tv, lam=0.0, n_inner=5), sc.tv_params(tv=tv, lam=0.1, n_inner=0)):
+        th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm)
+        np.testing.assert_array_equal(host(th), x)
+    c = np.full((4, 31, 77), 0.37, np.float32)
+    th, _, _, _ = sc.sci_tv_denoise(ctx, dev(c), sc.tv_params(tv=tv, lam=0.1, n_inner=8))
+    np.testing.assert_array_equal(host(th), c)
+    # lambda -> infinity: per-frame means
+    xs = np.random.default_rng(6).uniform(size=(3, 8, 8)).astype(np.float32)
+    th, _, _, _ = sc.sci_tv_denoise(ctx, dev(xs), sc.tv_params(tv=tv, lam=50.0, n_inner=3000))
+    means = xs.astype(np.float64).mean(axis=(1, 2), keepdims=True)
+    assert np.abs(host(th) - means).max() < 1e-4
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_dual_gap_matches_oracle(sc, ctx, tv):
+    x = np.random.default_rng(7).uniform(size=(5, 45, 66)).astype(np.float32)
+    dual = torch.empty((2, 5, 45, 66), device="cuda")
+    _, g_rel, _, _ = sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv=tv, lam=0.1, n_inner=12), dual_out=dual,
+                                       want_gap=True)
+    p = host(dual)
+    g_or, prim_or = orc.dual_gap(x, p, f32(0.1), tv)
+    g_gpu, prim_gpu = sc.sci_dual_gap(ctx, dev(x), dual, tv, 0.1)
+    assert abs(g_gpu - g_or) <= 1e-9 * prim_or
+    assert abs(prim_gpu - prim_or) <= 1e-10 * prim_or
+    assert abs(g_rel - g_or / prim_or) <= 1e-9
+    # constant input: TV = 0, gap = 0
+    c = np.full((2, 9, 9), 0.5, np.float32)
+    g0, p0 = sc.sci_dual_gap(ctx, dev(c), torch.zeros((2, 2, 9, 9), device="cuda"), tv, 0.1)
+    assert g0 == 0.0 and p0 == 0.0
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_gap_controlled_denoise(sc, ctx, tv):
+    x = np.random.default_rng(8).uniform(size=(4, 64, 64)).astype(np.float32)
+    prm = sc.tv_params(tv=tv, lam=0.1, gap_tol=1e-4, n_inner_max=2000, gap_check_every=5)
+    th, g, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, want_gap=True)
+    say(f"{tv}: gap<=1e-4 after {its} iterations (rel gap {g:.2e})")
+    assert st == sc.SCI_OK and g <= 1e-4 and its % 5 == 0
+    ref = orc.tv_denoise(x, f32(0.1), its, tv)
+    assert rel_l2(host(th), ref) <= REL_TOL
+    prm = sc.tv_params(tv=tv, lam=0.1, gap_tol=1e-12, n_inner_max=6, gap_check_every=4)
+    _, _, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, want_gap=True)
+    assert st == sc.SCI_NOT_CONVERGED and its == 6
+
+
+@pytest.mark.parametrize("dt,bound", [("bf16", 2e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_denoise_16bit_duals(sc, ctx, tv, dt, bound):
+    """16-bit dual storage: float32 arithmetic, rounding at every store. The
+    error against the FP64 oracle is bounded by the per-store rounding
+    (4 lambda u per iteration for u = 2^-8 (bf16) / 2^-11 (f16))."""
+    x = np.random.default_rng(9).uniform(size=(4, 50, 130)).astype(np.float32)
+    prm = sc.tv_params(tv=tv, lam=0.1, n_inner=10, dual_dtype=dt)
+    th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm)
+    ref = orc.tv_denoise(x, f32(0.1), 10, tv)
+    e = rel_l2(host(th), ref)
+    amax = np.abs(host(th) - ref).max()
+    u = 2.0 ** -8 if dt == "bf16" else 2.0 ** -11
+    say(f"{tv} {dt} duals: rel-L2 {e:.2e}, max-abs {amax:.2e} (per-step bound {4 * 0.1 * u:.2e})")
+    assert e <= bound
+    assert amax <= 10 * 4 * 0.1 * u
+
+
+# ---------------------------------------------------------------------------
+# GAP / ADMM.
+# ---------------------------------------------------------------------------
+
+def run_solver(sc, ctx, solver, Y, C, **kw):
+    prm = sc.solver_params(**kw)
+    fn = sc.sci_gap_tv if solver == "gap" else sc.sci_admm_tv
+    th = torch.empty(C.shape, device="cuda")
+    x, _ = fn(ctx, dev(Y), dev(C), prm, Theta_out=th)
+    return host(x), host(th)
+
+
+def oracle_solver(solver, Y, C, lam, rho, T, N, tv):
+    if solver == "gap":
+        return orc.gap_tv(Y, C, f32(lam), T, N, tv=tv)
+    return orc.admm_tv(Y, C, f32(lam), f32(rho), T, N, tv=tv)
+
+
+def test_gap_atv_256x8(sc, ctx):
+    cfg = synth.CONFIGS["gap_atv_256x8"]
+    pr = synth.problem_from_config("gap_atv_256x8")
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    x, th = run_solver(sc, ctx, "gap", Y, pr.masks, outer_iters=cfg["T"], tv="atv", lam=cfg["lam"],
+                       n_inner=cfg["N"])
+    xr, thr = orc.gap_tv(Y, pr.masks, f32(cfg["lam"]), cfg["T"], cfg["N"], tv="atv")
+    e, dp = rel_l2(x, xr), abs(orc.psnr(x, pr.truth) - orc.psnr(xr, pr.truth))
+    say(f"GAP-ATV 256x256x8 50x5: rel-L2 {e:.2e}, dPSNR {dp:.2e} dB, PSNR {orc.psnr(xr, pr.truth):.2f}")
+    assert e <= REL_TOL and dp <= PSNR_TOL
+    assert rel_l2(th, thr) <= REL_TOL
+
+
+@pytest.fixture(scope="module")
+def six_problem():
+    pr = synth.problem_from_config("six_256x8")
+    return pr, orc.measurement(pr.masks, pr.truth, pr.noise)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_six_variants_256x8(sc, ctx, six_problem, solver, tv):
+    cfg = synth.CONFIGS["six_256x8"]
+    pr, Y = six_problem
+    x, th = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=cfg["T"], rho=cfg["rho"], tv=tv,
+                       lam=cfg["lam"], n_inner=cfg["N"])
+    xr, thr = oracle_solver(solver, Y, pr.masks, cfg["lam"], cfg["rho"], cfg["T"], cfg["N"], tv)
+    e, dp = rel_l2(x, xr), abs(orc.psnr(x, pr.truth) - orc.psnr(xr, pr.truth))
+    say(f"{solver}-{tv} 256x256x8 100x10: rel-L2 {e:.2e}, dPSNR {dp:.2e} dB, oracle PSNR {orc.psnr(xr, pr.truth):.2f}")
+    assert e <= REL_TOL and dp <= PSNR_TOL
+    assert rel_l2(th, thr) <= REL_TOL
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_ragged_small_solves(sc, ctx, solver):
+    for (B, nx, ny), tv in (((3, 37, 101), "atv"), ((5, 64, 63), "itv2d"), ((10, 29, 130), "vtv"), ((1, 1, 1), "atv")):
+        pr = synth.make_problem(nx, ny, B, seed=nx + ny, sigma=0.01, radius=(2.0, 8.0))
+        Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+        x, th = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=7, rho=0.05, tv=tv, lam=0.1, n_inner=4)
+        xr, thr = oracle_solver(solver, Y, pr.masks, 0.1, 0.05, 7, 4, tv)
+        assert rel_l2(x, xr) <= REL_TOL, (B, nx, ny, tv)
+        assert rel_l2(th, thr) <= REL_TOL, (B, nx, ny, tv)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_graph_replay_matches_eager(sc, ctx, solver):
+    pr = synth.make_problem(96, 80, 8, seed=12, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    x0, t0 = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=6, rho=0.01, tv="itv2d", n_inner=5)
+    Yd, Cd = dev(Y), dev(pr.masks)
+    prm = sc.solver_params(outer_iters=6, rho=0.01, tv="itv2d", n_inner=5, use_graph=True)
+    fn = sc.sci_gap_tv if solver == "gap" else sc.sci_admm_tv
+    xg = torch.empty(Cd.shape, device="cuda")
+    tg = torch.empty(Cd.shape, device="cuda")
+    for rep in range(3):
+        xg.fill_(float("nan"))
+        fn(ctx, Yd, Cd, prm, X_out=xg, Theta_out=tg)
+        _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+        np.testing.assert_array_equal(host(xg), x0)
+        np.testing.assert_array_equal(host(tg), t0)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_constant_frames_fixed_point(sc, ctx, solver, tv):
+    B, nx, ny = 4, 40, 70
+    truth = np.broadcast_to(np.array([0.2, 0.5, 0.9, 0.1], np.float32)[:, None, None], (B, nx, ny)).copy()
+    C = synth.masks_bernoulli(np.random.default_rng(13), nx, ny, B)
+    Y = orc.measurement(C, truth)
+    prm = sc.solver_params(outer_iters=5, rho=0.01, tv=tv, n_inner=5)
+    fn = sc.sci_gap_tv if solver == "gap" else sc.sci_admm_tv
+    x, _ = fn(ctx, dev(Y), dev(C), prm, X_init=dev(truth))
+    assert np.abs(host(x) - truth).max() < 1e-6
+
+
+def test_gap_iterates_satisfy_measurement(sc, ctx):
+    pr = synth.make_problem(128, 96, 8, seed=14)
+    Y = orc.measurement(pr.masks, pr.truth)
+    S = (pr.masks.astype(np.float64) ** 2).sum(axis=0)
+    for T in (1, 4):
+        x, _ = run_solver(sc, ctx, "gap", Y, pr.masks, outer_iters=T, tv="vtv", n_inner=5)
+        f = orc.forward(pr.masks, x)
+        assert np.abs(f - Y)[S > 0].max() < 1e-5
+
+
+def test_metrics_match_oracle(sc, ctx):
+    r = np.random.default_rng(15)
+    a = r.uniform(size=(6, 33, 71)).astype(np.float32)
+    b = (a + r.normal(scale=0.03, size=a.shape)).astype(np.float32)
+    assert abs(sc.sci_psnr(ctx, dev(a), dev(b)) - orc.psnr(a, b)) < 1e-9
+    C = synth.masks_bernoulli(r, 33, 71, 6)
+    Y = r.uniform(size=(33, 71)).astype(np.float32)
+    rs = sc.sci_residual_sq(ctx, dev(C), dev(a), dev(Y))
+    assert abs(rs - orc.residual_sq(C, a, Y)) <= 1e-12 * rs
+
+
+def test_errors_are_reported(sc, ctx):
+    x = torch.zeros((2, 8, 8), device="cuda")
+    with pytest.raises(sc.SciError) as e:
+        sc.sci_tv_denoise(ctx, x, sc.tv_params(lam=-1.0))
+    assert e.value.status == sc.SCI_ERR_INVALID_ARG
+    with pytest.raises(sc.SciError) as e:
+        sc.sci_tv_denoise(ctx, x, sc.tv_params(lam=float("nan")))
+    assert e.value.status == sc.SCI_ERR_INVALID_ARG
+    with pytest.raises(sc.SciError) as e:
+        sc.sci_tv_denoise(ctx, x, sc.tv_params(), Theta_out=x)
+    assert e.value.status == sc.SCI_ERR_ALIAS
+    C = torch.ones((2, 8, 8), device="cuda")
+    Y = torch.zeros((8, 8), device="cuda")
+    with pytest.raises(sc.SciError) as e:
+        sc.sci_gap_tv(ctx, Y, C, sc.solver_params(outer_iters=-1))
+    assert e.value.status == sc.SCI_ERR_INVALID_ARG
+    with pytest.raises(sc.SciError) as e:
+        sc.sci_gap_tv(ctx, Y, C, sc.solver_params(outer_iters=2), X_out=C)
+    assert e.value.status == sc.SCI_ERR_ALIAS
+    with pytest.raises(sc.SciError) as e:
+        big = torch.zeros((33, 4, 4), device="cuda")
+        sc.sci_tv_denoise(ctx, big, sc.tv_params(tv="vtv"))
+    assert e.value.status == sc.SCI_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# The large CACTI-style workload at full size.
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cacti():
+    pr = synth.problem_from_config("cacti_1024x24")
+    return pr, orc.measurement(pr.masks, pr.truth, pr.noise)
+
+
+def test_cacti_full_size_two_outer_iterations(sc, ctx, cacti):
+    """Same kernels and launch shapes as the benchmark, at 1024x1024x24,
+    for two outer iterations the oracle can afford."""
+    pr, Y = cacti
+    x, th = run_solver(sc, ctx, "gap", Y, pr.masks, outer_iters=2, tv="itv2d", lam=0.1, n_inner=10)
+    xr, thr = orc.gap_tv(Y, pr.masks, f32(0.1), 2, 10, tv="itv2d")
+    e = rel_l2(x, xr)
+    say(f"GAP-ITV2D 1024x1024x24 T=2: rel-L2 {e:.2e}")
+    assert e <= REL_TOL and rel_l2(th, thr) <= REL_TOL
+
+
+def test_cacti_full_solve_properties(sc, ctx, cacti):
+    """Full 200 x 10 solve: every GAP iterate lies on {Phi x = Y} where
+    sum_k C_k^2 > 0, and the reconstruction beats the back-projection."""
+    pr, Y = cacti
+    x, _ = run_solver(sc, ctx, "gap", Y, pr.masks, outer_iters=200, tv="itv2d", lam=0.1, n_inner=10,
+                      use_graph=True)
+    assert np.isfinite(x).all()
+    S = (pr.masks.astype(np.float64) ** 2).sum(axis=0)
+    f = orc.forward(pr.masks, x)
+    assert np.abs(f - Y)[S > 0].max() < 1e-4
+    p_x = orc.psnr(x, pr.truth)
+    p_0 = orc.psnr(orc.adjoint(pr.masks, Y) / np.maximum(S, 1)[None], pr.truth)
+    say(f"GAP-ITV2D 1024x1024x24 200x10: PSNR {p_x:.2f} dB (back-projection {p_0:.2f})")
+    assert p_x > p_0 + 5.0
