@@ -83,6 +83,7 @@ def main() -> int:
     ap.add_argument("--outer", type=int, default=200, help="outer iterations per step (default: the full 200)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "stream", "fused"])
     ap.add_argument("--dual-dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--no-autotune", action="store_true", help="skip the tile-shape autotuner (default shape)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations of the oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -121,6 +122,15 @@ def main() -> int:
     Th_out = torch.empty_like(C)
     prm = scitv.solver_params(outer_iters=T, tv=cfg["tv"], lam=lam, n_inner=N, schedule=args.schedule,
                               dual_dtype=args.dual_dtype)
+
+    tuned = None
+    if not args.no_autotune and cfg["tv"] in ("atv", "itv2d") and args.schedule != "stream":
+        # tile shape of the fused denoiser, timed on this measurement's back-projection
+        x0 = scitv.sci_adjoint(h, C, Y)
+        best, passes, times = scitv.sci_autotune(h, x0, prm.tv)
+        tuned = {"best_shape": best, "rows_waves_cols": scitv.sci_tile_shape_info(best), "passes": passes,
+                 "ms_per_denoise_by_shape_and_passes": [[round(t, 4) for t in row] for row in times]}
+        del x0
 
     def step():
         scitv.sci_gap_tv(h, Y, C, prm, X_out=X_out, Theta_out=Th_out)
@@ -176,7 +186,7 @@ def main() -> int:
                    "schedule": args.schedule, "dual_dtype": args.dual_dtype, "graph": False},
         "roofline": roofline,
         "kernel_ms_per_step": {f: round(ms / steps, 3) for f, (n, ms) in fams.items()},
-        "psnr_db": round(psnr, 4), "residual_sq": resid,
+        "psnr_db": round(psnr, 4), "residual_sq": resid, "autotune": tuned,
     }
 
     if args.calibrate_copy:

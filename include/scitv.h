@@ -28,7 +28,7 @@
  *   - Every call validates its arguments before launching anything and
  *     returns a status code; no C++ exception crosses this interface.
  *     Outputs must not overlap inputs (SCI_ERR_ALIAS).
- *   - Sizes: nx, ny, B >= 1 and B*nx*ny < 2^31.
+ *   - Sizes: nx, ny, B >= 1, B <= 65535 and B*nx*ny < 2^31.
  *   - A context may be used from one host thread at a time. Calls that
  *     share a context and overlap on different streams race on its scratch.
  */
@@ -92,6 +92,11 @@ typedef struct {
                                 at most n_inner_max iterations); <= 0 runs exactly n_inner */
     int32_t n_inner_max;
     int32_t gap_check_every;
+    int32_t tile_shape;      /* fused schedule: 0 = autotuned for this problem (sci_autotune) or the
+                                default; k >= 1 = tile shape k (see sci_tile_shape_info) */
+    int32_t tile_passes;     /* fused schedule: passes over HBM per denoiser call (each runs about
+                                n_inner / tile_passes iterations, at most 10); 0 = autotuned or
+                                default (passes of about 5 iterations) */
 } sci_tv_params;
 
 /* Outer framework parameters (Algorithm 1; ADMM of Eq. (24)-(26)). */
@@ -158,6 +163,29 @@ int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float
  * Arguments as sci_gap_tv; rho from p->rho (rho = 0 reduces to GAP). */
 int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
                 float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
+
+/* ---- tile-shape autotuning of the fused schedule -------------------------- */
+
+/* Number of tile shapes of the fused denoiser kernel. */
+int sci_tile_shape_count(void);
+
+/* Shape k (1-based, as in sci_tv_params.tile_shape): a workgroup covers
+ * 64 * cols_per_lane columns x (rows_per_wave * waves_per_group) rows of one
+ * frame, halo included. Any output pointer may be NULL. */
+int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_per_group, int32_t *cols_per_lane);
+
+/* Time the fused denoiser (p->tv, p->lambda, p->n_inner, p->dual_dtype) on
+ * input X (video, device) for every tile shape and for 3 pass counts (the
+ * fewest passes of at most 10 iterations, one more, two more), and remember
+ * the fastest pair in the context for later calls with the same TV kind,
+ * dual dtype, sizes and n_inner whose tile_shape / tile_passes are 0.
+ * best_shape_out / best_passes_out (nullable, HOST) receive the winner;
+ * times_ms_out (nullable, HOST array of 3 * sci_tile_shape_count() doubles,
+ * [shape][pass-count candidate]) the mean time per denoiser call, NaN where a
+ * candidate was skipped. Synchronises `stream`. ATV and ITV2D only
+ * (SCI_ERR_UNSUPPORTED for VTV). */
+int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *X, int32_t *best_shape_out,
+                 int32_t *best_passes_out, double *times_ms_out, hipStream_t stream);
 
 /* ---- FP64 reductions on the GPU (results to HOST pointers) ---------------- */
 

@@ -4,7 +4,7 @@
 // Mapping. One wavefront owns a strip of 64 consecutive columns and walks
 // down a segment of rows. Lane l holds column j = 62*strip - 1 + l, so lanes
 // 0 and 63 are halo lanes and lanes 1..62 write results: horizontal
-// neighbours come from the adjacent lane by a cross-lane shuffle, vertical
+// neighbours come from the adjacent lane by a DPP wavefront shift, vertical
 // neighbours from the registers of the previous row. Each row step loads
 // p^(s), p^(s-1) (both channels) and x of the NEXT row once, coalesced
 // (64 lanes x 4 bytes), rebuilds w and theta for it on chip, and finishes
@@ -44,6 +44,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
     const bool jin = j >= 0 && j < ny;     // column inside the image
     const bool hin = j >= 0 && j < ny - 1; // column has a horizontal difference
     const bool outl = lane >= 1 && lane <= kStrip && j < ny;
+    const float step_h = hin ? step : 0.0f; // no horizontal difference at j = ny-1 (and outside)
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t V = plane * (uint32_t)B;
     const int kbase = (KB == 1) ? (int)blockIdx.y : 0;
@@ -66,12 +67,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
             wh0[kk] = load_w(o, hin);
             wv0[kk] = load_w(V + o, jin && i0 < nx - 1);
             const float xv = jin ? x[o] : 0.0f;
-            th0[kk] = theta_of(xv, __shfl_up(wh0[kk], 1), wh0[kk], wvm, wv0[kk], lam);
+            th0[kk] = theta_of(xv, from_left(wh0[kk]), wh0[kk], wvm, wv0[kk], lam);
         }
     }
 
     for (int i = i0; i < i1; ++i) {
         const bool nxt = i + 1 < nx;
+        const float step_v = nxt ? step : 0.0f; // no vertical difference in the last row
         float qh[KB], qv[KB];
         float n2 = 0.0f;
 #pragma unroll
@@ -84,13 +86,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
                     wh1 = load_w(o1, hin);
                     wv1 = load_w(V + o1, jin && i + 1 < nx - 1);
                     const float x1 = jin ? x[o1] : 0.0f;
-                    th1 = theta_of(x1, __shfl_up(wh1, 1), wh1, wv0[kk], wv1, lam);
+                    th1 = theta_of(x1, from_left(wh1), wh1, wv0[kk], wv1, lam);
                 }
-                const float thr = __shfl_down(th0[kk], 1);
-                const float zh = hin ? thr - th0[kk] : 0.0f;
-                const float zv = nxt ? th1 - th0[kk] : 0.0f;
-                qh[kk] = ascend(wh0[kk], zh, step);
-                qv[kk] = ascend(wv0[kk], zv, step);
+                const float zh = from_right(th0[kk]) - th0[kk];
+                const float zv = th1 - th0[kk];
+                qh[kk] = ascend(wh0[kk], zh, step_h);
+                qv[kk] = ascend(wv0[kk], zv, step_v);
                 if (TV == TV_VTV) n2 = norm2_add(n2, qh[kk], qv[kk]);
                 wh0[kk] = wh1;
                 wv0[kk] = wv1;
@@ -221,13 +222,6 @@ int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const
         return SCI_OK;
     }
     return SCI_ERR_INVALID_ARG;
-}
-
-bool fused_supported(int, int, int, int, int) { return false; }
-
-int launch_fgp_fused(int, int, int, int, int, const float *, const float *, float, float *, float *, hipStream_t)
-{
-    return SCI_ERR_UNSUPPORTED;
 }
 
 } // namespace sci

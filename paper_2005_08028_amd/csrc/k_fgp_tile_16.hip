@@ -1,0 +1,46 @@
+// Fused-schedule FGP passes with 16-bit dual storage (bf16, f16), default tile
+// shape, and the dispatcher over TV kind, storage type and tile shape.
+#include "k_fgp_tile.h"
+#include "k_fgp_tile_shapes.h"
+
+namespace sci {
+
+int launch_tile_atv_f32(int shape, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
+                        hipStream_t s);
+int launch_tile_itv_f32(int shape, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
+                        hipStream_t s);
+
+bool tile_supported(int tv) { return tv == TV_ATV || tv == TV_ITV2D; }
+
+int tile_shape_count() { return kTileShapes; }
+
+bool tile_shape_info(int shape, int *rows, int *waves, int *cols)
+{
+    switch (shape) {
+#define SCI_CASE(id, R, NW, C, WPE)                                                                                 \
+    case id: *rows = R; *waves = NW; *cols = C; return true;
+        SCI_TILE_SHAPES(SCI_CASE)
+#undef SCI_CASE
+    }
+    return false;
+}
+
+int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,
+                    const TilePass &tp, float lam, hipStream_t s)
+{
+    if (m < 1 || m > kTileMaxM || shape < 0 || shape >= kTileShapes) return SCI_ERR_INVALID_ARG;
+    if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;
+    if (dual_dtype == DT_F32)
+        return tv == TV_ATV ? launch_tile_atv_f32(shape, m, nx, ny, B, x, tp, lam, s)
+                            : launch_tile_itv_f32(shape, m, nx, ny, B, x, tp, lam, s);
+    // 16-bit storage: the default shape only
+    if (dual_dtype == DT_BF16)
+        return tv == TV_ATV ? launch_tile_shape<TV_ATV, DT_BF16, 4, 16, 1, 8>(m, nx, ny, B, x, tp, lam, s)
+                            : launch_tile_shape<TV_ITV2D, DT_BF16, 4, 16, 1, 8>(m, nx, ny, B, x, tp, lam, s);
+    if (dual_dtype == DT_F16)
+        return tv == TV_ATV ? launch_tile_shape<TV_ATV, DT_F16, 4, 16, 1, 8>(m, nx, ny, B, x, tp, lam, s)
+                            : launch_tile_shape<TV_ITV2D, DT_F16, 4, 16, 1, 8>(m, nx, ny, B, x, tp, lam, s);
+    return SCI_ERR_INVALID_ARG;
+}
+
+} // namespace sci

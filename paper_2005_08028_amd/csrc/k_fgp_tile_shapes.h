@@ -1,0 +1,18 @@
+// Tile shapes of the fused-schedule kernel, as (rows per wavefront R,
+// wavefronts per workgroup NW, columns per lane C, occupancy hint WPE).
+// Tile = (64*C) x (NW*R) pixels including the recomputed halo.
+#pragma once
+
+#define SCI_TILE_SHAPES(X)                                                                                          \
+    X(0, 4, 16, 1, 8) /* 64 x 64,   1024 threads */                                                                 \
+    X(1, 8, 16, 1, 4) /* 64 x 128,  1024 threads */                                                                 \
+    X(2, 8, 8, 1, 4)  /* 64 x 64,   512 threads  */                                                                 \
+    X(3, 4, 8, 1, 8)  /* 64 x 32,   512 threads  */                                                                 \
+    X(4, 4, 16, 2, 4) /* 128 x 64,  1024 threads */                                                                 \
+    X(5, 8, 8, 2, 2)  /* 128 x 64,  512 threads  */                                                                 \
+    X(6, 4, 8, 2, 4)  /* 128 x 32,  512 threads  */                                                                 \
+    X(7, 6, 16, 2, 4) /* 128 x 96,  1024 threads */
+
+namespace sci {
+constexpr int kTileShapes = 8;
+}

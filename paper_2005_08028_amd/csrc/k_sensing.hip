@@ -84,6 +84,55 @@ __global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, const 
     }
 }
 
+// Same projection with every frame of the pixel held in registers (KB >= B),
+// so theta, u and C are read from memory once.
+template <bool ADMM, int KB>
+__global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, const float *__restrict__ theta,
+                                                        const float *__restrict__ u, const float *__restrict__ C,
+                                                        const float *__restrict__ Y, const float *__restrict__ Sinv,
+                                                        float *__restrict__ x, float *__restrict__ svol)
+{
+    uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= npix) return;
+    float v[KB], c[KB], uu[KB];
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * npix + pix;
+            c[k] = C[o];
+            if (ADMM) {
+                uu[k] = u[o];
+                v[k] = theta[o] - uu[k];
+            } else {
+                v[k] = theta[o];
+            }
+            acc = fmaf(c[k], v[k], acc);
+        }
+    }
+    const float r = (Y[pix] - acc) * Sinv[pix];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * npix + pix;
+            const float xv = fmaf(c[k], r, v[k]);
+            x[o] = xv;
+            if (ADMM) svol[o] = uu[k] + xv;
+        }
+    }
+}
+
+template <bool ADMM>
+void launch_project(uint32_t npix, int B, const float *theta, const float *u, const float *C, const float *Y,
+                    const float *Sinv, float *x, float *svol, hipStream_t s)
+{
+    const dim3 g(grid_for(npix)), b(kBlock);
+    if (B <= 8) hipLaunchKernelGGL((k_project_reg<ADMM, 8>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
+    else if (B <= 16) hipLaunchKernelGGL((k_project_reg<ADMM, 16>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
+    else if (B <= 32) hipLaunchKernelGGL((k_project_reg<ADMM, 32>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
+    else hipLaunchKernelGGL((k_project<ADMM>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
+}
+
 __global__ __launch_bounds__(kBlock) void k_copy4(uint32_t n4, const uint32_t *__restrict__ src,
                                                   uint32_t *__restrict__ dst)
 {
@@ -133,17 +182,13 @@ void launch_weights(int nx, int ny, int B, const float *C, float rho, float *Sin
 void launch_gap_project(int nx, int ny, int B, const float *theta, const float *C, const float *Y,
                         const float *Sinv, float *x, hipStream_t s)
 {
-    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
-    hipLaunchKernelGGL(k_project<false>, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, theta,
-                       (const float *)nullptr, C, Y, Sinv, x, (float *)nullptr);
+    launch_project<false>((uint32_t)nx * (uint32_t)ny, B, theta, nullptr, C, Y, Sinv, x, nullptr, s);
 }
 
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
                          const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s)
 {
-    uint32_t npix = (uint32_t)nx * (uint32_t)ny;
-    hipLaunchKernelGGL(k_project<true>, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, theta, u, C, Y, Sinv,
-                       x, svol);
+    launch_project<true>((uint32_t)nx * (uint32_t)ny, B, theta, u, C, Y, Sinv, x, svol, s);
 }
 
 // Device-to-device copy and zero fill as plain kernels, so that they can be

@@ -21,7 +21,7 @@ struct Buf {
 };
 
 enum BufSlot {
-    WS_DUAL0 = 0, WS_DUAL1, WS_DUAL2, // rotating dual fields p^(s-1), p^(s), p^(s+1)
+    WS_DUAL0 = 0, WS_DUAL1, WS_DUAL2, WS_DUAL3, // rotating dual fields (p^(s-1), p^(s) in, two out)
     WS_THETA,                         // theta volume when the caller does not want it
     WS_SVOL,                          // ADMM denoiser input s = u + x
     WS_UVOL,                          // ADMM multiplier u
@@ -59,6 +59,8 @@ struct sci_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<sci::ProfRec> prof;
+    // fused-schedule tile shape chosen by the autotuner, per problem key
+    std::map<std::string, std::pair<int, int>> tuned; // (tile shape, number of passes)
 };
 
 namespace sci {
@@ -105,12 +107,32 @@ int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float
 // theta = x - lambda D^T p; when u_out is non-null also u_out = x - theta.
 int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const void *p, float lam,
                     float *theta, float *u_out, hipStream_t s);
-// All n inner iterations from a zero dual in one on-chip pass per tile, then
-// theta = x - lambda D^T p^(n) (and u_out = x - theta when non-null).
-// Returns false when the fused schedule does not cover the request.
-bool fused_supported(int tv, int nx, int ny, int B, int n);
-int launch_fgp_fused(int tv, int nx, int ny, int B, int n, const float *beta_tab, const float *x, float lam,
-                     float *theta, float *u_out, hipStream_t s);
+
+// ---- launchers (k_fgp_tile.hip) -----------------------------------------------
+// Fused schedule: m <= kTileMaxM inner iterations per pass over HBM.
+constexpr int kTileMaxM = 10;
+constexpr int kTuneSplits = 3; // pass counts tried by the autotuner: minimal, +1, +2
+// b[0] forms w^(s0) from the loaded p^(s0), p^(s0-1) (mode 2); b[t+1] forms
+// w^(s0+t+1) after iteration t of the pass.
+struct TileBeta {
+    float b[kTileMaxM + 1];
+};
+struct TilePass {
+    const void *pc = nullptr;  // p^(s0) (mode 1, 2)
+    const void *pp = nullptr;  // p^(s0-1) (mode 2)
+    int mode = 0;              // 0: w = 0, 1: w = p^(s0), 2: w = p^(s0) + b[0] (p^(s0) - p^(s0-1))
+    TileBeta beta{};
+    void *pn_out = nullptr;    // p^(s0+m)      (nullable)
+    void *pp_out = nullptr;    // p^(s0+m-1)    (nullable)
+    float *theta = nullptr;    // x - lambda D^T p^(s0+m) (nullable)
+    float *u_out = nullptr;    // x - theta     (nullable)
+};
+bool tile_supported(int tv);
+int tile_shape_count();
+bool tile_shape_info(int shape, int *rows, int *waves, int *cols);
+// shape: index into the tile-shape table (0 = default)
+int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,
+                    const TilePass &tp, float lam, hipStream_t s);
 
 // ---- launchers (k_reduce.hip) -------------------------------------------------
 // Deterministic two-stage FP64 reductions into out_dev (device doubles).

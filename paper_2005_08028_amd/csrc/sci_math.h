@@ -59,14 +59,21 @@ __device__ inline float theta_of(float x, float wh_left, float wh, float wv_up, 
     return fmaf(-lam, (wh_left - wh) + (wv_up - wv), x);
 }
 
-// q = w + step * z.
+// q = w + step * z. Entries of the dual that carry no difference take
+// step = 0 (so q = w, which is 0 there) instead of a masked z.
 __device__ inline float ascend(float w, float z, float step) { return fmaf(step, z, w); }
+
+// Cross-lane neighbours along j, as DPP wavefront shifts folded into the
+// consuming instruction: the value held by lane l-1 (0 in lane 0), and by
+// lane l+1 (0 in lane 63).
+__device__ inline float from_left(float v) { return __builtin_amdgcn_update_dpp(0.0f, v, 0x138, 0xF, 0xF, true); }
+__device__ inline float from_right(float v) { return __builtin_amdgcn_update_dpp(0.0f, v, 0x130, 0xF, 0xF, true); }
 
 // ATV projection q / max(1, |q|): equal to clamping q to [-1, 1].
 __device__ inline float proj_atv(float q) { return fminf(fmaxf(q, -1.0f), 1.0f); }
 
-// Isotropic scale 1 / max(1, sqrt(n2)) for a squared norm n2.
-__device__ inline float iso_scale(float n2) { return n2 > 1.0f ? __builtin_amdgcn_rsqf(n2) : 1.0f; }
+// Isotropic scale 1 / max(1, sqrt(n2)) = min(1, 1/sqrt(n2)) for a squared norm n2.
+__device__ inline float iso_scale(float n2) { return fminf(1.0f, __builtin_amdgcn_rsqf(n2)); }
 
 // Squared-norm accumulation (h^2 + v^2 added to acc).
 __device__ inline float norm2_add(float acc, float h, float v) { return fmaf(v, v, fmaf(h, h, acc)); }

@@ -31,6 +31,7 @@ int check_dims(sci_ctx *ctx, const sci_dims &d)
     if (d.nx < 1 || d.ny < 1 || d.B < 1) return fail(ctx, SCI_ERR_INVALID_ARG, "nx, ny and B must be >= 1");
     if ((int64_t)d.nx * d.ny * d.B >= ((int64_t)1 << 31))
         return fail(ctx, SCI_ERR_INVALID_ARG, "B*nx*ny must be < 2^31");
+    if (d.B > 65535) return fail(ctx, SCI_ERR_INVALID_ARG, "B must be <= 65535 (frames map to a grid dimension)");
     return SCI_OK;
 }
 
@@ -46,6 +47,9 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         return fail(ctx, SCI_ERR_INVALID_ARG, "unknown schedule");
     if (p.tv == SCI_TV_VTV && d.B > 32)
         return fail(ctx, SCI_ERR_UNSUPPORTED, "VTV denoiser supports B <= 32 frames");
+    if (p.tile_shape < 0 || p.tile_shape > tile_shape_count())
+        return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
+    if (p.tile_passes < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "tile_passes must be >= 0");
     return SCI_OK;
 }
 
@@ -62,33 +66,37 @@ struct Momentum {
     }
 };
 
-// Dual-field bookkeeping of one denoiser call: three rotating scratch
-// buffers hold p^(s-1), p^(s), p^(s+1) so no pass reads what it writes.
+// Dual-field bookkeeping of one denoiser call: four rotating scratch
+// buffers, so that a pass never writes a buffer it (or another tile of it)
+// reads: p^(s-1) and p^(s) in, up to two new fields out.
 struct FgpRun {
-    void *buf[3] = {nullptr, nullptr, nullptr};
+    void *buf[4] = {nullptr, nullptr, nullptr, nullptr};
     const void *cur = nullptr;  // p^(s) (nullptr = zero)
     const void *prev = nullptr; // p^(s-1)
     int iters = 0;
     double beta_prev = 0.0; // beta_(s-1), used to form w^(s)
     Momentum mom;
-    void *next_buffer() const
+    void *free_buffer(const void *also_exclude = nullptr) const
     {
         for (void *b : buf)
-            if (b != cur && b != prev) return b;
+            if (b != cur && b != prev && b != also_exclude) return b;
         return nullptr;
+    }
+    int mode(const sci_tv_params &p) const
+    {
+        if (!cur) return 0;                                   // w = 0
+        if (p.accel && iters > 0 && beta_prev != 0.0) return 2; // momentum
+        return 1;                                             // w = p^(s)
     }
 };
 
-// Enqueue `n` more inner iterations.
+// Enqueue `n` more inner iterations of the streaming schedule.
 int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
                 hipStream_t s)
 {
     for (int it = 0; it < n; ++it) {
-        int mode;
-        if (!r.cur) mode = 0;                                         // w = 0
-        else if (p.accel && r.iters > 0 && r.beta_prev != 0.0) mode = 2; // momentum
-        else mode = 1;                                                // w = p^(s)
-        void *out = r.next_buffer();
+        const int mode = r.mode(p);
+        void *out = r.free_buffer();
         ProfScope prof(ctx, PF_FGP_STREAM, s);
         int st = launch_fgp_stream(p.tv, p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, r.prev ? r.prev : r.cur, out,
                                    mode, (float)r.beta_prev, p.lambda, s);
@@ -104,10 +112,79 @@ int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const f
     return SCI_OK;
 }
 
+// Enqueue `n` more inner iterations of the fused schedule, in passes of at
+// most kTileMaxM iterations. The last pass also writes theta (and u_out)
+// when `theta` is non-null, and keeps p^(N) in r.cur when keep_dual is set.
+std::string tune_key(const sci_tv_params &p, const sci_dims &d)
+{
+    char buf[128];
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d", p.tv, p.dual_dtype, d.nx, d.ny, d.B, p.n_inner);
+    return buf;
+}
+
+constexpr int kDefaultPassLen = 5;
+
+// Tile shape and number of passes of the fused schedule: explicit
+// (tile_shape / tile_passes >= 1), else the autotuned choice for this
+// problem, else shape 0 and passes of about kDefaultPassLen iterations.
+void pick_tiling(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d, int n, int *shape, int *npass)
+{
+    *shape = 0;
+    *npass = (n + kDefaultPassLen - 1) / kDefaultPassLen;
+    auto it = ctx->tuned.find(tune_key(p, d));
+    if (it != ctx->tuned.end()) {
+        *shape = it->second.first;
+        *npass = it->second.second;
+    }
+    if (p.tile_shape >= 1) *shape = p.tile_shape - 1;
+    if (p.tile_passes >= 1) *npass = p.tile_passes;
+    const int min_pass = (n + kTileMaxM - 1) / kTileMaxM;
+    if (*npass < min_pass) *npass = min_pass;
+    if (*npass > n) *npass = n;
+}
+
+int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
+                     float *theta, float *u_out, bool keep_dual, hipStream_t s)
+{
+    int shape = 0, npass = 1;
+    pick_tiling(ctx, p, d, n, &shape, &npass);
+    for (int q = 0; q < npass; ++q) {
+        const int m = n / npass + (q < n % npass ? 1 : 0);
+        const bool last = q == npass - 1;
+        TilePass tp;
+        tp.mode = r.mode(p);
+        tp.pc = r.cur;
+        tp.pp = r.prev ? r.prev : r.cur;
+        tp.beta.b[0] = (float)r.beta_prev;
+        double bl = r.beta_prev;
+        for (int t = 0; t < m; ++t) {
+            const double b = r.mom.step();
+            bl = p.accel ? b : 0.0;
+            tp.beta.b[t + 1] = (float)bl;
+        }
+        void *pn = (!last || keep_dual) ? r.free_buffer() : nullptr;
+        void *ppn = !last ? r.free_buffer(pn) : nullptr;
+        tp.pn_out = pn;
+        tp.pp_out = ppn;
+        tp.theta = last ? theta : nullptr;
+        tp.u_out = last ? u_out : nullptr;
+        ProfScope prof(ctx, PF_FGP_FUSED, s);
+        int st = launch_fgp_tile(p.tv, p.dual_dtype, m, shape, d.nx, d.ny, d.B, x, tp, p.lambda, s);
+        if (st != SCI_OK) return fail(ctx, st, "fused FGP pass not available for this request");
+        st = check_launch(ctx, "k_fgp_tile");
+        if (st != SCI_OK) return st;
+        r.beta_prev = bl;
+        r.prev = ppn;
+        r.cur = pn;
+        r.iters += m;
+    }
+    return SCI_OK;
+}
+
 int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s)
 {
     const size_t bytes = 2 * vol_elems(d) * dual_elem_bytes(dual_dtype);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         int st = ensure_ws(ctx, (BufSlot)(WS_DUAL0 + k), bytes, s);
         if (st != SCI_OK) return st;
     }
@@ -116,42 +193,39 @@ int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s)
 
 void bind_duals(sci_ctx *ctx, FgpRun &r)
 {
-    for (int k = 0; k < 3; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
+    for (int k = 0; k < 4; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
+}
+
+bool use_fused(const sci_tv_params &p)
+{
+    if (p.schedule == SCI_SCHED_STREAM) return false;
+    if (p.schedule == SCI_SCHED_FUSED) return true;
+    return tile_supported(p.tv) && p.n_inner >= 2;
 }
 
 // One denoiser call with a fixed iteration count, as used inside the outer
 // loops: theta = x - lambda D^T p^(N), and u_out = x - theta when non-null.
-// `warm` (nullable) is a scratch dual buffer holding the starting dual; the
-// final dual is left in r.cur.
+// `warm` (nullable) holds the starting dual; when keep_dual is set the final
+// dual is left in r.cur.
 int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, float *theta,
-                  float *u_out, const void *warm, FgpRun &r, hipStream_t s)
+                  float *u_out, const void *warm, bool keep_dual, FgpRun &r, hipStream_t s)
 {
     const size_t vb = vol_elems(d) * sizeof(float);
-    if (p.lambda == 0.0f || p.n_inner == 0) {
-        launch_copy(x, theta, vb, s);
-        if (u_out) launch_zero(u_out, vb, s);
-        r.cur = warm;
-        return check_launch(ctx, "copy");
-    }
-    const bool fused = p.schedule != SCI_SCHED_STREAM && !warm && p.dual_dtype == SCI_DUAL_F32 &&
-                       fused_supported(p.tv, d.nx, d.ny, d.B, p.n_inner);
-    if (p.schedule == SCI_SCHED_FUSED && !fused)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "fused schedule needs a cold start, float32 duals and a supported shape");
-    if (fused) {
-        float beta[256];
-        Momentum m;
-        for (int k = 0; k < p.n_inner && k < 256; ++k) beta[k] = p.accel ? (float)m.step() : 0.0f;
-        ProfScope prof(ctx, PF_FGP_FUSED, s);
-        int st = launch_fgp_fused(p.tv, d.nx, d.ny, d.B, p.n_inner, beta, x, p.lambda, theta, u_out, s);
-        if (st != SCI_OK) return fail(ctx, st, "fused FGP launch");
-        r.cur = nullptr;
-        return check_launch(ctx, "k_fgp_fused");
-    }
     r.cur = warm;
     r.prev = nullptr;
     r.iters = 0;
     r.beta_prev = 0.0;
     r.mom = Momentum();
+    if (p.lambda == 0.0f || p.n_inner == 0) {
+        launch_copy(x, theta, vb, s);
+        if (u_out) launch_zero(u_out, vb, s);
+        return check_launch(ctx, "copy");
+    }
+    if (use_fused(p)) {
+        if (!tile_supported(p.tv))
+            return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule covers ATV and ITV2D (VTV couples all frames)");
+        return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);
+    }
     int st = fgp_iterate(ctx, d, p, x, r, p.n_inner, s);
     if (st != SCI_OK) return st;
     ProfScope prof(ctx, PF_TV_THETA, s);
@@ -232,7 +306,7 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
             }
             st = check_launch(ctx, "k_project");
             if (st != SCI_OK) return st;
-            st = denoise_fixed(ctx, d, a.p.tv, a.X_out, theta, nullptr, warm, r, s);
+            st = denoise_fixed(ctx, d, a.p.tv, a.X_out, theta, nullptr, warm, a.p.warm_dual != 0, r, s);
         } else {
             {
                 ProfScope prof(ctx, PF_PROJECT, s);
@@ -241,7 +315,7 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
             st = check_launch(ctx, "k_project");
             if (st != SCI_OK) return st;
             // theta = TVdenoise(s); u = s - theta  (= u + x - theta)
-            st = denoise_fixed(ctx, d, a.p.tv, svol, theta, u, warm, r, s);
+            st = denoise_fixed(ctx, d, a.p.tv, svol, theta, u, warm, a.p.warm_dual != 0, r, s);
         }
         if (st != SCI_OK) return st;
         if (a.p.warm_dual) warm = r.cur;
@@ -383,9 +457,9 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
 
     sci_tv_params q = *p;
     const bool want_dual = dual_out || rel_gap_out || adaptive;
-    if (want_dual && q.schedule == SCI_SCHED_FUSED)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule does not return the dual field");
-    if (want_dual) q.schedule = SCI_SCHED_STREAM;
+    if (adaptive && q.schedule == SCI_SCHED_FUSED)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "the gap-controlled loop runs on the streaming schedule");
+    if (adaptive) q.schedule = SCI_SCHED_STREAM;
     FgpRun r;
     bind_duals(ctx, r);
 
@@ -408,7 +482,8 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
     int status = SCI_OK;
     double gap = 0.0, primal = 0.0;
     if (!adaptive) {
-        if ((st = denoise_fixed(ctx, d, q, X_in, Theta_out, nullptr, dual_init, r, stream)) != SCI_OK) return st;
+        if ((st = denoise_fixed(ctx, d, q, X_in, Theta_out, nullptr, dual_init, want_dual, r, stream)) != SCI_OK)
+            return st;
         if (rel_gap_out) {
             if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_in, r.cur, &gap, &primal, stream)) != SCI_OK)
                 return st;
@@ -452,6 +527,82 @@ int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const floa
                 float *Theta_out, const float *X_init, hipStream_t stream)
 {
     return run_outer(ctx, d, p, Y, C, X_out, Theta_out, X_init, true, stream);
+}
+
+int sci_tile_shape_count(void) { return tile_shape_count(); }
+
+int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_per_group, int32_t *cols_per_lane)
+{
+    int r = 0, w = 0, c = 0;
+    if (!tile_shape_info(shape - 1, &r, &w, &c)) return SCI_ERR_INVALID_ARG;
+    if (rows_per_wave) *rows_per_wave = r;
+    if (waves_per_group) *waves_per_group = w;
+    if (cols_per_lane) *cols_per_lane = c;
+    return SCI_OK;
+}
+
+int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *X, int32_t *best_shape_out,
+                 int32_t *best_passes_out, double *times_ms_out, hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!p || !X) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    if ((st = check_tv(ctx, *p, d)) != SCI_OK) return st;
+    if (!tile_supported(p->tv)) return fail(ctx, SCI_ERR_UNSUPPORTED, "only the fused schedule (ATV, ITV2D) is tuned");
+    if (p->lambda == 0.0f || p->n_inner == 0) return fail(ctx, SCI_ERR_INVALID_ARG, "nothing to tune: lambda or n_inner is 0");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    const size_t vb = vol_elems(d) * sizeof(float);
+    if ((st = ensure_duals(ctx, d, p->dual_dtype, stream)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_THETA, vb, stream)) != SCI_OK) return st;
+    float *theta = (float *)ctx->ws[WS_THETA].ptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, SCI_ERR_HIP, "hipEventCreate");
+    const int nshape = tile_shape_count();
+    const int n = p->n_inner;
+    const int pmin = (n + kTileMaxM - 1) / kTileMaxM;
+    const int reps = 3;
+    int best_s = 0, best_p = pmin;
+    double best_ms = 1e300;
+    sci_tv_params q = *p;
+    q.schedule = SCI_SCHED_FUSED;
+    FgpRun r;
+    bind_duals(ctx, r);
+    for (int sh = 0; sh < nshape && st == SCI_OK; ++sh) {
+        for (int k = 0; k < kTuneSplits && st == SCI_OK; ++k) {
+            const int np = pmin + k;
+            if (times_ms_out) times_ms_out[sh * kTuneSplits + k] = NAN;
+            if (np > n) continue;
+            q.tile_shape = sh + 1;
+            q.tile_passes = np;
+            st = denoise_fixed(ctx, d, q, X, theta, nullptr, nullptr, false, r, stream); // warm-up
+            if (st == SCI_OK && hipEventRecord(e0, stream) != hipSuccess) st = fail(ctx, SCI_ERR_HIP, "hipEventRecord");
+            for (int rep = 0; rep < reps && st == SCI_OK; ++rep)
+                st = denoise_fixed(ctx, d, q, X, theta, nullptr, nullptr, false, r, stream);
+            if (st != SCI_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(ctx, SCI_ERR_HIP, "autotune timing");
+                break;
+            }
+            const double t = (double)ms / reps;
+            if (times_ms_out) times_ms_out[sh * kTuneSplits + k] = t;
+            if (t < best_ms) {
+                best_ms = t;
+                best_s = sh;
+                best_p = np;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SCI_OK) return st;
+    ctx->tuned[tune_key(*p, d)] = std::make_pair(best_s, best_p);
+    if (best_shape_out) *best_shape_out = best_s + 1;
+    if (best_passes_out) *best_passes_out = best_p;
+    return SCI_OK;
 }
 
 int sci_psnr(sci_ctx *ctx, int64_t count, const float *a, const float *ref, double peak, double *out_host,

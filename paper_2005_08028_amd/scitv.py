@@ -44,7 +44,8 @@ class sci_dims(ctypes.Structure):
 class sci_tv_params(ctypes.Structure):
     _fields_ = [("tv", ctypes.c_int32), ("lambda_", ctypes.c_float), ("n_inner", ctypes.c_int32),
                 ("accel", ctypes.c_int32), ("dual_dtype", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("gap_tol", ctypes.c_double), ("n_inner_max", ctypes.c_int32), ("gap_check_every", ctypes.c_int32)]
+                ("gap_tol", ctypes.c_double), ("n_inner_max", ctypes.c_int32), ("gap_check_every", ctypes.c_int32),
+                ("tile_shape", ctypes.c_int32), ("tile_passes", ctypes.c_int32)]
 
 
 class sci_solver_params(ctypes.Structure):
@@ -73,6 +74,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_dual_gap": (I, [V, D, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, V, V, P(ctypes.c_double),
                              P(ctypes.c_double), V]),
         "sci_profile_enable": (I, [V, I]),
+        "sci_tile_shape_count": (I, []),
+        "sci_tile_shape_info": (I, [ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
+        "sci_autotune": (I, [V, D, P(sci_tv_params), V, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_double),
+                             V]),
         "sci_profile_read": (I, [V, ctypes.c_char_p, P(ctypes.c_int64), P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -125,11 +130,11 @@ def _dims(vol: torch.Tensor) -> sci_dims:
 
 
 def tv_params(tv="atv", lam=0.1, n_inner=5, accel=True, dual_dtype="f32", schedule="auto", gap_tol=0.0,
-              n_inner_max=0, gap_check_every=0) -> sci_tv_params:
+              n_inner_max=0, gap_check_every=0, tile_shape=0, tile_passes=0) -> sci_tv_params:
     return sci_tv_params(TV[tv] if isinstance(tv, str) else int(tv), float(lam), int(n_inner), int(bool(accel)),
                          DUAL[dual_dtype] if isinstance(dual_dtype, str) else int(dual_dtype),
                          SCHED[schedule] if isinstance(schedule, str) else int(schedule), float(gap_tol),
-                         int(n_inner_max), int(gap_check_every))
+                         int(n_inner_max), int(gap_check_every), int(tile_shape), int(tile_passes))
 
 
 def solver_params(outer_iters=50, rho=0.0, warm_dual=False, use_graph=False, **tv) -> sci_solver_params:
@@ -231,6 +236,29 @@ def sci_dual_gap(ctx, X, p, tv="atv", lam=0.1, stream=None):
                                  _dev(X, name="X"), _dev(p, p.dtype, (2,) + tuple(X.shape), "p"), ctypes.byref(g),
                                  ctypes.byref(pr), _stream(stream)))
     return g.value, pr.value
+
+
+def sci_tile_shape_count() -> int:
+    return lib.sci_tile_shape_count()
+
+
+def sci_tile_shape_info(shape: int):
+    """(rows per wavefront, wavefronts per workgroup, columns per lane) of a 1-based shape."""
+    r, w, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(None, lib.sci_tile_shape_info(int(shape), ctypes.byref(r), ctypes.byref(w), ctypes.byref(c)))
+    return r.value, w.value, c.value
+
+
+def sci_autotune(ctx, X: torch.Tensor, params: sci_tv_params, stream=None):
+    """Time every fused (tile shape, pass count) on X; returns (best 1-based
+    shape, best pass count, [[ms per pass-count candidate] per shape])."""
+    n = lib.sci_tile_shape_count()
+    best, passes = ctypes.c_int32(0), ctypes.c_int32(0)
+    times = (ctypes.c_double * (3 * n))()
+    _check(ctx, lib.sci_autotune(ctx, _dims(X), ctypes.byref(params), _dev(X, name="X"), ctypes.byref(best),
+                                 ctypes.byref(passes), times, _stream(stream)))
+    t = list(times)
+    return best.value, passes.value, [t[3 * k:3 * k + 3] for k in range(n)]
 
 
 def sci_profile_enable(ctx, enable: bool = True) -> None:

@@ -90,22 +90,85 @@ def test_forward_adjoint(sc, ctx, B, nx, ny):
 DEN_SHAPES = [(1, 1, 1), (1, 2, 2), (2, 5, 3), (3, 17, 63), (2, 33, 125), (4, 130, 64), (9, 20, 70), (24, 16, 64)]
 
 
-@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+@pytest.mark.parametrize("tv,schedule", [("atv", "stream"), ("itv2d", "stream"), ("vtv", "stream"),
+                                         ("atv", "fused"), ("itv2d", "fused")])
 @pytest.mark.parametrize("B,nx,ny", DEN_SHAPES)
-def test_denoise_matches_oracle(sc, ctx, tv, B, nx, ny):
+def test_denoise_matches_oracle(sc, ctx, tv, schedule, B, nx, ny):
     r = np.random.default_rng(B * 7 + nx * 13 + ny)
     x = r.uniform(size=(B, nx, ny)).astype(np.float32)
     for n, accel in ((1, True), (2, True), (7, True), (5, False)):
-        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, schedule="stream")
+        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, schedule=schedule)
         dual = torch.empty((2, B, nx, ny), device="cuda")
         th, _, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, dual_out=dual)
         ref, pref = orc.tv_denoise(x, f32(0.1), n, tv, accel=accel, return_dual=True)
         e = rel_l2(host(th), ref)
         ep = np.abs(host(dual) - pref).max()
-        say(f"denoise {tv} B={B} {nx}x{ny} N={n} accel={accel}: rel-L2 {e:.2e}, dual max-abs {ep:.2e}")
+        say(f"denoise {tv}/{schedule} B={B} {nx}x{ny} N={n} accel={accel}: rel-L2 {e:.2e}, dual max-abs {ep:.2e}")
         assert its == n
         assert e <= REL_TOL
         assert ep <= 1e-4
+
+
+FUSED_SHAPES = [(1, 1, 1), (2, 3, 2), (1, 5, 300), (3, 250, 130), (2, 118, 54), (2, 117, 53), (1, 240, 107)]
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+@pytest.mark.parametrize("B,nx,ny", FUSED_SHAPES)
+def test_fused_schedule_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
+    """The tiled multi-iteration passes evaluate the same per-voxel
+    expressions as one-pass-per-iteration streaming: identical bits with
+    float32 dual storage, for every pass split (N = 1..13), with and without
+    momentum, cold and warm starts. With 16-bit storage the fused schedule
+    rounds the dual only between passes (float32 registers inside a pass), so
+    both schedules are held to the mixed-precision bound against the oracle
+    instead, the fused one being no less accurate."""
+    r = np.random.default_rng(nx * 31 + ny + B)
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    p0 = orc.project_dual(r.normal(size=(2, B, nx, ny)), tv).astype(np.float32)
+    cases = [(n, True, False, "f32") for n in (1, 2, 3, 4, 5, 6, 7, 10, 13)]
+    cases += [(5, False, False, "f32"), (7, True, True, "f32"), (9, True, False, "bf16"), (8, True, True, "f16")]
+    for n, accel, warm, dt in cases:
+        outs = []
+        for schedule in ("stream", "fused"):
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, schedule=schedule, dual_dtype=dt)
+            ddt = sc.DUAL_TORCH[prm.dual_dtype]
+            dual = torch.empty((2, B, nx, ny), device="cuda", dtype=ddt)
+            init = dev(p0, ddt) if warm else None
+            th, _, _, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=dual)
+            outs.append((host(th), host(dual)))
+        if dt == "f32":
+            np.testing.assert_array_equal(outs[0][0], outs[1][0], err_msg=f"theta N={n} accel={accel} warm={warm}")
+            np.testing.assert_array_equal(outs[0][1], outs[1][1], err_msg=f"dual N={n} accel={accel} warm={warm}")
+        else:
+            ref = orc.tv_denoise(x.cpu().numpy(), f32(0.1), n, tv, accel=accel, p_init=p0 if warm else None)
+            u = 2.0 ** -8 if dt == "bf16" else 2.0 ** -11
+            e_s, e_f = np.abs(outs[0][0] - ref).max(), np.abs(outs[1][0] - ref).max()
+            assert e_s <= 10 * 4 * 0.1 * u and e_f <= 10 * 4 * 0.1 * u, (e_s, e_f)
+            assert e_f <= 1.5 * e_s + 1e-6, (e_s, e_f)
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+def test_every_tile_shape_gives_identical_bits(sc, ctx, tv):
+    r = np.random.default_rng(17)
+    for B, nx, ny in ((2, 200, 150), (1, 33, 70)):
+        x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+        ref = None
+        for shape in range(1, sc.sci_tile_shape_count() + 1):
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=10, schedule="fused", tile_shape=shape)
+            th, _, _, _ = sc.sci_tv_denoise(ctx, x, prm)
+            th = host(th)
+            if ref is None:
+                ref = th
+            np.testing.assert_array_equal(th, ref, err_msg=f"shape {shape} {sc.sci_tile_shape_info(shape)}")
+        best, passes, times = sc.sci_autotune(ctx, x, sc.tv_params(tv=tv, lam=0.1, n_inner=10))
+        assert 1 <= best <= sc.sci_tile_shape_count() and 1 <= passes <= 3
+        assert all(t > 0 for row in times for t in row)
+        for np_ in (1, 2, 3, 10):
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=10, schedule="fused", tile_passes=np_)
+            th, _, _, _ = sc.sci_tv_denoise(ctx, x, prm)
+            np.testing.assert_array_equal(host(th), ref, err_msg=f"{np_} passes")
+        th, _, _, _ = sc.sci_tv_denoise(ctx, x, sc.tv_params(tv=tv, lam=0.1, n_inner=10))
+        np.testing.assert_array_equal(host(th), ref)
 
 
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
@@ -231,19 +294,23 @@ def test_gap_atv_256x8(sc, ctx):
 @pytest.fixture(scope="module")
 def six_problem():
     pr = synth.problem_from_config("six_256x8")
-    return pr, orc.measurement(pr.masks, pr.truth, pr.noise)
+    return pr, orc.measurement(pr.masks, pr.truth, pr.noise), {}
 
 
+@pytest.mark.parametrize("schedule", ["auto", "stream"])
 @pytest.mark.parametrize("solver", ["gap", "admm"])
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
-def test_six_variants_256x8(sc, ctx, six_problem, solver, tv):
+def test_six_variants_256x8(sc, ctx, six_problem, solver, tv, schedule):
     cfg = synth.CONFIGS["six_256x8"]
-    pr, Y = six_problem
+    pr, Y, cache = six_problem
     x, th = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=cfg["T"], rho=cfg["rho"], tv=tv,
-                       lam=cfg["lam"], n_inner=cfg["N"])
-    xr, thr = oracle_solver(solver, Y, pr.masks, cfg["lam"], cfg["rho"], cfg["T"], cfg["N"], tv)
+                       lam=cfg["lam"], n_inner=cfg["N"], schedule=schedule)
+    if (solver, tv) not in cache:
+        cache[(solver, tv)] = oracle_solver(solver, Y, pr.masks, cfg["lam"], cfg["rho"], cfg["T"], cfg["N"], tv)
+    xr, thr = cache[(solver, tv)]
     e, dp = rel_l2(x, xr), abs(orc.psnr(x, pr.truth) - orc.psnr(xr, pr.truth))
-    say(f"{solver}-{tv} 256x256x8 100x10: rel-L2 {e:.2e}, dPSNR {dp:.2e} dB, oracle PSNR {orc.psnr(xr, pr.truth):.2f}")
+    say(f"{solver}-{tv}/{schedule} 256x256x8 100x10: rel-L2 {e:.2e}, dPSNR {dp:.2e} dB, "
+        f"oracle PSNR {orc.psnr(xr, pr.truth):.2f}")
     assert e <= REL_TOL and dp <= PSNR_TOL
     assert rel_l2(th, thr) <= REL_TOL
 
@@ -257,6 +324,22 @@ def test_ragged_small_solves(sc, ctx, solver):
         xr, thr = oracle_solver(solver, Y, pr.masks, 0.1, 0.05, 7, 4, tv)
         assert rel_l2(x, xr) <= REL_TOL, (B, nx, ny, tv)
         assert rel_l2(th, thr) <= REL_TOL, (B, nx, ny, tv)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("tv", ["atv", "vtv"])
+def test_warm_dual_schedules_agree(sc, ctx, solver, tv):
+    """Keeping the dual across outer iterations: the fused and streaming
+    schedules agree bit for bit, and both differ from the cold start."""
+    pr = synth.make_problem(130, 120, 6, seed=16, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    outs = {}
+    for schedule in ("stream", "auto"):
+        outs[schedule] = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=8, rho=0.01, tv=tv, n_inner=5,
+                                    warm_dual=True, schedule=schedule)
+    np.testing.assert_array_equal(outs["stream"][0], outs["auto"][0])
+    cold = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=8, rho=0.01, tv=tv, n_inner=5)
+    assert np.abs(cold[0] - outs["auto"][0]).max() > 1e-6
 
 
 @pytest.mark.parametrize("solver", ["gap", "admm"])
