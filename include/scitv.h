@@ -164,6 +164,40 @@ int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float
 int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
                 float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
 
+/* ---- batched solve --------------------------------------------------------- */
+
+/* One measurement of a batch: sizes, inputs and outputs as for sci_gap_tv. */
+typedef struct {
+    sci_dims d;
+    const float *Y;          /* image [nx][ny] */
+    const float *C;          /* masks, video [B][nx][ny] */
+    float *X_out;            /* video: x^(T) */
+    float *Theta_out;        /* video: theta^(T) (nullable) */
+    int32_t outer_iters;     /* > 0: this problem's MaxIter; 0: the batch's p->outer_iters */
+} sci_problem;
+
+/* GAP (Eq. (21)-(22)) for n independent measurements of different sizes in
+ * one go: each outer iteration is one projection launch and one fused
+ * denoise launch that cover every problem still iterating, and with
+ * p->use_graph the whole loop is one HIP graph launch. Results are
+ * bit-identical to sci_gap_tv on each problem with the fused schedule.
+ * Requirements: ATV or ITV2D, lambda > 0, 1 <= n_inner <= 10, cold start
+ * (warm_dual = 0), B <= 32 per problem; dual_dtype and schedule are
+ * ignored (the dual never leaves the chip). Outputs of different problems
+ * must not overlap. The tile shape is p->tv.tile_shape, else the one
+ * sci_autotune_batched chose for this batch, else the default. */
+int sci_gap_tv_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const sci_solver_params *p,
+                       hipStream_t stream);
+
+/* Time the batched denoise launch of this batch with every tile shape and
+ * remember the fastest for later sci_gap_tv_batched calls on a batch of the
+ * same sizes, TV kind and n_inner. Uses the problems' X_out / Theta_out as
+ * scratch. best_shape_out (nullable, HOST): 1-based winner; times_ms_out
+ * (nullable, HOST array of sci_tile_shape_count() doubles): mean time of one
+ * batched denoise launch per shape. Synchronises `stream`. */
+int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const sci_solver_params *p,
+                         int32_t *best_shape_out, double *times_ms_out, hipStream_t stream);
+
 /* ---- tile-shape autotuning of the fused schedule -------------------------- */
 
 /* Number of tile shapes of the fused denoiser kernel. */

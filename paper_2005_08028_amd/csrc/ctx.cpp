@@ -43,7 +43,7 @@ int ensure_ws(sci_ctx *ctx, BufSlot slot, size_t bytes, hipStream_t stream)
         b.ptr = nullptr;
         b.bytes = 0;
         // graphs captured earlier may point at the freed buffer
-        for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+        for (auto &kv : ctx->graphs) destroy_graph(kv.second);
         ctx->graphs.clear();
     }
     hipError_t e = hipMalloc(&b.ptr, bytes);
@@ -63,6 +63,14 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
 }
 
 size_t dual_elem_bytes(int dual_dtype) { return dual_dtype == SCI_DUAL_F32 ? 4 : 2; }
+
+void destroy_graph(GraphEntry &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.owned) (void)hipFree(g.owned);
+    g.exec = nullptr;
+    g.owned = nullptr;
+}
 
 static hipEvent_t pool_event(sci_ctx *ctx)
 {
@@ -128,7 +136,7 @@ void sci_destroy(sci_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    for (auto &kv : ctx->graphs) sci::destroy_graph(kv.second);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &b : ctx->ws)
         if (b.ptr) (void)hipFree(b.ptr);

@@ -41,34 +41,29 @@ __device__ inline int xcd_contiguous(int wg, int nwg)
     return c < r ? c * (q + 1) + idx : r * (q + 1) + (c - r) * q + idx;
 }
 
-template <int TV, int M, int DT, int R, int NW, int C, int WPE>
-__global__ __launch_bounds__(64 * NW, WPE) void k_fgp_tile(int nx, int ny, int ntx, int ntiles,
-                                                           const float *__restrict__ x,
-                                                           const typename Dual<DT>::T *__restrict__ pc,
-                                                           const typename Dual<DT>::T *__restrict__ pp, int mode,
-                                                           TileBeta bt, float lam, float step,
-                                                           typename Dual<DT>::T *__restrict__ pn_out,
-                                                           typename Dual<DT>::T *__restrict__ pp_out,
-                                                           float *__restrict__ theta_out, float *__restrict__ u_out)
+// One tile of one frame: (tx, ty) tile coordinates, frame offset fo (in
+// elements), V = elements per dual channel of the whole video.
+template <int TV, int M, int DT, int R, int NW, int C>
+__device__ __forceinline__ void fgp_tile_body(int nx, int ny, int tx, int ty, uint32_t fo, uint32_t V,
+                                              const float *__restrict__ x,
+                                              const typename Dual<DT>::T *__restrict__ pc,
+                                              const typename Dual<DT>::T *__restrict__ pp, int mode,
+                                              const TileBeta &bt, float lam, float step,
+                                              typename Dual<DT>::T *__restrict__ pn_out,
+                                              typename Dual<DT>::T *__restrict__ pp_out,
+                                              float *__restrict__ theta_out, float *__restrict__ u_out,
+                                              float (*lds_v)[64 * C], float (*lds_t)[64 * C])
 {
     using D = Dual<DT>;
     constexpr int TW = 64 * C;              // tile width incl. halo
     constexpr int TXO = TW - 2 * M - 1;     // interior columns per tile
     constexpr int TYO = NW * R - 2 * M - 1; // interior rows per tile
     static_assert(TXO > 0 && TYO > 0, "tile too small for the pass length");
-    __shared__ float lds_v[NW][TW]; // last-row vertical dual of each wavefront
-    __shared__ float lds_t[NW][TW]; // first-row theta of each wavefront
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
-    const int frame = lin / ntiles, tile = lin % ntiles;
-    const int tx = tile % ntx, ty = tile / ntx;
     const int j0 = tx * TXO - (M + 1) + lane * C; // column of this lane's first pixel
     const int ibase = ty * TYO - (M + 1) + wv * R;
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t V = plane * (gridDim.x / (uint32_t)ntiles);
-    const uint32_t fo = (uint32_t)frame * plane;
 
     bool jin[C], hj[C];
     float step_h[C]; // horizontal differences exist for 0 <= j < ny-1
@@ -202,6 +197,26 @@ __global__ __launch_bounds__(64 * NW, WPE) void k_fgp_tile(int nx, int ny, int n
                 }
             }
     }
+}
+
+template <int TV, int M, int DT, int R, int NW, int C, int WPE>
+__global__ __launch_bounds__(64 * NW, WPE) void k_fgp_tile(int nx, int ny, int ntx, int ntiles,
+                                                           const float *__restrict__ x,
+                                                           const typename Dual<DT>::T *__restrict__ pc,
+                                                           const typename Dual<DT>::T *__restrict__ pp, int mode,
+                                                           TileBeta bt, float lam, float step,
+                                                           typename Dual<DT>::T *__restrict__ pn_out,
+                                                           typename Dual<DT>::T *__restrict__ pp_out,
+                                                           float *__restrict__ theta_out, float *__restrict__ u_out)
+{
+    __shared__ float lds_v[NW][64 * C]; // last-row vertical dual of each wavefront
+    __shared__ float lds_t[NW][64 * C]; // first-row theta of each wavefront
+    const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    const int frame = lin / ntiles, tile = lin % ntiles;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    fgp_tile_body<TV, M, DT, R, NW, C>(nx, ny, tile % ntx, tile / ntx, (uint32_t)frame * plane,
+                                       plane * (gridDim.x / (uint32_t)ntiles), x, pc, pp, mode, bt, lam, step,
+                                       pn_out, pp_out, theta_out, u_out, lds_v, lds_t);
 }
 
 template <int TV, int M, int DT, int R, int NW, int C, int WPE>

@@ -28,12 +28,17 @@ enum BufSlot {
     WS_SINV,                          // 1 / (sum_k C_k^2 + rho) image
     WS_PARTIAL,                       // FP64 block partials of the reductions
     WS_XTMP,                          // denoiser input copy when X_in aliases the output
+    WS_BATCH,                         // batched solve: per-problem Sinv and theta
+    WS_BDESC,                         // batched solve: device problem table (eager path)
     WS_COUNT
 };
 
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
+    void *owned = nullptr; // device memory the graph reads (freed with it)
 };
+
+void destroy_graph(GraphEntry &g);
 
 // Kernel families timed by the profiler.
 enum ProfFamily { PF_FGP_STREAM = 0, PF_FGP_FUSED, PF_TV_THETA, PF_PROJECT, PF_SETUP, PF_COUNT };

@@ -385,7 +385,7 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
         e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail_hip(ctx, e, "hipGraphInstantiate");
-        it = ctx->graphs.emplace(key, GraphEntry{exec}).first;
+        it = ctx->graphs.emplace(key, GraphEntry{exec, nullptr}).first;
     }
     hipError_t e = hipGraphLaunch(it->second.exec, s);
     if (e != hipSuccess) return fail_hip(ctx, e, "hipGraphLaunch");

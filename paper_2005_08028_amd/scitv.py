@@ -53,6 +53,11 @@ class sci_solver_params(ctypes.Structure):
                 ("warm_dual", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
+class sci_problem(ctypes.Structure):
+    _fields_ = [("d", sci_dims), ("Y", ctypes.c_void_p), ("C", ctypes.c_void_p), ("X_out", ctypes.c_void_p),
+                ("Theta_out", ctypes.c_void_p), ("outer_iters", ctypes.c_int32)]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build() (hipcc, gfx950)")
@@ -74,6 +79,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_dual_gap": (I, [V, D, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, V, V, P(ctypes.c_double),
                              P(ctypes.c_double), V]),
         "sci_profile_enable": (I, [V, I]),
+        "sci_gap_tv_batched": (I, [V, ctypes.c_int32, P(sci_problem), P(sci_solver_params), V]),
+        "sci_autotune_batched": (I, [V, ctypes.c_int32, P(sci_problem), P(sci_solver_params), P(ctypes.c_int32),
+                                     P(ctypes.c_double), V]),
         "sci_tile_shape_count": (I, []),
         "sci_tile_shape_info": (I, [ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
         "sci_autotune": (I, [V, D, P(sci_tv_params), V, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_double),
@@ -208,6 +216,35 @@ def sci_gap_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None,
 def sci_admm_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None, X_init=None, stream=None):
     """ADMM-TV; returns (X_out, Theta_out)."""
     return _outer(lib.sci_admm_tv, ctx, Y, C, params, X_out, Theta_out, X_init, stream)
+
+
+def _problems(items):
+    """items: sequence of dicts with Y, C, X_out, optional Theta_out, optional outer_iters."""
+    arr = (sci_problem * len(items))()
+    for k, it in enumerate(items):
+        C = it["C"]
+        d = _dims(C)
+        arr[k] = sci_problem(d, _dev(it["Y"], shape=(d.nx, d.ny), name="Y"), _dev(C, name="C"),
+                             _dev(it["X_out"], shape=C.shape, name="X_out"),
+                             _dev(it.get("Theta_out"), shape=C.shape, name="Theta_out"), int(it.get("outer_iters", 0)))
+    return arr
+
+
+def sci_gap_tv_batched(ctx, items, params: sci_solver_params, stream=None):
+    """GAP-TV for a list of measurements (dicts with Y, C, X_out[, Theta_out, outer_iters])."""
+    arr = _problems(items)
+    _check(ctx, lib.sci_gap_tv_batched(ctx, len(items), arr, ctypes.byref(params), _stream(stream)))
+
+
+def sci_autotune_batched(ctx, items, params: sci_solver_params, stream=None):
+    """Returns (best 1-based tile shape, [ms per shape]) for the batched denoise launch."""
+    arr = _problems(items)
+    n = lib.sci_tile_shape_count()
+    best = ctypes.c_int32(0)
+    times = (ctypes.c_double * n)()
+    _check(ctx, lib.sci_autotune_batched(ctx, len(items), arr, ctypes.byref(params), ctypes.byref(best), times,
+                                         _stream(stream)))
+    return best.value, list(times)
 
 
 def sci_psnr(ctx, a: torch.Tensor, ref: torch.Tensor, peak: float = 1.0, stream=None) -> float:

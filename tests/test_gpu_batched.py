@@ -1,0 +1,103 @@
+"""GPU: batched GAP-TV over measurements of different sizes equals the
+per-measurement solves bit for bit, and the per-measurement solves equal the
+FP64 oracle to the parity bar."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2005_08028_amd import synth  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_08028_amd import scitv
+    return scitv
+
+
+@pytest.fixture(scope="module")
+def ctx(sc):
+    c = sc.Context(0)
+    yield c.handle
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float32)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+SIZES = [(37, 101, 3, 4), (64, 64, 8, 6), (130, 70, 10, 0), (1, 1, 1, 2), (200, 257, 16, 5), (96, 50, 5, 3)]
+
+
+def make_batch(seed=0):
+    items, refs = [], []
+    for k, (nx, ny, B, T) in enumerate(SIZES):
+        pr = synth.make_problem(nx, ny, B, seed=seed + k, sigma=0.01, mask_p=0.3 + 0.08 * k,
+                                radius=(2.0, 0.2 * max(nx, ny) + 3))
+        Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+        items.append(dict(Y=dev(Y), C=dev(pr.masks), X_out=torch.empty((B, nx, ny), device="cuda"),
+                          Theta_out=torch.empty((B, nx, ny), device="cuda") if k % 2 == 0 else None,
+                          outer_iters=T))
+        refs.append((pr, Y))
+    return items, refs
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_equals_per_problem(sc, ctx, tv, use_graph):
+    items, refs = make_batch(10)
+    prm = sc.solver_params(outer_iters=3, tv=tv, lam=0.1, n_inner=5, use_graph=use_graph)
+    for rep in range(2):
+        for it in items:
+            it["X_out"].fill_(float("nan"))
+        sc.sci_gap_tv_batched(ctx, items, prm)
+        for it, (pr, Y) in zip(items, refs):
+            T = it["outer_iters"] or 3
+            one = sc.solver_params(outer_iters=T, tv=tv, lam=0.1, n_inner=5, schedule="fused")
+            th = torch.empty_like(it["C"])
+            x, _ = sc.sci_gap_tv(ctx, it["Y"], it["C"], one, Theta_out=th)
+            np.testing.assert_array_equal(host(it["X_out"]), host(x))
+            if it["Theta_out"] is not None:
+                np.testing.assert_array_equal(host(it["Theta_out"]), host(th))
+
+
+def test_batched_matches_oracle(sc, ctx):
+    items, refs = make_batch(20)
+    prm = sc.solver_params(outer_iters=3, tv="atv", lam=0.1, n_inner=4)
+    sc.sci_gap_tv_batched(ctx, items, prm)
+    for it, (pr, Y) in zip(items, refs):
+        T = it["outer_iters"] or 3
+        ref, _ = orc.gap_tv(Y, pr.masks, float(np.float32(0.1)), T, 4, tv="atv")
+        got = host(it["X_out"])
+        assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def test_batched_autotune_keeps_results(sc, ctx):
+    items, _ = make_batch(30)
+    prm = sc.solver_params(outer_iters=2, tv="itv2d", lam=0.1, n_inner=6)
+    sc.sci_gap_tv_batched(ctx, items, prm)
+    before = [host(it["X_out"]) for it in items]
+    best, times = sc.sci_autotune_batched(ctx, items, prm)
+    assert 1 <= best <= sc.sci_tile_shape_count() and all(t > 0 for t in times)
+    sc.sci_gap_tv_batched(ctx, items, prm)
+    for it, b in zip(items, before):
+        np.testing.assert_array_equal(host(it["X_out"]), b)
+
+
+def test_batched_rejects_unsupported(sc, ctx):
+    items, _ = make_batch(40)
+    for kw in (dict(tv="vtv"), dict(n_inner=11), dict(lam=0.0)):
+        args = dict(outer_iters=2, tv="atv", lam=0.1, n_inner=5)
+        args.update(kw)
+        with pytest.raises(sc.SciError):
+            sc.sci_gap_tv_batched(ctx, items, sc.solver_params(**args))
