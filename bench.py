@@ -10,10 +10,12 @@ HBM before the timed region starts.
 
 Prints ONE JSON line: the throughput in voxel-iterations per second
 (voxels x inner iterations / s), the roofline position of the dominant kernel
-(timed live with HIP events inside the library), the HBM traffic measured by
-rocprofv3 counters when the committed counter summary still matches the
-kernel source, and the FP64 oracle timed on the host cores on a bounded
-sample of the same workload.
+(its launches timed live with HIP events inside the library), the HBM traffic
+measured by rocprofv3 counters when the committed counter summary still
+matches the kernel source and tile choice, the FP64 oracle timed on the host
+cores on a bounded sample of the same workload, and the side measurements:
+time-to-PSNR of the batched solve against per-measurement solves, and the
+16-bit dual storage variants with their error.
 """
 from __future__ import annotations
 
@@ -29,7 +31,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GAP-TV voxel-iter/s, % HBM roofline; time-to-PSNR learned/batched vs plain"
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic_fgp_cacti_1024x24.txt")
+# FP32 VALU lane-operations per second with packed FP32 disabled:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+# FP32 VALU operations per voxel of one FGP inner iteration, counted from the
+# algorithm (Algorithm 1, FGP box): theta = x - lambda D^T w (2 sub, 1 add,
+# 1 fma), z = D theta (2 sub), q = w + z/(8 lambda) (2 fma), projection
+# (ATV: 2 clamps; ITV2D: squared norm 2, 1/sqrt and min 2, 2 mul), momentum
+# w = p + beta (p - p_prev) (2 sub, 2 fma).
+OPS_PER_VOXEL_ITER = {"atv": 14, "itv2d": 18}
+OPS_THETA_EPILOGUE = 4  # theta = x - lambda D^T p once per voxel at the end of the pass
 
 
 def fgp_stream_bytes_per_voxel(n_inner: int, elem: int) -> float:
@@ -49,30 +62,143 @@ def fgp_stream_bytes_per_voxel(n_inner: int, elem: int) -> float:
     return total
 
 
-def kernel_source_hash() -> str:
+def source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in ("k_fgp.hip", "sci_math.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2005_08028_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(family: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+KERNEL_SOURCES = {
+    "fgp_stream": ("k_fgp.hip", "sci_math.h"),
+    "fgp_fused": ("k_fgp_tile.h", "k_fgp_tile_shapes.h", "sci_math.h"),
+}
+
+
+def read_traffic(family: str, tag: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
+    when it is missing or was taken on another kernel source or tile choice."""
+    path = os.path.join(PROFILE_DIR, f"hbm_traffic_{family}_cacti_1024x24.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(PROFILE_TRAFFIC):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_family") != family or kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != source_hash(KERNEL_SOURCES[family]) or kv.get("tiling", "") != tag:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def passes_of(tag: str) -> int:
+    # tag = "shape<k>/passes<p>"
+    try:
+        return int(tag.split("passes")[1])
+    except (IndexError, ValueError):
+        return 1
+
+
+def roofline_for(family, n_launch, ms_total, V, N, tv, elem, tag):
+    avg_s = ms_total / n_launch / 1e3
+    out = {"kernel": family, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch}
+    if family == "fgp_stream":
+        b = V * fgp_stream_bytes_per_voxel(N, elem) / N
+        out.update({"bound": "hbm", "achieved": round(b / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(b / avg_s / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_launch": b})
+    elif family == "fgp_fused":
+        m = N / passes_of(tag)  # inner iterations per launch
+        ops = V * (m * OPS_PER_VOXEL_ITER[tv] + OPS_THETA_EPILOGUE / passes_of(tag))
+        a = ops / avg_s / 1e12
+        out.update({"bound": "alu", "achieved": round(a, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                    "unit": "TOP/s (fp32 VALU lane-ops)", "frac": round(a / VALU_PEAK_TOPS, 4),
+                    "ops_per_launch": ops})
+        if passes_of(tag) == 1:  # one pass: reads x, writes theta
+            out["hbm_GBs_algorithmic"] = round(V * 8.0 / avg_s / 1e9, 1)
+    out["traffic"] = read_traffic(family, tag) if family in KERNEL_SOURCES else None
+    return out
+
+
+def measure_batched(scitv, synth, h, dev, steps):
+    """Batched solve of 64 measurements of mixed sizes against the same
+    measurements solved one by one (default tiles, no graph), both run to
+    each measurement's time-to-PSNR iteration count."""
+    import torch
+    specs = synth.batched_specs(64, seed=4000)
+    lam, T, N = 0.1, 50, 5
+    items = []
+    truths = []
+    t0 = time.perf_counter()
+    for sp in specs:
+        pr = synth.make_problem(sp["nx"], sp["ny"], sp["B"], sp["seed"], mask=sp["mask"], mask_p=sp["mask_p"],
+                                sigma=sp["sigma"])
+        C = torch.from_numpy(pr.masks).to(dev)
+        Xt = torch.from_numpy(pr.truth).to(dev)
+        Y = scitv.sci_forward(h, C, Xt) + torch.from_numpy(pr.noise).to(dev)
+        items.append(dict(Y=Y, C=C, X_out=torch.empty_like(C), Theta_out=torch.empty_like(C), outer_iters=T))
+        truths.append(Xt)
+    gen_s = time.perf_counter() - t0
+    voxels = sum(it["C"].numel() for it in items)
+    # reference PSNR at the full iteration count (batched == per-problem bit for bit)
+    prm = scitv.solver_params(outer_iters=T, tv="atv", lam=lam, n_inner=N, use_graph=False)
+    scitv.sci_gap_tv_batched(h, items, prm)
+    full = [scitv.sci_psnr(h, it["X_out"], xt) for it, xt in zip(items, truths)]
+    # time-to-PSNR: first outer iteration reaching (full PSNR - 0.1 dB)
+    one = scitv.solver_params(outer_iters=1, tv="atv", lam=lam, n_inner=N)
+    tstar = []
+    for it, xt, pf in zip(items, truths, full):
+        th = scitv.sci_adjoint(h, it["C"], it["Y"])
+        x = torch.empty_like(th)
+        th2 = torch.empty_like(th)
+        ts = T
+        for t in range(1, T + 1):
+            scitv.sci_gap_tv(h, it["Y"], it["C"], one, X_out=x, Theta_out=th2, X_init=th)
+            th, th2 = th2, th
+            if scitv.sci_psnr(h, x, xt) >= pf - 0.1:
+                ts = t
+                break
+        tstar.append(ts)
+    for it, ts in zip(items, tstar):
+        it["outer_iters"] = ts
+    # plain: one sci_gap_tv per measurement, default tiles, no graph
+    plain = [scitv.solver_params(outer_iters=ts, tv="atv", lam=lam, n_inner=N, tile_shape=1) for ts in tstar]
+
+    def run_plain():
+        for it, pp in zip(items, plain):
+            scitv.sci_gap_tv(h, it["Y"], it["C"], pp, X_out=it["X_out"], Theta_out=it["Theta_out"])
+
+    bprm = scitv.solver_params(outer_iters=T, tv="atv", lam=lam, n_inner=N, use_graph=True)
+    best, times = scitv.sci_autotune_batched(h, items, bprm)
+
+    def run_batched():
+        scitv.sci_gap_tv_batched(h, items, bprm)
+
+    res = {}
+    for name, fn in (("plain", run_plain), ("batched", run_batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps * 1e3
+    got = [scitv.sci_psnr(h, it["X_out"], xt) for it, xt in zip(items, truths)]
+    ok = all(g >= f - 0.1 - 1e-9 for g, f in zip(got, full))
+    return {
+        "workload": "64 measurements, nx=ny in {256,512,1024}, B in {8,10,16}, Bernoulli(p in [0.3,0.7]) masks, "
+                    "sigma in [0,0.02]; GAP-ATV lambda=0.1, 5 FGP inner, each run to its time-to-PSNR iteration "
+                    "(full-50-iteration PSNR - 0.1 dB)",
+        "voxels": voxels, "t_star_mean": sum(tstar) / len(tstar), "t_star_min": min(tstar), "t_star_max": max(tstar),
+        "plain_ms": round(res["plain"], 3), "batched_ms": round(res["batched"], 3),
+        "speedup_batched_vs_plain": round(res["plain"] / res["batched"], 3),
+        "batched_tile_shape": best, "batched_shape_ms": [round(t, 4) for t in times],
+        "all_reach_target_psnr": ok, "input_generation_s": round(gen_s, 1),
+    }
 
 
 def main() -> int:
@@ -83,9 +209,10 @@ def main() -> int:
     ap.add_argument("--outer", type=int, default=200, help="outer iterations per step (default: the full 200)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "stream", "fused"])
     ap.add_argument("--dual-dtype", default="f32", choices=["f32", "bf16", "f16"])
-    ap.add_argument("--no-autotune", action="store_true", help="skip the tile-shape autotuner (default shape)")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the tile autotuner (default shape and passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations of the oracle sample")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and 16-bit side measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 1 GiB device copies (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -124,12 +251,14 @@ def main() -> int:
                               dual_dtype=args.dual_dtype)
 
     tuned = None
-    if not args.no_autotune and cfg["tv"] in ("atv", "itv2d") and args.schedule != "stream":
-        # tile shape of the fused denoiser, timed on this measurement's back-projection
+    tag = "shape1/passes%d" % ((N + 4) // 5)
+    if not args.no_autotune and cfg["tv"] in ("atv", "itv2d"):
+        # tile shape and pass count of the fused denoiser, timed on this measurement's back-projection
         x0 = scitv.sci_adjoint(h, C, Y)
         best, passes, times = scitv.sci_autotune(h, x0, prm.tv)
         tuned = {"best_shape": best, "rows_waves_cols": scitv.sci_tile_shape_info(best), "passes": passes,
                  "ms_per_denoise_by_shape_and_passes": [[round(t, 4) for t in row] for row in times]}
+        tag = "shape%d/passes%d" % (best, passes if args.schedule != "stream" else N)
         del x0
 
     def step():
@@ -156,23 +285,9 @@ def main() -> int:
         if n:
             fams[fam] = (n, ms)
     dom = max(fams, key=lambda f: fams[f][1])
-    n_dom, ms_dom = fams[dom]
-    avg_s = ms_dom / n_dom / 1e3
     elem = 4 if args.dual_dtype == "f32" else 2
-    if dom == "fgp_stream":
-        bytes_per_launch = V * fgp_stream_bytes_per_voxel(N, elem) / N
-    elif dom == "fgp_fused":
-        bytes_per_launch = V * 8.0  # read x, write theta; the dual never leaves the chip
-    else:
-        bytes_per_launch = None
-    achieved = bytes_per_launch / avg_s / 1e9 if bytes_per_launch else None
-    traffic = read_traffic(dom)
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": traffic, "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_dom,
-        "bytes_per_launch": bytes_per_launch,
-    }
+    roofline = roofline_for(dom, fams[dom][0], fams[dom][1], V, N, cfg["tv"], elem,
+                            tag if dom == "fgp_fused" else "stream")
 
     steps = args.steps
     value = V * T * N * steps / elapsed
@@ -183,7 +298,7 @@ def main() -> int:
         "config": {"workload": f"{wl}: GAP-ITV2D {nx}x{ny}x{B}, {T} outer x {N} inner FGP, lambda={lam}, "
                                f"shifted Bernoulli(0.5) masks, textured moving-shape scene",
                    "nx": nx, "ny": ny, "B": B, "outer_iters": T, "inner_iters": N, "tv": cfg["tv"],
-                   "schedule": args.schedule, "dual_dtype": args.dual_dtype, "graph": False},
+                   "schedule": args.schedule, "dual_dtype": args.dual_dtype, "graph": False, "tiling": tag},
         "roofline": roofline,
         "kernel_ms_per_step": {f: round(ms / steps, 3) for f, (n, ms) in fams.items()},
         "psnr_db": round(psnr, 4), "residual_sq": resid, "autotune": tuned,
@@ -197,6 +312,28 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = a.numel() * 4
+
+    if not args.no_extras:
+        # 16-bit dual storage on the streaming schedule (the fused single pass keeps duals on chip)
+        ref = X_out.clone()
+        mp = {}
+        for dt in ("f32", "bf16", "f16"):
+            p16 = scitv.solver_params(outer_iters=T, tv=cfg["tv"], lam=lam, n_inner=N, schedule="stream",
+                                      dual_dtype=dt)
+            scitv.sci_autotune(h, X_out, p16.tv)
+            x16 = torch.empty_like(C)
+            scitv.sci_gap_tv(h, Y, C, p16, X_out=x16)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            scitv.sci_gap_tv(h, Y, C, p16, X_out=x16)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            rel = float(torch.linalg.vector_norm((x16 - ref).double()) / torch.linalg.vector_norm(ref.double()))
+            mp[dt] = {"ms_per_solve": round(ms, 2), "voxel_iter_per_s": V * T * N / (ms / 1e3),
+                      "rel_l2_vs_fused_fp32": rel,
+                      "dpsnr_db_vs_fused_fp32": round(scitv.sci_psnr(h, x16, X_true) - psnr, 5)}
+        out["dual_storage_stream_schedule"] = mp
+        out["batched"] = measure_batched(scitv, synth, h, dev, max(1, min(steps, 3)))
 
     if not args.no_cpu_baseline:
         from oracle import oracle as orc

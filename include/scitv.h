@@ -212,7 +212,9 @@ int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_pe
  * input X (video, device) for every tile shape and for 3 pass counts (the
  * fewest passes of at most 10 iterations, one more, two more), and remember
  * the fastest pair in the context for later calls with the same TV kind,
- * dual dtype, sizes and n_inner whose tile_shape / tile_passes are 0.
+ * dual dtype, sizes and n_inner whose tile_shape / tile_passes are 0. With
+ * p->schedule == SCI_SCHED_STREAM the one-iteration-per-pass configuration
+ * is tuned instead (tile shape only; the other pass-count entries are NaN).
  * best_shape_out / best_passes_out (nullable, HOST) receive the winner;
  * times_ms_out (nullable, HOST array of 3 * sci_tile_shape_count() doubles,
  * [shape][pass-count candidate]) the mean time per denoiser call, NaN where a

@@ -10,10 +10,11 @@
 // (64 lanes x 4 bytes), rebuilds w and theta for it on chip, and finishes
 // the current row: z = D theta, q = w + z/(8 lambda), projection, store.
 //
-// ATV and ITV2D project each voxel on its own, so a frame is a grid
-// dimension and each lane handles one frame. VTV normalises all 2B dual
-// values of a pixel together, so each lane carries every frame of its column
-// in registers (KB >= B) and projects once all frames of the row are done.
+// Used for VTV, which normalises all 2B dual values of a pixel together: each
+// lane carries every frame of its column in registers (KB >= B) and projects
+// once all frames of the row are done. (The kernel also handles one frame per
+// lane, KB = 1, for the per-voxel projections; ATV and ITV2D stream through
+// the 2D tile kernel with one iteration per pass instead.)
 #include <hip/hip_runtime.h>
 
 #include "sci_internal.h"
@@ -25,7 +26,16 @@ namespace {
 constexpr int kWaves = 4;  // wavefronts per workgroup
 constexpr int kStrip = 62; // result columns per wavefront
 
-template <int TV, int KB, int DT>
+// PF = rows of loads kept in flight ahead of the row being finished (0 for
+// VTV, whose B frames per row already give many loads in flight).
+//
+// Raw loads of one row of one frame: p^(s), p^(s-1) (both channels) and x,
+// zero where no difference exists (or outside the image).
+struct RowLoad {
+    float ph, pv, pph, ppv, x;
+};
+
+template <int TV, int KB, int DT, int PF>
 __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int B, int rows, int nstrips,
                                                             int nwaves, const float *__restrict__ x,
                                                             const typename Dual<DT>::T *__restrict__ pc,
@@ -50,43 +60,70 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
     const int kbase = (KB == 1) ? (int)blockIdx.y : 0;
     const int nk = (KB == 1) ? 1 : B;
 
-    // w at offset o (channel offset already added), 0 where no difference exists
-    auto load_w = [&](uint32_t o, bool valid) -> float {
-        if (mode == 0 || !valid) return 0.0f;
-        float p = D::ld(pc, o);
-        return mode == 2 ? extrapolate(p, D::ld(pp, o), beta) : p;
+    // row i of frame slot kk (i < nx)
+    auto load_row = [&](int kk, int i) -> RowLoad {
+        RowLoad l{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        const uint32_t o = (uint32_t)(kbase + kk) * plane + (uint32_t)i * ny + j;
+        const bool vin = jin && i < nx - 1;
+        if (jin) l.x = x[o];
+        if (mode != 0) {
+            if (hin) l.ph = D::ld(pc, o);
+            if (vin) l.pv = D::ld(pc, V + o);
+            if (mode == 2) {
+                if (hin) l.pph = D::ld(pp, o);
+                if (vin) l.ppv = D::ld(pp, V + o);
+            }
+        }
+        return l;
     };
+    auto w_of = [&](float p, float ppv) -> float { return mode == 2 ? extrapolate(p, ppv, beta) : p; };
 
     float wh0[KB], wv0[KB], th0[KB];
+    RowLoad nxt[KB], nxt2[KB];
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
         if (kk < nk) {
-            const uint32_t fo = (uint32_t)(kbase + kk) * plane;
-            const float wvm = (i0 >= 1) ? load_w(V + fo + (uint32_t)(i0 - 1) * ny + j, jin) : 0.0f;
-            const uint32_t o = fo + (uint32_t)i0 * ny + j;
-            wh0[kk] = load_w(o, hin);
-            wv0[kk] = load_w(V + o, jin && i0 < nx - 1);
-            const float xv = jin ? x[o] : 0.0f;
-            th0[kk] = theta_of(xv, from_left(wh0[kk]), wh0[kk], wvm, wv0[kk], lam);
+            float wvm = 0.0f;
+            if (i0 >= 1) {
+                const RowLoad u = load_row(kk, i0 - 1);
+                wvm = w_of(u.pv, u.ppv);
+            }
+            const RowLoad c = load_row(kk, i0);
+            if (PF >= 1 && i0 + 1 < nx) nxt[kk] = load_row(kk, i0 + 1);
+            if (PF >= 2 && i0 + 2 < nx) nxt2[kk] = load_row(kk, i0 + 2);
+            wh0[kk] = w_of(c.ph, c.pph);
+            wv0[kk] = w_of(c.pv, c.ppv);
+            th0[kk] = theta_of(c.x, from_left(wh0[kk]), wh0[kk], wvm, wv0[kk], lam);
         }
     }
 
     for (int i = i0; i < i1; ++i) {
-        const bool nxt = i + 1 < nx;
-        const float step_v = nxt ? step : 0.0f; // no vertical difference in the last row
+        const bool has_next = i + 1 < nx;
+        const float step_v = has_next ? step : 0.0f; // no vertical difference in the last row
         float qh[KB], qv[KB];
         float n2 = 0.0f;
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
             if (kk < nk) {
-                const uint32_t fo = (uint32_t)(kbase + kk) * plane;
+                // PF = 0: load row i+1 now; PF = 1, 2: it was loaded PF steps ago,
+                // and the load PF rows ahead starts here
+                RowLoad r1{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (PF == 0) {
+                    if (has_next) r1 = load_row(kk, i + 1);
+                } else {
+                    r1 = nxt[kk];
+                    if (PF == 2) {
+                        nxt[kk] = nxt2[kk];
+                        if (i + 3 < nx && i + 3 <= i1) nxt2[kk] = load_row(kk, i + 3);
+                    } else if (i + 2 < nx && i + 2 <= i1) {
+                        nxt[kk] = load_row(kk, i + 2);
+                    }
+                }
                 float wh1 = 0.0f, wv1 = 0.0f, th1 = 0.0f;
-                if (nxt) {
-                    const uint32_t o1 = fo + (uint32_t)(i + 1) * ny + j;
-                    wh1 = load_w(o1, hin);
-                    wv1 = load_w(V + o1, jin && i + 1 < nx - 1);
-                    const float x1 = jin ? x[o1] : 0.0f;
-                    th1 = theta_of(x1, from_left(wh1), wh1, wv0[kk], wv1, lam);
+                if (has_next) {
+                    wh1 = w_of(r1.ph, r1.pph);
+                    wv1 = w_of(r1.pv, r1.ppv);
+                    th1 = theta_of(r1.x, from_left(wh1), wh1, wv0[kk], wv1, lam);
                 }
                 const float zh = from_right(th0[kk]) - th0[kk];
                 const float zv = th1 - th0[kk];
@@ -155,7 +192,7 @@ int pick_rows(int nx, int nstrips, int frames_in_grid)
     return rows;
 }
 
-template <int TV, int KB, int DT>
+template <int TV, int KB, int DT, int PF = (KB == 1 ? 2 : 0)>
 void launch_stream_t(int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn, int mode,
                      float beta, float lam, hipStream_t s)
 {
@@ -165,7 +202,7 @@ void launch_stream_t(int nx, int ny, int B, const float *x, const void *pc, cons
     const int rows = pick_rows(nx, nstrips, frames);
     const int nwaves = nstrips * ((nx + rows - 1) / rows);
     const dim3 grid((nwaves + kWaves - 1) / kWaves, frames);
-    hipLaunchKernelGGL((k_fgp_stream<TV, KB, DT>), grid, dim3(64 * kWaves), 0, s, nx, ny, B, rows, nstrips, nwaves,
+    hipLaunchKernelGGL((k_fgp_stream<TV, KB, DT, PF>), grid, dim3(64 * kWaves), 0, s, nx, ny, B, rows, nstrips, nwaves,
                        x, (const T *)pc, (const T *)pp, (T *)pn, mode, beta, lam, 1.0f / (8.0f * lam));
 }
 
@@ -173,11 +210,9 @@ template <int DT>
 int launch_stream_dt(int tv, int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn,
                      int mode, float beta, float lam, hipStream_t s)
 {
-    if (tv == TV_ATV) {
-        launch_stream_t<TV_ATV, 1, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    } else if (tv == TV_ITV2D) {
-        launch_stream_t<TV_ITV2D, 1, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    } else if (B <= 8) {
+    // ATV and ITV2D stream through the tile kernel with one iteration per pass
+    if (tv != TV_VTV) return SCI_ERR_UNSUPPORTED;
+    if (B <= 8) {
         launch_stream_t<TV_VTV, 8, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
     } else if (B <= 16) {
         launch_stream_t<TV_VTV, 16, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);

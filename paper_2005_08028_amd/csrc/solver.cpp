@@ -90,10 +90,22 @@ struct FgpRun {
     }
 };
 
-// Enqueue `n` more inner iterations of the streaming schedule.
+// Tile shape used for one-iteration passes (128 x 64 tiles, 2 columns per lane).
+constexpr int kStreamTileShape = 4;
+
+int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
+                     float *theta, float *u_out, bool keep_dual, hipStream_t s, int force_shape = -1,
+                     int force_passes = -1);
+int stream_tile_shape(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d);
+
+// Enqueue `n` more inner iterations of the streaming schedule: one pass over
+// HBM per iteration. ATV and ITV2D run the tile kernel with one iteration per
+// pass; VTV (all frames of a pixel coupled) runs the row-streaming kernel.
 int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
                 hipStream_t s)
 {
+    if (tile_supported(p.tv))
+        return fgp_tile_iterate(ctx, d, p, x, r, n, nullptr, nullptr, true, s, stream_tile_shape(ctx, p, d), n);
     for (int it = 0; it < n; ++it) {
         const int mode = r.mode(p);
         void *out = r.free_buffer();
@@ -112,14 +124,23 @@ int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const f
     return SCI_OK;
 }
 
-// Enqueue `n` more inner iterations of the fused schedule, in passes of at
-// most kTileMaxM iterations. The last pass also writes theta (and u_out)
-// when `theta` is non-null, and keeps p^(N) in r.cur when keep_dual is set.
+// Tuning key: the streaming schedule (one iteration per pass) is tuned
+// separately from the multi-iteration passes.
 std::string tune_key(const sci_tv_params &p, const sci_dims &d)
 {
     char buf[128];
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d", p.tv, p.dual_dtype, d.nx, d.ny, d.B, p.n_inner);
+    snprintf(buf, sizeof buf, "%s|%d|%d|%d|%d|%d|%d", p.schedule == SCI_SCHED_STREAM ? "stream" : "fused", p.tv,
+             p.dual_dtype, d.nx, d.ny, d.B, p.n_inner);
     return buf;
+}
+
+int stream_tile_shape(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
+{
+    sci_tv_params q = p;
+    q.schedule = SCI_SCHED_STREAM;
+    auto it = ctx->tuned.find(tune_key(q, d));
+    if (p.tile_shape >= 1) return p.tile_shape - 1;
+    return it == ctx->tuned.end() ? kStreamTileShape : it->second.first;
 }
 
 constexpr int kDefaultPassLen = 5;
@@ -144,10 +165,12 @@ void pick_tiling(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d, 
 }
 
 int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
-                     float *theta, float *u_out, bool keep_dual, hipStream_t s)
+                     float *theta, float *u_out, bool keep_dual, hipStream_t s, int force_shape, int force_passes)
 {
     int shape = 0, npass = 1;
     pick_tiling(ctx, p, d, n, &shape, &npass);
+    if (force_shape >= 0) shape = force_shape;
+    if (force_passes >= 1) npass = force_passes;
     for (int q = 0; q < npass; ++q) {
         const int m = n / npass + (q < n % npass ? 1 : 0);
         const bool last = q == npass - 1;
@@ -163,18 +186,19 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
             tp.beta.b[t + 1] = (float)bl;
         }
         void *pn = (!last || keep_dual) ? r.free_buffer() : nullptr;
-        void *ppn = !last ? r.free_buffer(pn) : nullptr;
+        // a one-iteration pass hands p^(s0) on as the next pass's p^(s-1)
+        void *ppn = ((!last || keep_dual) && m > 1) ? r.free_buffer(pn) : nullptr;
         tp.pn_out = pn;
         tp.pp_out = ppn;
         tp.theta = last ? theta : nullptr;
         tp.u_out = last ? u_out : nullptr;
-        ProfScope prof(ctx, PF_FGP_FUSED, s);
+        ProfScope prof(ctx, m == 1 ? PF_FGP_STREAM : PF_FGP_FUSED, s);
         int st = launch_fgp_tile(p.tv, p.dual_dtype, m, shape, d.nx, d.ny, d.B, x, tp, p.lambda, s);
         if (st != SCI_OK) return fail(ctx, st, "fused FGP pass not available for this request");
         st = check_launch(ctx, "k_fgp_tile");
         if (st != SCI_OK) return st;
         r.beta_prev = bl;
-        r.prev = ppn;
+        r.prev = (m == 1) ? r.cur : ppn;
         r.cur = pn;
         r.iters += m;
     }
@@ -226,6 +250,9 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
             return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule covers ATV and ITV2D (VTV couples all frames)");
         return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);
     }
+    if (tile_supported(p.tv))
+        return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s, stream_tile_shape(ctx, p, d),
+                                p.n_inner);
     int st = fgp_iterate(ctx, d, p, x, r, p.n_inner, s);
     if (st != SCI_OK) return st;
     ProfScope prof(ctx, PF_TV_THETA, s);
@@ -565,15 +592,16 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     const int reps = 3;
     int best_s = 0, best_p = pmin;
     double best_ms = 1e300;
+    const bool one_per_pass = p->schedule == SCI_SCHED_STREAM;
     sci_tv_params q = *p;
-    q.schedule = SCI_SCHED_FUSED;
+    q.schedule = one_per_pass ? SCI_SCHED_STREAM : SCI_SCHED_FUSED;
     FgpRun r;
     bind_duals(ctx, r);
     for (int sh = 0; sh < nshape && st == SCI_OK; ++sh) {
         for (int k = 0; k < kTuneSplits && st == SCI_OK; ++k) {
-            const int np = pmin + k;
+            const int np = one_per_pass ? n : pmin + k;
             if (times_ms_out) times_ms_out[sh * kTuneSplits + k] = NAN;
-            if (np > n) continue;
+            if (np > n || (one_per_pass && k > 0)) continue;
             q.tile_shape = sh + 1;
             q.tile_passes = np;
             st = denoise_fixed(ctx, d, q, X, theta, nullptr, nullptr, false, r, stream); // warm-up
@@ -599,7 +627,7 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SCI_OK) return st;
-    ctx->tuned[tune_key(*p, d)] = std::make_pair(best_s, best_p);
+    ctx->tuned[tune_key(q, d)] = std::make_pair(best_s, best_p);
     if (best_shape_out) *best_shape_out = best_s + 1;
     if (best_passes_out) *best_passes_out = best_p;
     return SCI_OK;
