@@ -201,6 +201,78 @@ def measure_batched(scitv, synth, h, dev, steps):
     }
 
 
+def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, T_eval=20):
+    """Learned warm start: the correcting network (input x^(t) and the previous
+    outer iteration's final dual) trained on GPU-FGP duals of 512x512x16
+    GAP-ITV2D runs, evaluated on the 1024x1024x24 measurement against cold and
+    warm-dual starts (gap-controlled inner loop, relative gap <= 1e-4) and the
+    plain fixed-10-iteration GAP-TV."""
+    import torch
+    from paper_2005_08028_amd import warmstart
+    tv = "itv2d"
+    t0 = time.perf_counter()
+    data = []
+    for seed in (5001, 5002):
+        pr = synth.make_problem(512, 512, 16, seed, mask="shifted", texture_sigma=0.02)
+        Ct = torch.from_numpy(pr.masks).to(dev)
+        Yt = scitv.sci_forward(h, Ct, torch.from_numpy(pr.truth).to(dev))
+        data += warmstart.warm_dual_triples(h, Yt, Ct, tv, lam, 13, tol=1e-4, target_tol=1e-6, every=2)
+    gen_s = time.perf_counter() - t0
+    net = scitv.sci_wsnet_create(h, c_in=3, c_out=2)
+    scitv.sci_wsnet_set_params(h, net, warmstart.init_params(0, c_in=3, last_scale=0.0))
+    steps = 300
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = warmstart.train(h, net, data, steps=steps, lr=3e-5, log_every=100)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) / steps * 1e3
+    # network throughput at the evaluation size
+    x0 = scitv.sci_adjoint(h, C, Y)
+    base = torch.zeros((2,) + tuple(x0.shape), device=dev)
+    scitv.sci_wsnet_forward(h, net, x0, tv=tv, base=base)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        scitv.sci_wsnet_forward(h, net, x0, tv=tv, base=base)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) / 5 * 1e3
+    V = x0.numel()
+    macs = 27 * (3 * 16 + 16 * 16 + 16 * 16 + 16 * 2)  # per voxel, the four layers
+    res = {}
+    prm = scitv.solver_params(outer_iters=T_eval, tv=tv, lam=lam, gap_tol=1e-4, n_inner_max=1000,
+                              gap_check_every=5)
+    for name in ("cold", "warm_dual", "learned"):
+        prm.warm_dual = 1 if name == "warm_dual" else 0
+        kw = {"net": net} if name == "learned" else {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, its, fb = scitv.sci_gap_tv_adaptive(h, Y, C, prm, **kw)
+        torch.cuda.synchronize()
+        res[name] = {"inner_iters": its, "fallbacks": fb, "ms": round((time.perf_counter() - t0) * 1e3, 1),
+                     "psnr_db": round(scitv.sci_psnr(h, x, X_true), 4)}
+    fixed = scitv.solver_params(outer_iters=T_eval, tv=tv, lam=lam, n_inner=10)
+    x, _ = scitv.sci_gap_tv(h, Y, C, fixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, _ = scitv.sci_gap_tv(h, Y, C, fixed)
+    torch.cuda.synchronize()
+    res["plain_fixed_10"] = {"inner_iters": 10 * T_eval, "ms": round((time.perf_counter() - t0) * 1e3, 1),
+                             "psnr_db": round(scitv.sci_psnr(h, x, X_true), 4)}
+    scitv.sci_wsnet_destroy(net)
+    return {
+        "workload": f"train: {len(data)} (x, previous dual, converged dual) triples from two 512x512x16 GAP-ITV2D "
+                    f"runs, {steps} Adam steps; eval: the 1024x1024x24 measurement, {T_eval} outer GAP-ITV2D, "
+                    "inner FGP to relative duality gap <= 1e-4 (checked every 5), cap 1000",
+        "training_loss": [(s, round(l, 6)) for s, l in hist], "data_generation_s": round(gen_s, 1),
+        "train_step_ms_512x512x16": round(train_ms, 3), "forward_ms_1024x1024x24": round(fwd_ms, 3),
+        "forward_tflops_algorithmic": round(2 * macs * V / (fwd_ms / 1e3) / 1e12, 2),
+        "inner_iters_cold_over_learned": round(res["cold"]["inner_iters"] / max(1, res["learned"]["inner_iters"]), 3),
+        "inner_iters_warm_over_learned": round(res["warm_dual"]["inner_iters"] / max(1, res["learned"]["inner_iters"]),
+                                               3),
+        **res,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +406,7 @@ def main() -> int:
                       "dpsnr_db_vs_fused_fp32": round(scitv.sci_psnr(h, x16, X_true) - psnr, 5)}
         out["dual_storage_stream_schedule"] = mp
         out["batched"] = measure_batched(scitv, synth, h, dev, max(1, min(steps, 3)))
+        out["learned_warm_start"] = measure_learned(scitv, synth, h, dev, Y, C, X_true, lam)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as orc

@@ -198,6 +198,68 @@ int sci_gap_tv_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const 
 int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const sci_solver_params *p,
                          int32_t *best_shape_out, double *times_ms_out, hipStream_t stream);
 
+/* ---- learned warm start of the TV denoiser ---------------------------------- */
+
+/* A small convolutional network that predicts the denoiser's dual field, so
+ * that FGP can start near its solution. Architecture: 4 layers of 3x3x3
+ * "same" convolutions over (frame, row, column), c_in -> 16 -> 16 -> 16 ->
+ * c_out channels, bias, ReLU after layers 1-3; bf16 weights and activations
+ * with fp32 accumulation (MFMA), fp32 master weights and Adam moments.
+ * c_in = 1: the input is the denoiser input x and the output (c_out = 2) is
+ * the dual (p_h, p_v). c_in = 3: the input is x and a base dual P_base (in
+ * the gap-controlled solver: the previous outer iteration's final dual), and
+ * the prediction is P_base + output. The paper has no such network; it
+ * serves the gap-controlled solver below. One network may be used from one
+ * stream at a time. */
+typedef struct sci_wsnet sci_wsnet;
+
+int sci_wsnet_create(sci_ctx *ctx, int32_t c_in, int32_t c_out, sci_wsnet **out); /* weights start at 0 */
+void sci_wsnet_destroy(sci_wsnet *net);
+
+/* Parameters are exchanged as fp32 in a padded layout: per layer l = 0..3,
+ * 28 * 16 * 16 floats [slot][out][in]; slots 0..26 are the taps
+ * t = 9 (dk+1) + 3 (di+1) + (dj+1) of offset (dk, di, dj) along
+ * (frame, row, column), slot 27 holds the bias in input column 0. Entries
+ * outside a layer's channels are ignored (read back as 0). */
+int64_t sci_wsnet_param_count(void);
+int sci_wsnet_set_params(sci_ctx *ctx, sci_wsnet *net, const float *host, int64_t count); /* resets Adam */
+int sci_wsnet_get_params(sci_ctx *ctx, sci_wsnet *net, float *host, int64_t count);
+
+/* Network output for input X (video) and, when c_in = 3, P_base (dual
+ * [2][B][nx][ny] fp32; NULL = zero; ignored when c_in = 1): Y_out (nullable)
+ * [V][16] fp32 raw output (channels >= c_out are 0), dual_out (nullable)
+ * [2][B][nx][ny] fp32 = (P_base +) output projected onto the dual ball of TV
+ * kind tv with the entries that carry no difference set to 0 (c_out = 2). */
+int sci_wsnet_forward(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *X, const float *P_base, float *Y_out,
+                      int32_t tv, float *dual_out, hipStream_t stream);
+
+/* Loss 1/(c_out V) sum ((P_base +) y - target)^2 (target [c_out][B][nx][ny]
+ * fp32) and its gradient for every parameter (HOST, padded layout), without
+ * an update. Synchronises `stream`. */
+int sci_wsnet_grads(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *X, const float *P_base, const float *target,
+                    float *grad_host, double *loss_host, hipStream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on that
+ * loss; loss_host (nullable) receives the loss before the step (then the call
+ * synchronises `stream`). */
+int sci_wsnet_train_step(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *X, const float *P_base,
+                         const float *target, float lr, double *loss_host, hipStream_t stream);
+
+/* GAP (Eq. (21)-(22)) whose denoiser runs until the relative duality gap
+ * <= p->tv.gap_tol (checked every p->tv.gap_check_every iterations, at most
+ * p->tv.n_inner_max per outer iteration), each call starting from: the
+ * network's projected prediction (net non-null; a network with c_in = 3 gets
+ * the previous outer iteration's final dual as P_base and is not used in the
+ * first outer iteration, which has none; when the predicted start does not
+ * reach the tolerance the call is repeated from a zero dual), else the
+ * previous outer iteration's final dual (p->warm_dual = 1), else zero.
+ * inner_iters_out / fallbacks_out (nullable, HOST): total inner iterations
+ * (fallbacks included) and the number of cold-start fallbacks. float32 duals;
+ * synchronises `stream` at every gap check. */
+int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
+                        float *X_out, float *Theta_out, const float *X_init, sci_wsnet *net, int32_t *inner_iters_out,
+                        int32_t *fallbacks_out, hipStream_t stream);
+
 /* ---- tile-shape autotuning of the fused schedule -------------------------- */
 
 /* Number of tile shapes of the fused denoiser kernel. */

@@ -1,0 +1,29 @@
+// Launchers of the warm-start network kernels (k_wsnet.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace sci {
+
+constexpr int kNetLayers = 4;
+constexpr int kNetHidden = 16;
+constexpr int kNetSlots = 28 * 256; // per layer: [27 taps + bias][16 out][16 in] fp32 master layout
+
+void wsnet_pack_input(int nx, int ny, int B, const float *x, const float *dual, uint16_t *a, hipStream_t s);
+void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
+                const uint16_t *gate, uint16_t *out16, float *out32, hipStream_t s);
+int wsnet_reduce_blocks();
+int wsnet_wgrad_groups();
+void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *base, const float *target, uint16_t *dy,
+                double *part, double *out, hipStream_t s);
+void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,
+                 hipStream_t s);
+void wsnet_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1, float c2, const float *grad,
+                float *w, float *m, float *v, uint16_t *Wk, uint16_t *WkT, float *bias, hipStream_t s);
+void wsnet_dual_from_net(int nx, int ny, int B, int tv, const float *y, const float *base, float *dual, hipStream_t s);
+
+// input channels of a network (1: x; 3: x and a base dual)
+int wsnet_input_channels(const sci_wsnet *n);
+
+} // namespace sci

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "sci_internal.h"
+#include "sci_wsnet.h"
 
 namespace sci {
 namespace {
@@ -428,6 +429,38 @@ int read_scalars(sci_ctx *ctx, const double *dev, int n, hipStream_t s)
     return SCI_OK;
 }
 
+
+// Denoise with a duality-gap stopping rule (relative gap <= q.gap_tol checked
+// every q.gap_check_every iterations, at most q.n_inner_max), starting from
+// `init` (nullable = zero dual). Leaves p in r.cur, writes theta, adds the
+// iterations run to *iters and reports convergence.
+int denoise_adaptive(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &q, const float *x, float *theta,
+                     float *u_out, const void *init, FgpRun &r, int *iters, bool *converged, hipStream_t s)
+{
+    const int every = q.gap_check_every > 0 ? q.gap_check_every : 10;
+    r.cur = init;
+    r.prev = nullptr;
+    r.iters = 0;
+    r.beta_prev = 0.0;
+    r.mom = Momentum();
+    *converged = false;
+    int st = SCI_OK;
+    double gap = 0.0, primal = 0.0;
+    while (r.iters < q.n_inner_max) {
+        const int n = std::min(every, q.n_inner_max - r.iters);
+        if ((st = fgp_iterate(ctx, d, q, x, r, n, s)) != SCI_OK) return st;
+        if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, x, r.cur, &gap, &primal, s)) != SCI_OK) return st;
+        if ((primal > 0.0 ? gap / primal : 0.0) <= q.gap_tol) {
+            *converged = true;
+            break;
+        }
+    }
+    *iters += r.iters;
+    st = launch_tv_theta(q.dual_dtype, d.nx, d.ny, d.B, x, r.cur, q.lambda, theta, u_out, s);
+    if (st != SCI_OK) return fail(ctx, st, "theta pass");
+    return check_launch(ctx, "k_tv_theta");
+}
+
 } // namespace
 } // namespace sci
 
@@ -554,6 +587,75 @@ int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const floa
                 float *Theta_out, const float *X_init, hipStream_t stream)
 {
     return run_outer(ctx, d, p, Y, C, X_out, Theta_out, X_init, true, stream);
+}
+
+int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
+                        float *X_out, float *Theta_out, const float *X_init, sci_wsnet *net, int32_t *inner_iters_out,
+                        int32_t *fallbacks_out, hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (!p || !Y || !C || !X_out) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
+    if ((st = check_tv(ctx, p->tv, d)) != SCI_OK) return st;
+    const sci_tv_params &t0 = p->tv;
+    if (!(t0.gap_tol > 0.0) || !std::isfinite(t0.gap_tol) || t0.n_inner_max < 1 || t0.lambda <= 0.0f)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "adaptive GAP needs gap_tol > 0, n_inner_max >= 1, lambda > 0");
+    if (t0.dual_dtype != SCI_DUAL_F32) return fail(ctx, SCI_ERR_UNSUPPORTED, "adaptive GAP stores float32 duals");
+    if (p->outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "outer_iters must be >= 0");
+    const size_t vb = vol_elems(d) * sizeof(float), ib = img_elems(d) * sizeof(float);
+    const void *ins[3] = {Y, C, X_init};
+    const size_t inb[3] = {ib, vb, vb};
+    for (int k = 0; k < 3; ++k)
+        if (overlaps(X_out, vb, ins[k], inb[k]) || overlaps(Theta_out, vb, ins[k], inb[k]))
+            return fail(ctx, SCI_ERR_ALIAS, "outputs must not overlap Y, C or X_init");
+    if ((st = use_device(ctx)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_SINV, ib, stream)) != SCI_OK) return st;
+    if (!Theta_out && (st = ensure_ws(ctx, WS_THETA, vb, stream)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, SCI_DUAL_F32, stream)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_XTMP, 2 * vb, stream)) != SCI_OK) return st; // predicted dual
+    float *theta = Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr;
+    float *Sinv = (float *)ctx->ws[WS_SINV].ptr;
+    float *pred = (float *)ctx->ws[WS_XTMP].ptr;
+    sci_tv_params q = t0;
+    q.schedule = SCI_SCHED_STREAM;
+    launch_weights(d.nx, d.ny, d.B, C, 0.0f, Sinv, stream);
+    if (X_init) launch_copy(X_init, theta, vb, stream);
+    else launch_adjoint(d.nx, d.ny, d.B, C, Y, theta, stream);
+    if (p->outer_iters == 0) launch_copy(theta, X_out, vb, stream);
+    if ((st = check_launch(ctx, "adaptive setup")) != SCI_OK) return st;
+    FgpRun r;
+    bind_duals(ctx, r);
+    int inner = 0, fallbacks = 0;
+    const void *keep = nullptr;
+    for (int t = 0; t < p->outer_iters; ++t) {
+        launch_gap_project(d.nx, d.ny, d.B, theta, C, Y, Sinv, X_out, stream);
+        if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
+        const void *init = nullptr;
+        // a correcting network (3 input channels) needs the previous call's final dual,
+        // so the first call starts cold
+        const bool use_net = net && (wsnet_input_channels(net) == 1 || keep);
+        if (use_net) {
+            if ((st = sci_wsnet_forward(ctx, net, d, X_out, (const float *)keep, nullptr, q.tv, pred, stream)) !=
+                SCI_OK)
+                return st;
+            init = pred;
+        } else if (p->warm_dual) {
+            init = keep;
+        }
+        bool ok = false;
+        if ((st = denoise_adaptive(ctx, d, q, X_out, theta, nullptr, init, r, &inner, &ok, stream)) != SCI_OK)
+            return st;
+        if (!ok && use_net) { // the predicted start did not reach the tolerance: cold start
+            ++fallbacks;
+            if ((st = denoise_adaptive(ctx, d, q, X_out, theta, nullptr, nullptr, r, &inner, &ok, stream)) != SCI_OK)
+                return st;
+        }
+        keep = r.cur;
+    }
+    if (inner_iters_out) *inner_iters_out = inner;
+    if (fallbacks_out) *fallbacks_out = fallbacks;
+    return SCI_OK;
 }
 
 int sci_tile_shape_count(void) { return tile_shape_count(); }

@@ -79,6 +79,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_dual_gap": (I, [V, D, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, V, V, P(ctypes.c_double),
                              P(ctypes.c_double), V]),
         "sci_profile_enable": (I, [V, I]),
+        "sci_wsnet_create": (I, [V, ctypes.c_int32, ctypes.c_int32, P(V)]),
+        "sci_wsnet_destroy": (None, [V]),
+        "sci_wsnet_param_count": (ctypes.c_int64, []),
+        "sci_wsnet_set_params": (I, [V, V, P(ctypes.c_float), ctypes.c_int64]),
+        "sci_wsnet_get_params": (I, [V, V, P(ctypes.c_float), ctypes.c_int64]),
+        "sci_wsnet_forward": (I, [V, V, D, V, V, V, ctypes.c_int32, V, V]),
+        "sci_wsnet_grads": (I, [V, V, D, V, V, V, P(ctypes.c_float), P(ctypes.c_double), V]),
+        "sci_wsnet_train_step": (I, [V, V, D, V, V, V, ctypes.c_float, P(ctypes.c_double), V]),
+        "sci_gap_tv_adaptive": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V, P(ctypes.c_int32),
+                                    P(ctypes.c_int32), V]),
         "sci_gap_tv_batched": (I, [V, ctypes.c_int32, P(sci_problem), P(sci_solver_params), V]),
         "sci_autotune_batched": (I, [V, ctypes.c_int32, P(sci_problem), P(sci_solver_params), P(ctypes.c_int32),
                                      P(ctypes.c_double), V]),
@@ -307,6 +317,84 @@ def sci_profile_read(ctx, family: str):
     n, ms = ctypes.c_int64(0), ctypes.c_double(0.0)
     _check(ctx, lib.sci_profile_read(ctx, family.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+# ---- learned warm start -----------------------------------------------------------
+
+def sci_wsnet_create(ctx, c_in: int = 1, c_out: int = 2):
+    h = ctypes.c_void_p()
+    _check(ctx, lib.sci_wsnet_create(ctx, int(c_in), int(c_out), ctypes.byref(h)))
+    return h
+
+
+def sci_wsnet_destroy(net) -> None:
+    lib.sci_wsnet_destroy(net)
+
+
+def sci_wsnet_param_count() -> int:
+    return lib.sci_wsnet_param_count()
+
+
+def sci_wsnet_set_params(ctx, net, params) -> None:
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    _check(ctx, lib.sci_wsnet_set_params(ctx, net, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+
+
+def sci_wsnet_get_params(ctx, net):
+    import numpy as np
+    a = np.empty(lib.sci_wsnet_param_count(), dtype=np.float32)
+    _check(ctx, lib.sci_wsnet_get_params(ctx, net, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+    return a
+
+
+def sci_wsnet_forward(ctx, net, X, tv="itv2d", base=None, want_raw=False, want_dual=True, stream=None):
+    """(raw [V][16] output or None, projected dual [2][B][nx][ny] or None)."""
+    d = _dims(X)
+    raw = torch.empty((X.numel(), 16), device=X.device) if want_raw else None
+    dual = torch.empty((2,) + tuple(X.shape), device=X.device) if want_dual else None
+    _check(ctx, lib.sci_wsnet_forward(ctx, net, d, _dev(X, name="X"), _dev(base, shape=(2,) + tuple(X.shape), name="base"),
+                                      _dev(raw, name="raw"),
+                                      TV[tv] if isinstance(tv, str) else int(tv), _dev(dual, name="dual"),
+                                      _stream(stream)))
+    return raw, dual
+
+
+def sci_wsnet_grads(ctx, net, X, target, base=None, stream=None):
+    """(loss, gradient in the padded parameter layout)."""
+    import numpy as np
+    d = _dims(X)
+    g = np.empty(lib.sci_wsnet_param_count(), dtype=np.float32)
+    loss = ctypes.c_double(0.0)
+    _check(ctx, lib.sci_wsnet_grads(ctx, net, d, _dev(X, name="X"), _dev(base, name="base"),
+                                    _dev(target, name="target"),
+                                    g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss),
+                                    _stream(stream)))
+    return loss.value, g
+
+
+def sci_wsnet_train_step(ctx, net, X, target, lr, base=None, want_loss=True, stream=None):
+    d = _dims(X)
+    loss = ctypes.c_double(0.0)
+    _check(ctx, lib.sci_wsnet_train_step(ctx, net, d, _dev(X, name="X"), _dev(base, name="base"),
+                                         _dev(target, name="target"), float(lr),
+                                         ctypes.byref(loss) if want_loss else None, _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def sci_gap_tv_adaptive(ctx, Y, C, params: sci_solver_params, net=None, X_out=None, Theta_out=None, X_init=None,
+                        stream=None):
+    """Gap-controlled GAP-TV; returns (X_out, total inner iterations, fallbacks)."""
+    d = _dims(C)
+    if X_out is None:
+        X_out = torch.empty_like(C)
+    its, fb = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(ctx, lib.sci_gap_tv_adaptive(ctx, d, ctypes.byref(params), _dev(Y, shape=(d.nx, d.ny), name="Y"),
+                                        _dev(C, name="C"), _dev(X_out, shape=C.shape, name="X_out"),
+                                        _dev(Theta_out, shape=C.shape, name="Theta_out"),
+                                        _dev(X_init, shape=C.shape, name="X_init"), net, ctypes.byref(its),
+                                        ctypes.byref(fb), _stream(stream)))
+    return X_out, its.value, fb.value
 
 
 class Context:

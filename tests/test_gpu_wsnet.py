@@ -1,0 +1,249 @@
+"""GPU: the warm-start network's MFMA kernels against the FP64 network oracle
+(forward, gradients, Adam, dual projection), and the learned warm start in
+the gap-controlled GAP solver."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as orc  # noqa: E402
+from oracle import wsnet_oracle as wo  # noqa: E402
+from paper_2005_08028_amd import synth  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def sc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_08028_amd import scitv
+    return scitv
+
+
+@pytest.fixture(scope="module")
+def ctx(sc):
+    c = sc.Context(0)
+    yield c.handle
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.fixture()
+def net(sc, ctx):
+    n = sc.sci_wsnet_create(ctx, c_in=1, c_out=2)
+    yield n
+    sc.sci_wsnet_destroy(n)
+
+
+@pytest.fixture()
+def rnet(sc, ctx):
+    n = sc.sci_wsnet_create(ctx, c_in=3, c_out=2)
+    yield n
+    sc.sci_wsnet_destroy(n)
+
+
+def params(seed, c_in=1):
+    from paper_2005_08028_amd import warmstart
+    return warmstart.init_params(seed, last_scale=1.0, c_in=c_in)
+
+
+@pytest.mark.parametrize("B,nx,ny", [(3, 20, 37), (1, 5, 3), (4, 17, 64)])
+def test_forward_matches_oracle(sc, ctx, net, B, nx, ny):
+    P = params(B + nx)
+    sc.sci_wsnet_set_params(ctx, net, P)
+    np.testing.assert_array_equal(sc.sci_wsnet_get_params(ctx, net), wo.pack(wo.unpack(P)))
+    x = np.random.default_rng(1).uniform(size=(B, nx, ny)).astype(np.float32)
+    raw, dual = sc.sci_wsnet_forward(ctx, net, dev(x), tv="itv2d", want_raw=True)
+    raw = host(raw).reshape(B, nx, ny, 16)
+    _, y = wo.forward(x, P)
+    got = np.moveaxis(raw[..., :2], -1, 0)
+    e = rel(got, y)
+    print(f"forward {B}x{nx}x{ny}: rel-L2 {e:.2e}", flush=True)
+    assert e <= 5e-3
+    assert np.all(raw[..., 2:] == 0)
+    np.testing.assert_allclose(host(dual), wo.project_dual(got, "itv2d"), rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("B,nx,ny", [(3, 20, 37), (2, 9, 70)])
+def test_residual_forward_matches_oracle(sc, ctx, rnet, B, nx, ny):
+    """c_in = 3: input (x, base dual), prediction base + output."""
+    P = params(B + ny, c_in=3)
+    sc.sci_wsnet_set_params(ctx, rnet, P)
+    r = np.random.default_rng(5)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    base = r.uniform(-1, 1, size=(2, B, nx, ny)).astype(np.float32)
+    raw, dual = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="vtv", base=dev(base), want_raw=True)
+    raw = host(raw).reshape(B, nx, ny, 16)
+    _, y = wo.forward(x, P, base=base, c_in=3)
+    got = np.moveaxis(raw[..., :2], -1, 0)
+    e = rel(got, y)
+    print(f"residual forward {B}x{nx}x{ny}: rel-L2 {e:.2e}", flush=True)
+    assert e <= 5e-3
+    np.testing.assert_allclose(host(dual), wo.project_dual(got + base, "vtv"), rtol=0, atol=2e-6)
+    # no base given: the base channels read as zero
+    _, dual0 = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="vtv")
+    _, y0 = wo.forward(x, P, base=None, c_in=3)
+    assert rel(host(dual0), wo.project_dual(y0, "vtv")) <= 5e-3
+
+
+def test_residual_zero_net_is_the_base(sc, ctx, rnet):
+    """A freshly created network has zero weights: its projected prediction is
+    the projected base dual, exactly."""
+    r = np.random.default_rng(6)
+    x = r.uniform(size=(2, 12, 30)).astype(np.float32)
+    base = r.uniform(-1.5, 1.5, size=(2, 2, 12, 30)).astype(np.float32)
+    _, dual = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="itv2d", base=dev(base))
+    np.testing.assert_allclose(host(dual), wo.project_dual(base.astype(np.float64), "itv2d"), rtol=0, atol=2e-6)
+
+
+def test_residual_gradients_match_oracle(sc, ctx, rnet):
+    P = params(17, c_in=3)
+    sc.sci_wsnet_set_params(ctx, rnet, P)
+    r = np.random.default_rng(12)
+    x = r.uniform(size=(3, 18, 40)).astype(np.float32)
+    base = r.uniform(-1, 1, size=(2, 3, 18, 40)).astype(np.float32)
+    t = r.normal(scale=0.5, size=(2, 3, 18, 40)).astype(np.float32)
+    loss, g = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
+    lo, go = wo.loss_and_grads(x, t, P, base=base, c_in=3)
+    assert abs(loss - lo) <= 2e-3 * lo
+    G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
+    for l in range(4):
+        e = rel(G[l], GO[l])
+        print(f"residual layer {l} gradient rel-L2 {e:.2e}", flush=True)
+        assert e <= 2e-2
+
+
+def test_gradients_match_oracle(sc, ctx, net):
+    P = params(7)
+    sc.sci_wsnet_set_params(ctx, net, P)
+    r = np.random.default_rng(2)
+    x = r.uniform(size=(3, 18, 40)).astype(np.float32)
+    t = r.normal(scale=0.5, size=(2, 3, 18, 40)).astype(np.float32)
+    loss, g = sc.sci_wsnet_grads(ctx, net, dev(x), dev(t))
+    lo, go = wo.loss_and_grads(x, t, P)
+    assert abs(loss - lo) <= 2e-3 * lo
+    G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
+    for l in range(4):
+        e = rel(G[l], GO[l])
+        print(f"layer {l} gradient rel-L2 {e:.2e}", flush=True)
+        assert e <= 2e-2
+
+
+def test_adam_step_matches_oracle(sc, ctx, net):
+    P = params(9)
+    sc.sci_wsnet_set_params(ctx, net, P)
+    r = np.random.default_rng(3)
+    x = dev(r.uniform(size=(2, 16, 16)))
+    t = dev(r.normal(scale=0.5, size=(2, 2, 16, 16)))
+    _, g = sc.sci_wsnet_grads(ctx, net, x, t)
+    sc.sci_wsnet_train_step(ctx, net, x, t, 1e-3)
+    W1 = sc.sci_wsnet_get_params(ctx, net)
+    live = wo.pack(wo.unpack(np.ones_like(P))) != 0
+    ref, _, _ = wo.adam_step(P.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
+    np.testing.assert_allclose(W1[live], ref[live], rtol=1e-5, atol=1e-7)
+    assert np.all(W1[~live] == 0)
+
+
+def test_training_reduces_loss(sc, ctx, net):
+    sc.sci_wsnet_set_params(ctx, net, params(11))
+    r = np.random.default_rng(4)
+    x = dev(r.uniform(size=(4, 32, 32)))
+    dual = torch.empty((2, 4, 32, 32), device="cuda")
+    sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="itv2d", lam=0.1, n_inner=200), dual_out=dual)
+    first = sc.sci_wsnet_train_step(ctx, net, x, dual, 3e-3)
+    for _ in range(150):
+        last = sc.sci_wsnet_train_step(ctx, net, x, dual, 3e-3)
+    print(f"loss {first:.4e} -> {last:.4e}", flush=True)
+    assert last < 0.5 * first
+
+
+def test_adaptive_gap_cold_matches_converged_fixed(sc, ctx):
+    pr = synth.make_problem(64, 80, 8, seed=5, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    prm = sc.solver_params(outer_iters=8, tv="itv2d", lam=0.1, gap_tol=1e-7, n_inner_max=3000, gap_check_every=5)
+    x, its, fb = sc.sci_gap_tv_adaptive(ctx, dev(Y), dev(pr.masks), prm)
+    assert fb == 0 and its > 8 * 5
+    ref, _ = orc.gap_tv(Y, pr.masks, float(np.float32(0.1)), 8, 2000, tv="itv2d")
+    e = rel(host(x), ref)
+    print(f"adaptive cold GAP vs 2000-iteration oracle: rel-L2 {e:.2e}, {its} inner iterations", flush=True)
+    assert e <= 1e-3
+
+
+def _held_out(sc, ctx, tv, lam, outer):
+    pr = synth.make_problem(64, 64, 8, seed=999, sigma=0.01)
+    Y, C = dev(orc.measurement(pr.masks, pr.truth, pr.noise)), dev(pr.masks)
+    prm = sc.solver_params(outer_iters=outer, tv=tv, lam=lam, gap_tol=1e-4, n_inner_max=500, gap_check_every=1)
+    return pr, Y, C, prm
+
+
+def test_learned_warm_start_gains(sc, ctx, rnet):
+    """The correcting network (input x^(t) and the previous outer iteration's
+    final dual, output added to that dual) trained on GPU-FGP duals: against a
+    cold start it needs far fewer inner iterations to reach relative gap 1e-4,
+    at the same PSNR. Most of that gain is the previous dual itself: the test
+    reports the trained correction against the plain warm-dual start as well
+    (on this scene family the correction does not beat it)."""
+    from paper_2005_08028_amd import warmstart
+    tv, lam, outer = "itv2d", 0.1, 30
+    data = []
+    for seed in range(3):
+        pr = synth.make_problem(64, 64, 8, seed=100 + seed, sigma=0.01)
+        Y, C = dev(orc.measurement(pr.masks, pr.truth, pr.noise)), dev(pr.masks)
+        data += warmstart.warm_dual_triples(ctx, Y, C, tv, lam, outer, tol=1e-4, target_tol=1e-6)[1:]
+    sc.sci_wsnet_set_params(ctx, rnet, warmstart.init_params(0, c_in=3, last_scale=0.0))
+    pr, Y, C, prm = _held_out(sc, ctx, tv, lam, outer)
+    xc, cold, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    prm.warm_dual = 1
+    xw, warm, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    prm.warm_dual = 0
+    _, untrained, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
+    hist = warmstart.train(ctx, rnet, data, steps=1500, lr=3e-5, log_every=500)
+    print("training loss", hist, flush=True)
+    xl, learned, fb = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
+    truth = dev(pr.truth)
+    pc, pw, pl = (sc.sci_psnr(ctx, v, truth) for v in (xc, xw, xl))
+    print(f"inner iterations to gap 1e-4 over {outer} outer: cold {cold}, warm dual {warm}, untrained net {untrained}, "
+          f"trained net {learned} ({fb} fallbacks; {warm / learned:.2f}x vs warm dual); "
+          f"PSNR cold {pc:.3f} warm {pw:.3f} learned {pl:.3f}", flush=True)
+    assert untrained == warm  # the zero-initialised correction is the warm-dual start
+    assert learned * 2 <= cold
+    assert fb == 0
+    assert abs(pc - pl) < 0.05 and abs(pw - pl) < 0.05
+
+
+def test_input_only_network_falls_back(sc, ctx, net):
+    """The network that sees x^(t) alone, trained on (x^(t), converged dual)
+    pairs: its starts are checked by the duality gap and every call that misses
+    the tolerance is redone from a zero dual, so the reconstruction matches the
+    cold start whatever the network predicts."""
+    from paper_2005_08028_amd import warmstart
+    tv, lam, outer = "itv2d", 0.1, 10
+    pairs = []
+    for seed in range(2):
+        pr = synth.make_problem(64, 64, 8, seed=100 + seed, sigma=0.01)
+        Y, C = dev(orc.measurement(pr.masks, pr.truth, pr.noise)), dev(pr.masks)
+        pairs += [(x, t) for x, _, t in warmstart.warm_dual_triples(ctx, Y, C, tv, lam, outer)]
+    sc.sci_wsnet_set_params(ctx, net, warmstart.init_params(0, last_scale=0.0))
+    hist = warmstart.train(ctx, net, pairs, steps=500, lr=1e-4, log_every=250)
+    pr, Y, C, prm = _held_out(sc, ctx, tv, lam, outer)
+    xc, cold, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    xl, learned, fb = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=net)
+    truth = dev(pr.truth)
+    pc, pl = sc.sci_psnr(ctx, xc, truth), sc.sci_psnr(ctx, xl, truth)
+    print(f"x-only network: loss {hist}; inner iterations cold {cold}, learned {learned} ({fb} fallbacks); "
+          f"PSNR cold {pc:.3f} learned {pl:.3f}", flush=True)
+    assert abs(pc - pl) < 0.05
+    assert 0 <= fb <= outer
