@@ -57,8 +57,8 @@ def _load():
         "orc_fgp_beta": (None, [i, P]),
         "orc_tv_denoise": (i, [i, i, i, i, d, i, i, i, i, P, P, P, P, P]),
         "orc_dual_gap": (d, [i, i, i, i, d, P, P, P]),
-        "orc_gap_tv": (i, [i, i, i, i, d, i, i, i, P, P, P, P, P]),
-        "orc_admm_tv": (i, [i, i, i, i, d, d, i, i, i, P, P, P, P, P]),
+        "orc_gap_tv": (i, [i, i, i, i, d, i, i, i, i, i, P, P, P, P, P]),
+        "orc_admm_tv": (i, [i, i, i, i, d, d, i, i, i, i, i, P, P, P, P, P]),
         "orc_psnr": (d, [ctypes.c_long, P, P, d]),
         "orc_residual_sq": (d, [i, i, i, P, P, P]),
     }
@@ -181,19 +181,20 @@ def dual_gap(x, p, lam, tv):
     return g, prim.value
 
 
-def gap_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None):
-    """GAP-TV (Eq. (21)-(22), Algorithm 1). Returns (x^(T), theta^(T))."""
+def gap_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None, warm_dual=False, chambolle04=False):
+    """GAP-TV (Eq. (21)-(22), Algorithm 1). Returns (x^(T), theta^(T)).
+    warm_dual: each denoiser call starts from the previous call's final dual."""
     Y, C = _d(Y), _d(C)
     B, nx, ny = _dims(C)
     x = np.empty((B, nx, ny))
     th = np.empty((B, nx, ny))
     xi = None if x_init is None else _d(x_init)
-    _load().orc_gap_tv(_kind(tv), B, nx, ny, float(lam), int(T), int(N), int(bool(accel)), _p(Y), _p(C),
-                       _p(xi), _p(x), _p(th))
+    _load().orc_gap_tv(_kind(tv), B, nx, ny, float(lam), int(T), int(N), int(bool(accel)), int(bool(warm_dual)),
+                       int(bool(chambolle04)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
     return x, th
 
 
-def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None):
+def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None, warm_dual=False, chambolle04=False):
     """ADMM-TV (Eq. (24)-(26)). Returns (x^(T), theta^(T))."""
     Y, C = _d(Y), _d(C)
     B, nx, ny = _dims(C)
@@ -201,7 +202,7 @@ def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None):
     th = np.empty((B, nx, ny))
     xi = None if x_init is None else _d(x_init)
     _load().orc_admm_tv(_kind(tv), B, nx, ny, float(lam), float(rho), int(T), int(N), int(bool(accel)),
-                        _p(Y), _p(C), _p(xi), _p(x), _p(th))
+                        int(bool(warm_dual)), int(bool(chambolle04)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
     return x, th
 
 

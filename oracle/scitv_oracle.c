@@ -247,7 +247,7 @@ int orc_tv_denoise(int kind, int B, int nx, int ny, double lambda, int n_iter, i
     if (lambda == 0.0 || n_iter == 0) {
         memcpy(theta_out, x, V * sizeof(double));
         if (ph_out) {
-            if (p_init) { memcpy(ph_out, p_init, V * sizeof(double)); memcpy(pv_out, p_init + V, V * sizeof(double)); }
+            if (p_init) { memmove(ph_out, p_init, V * sizeof(double)); memmove(pv_out, p_init + V, V * sizeof(double)); }
             else { memset(ph_out, 0, V * sizeof(double)); memset(pv_out, 0, V * sizeof(double)); }
         }
         return 0;
@@ -376,8 +376,12 @@ double orc_dual_gap(int kind, int B, int nx, int ny, double lambda, const double
  *   theta^(0) = Phi^T y (or x_init)
  *   x^(t+1)     = theta^(t) + Phi^T (Phi Phi^T)^+ (y - Phi theta^(t))
  *   theta^(t+1) = TVdenoise(x^(t+1))
- * for exactly T outer iterations; returns x^(T) and theta^(T). */
-int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel,
+ * for exactly T outer iterations; returns x^(T) and theta^(T).
+ * warm: each denoiser call starts from the dual the previous call ended with
+ *   (Algorithm 1 initialises p before the outer loop; the first call starts
+ *   from zero); otherwise every call starts from zero.
+ * chambolle04: the denoiser's semi-implicit denominator variant (Sec. 2.3). */
+int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel, int warm, int chambolle04,
                const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
 {
     size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
@@ -386,6 +390,7 @@ int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int
     double *th = (double *)malloc(V * sizeof(double));
     double *x = (double *)malloc(V * sizeof(double));
     double *cr = (double *)malloc(V * sizeof(double));
+    double *P = (double *)calloc(2 * V, sizeof(double)); /* carried dual [2][V] */
     orc_weights(B, nx, ny, C, 0.0, Sinv);
     if (x_init) memcpy(th, x_init, V * sizeof(double));
     else orc_adjoint(B, nx, ny, C, Y, th);
@@ -395,11 +400,11 @@ int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int
         for (size_t c = 0; c < n; ++c) r[c] = (Y[c] - r[c]) * Sinv[c];
         orc_adjoint(B, nx, ny, C, r, cr);                    /* Phi^T (.) */
         for (size_t c = 0; c < V; ++c) x[c] = th[c] + cr[c];
-        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, 0, 0, x, NULL, th, NULL, NULL);
+        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, chambolle04, 0, x, warm ? P : NULL, th, P, P + V);
     }
     memcpy(x_out, x, V * sizeof(double));
     if (theta_out) memcpy(theta_out, th, V * sizeof(double));
-    free(Sinv); free(r); free(th); free(x); free(cr);
+    free(Sinv); free(r); free(th); free(x); free(cr); free(P);
     return 0;
 }
 
@@ -409,10 +414,12 @@ int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int
  *     (matrix inversion lemma; Phi Phi^T is diagonal so this is element-wise)
  *   theta^(t+1) = TVdenoise(u^(t) + x^(t+1))  with weight lambda
  *   u^(t+1)     = u^(t) + x^(t+1) - theta^(t+1). */
-int orc_admm_tv(int kind, int B, int nx, int ny, double lambda, double rho, int T, int N, int accel,
-                const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
+int orc_admm_tv(int kind, int B, int nx, int ny, double lambda, double rho, int T, int N, int accel, int warm,
+                int chambolle04, const double *Y, const double *C, const double *x_init, double *x_out,
+                double *theta_out)
 {
     size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
+    double *P = (double *)calloc(2 * V, sizeof(double)); /* carried dual [2][V] (warm, as in GAP) */
     double *Sinv = (double *)malloc(n * sizeof(double));
     double *r = (double *)malloc(n * sizeof(double));
     double *th = (double *)malloc(V * sizeof(double));
@@ -431,12 +438,12 @@ int orc_admm_tv(int kind, int B, int nx, int ny, double lambda, double rho, int 
         orc_adjoint(B, nx, ny, C, r, cr);
         for (size_t c = 0; c < V; ++c) x[c] = v[c] + cr[c];
         for (size_t c = 0; c < V; ++c) v[c] = u[c] + x[c];  /* denoiser input */
-        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, 0, 0, v, NULL, th, NULL, NULL);
+        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, chambolle04, 0, v, warm ? P : NULL, th, P, P + V);
         for (size_t c = 0; c < V; ++c) u[c] = u[c] + x[c] - th[c];
     }
     memcpy(x_out, x, V * sizeof(double));
     if (theta_out) memcpy(theta_out, th, V * sizeof(double));
-    free(Sinv); free(r); free(th); free(u); free(v); free(x); free(cr);
+    free(Sinv); free(r); free(th); free(u); free(v); free(x); free(cr); free(P);
     return 0;
 }
 

@@ -493,3 +493,78 @@ def test_fgp_and_pg_rate_bounds(tv):
         assert 0.5 * (th ** 2).sum() - h_star <= 2 * L * R2 / (n + 1) ** 2 + 1e-12
         th = orc.tv_denoise(x, lam, n, tv, accel=False)
         assert 0.5 * (th ** 2).sum() - h_star <= L * R2 / (2 * n) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Denoiser and outer-loop variants: Chambolle-2004 denominator, warm dual.
+# ---------------------------------------------------------------------------
+
+def kind_norm(z, tv):
+    """|z| measured per the TV kind, broadcast to z's shape."""
+    if tv == "atv":
+        return np.abs(z)
+    if tv == "itv2d":
+        return np.broadcast_to(np.sqrt(z[0] ** 2 + z[1] ** 2), z.shape)
+    return np.broadcast_to(np.sqrt((z[0] ** 2 + z[1] ** 2).sum(axis=0)), z.shape)
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_chambolle04_first_step_closed_form(tv):
+    """One semi-implicit step from p = 0: z = D x, p1 = (z/(8 lam)) / (1 + |z|/(8 lam))
+    with |z| per the TV kind, theta = x - lam D^T p1 (dense D)."""
+    x = rng(40).uniform(size=(3, 6, 7))
+    lam = 0.15
+    st = 1.0 / (8 * lam)
+    z = dense_grad(x)
+    p1 = st * z / (1.0 + st * kind_norm(z, tv))
+    th, p = orc.tv_denoise(x, lam, 1, tv, accel=False, chambolle04=True, return_dual=True)
+    np.testing.assert_allclose(p, p1, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(th, x - lam * dense_grad_adj(p1), rtol=0, atol=1e-14)
+    # the step stays inside the dual ball without a projection
+    assert dual_norm_max(p, tv) < 1.0
+
+
+def explicit_gap(Y, C, lam, T, N, tv, warm):
+    """GAP written out from the primitives, the dual carried by hand."""
+    S = orc.weights(C)
+    th = orc.adjoint(C, Y)
+    p = None
+    for _ in range(T):
+        x = th + orc.adjoint(C, (Y - orc.forward(C, th)) * S)
+        th, pn = orc.tv_denoise(x, lam, N, tv, p_init=p if warm else None, return_dual=True)
+        p = pn
+    return x, th
+
+
+@pytest.mark.parametrize("tv", ["atv", "vtv"])
+def test_warm_dual_gap(tv):
+    C, X, Y = small_problem(41, B=3, nx=9, ny=8)
+    # driver against the loop written out
+    xw, tw = orc.gap_tv(Y, C, 0.1, 4, 3, tv=tv, warm_dual=True)
+    xe, te = explicit_gap(Y, C, 0.1, 4, 3, tv, warm=True)
+    np.testing.assert_allclose(xw, xe, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(tw, te, rtol=0, atol=1e-14)
+    # one outer iteration has no previous dual: same as the cold start
+    np.testing.assert_array_equal(orc.gap_tv(Y, C, 0.1, 1, 3, tv=tv, warm_dual=True)[0],
+                                  orc.gap_tv(Y, C, 0.1, 1, 3, tv=tv)[0])
+    # few inner iterations: the start matters
+    xc, _ = orc.gap_tv(Y, C, 0.1, 4, 3, tv=tv)
+    assert np.abs(xc - xw).max() > 1e-6
+    # converged inner solves: the prox is unique, so the start does not matter
+    xw, _ = orc.gap_tv(Y, C, 0.1, 3, 3000, tv=tv, warm_dual=True)
+    xc, _ = orc.gap_tv(Y, C, 0.1, 3, 3000, tv=tv)
+    assert np.abs(xc - xw).max() < 1e-7
+
+
+def test_warm_dual_admm_and_chambolle04_outer():
+    C, X, Y = small_problem(42, B=3, nx=7, ny=8)
+    xw, _ = orc.admm_tv(Y, C, 0.1, 0.05, 3, 3000, tv="itv2d", warm_dual=True)
+    xc, _ = orc.admm_tv(Y, C, 0.1, 0.05, 3, 3000, tv="itv2d")
+    assert np.abs(xc - xw).max() < 1e-7
+    xw, _ = orc.admm_tv(Y, C, 0.1, 0.05, 3, 4, tv="itv2d", warm_dual=True)
+    xc, _ = orc.admm_tv(Y, C, 0.1, 0.05, 3, 4, tv="itv2d")
+    assert np.abs(xc - xw).max() > 1e-6
+    # the semi-implicit denoiser converges to the same prox inside GAP
+    xs, _ = orc.gap_tv(Y, C, 0.1, 2, 3000, tv="itv2d")
+    xh, _ = orc.gap_tv(Y, C, 0.1, 2, 20000, tv="itv2d", accel=False, chambolle04=True)
+    assert np.abs(xs - xh).max() < 1e-4
