@@ -71,11 +71,12 @@ typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_
 
 /* How the inner denoiser iterations are scheduled on the GPU:
  *   STREAM: one pass over HBM per inner iteration (dual fields in memory);
- *   FUSED : all inner iterations of one denoiser call in one on-chip pass
- *           per tile (dual fields never leave the chip; cold start and
- *           float32 duals only);
+ *   FUSED : up to 10 inner iterations per on-chip pass over each tile, the
+ *           dual fields written back only between passes (ATV and ITV2D;
+ *           not the Chambolle-2004 step);
  *   AUTO  : FUSED where it applies, else STREAM.
- * Both schedules evaluate the same per-voxel expressions. */
+ * Both schedules evaluate the same per-voxel expressions (bit for bit with
+ * float32 duals; 16-bit duals are rounded where they are stored). */
 typedef enum { SCI_SCHED_AUTO = 0, SCI_SCHED_STREAM = 1, SCI_SCHED_FUSED = 2 } sci_schedule;
 
 /* TV denoiser parameters: theta = argmin 1/2 ||theta - x||^2 + lambda TV(theta)
@@ -89,7 +90,9 @@ typedef struct {
     int32_t schedule;        /* sci_schedule */
     double gap_tol;          /* sci_tv_denoise only: > 0 iterates until the relative duality
                                 gap <= gap_tol (checked every gap_check_every iterations,
-                                at most n_inner_max iterations); <= 0 runs exactly n_inner */
+                                at most n_inner_max iterations; on the fused schedule the
+                                iterations between two checks run in on-chip passes of up to
+                                10); <= 0 runs exactly n_inner */
     int32_t n_inner_max;
     int32_t gap_check_every;
     int32_t tile_shape;      /* fused schedule: 0 = autotuned for this problem (sci_autotune) or the
@@ -97,6 +100,10 @@ typedef struct {
     int32_t tile_passes;     /* fused schedule: passes over HBM per denoiser call (each runs about
                                 n_inner / tile_passes iterations, at most 10); 0 = autotuned or
                                 default (passes of about 5 iterations) */
+    int32_t chambolle04;     /* 1 = Chambolle's (2004) semi-implicit step (Sec. 2.3):
+                                p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)), z = D theta, |z| per
+                                the TV kind, in place of the projection of w + z/(8 lambda);
+                                float32 duals, streaming schedule only. 0 = projection */
 } sci_tv_params;
 
 /* Outer framework parameters (Algorithm 1; ADMM of Eq. (24)-(26)). */

@@ -50,6 +50,7 @@ int validate(sci_ctx *ctx, int n, const sci_problem *probs, const sci_solver_par
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p->outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "outer_iters must be >= 0");
     if (p->warm_dual) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: cold-start denoiser only");
+    if (t.chambolle04) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: projection step only (no Chambolle-2004 step)");
     for (int i = 0; i < n; ++i) {
         const sci_problem &q = probs[i];
         if (q.d.nx < 1 || q.d.ny < 1 || q.d.B < 1 || (int64_t)q.d.nx * q.d.ny * q.d.B >= ((int64_t)1 << 31))
@@ -316,6 +317,7 @@ int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, cons
     (void)hipEventDestroy(e1);
     if (st != SCI_OK) return st;
     ctx->tuned[batch_key(*p, n, probs)] = std::make_pair(best, 1);
+    if ((st = drop_graphs(ctx)) != SCI_OK) return st;
     if (best_shape_out) *best_shape_out = best + 1;
     return SCI_OK;
 }

@@ -64,6 +64,16 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
 
 size_t dual_elem_bytes(int dual_dtype) { return dual_dtype == SCI_DUAL_F32 ? 4 : 2; }
 
+int drop_graphs(sci_ctx *ctx)
+{
+    if (ctx->graphs.empty()) return SCI_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipDeviceSynchronize");
+    for (auto &kv : ctx->graphs) destroy_graph(kv.second);
+    ctx->graphs.clear();
+    return SCI_OK;
+}
+
 void destroy_graph(GraphEntry &g)
 {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);

@@ -14,7 +14,13 @@
 // lane carries every frame of its column in registers (KB >= B) and projects
 // once all frames of the row are done. (The kernel also handles one frame per
 // lane, KB = 1, for the per-voxel projections; ATV and ITV2D stream through
-// the 2D tile kernel with one iteration per pass instead.)
+// the 2D tile kernel with one iteration per pass instead, except in the
+// Chambolle-2004 variant below.)
+//
+// CH = 1 replaces the projection P_K(q) by Chambolle's (2004) semi-implicit
+// step p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)) (Sec. 2.3), with |z|
+// taken per component (ATV), per voxel (ITV2D) or per pixel over all frames
+// (VTV); it runs on this kernel for every TV kind.
 #include <hip/hip_runtime.h>
 
 #include "sci_internal.h"
@@ -35,7 +41,7 @@ struct RowLoad {
     float ph, pv, pph, ppv, x;
 };
 
-template <int TV, int KB, int DT, int PF>
+template <int TV, int KB, int DT, int PF, int CH>
 __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int B, int rows, int nstrips,
                                                             int nwaves, const float *__restrict__ x,
                                                             const typename Dual<DT>::T *__restrict__ pc,
@@ -101,6 +107,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
         const bool has_next = i + 1 < nx;
         const float step_v = has_next ? step : 0.0f; // no vertical difference in the last row
         float qh[KB], qv[KB];
+        float sh[KB], sv[KB]; // z/(8 lambda) where the difference exists (CH only)
         float n2 = 0.0f;
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
@@ -127,20 +134,35 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
                 }
                 const float zh = from_right(th0[kk]) - th0[kk];
                 const float zv = th1 - th0[kk];
-                qh[kk] = ascend(wh0[kk], zh, step_h);
-                qv[kk] = ascend(wv0[kk], zv, step_v);
-                if (TV == TV_VTV) n2 = norm2_add(n2, qh[kk], qv[kk]);
+                if (CH) {
+                    sh[kk] = step_h * zh;
+                    sv[kk] = step_v * zv;
+                    qh[kk] = wh0[kk] + sh[kk];
+                    qv[kk] = wv0[kk] + sv[kk];
+                    if (TV == TV_VTV) n2 = norm2_add(n2, sh[kk], sv[kk]);
+                } else {
+                    qh[kk] = ascend(wh0[kk], zh, step_h);
+                    qv[kk] = ascend(wv0[kk], zv, step_v);
+                    if (TV == TV_VTV) n2 = norm2_add(n2, qh[kk], qv[kk]);
+                }
                 wh0[kk] = wh1;
                 wv0[kk] = wv1;
                 th0[kk] = th1;
             }
         }
-        const float vsc = (TV == TV_VTV) ? iso_scale(n2) : 1.0f;
+        const float vsc = (TV == TV_VTV) ? (CH ? semi_implicit_scale(n2) : iso_scale(n2)) : 1.0f;
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk) {
             if (kk < nk) {
                 float ph, pv;
-                if (TV == TV_ATV) {
+                if (CH && TV == TV_ATV) {
+                    ph = qh[kk] / (1.0f + fabsf(sh[kk]));
+                    pv = qv[kk] / (1.0f + fabsf(sv[kk]));
+                } else if (CH && TV == TV_ITV2D) {
+                    const float s = semi_implicit_scale(norm2_add(0.0f, sh[kk], sv[kk]));
+                    ph = qh[kk] * s;
+                    pv = qv[kk] * s;
+                } else if (TV == TV_ATV) {
                     ph = proj_atv(qh[kk]);
                     pv = proj_atv(qv[kk]);
                 } else if (TV == TV_ITV2D) {
@@ -192,7 +214,7 @@ int pick_rows(int nx, int nstrips, int frames_in_grid)
     return rows;
 }
 
-template <int TV, int KB, int DT, int PF = (KB == 1 ? 2 : 0)>
+template <int TV, int KB, int DT, int CH = 0, int PF = (KB == 1 ? 2 : 0)>
 void launch_stream_t(int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn, int mode,
                      float beta, float lam, hipStream_t s)
 {
@@ -202,7 +224,7 @@ void launch_stream_t(int nx, int ny, int B, const float *x, const void *pc, cons
     const int rows = pick_rows(nx, nstrips, frames);
     const int nwaves = nstrips * ((nx + rows - 1) / rows);
     const dim3 grid((nwaves + kWaves - 1) / kWaves, frames);
-    hipLaunchKernelGGL((k_fgp_stream<TV, KB, DT, PF>), grid, dim3(64 * kWaves), 0, s, nx, ny, B, rows, nstrips, nwaves,
+    hipLaunchKernelGGL((k_fgp_stream<TV, KB, DT, PF, CH>), grid, dim3(64 * kWaves), 0, s, nx, ny, B, rows, nstrips, nwaves,
                        x, (const T *)pc, (const T *)pp, (T *)pn, mode, beta, lam, 1.0f / (8.0f * lam));
 }
 
@@ -224,7 +246,33 @@ int launch_stream_dt(int tv, int nx, int ny, int B, const float *x, const void *
     return SCI_OK;
 }
 
+// Chambolle-2004 step, float32 duals, every TV kind
+int launch_stream_ch(int tv, int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn,
+                     int mode, float beta, float lam, hipStream_t s)
+{
+    switch (tv) {
+    case TV_ATV: launch_stream_t<TV_ATV, 1, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s); return SCI_OK;
+    case TV_ITV2D:
+        launch_stream_t<TV_ITV2D, 1, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+        return SCI_OK;
+    case TV_VTV:
+        if (B <= 8) launch_stream_t<TV_VTV, 8, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+        else if (B <= 16) launch_stream_t<TV_VTV, 16, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+        else if (B <= 32) launch_stream_t<TV_VTV, 32, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+        else return SCI_ERR_UNSUPPORTED;
+        return SCI_OK;
+    }
+    return SCI_ERR_INVALID_ARG;
+}
+
 } // namespace
+
+int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
+                                  const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s)
+{
+    if (dual_dtype != DT_F32) return SCI_ERR_UNSUPPORTED;
+    return launch_stream_ch(tv, nx, ny, B, x, p_cur, p_prev, p_next, mode, beta, lam, s);
+}
 
 int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                       const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s)

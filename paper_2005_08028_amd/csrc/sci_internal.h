@@ -39,6 +39,9 @@ struct GraphEntry {
 };
 
 void destroy_graph(GraphEntry &g);
+// Destroy every captured graph (after a device synchronisation): the tiling
+// they froze may no longer be the tuned one.
+int drop_graphs(sci_ctx *ctx);
 
 // Kernel families timed by the profiler.
 enum ProfFamily { PF_FGP_STREAM = 0, PF_FGP_FUSED, PF_TV_THETA, PF_PROJECT, PF_SETUP, PF_COUNT };
@@ -109,6 +112,10 @@ void launch_zero(void *dst, size_t bytes, hipStream_t s);
 // w = 0 (mode 0), w = p_cur (mode 1), w = p_cur + beta (p_cur - p_prev) (mode 2).
 int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                       const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
+// The same iteration with Chambolle's (2004) semi-implicit step in place of
+// the projection (float32 duals; every TV kind).
+int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
+                                  const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
 // theta = x - lambda D^T p; when u_out is non-null also u_out = x - theta.
 int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const void *p, float lam,
                     float *theta, float *u_out, hipStream_t s);

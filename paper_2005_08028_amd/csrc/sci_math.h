@@ -75,6 +75,10 @@ __device__ inline float proj_atv(float q) { return fminf(fmaxf(q, -1.0f), 1.0f);
 // Isotropic scale 1 / max(1, sqrt(n2)) = min(1, 1/sqrt(n2)) for a squared norm n2.
 __device__ inline float iso_scale(float n2) { return fminf(1.0f, __builtin_amdgcn_rsqf(n2)); }
 
+// Semi-implicit (Chambolle 2004) scale 1 / (1 + sqrt(n2)) for the squared
+// norm n2 of z/(8 lambda).
+__device__ inline float semi_implicit_scale(float n2) { return 1.0f / (1.0f + __builtin_sqrtf(n2)); }
+
 // Squared-norm accumulation (h^2 + v^2 added to acc).
 __device__ inline float norm2_add(float acc, float h, float v) { return fmaf(v, v, fmaf(h, h, acc)); }
 

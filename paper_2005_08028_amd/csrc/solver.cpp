@@ -51,6 +51,9 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
     if (p.tile_shape < 0 || p.tile_shape > tile_shape_count())
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p.tile_passes < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "tile_passes must be >= 0");
+    if (p.chambolle04 != 0 && p.chambolle04 != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "chambolle04 must be 0 or 1");
+    if (p.chambolle04 && (p.dual_dtype != SCI_DUAL_F32 || p.schedule == SCI_SCHED_FUSED))
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "the Chambolle-2004 step runs with float32 duals on the streaming schedule");
     return SCI_OK;
 }
 
@@ -105,14 +108,15 @@ int stream_tile_shape(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims
 int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
                 hipStream_t s)
 {
-    if (tile_supported(p.tv))
+    if (tile_supported(p.tv) && !p.chambolle04)
         return fgp_tile_iterate(ctx, d, p, x, r, n, nullptr, nullptr, true, s, stream_tile_shape(ctx, p, d), n);
     for (int it = 0; it < n; ++it) {
         const int mode = r.mode(p);
         void *out = r.free_buffer();
         ProfScope prof(ctx, PF_FGP_STREAM, s);
-        int st = launch_fgp_stream(p.tv, p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, r.prev ? r.prev : r.cur, out,
-                                   mode, (float)r.beta_prev, p.lambda, s);
+        auto launch = p.chambolle04 ? launch_fgp_stream_chambolle04 : launch_fgp_stream;
+        int st = launch(p.tv, p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, r.prev ? r.prev : r.cur, out, mode,
+                        (float)r.beta_prev, p.lambda, s);
         if (st != SCI_OK) return fail(ctx, st, "FGP pass not available for this request");
         st = check_launch(ctx, "k_fgp_stream");
         if (st != SCI_OK) return st;
@@ -223,7 +227,7 @@ void bind_duals(sci_ctx *ctx, FgpRun &r)
 
 bool use_fused(const sci_tv_params &p)
 {
-    if (p.schedule == SCI_SCHED_STREAM) return false;
+    if (p.schedule == SCI_SCHED_STREAM || p.chambolle04) return false;
     if (p.schedule == SCI_SCHED_FUSED) return true;
     return tile_supported(p.tv) && p.n_inner >= 2;
 }
@@ -251,7 +255,7 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
             return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule covers ATV and ITV2D (VTV couples all frames)");
         return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);
     }
-    if (tile_supported(p.tv))
+    if (tile_supported(p.tv) && !p.chambolle04)
         return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s, stream_tile_shape(ctx, p, d),
                                 p.n_inner);
     int st = fgp_iterate(ctx, d, p, x, r, p.n_inner, s);
@@ -355,8 +359,9 @@ std::string graph_key(const OuterArgs &a)
 {
     char buf[512];
     const sci_tv_params &t = a.p.tv;
-    snprintf(buf, sizeof buf, "%d|%d,%d,%d|%d,%.9g,%d,%d,%d,%d|%d,%.9g,%d|%p,%p,%p,%p,%p", a.admm ? 1 : 0, a.d.nx,
-             a.d.ny, a.d.B, t.tv, (double)t.lambda, t.n_inner, t.accel, t.dual_dtype, t.schedule, a.p.outer_iters,
+    snprintf(buf, sizeof buf, "%d|%d,%d,%d|%d,%.9g,%d,%d,%d,%d,%d,%d,%d|%d,%.9g,%d|%p,%p,%p,%p,%p", a.admm ? 1 : 0,
+             a.d.nx, a.d.ny, a.d.B, t.tv, (double)t.lambda, t.n_inner, t.accel, t.dual_dtype, t.schedule,
+             t.chambolle04, t.tile_shape, t.tile_passes, a.p.outer_iters,
              (double)a.p.rho, a.p.warm_dual, (const void *)a.Y, (const void *)a.C, (const void *)a.X_init,
              (void *)a.X_out, (void *)a.theta);
     return buf;
@@ -430,6 +435,19 @@ int read_scalars(sci_ctx *ctx, const double *dev, int n, hipStream_t s)
 }
 
 
+// `n` more inner iterations of a gap-controlled denoiser call: on-chip passes
+// of up to kTileMaxM iterations where the fused schedule applies, else one
+// pass per iteration. The dual stays in r.cur for the gap check.
+int fgp_chunk(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &q, const float *x, FgpRun &r, int n, hipStream_t s)
+{
+    const bool fused = q.schedule != SCI_SCHED_STREAM && !q.chambolle04 && tile_supported(q.tv);
+    if (q.schedule == SCI_SCHED_FUSED && !fused)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule covers ATV and ITV2D (VTV couples all frames)");
+    if (fused)
+        return fgp_tile_iterate(ctx, d, q, x, r, n, nullptr, nullptr, true, s, -1, (n + kTileMaxM - 1) / kTileMaxM);
+    return fgp_iterate(ctx, d, q, x, r, n, s);
+}
+
 // Denoise with a duality-gap stopping rule (relative gap <= q.gap_tol checked
 // every q.gap_check_every iterations, at most q.n_inner_max), starting from
 // `init` (nullable = zero dual). Leaves p in r.cur, writes theta, adds the
@@ -448,7 +466,7 @@ int denoise_adaptive(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &q, co
     double gap = 0.0, primal = 0.0;
     while (r.iters < q.n_inner_max) {
         const int n = std::min(every, q.n_inner_max - r.iters);
-        if ((st = fgp_iterate(ctx, d, q, x, r, n, s)) != SCI_OK) return st;
+        if ((st = fgp_chunk(ctx, d, q, x, r, n, s)) != SCI_OK) return st;
         if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, x, r.cur, &gap, &primal, s)) != SCI_OK) return st;
         if ((primal > 0.0 ? gap / primal : 0.0) <= q.gap_tol) {
             *converged = true;
@@ -517,9 +535,6 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
 
     sci_tv_params q = *p;
     const bool want_dual = dual_out || rel_gap_out || adaptive;
-    if (adaptive && q.schedule == SCI_SCHED_FUSED)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "the gap-controlled loop runs on the streaming schedule");
-    if (adaptive) q.schedule = SCI_SCHED_STREAM;
     FgpRun r;
     bind_duals(ctx, r);
 
@@ -554,7 +569,7 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
         status = SCI_NOT_CONVERGED;
         while (r.iters < q.n_inner_max) {
             const int n = std::min(every, q.n_inner_max - r.iters);
-            if ((st = fgp_iterate(ctx, d, q, X_in, r, n, stream)) != SCI_OK) return st;
+            if ((st = fgp_chunk(ctx, d, q, X_in, r, n, stream)) != SCI_OK) return st;
             if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_in, r.cur, &gap, &primal, stream)) != SCI_OK)
                 return st;
             const double rel = primal > 0.0 ? gap / primal : 0.0;
@@ -617,8 +632,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     float *theta = Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr;
     float *Sinv = (float *)ctx->ws[WS_SINV].ptr;
     float *pred = (float *)ctx->ws[WS_XTMP].ptr;
-    sci_tv_params q = t0;
-    q.schedule = SCI_SCHED_STREAM;
+    const sci_tv_params &q = t0;
     launch_weights(d.nx, d.ny, d.B, C, 0.0f, Sinv, stream);
     if (X_init) launch_copy(X_init, theta, vb, stream);
     else launch_adjoint(d.nx, d.ny, d.B, C, Y, theta, stream);
@@ -730,6 +744,7 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     (void)hipEventDestroy(e1);
     if (st != SCI_OK) return st;
     ctx->tuned[tune_key(q, d)] = std::make_pair(best_s, best_p);
+    if ((st = drop_graphs(ctx)) != SCI_OK) return st;
     if (best_shape_out) *best_shape_out = best_s + 1;
     if (best_passes_out) *best_passes_out = best_p;
     return SCI_OK;

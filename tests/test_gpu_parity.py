@@ -242,6 +242,47 @@ def test_gap_controlled_denoise(sc, ctx, tv):
     assert st == sc.SCI_NOT_CONVERGED and its == 6
 
 
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_gap_controlled_schedules_agree(sc, ctx, tv):
+    """Gap-controlled denoising: iterations between gap checks run as on-chip
+    passes (auto) or one pass each (stream); same iterates bit for bit."""
+    x = np.random.default_rng(10).uniform(size=(3, 70, 90)).astype(np.float32)
+    p0 = np.random.default_rng(11).uniform(-0.5, 0.5, size=(2, 3, 70, 90)).astype(np.float32)
+    out = {}
+    for schedule in ("stream", "auto"):
+        prm = sc.tv_params(tv=tv, lam=0.1, gap_tol=1e-4, n_inner_max=3000, gap_check_every=7, schedule=schedule)
+        dual = torch.empty((2, 3, 70, 90), device="cuda")
+        th, g, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=dev(p0), dual_out=dual, want_gap=True)
+        out[schedule] = (host(th), host(dual), its, g)
+    say(f"{tv}: gap-controlled {out['auto'][2]} iterations on both schedules")
+    assert out["stream"][2] == out["auto"][2]
+    np.testing.assert_array_equal(out["stream"][0], out["auto"][0])
+    np.testing.assert_array_equal(out["stream"][1], out["auto"][1])
+    ref = orc.tv_denoise(x, f32(0.1), out["auto"][2], tv, p_init=p0)
+    assert rel_l2(out["auto"][0], ref) <= REL_TOL
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (2, 5, 3), (3, 17, 63), (4, 130, 64), (9, 20, 70), (24, 16, 64)])
+def test_chambolle04_matches_oracle(sc, ctx, tv, B, nx, ny):
+    """Chambolle's (2004) semi-implicit step in place of the projection."""
+    r = np.random.default_rng(B * 5 + nx * 3 + ny)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    p0 = r.uniform(-0.5, 0.5, size=(2, B, nx, ny)).astype(np.float32)
+    for n, accel, warm in ((1, False, False), (6, False, False), (6, True, False), (5, False, True)):
+        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, chambolle04=True)
+        dual = torch.empty((2, B, nx, ny), device="cuda")
+        th, _, its, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=dev(p0) if warm else None, dual_out=dual)
+        ref, pref = orc.tv_denoise(x, f32(0.1), n, tv, accel=accel, chambolle04=True,
+                                   p_init=p0 if warm else None, return_dual=True)
+        e = rel_l2(host(th), ref)
+        ep = np.abs(host(dual) - pref).max()
+        say(f"chambolle04 {tv} B={B} {nx}x{ny} N={n} accel={accel} warm={warm}: rel-L2 {e:.2e}, dual {ep:.2e}")
+        assert e <= REL_TOL and ep <= 1e-4
+    with pytest.raises(RuntimeError):
+        sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv=tv, n_inner=3, chambolle04=True, dual_dtype="bf16"))
+
+
 @pytest.mark.parametrize("dt,bound", [("bf16", 2e-2), ("f16", 3e-3)])
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 def test_denoise_16bit_duals(sc, ctx, tv, dt, bound):
@@ -324,6 +365,24 @@ def test_ragged_small_solves(sc, ctx, solver):
         xr, thr = oracle_solver(solver, Y, pr.masks, 0.1, 0.05, 7, 4, tv)
         assert rel_l2(x, xr) <= REL_TOL, (B, nx, ny, tv)
         assert rel_l2(th, thr) <= REL_TOL, (B, nx, ny, tv)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("tv,cham", [("atv", False), ("itv2d", False), ("vtv", False), ("itv2d", True),
+                                     ("vtv", True)])
+def test_warm_dual_and_chambolle04_outer_match_oracle(sc, ctx, solver, tv, cham):
+    """Outer loops with the dual carried across outer iterations (and the
+    Chambolle-2004 step) against the oracle's drivers."""
+    pr = synth.make_problem(70, 90, 6, seed=17, sigma=0.01, radius=(3.0, 12.0))
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (True, False) if cham else (True,):
+        x, th = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=9, rho=0.05, tv=tv, lam=0.1, n_inner=4,
+                           warm_dual=warm, chambolle04=cham)
+        fn = orc.gap_tv if solver == "gap" else (lambda *a, **k: orc.admm_tv(a[0], a[1], a[2], f32(0.05), *a[3:], **k))
+        xr, thr = fn(Y, pr.masks, f32(0.1), 9, 4, tv=tv, warm_dual=warm, chambolle04=cham)
+        e = rel_l2(x, xr)
+        say(f"{solver} {tv} warm={warm} chambolle04={cham}: rel-L2 {e:.2e}")
+        assert e <= REL_TOL and rel_l2(th, thr) <= REL_TOL
 
 
 @pytest.mark.parametrize("solver", ["gap", "admm"])
