@@ -11,6 +11,7 @@ duals ``[2][B][nx][ny]``.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -59,6 +60,9 @@ def _load():
         "orc_dual_gap": (d, [i, i, i, i, d, P, P, P]),
         "orc_gap_tv": (i, [i, i, i, i, d, i, i, i, i, i, P, P, P, P, P]),
         "orc_admm_tv": (i, [i, i, i, i, d, d, i, i, i, i, i, P, P, P, P, P]),
+        "orc_lipschitz": (d, [i, i, i, P]),
+        "orc_fista_tv": (i, [i, i, i, i, d, i, i, i, P, P, P, P, P]),
+        "orc_twist_tv": (i, [i, i, i, i, d, d, d, i, i, i, P, P, P, P, P]),
         "orc_psnr": (d, [ctypes.c_long, P, P, d]),
         "orc_residual_sq": (d, [i, i, i, P, P, P]),
     }
@@ -203,6 +207,54 @@ def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None, warm_dual=F
     xi = None if x_init is None else _d(x_init)
     _load().orc_admm_tv(_kind(tv), B, nx, ny, float(lam), float(rho), int(T), int(N), int(bool(accel)),
                         int(bool(warm_dual)), int(bool(chambolle04)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
+    return x, th
+
+
+def lipschitz(C):
+    """L(f) = max_ij sum_k C_kij^2 (largest eigenvalue of Phi^T Phi)."""
+    C = _d(C)
+    B, nx, ny = _dims(C)
+    return _load().orc_lipschitz(B, nx, ny, _p(C))
+
+
+def twist_default_ab(xi1=0.1, xim=1.0):
+    """TwIST's alpha, beta from the spectrum bounds [xi1, xim] of the scaled
+    Phi^T Phi: rho = (1 - sqrt(xi1/xim)) / (1 + sqrt(xi1/xim)),
+    alpha = 1 + rho^2, beta = 2 alpha / (xi1 + xim). Phi^T Phi is singular in
+    SCI (rank nx*ny of B*nx*ny), so xi1 is a chosen bound, 0.1 by default."""
+    k = math.sqrt(xi1 / xim)
+    rho = (1.0 - k) / (1.0 + k)
+    alpha = 1.0 + rho * rho
+    return alpha, 2.0 * alpha / (xi1 + xim)
+
+
+def fista_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None):
+    """FISTA with the TV prox (Sec. 2.2). Returns (x^(T), theta^(T+1))."""
+    Y, C = _d(Y), _d(C)
+    B, nx, ny = _dims(C)
+    x = np.empty((B, nx, ny))
+    th = np.empty((B, nx, ny))
+    xi = None if x_init is None else _d(x_init)
+    rc = _load().orc_fista_tv(_kind(tv), B, nx, ny, float(lam), int(T), int(N), int(bool(accel)), _p(Y), _p(C),
+                              _p(xi), _p(x), _p(th))
+    if rc != 0:
+        raise ValueError("FISTA needs a nonzero mask (L(f) > 0)")
+    return x, th
+
+
+def twist_tv(Y, C, lam, T, N, tv="atv", alpha=None, beta=None, accel=True, x_init=None):
+    """TwIST with the TV denoiser (Sec. 2.2). Returns (x^(T), theta^(T-1))."""
+    if alpha is None or beta is None:
+        alpha, beta = twist_default_ab()
+    Y, C = _d(Y), _d(C)
+    B, nx, ny = _dims(C)
+    x = np.empty((B, nx, ny))
+    th = np.empty((B, nx, ny))
+    xi = None if x_init is None else _d(x_init)
+    rc = _load().orc_twist_tv(_kind(tv), B, nx, ny, float(lam), float(alpha), float(beta), int(T), int(N),
+                              int(bool(accel)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
+    if rc != 0:
+        raise ValueError("TwIST needs a nonzero mask (L(f) > 0)")
     return x, th
 
 

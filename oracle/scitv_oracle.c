@@ -447,6 +447,121 @@ int orc_admm_tv(int kind, int B, int nx, int ny, double lambda, double rho, int 
     return 0;
 }
 
+/* L(f) for f(x) = 1/2 ||y - Phi x||^2: the largest eigenvalue of Phi^T Phi,
+ * which equals that of Phi Phi^T = diag(S), S_ij = sum_k C_kij^2 (Sec. 2.2,
+ * FISTA; the nonzero spectra of Phi^T Phi and Phi Phi^T coincide). */
+double orc_lipschitz(int B, int nx, int ny, const double *C)
+{
+    double L = 0.0;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < B; ++k) {
+                const double c = C[IDX(k, i, j)];
+                s += c * c;
+            }
+            if (s > L) L = s;
+        }
+    return L;
+}
+
+/* z = theta + (1/L) Phi^T (y - Phi theta): the gradient step on f. */
+static void grad_step(int B, int nx, int ny, const double *C, const double *Y, double invL, const double *th,
+                      double *r, double *cr, double *z)
+{
+    size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
+    orc_forward(B, nx, ny, C, th, r);
+    for (size_t c = 0; c < n; ++c) r[c] = (Y[c] - r[c]) * invL;
+    orc_adjoint(B, nx, ny, C, r, cr);
+    for (size_t c = 0; c < V; ++c) z[c] = th[c] + cr[c];
+}
+
+/* FISTA (Sec. 2.2) for 1/2 ||y - Phi x||^2 + lambda TV(x):
+ *   theta^(1) = x^(0) = Phi^T y (or x_init), tau^(1) = 1
+ *   z^(t)       = theta^(t) + (1/L) Phi^T (y - Phi theta^(t))
+ *   x^(t)       = TVdenoise(z^(t)) with weight lambda / L (the proximal step
+ *                 of lambda TV at step 1/L)
+ *   tau^(t+1)   = (1 + sqrt(1 + 4 tau^(t)^2)) / 2
+ *   theta^(t+1) = x^(t) + (tau^(t) - 1) / tau^(t+1) (x^(t) - x^(t-1))
+ * (the printed extrapolation uses x^(t+1) - x^(t), which is not yet known at
+ * that point; Beck and Teboulle's method extrapolates along x^(t) - x^(t-1)).
+ * Returns x^(T) and theta^(T+1); -1 if every mask entry is zero (L = 0). */
+int orc_fista_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel, const double *Y,
+                 const double *C, const double *x_init, double *x_out, double *theta_out)
+{
+    size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
+    const double L = orc_lipschitz(B, nx, ny, C);
+    if (!(L > 0.0)) return -1;
+    double *r = (double *)malloc(n * sizeof(double));
+    double *cr = (double *)malloc(V * sizeof(double));
+    double *th = (double *)malloc(V * sizeof(double));
+    double *z = (double *)malloc(V * sizeof(double));
+    double *x = (double *)malloc(V * sizeof(double));
+    double *xp = (double *)malloc(V * sizeof(double));
+    if (x_init) memcpy(th, x_init, V * sizeof(double));
+    else orc_adjoint(B, nx, ny, C, Y, th);
+    memcpy(x, th, V * sizeof(double)); /* x^(0) */
+    double tau = 1.0;
+    for (int t = 1; t <= T; ++t) {
+        memcpy(xp, x, V * sizeof(double));
+        grad_step(B, nx, ny, C, Y, 1.0 / L, th, r, cr, z);
+        orc_tv_denoise(kind, B, nx, ny, lambda / L, N, accel, 0, 0, z, NULL, x, NULL, NULL);
+        const double tau1 = (1.0 + sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+        const double c = (tau - 1.0) / tau1;
+        for (size_t k = 0; k < V; ++k) th[k] = x[k] + c * (x[k] - xp[k]);
+        tau = tau1;
+    }
+    memcpy(x_out, x, V * sizeof(double));
+    if (theta_out) memcpy(theta_out, th, V * sizeof(double));
+    free(r); free(cr); free(th); free(z); free(x); free(xp);
+    return 0;
+}
+
+/* TwIST (Sec. 2.2) for the same objective:
+ *   x^(0) = Phi^T y (or x_init)
+ *   z^(t)     = x^(t) + (1/L) Phi^T (y - Phi x^(t))   (the printed step 1 assumes
+ *               Phi scaled to ||Phi|| <= 1; 1/L is that scaling)
+ *   theta^(t) = TVdenoise(z^(t)) with weight lambda / L
+ *   x^(1)     = theta^(0)  (one plain iterative-shrinkage step starts the
+ *               two-step recursion, which needs x^(t-1))
+ *   x^(t+1)   = (1 - alpha) x^(t-1) + (alpha - beta) x^(t) + beta theta^(t),  t >= 1
+ * Returns x^(T) and theta^(T-1) (the last denoiser output; x^(0) when T = 0);
+ * -1 if L = 0. */
+int orc_twist_tv(int kind, int B, int nx, int ny, double lambda, double alpha, double beta, int T, int N, int accel,
+                 const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
+{
+    size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
+    const double L = orc_lipschitz(B, nx, ny, C);
+    if (!(L > 0.0)) return -1;
+    double *r = (double *)malloc(n * sizeof(double));
+    double *cr = (double *)malloc(V * sizeof(double));
+    double *th = (double *)malloc(V * sizeof(double));
+    double *z = (double *)malloc(V * sizeof(double));
+    double *x = (double *)malloc(V * sizeof(double));
+    double *xp = (double *)malloc(V * sizeof(double));
+    if (x_init) memcpy(x, x_init, V * sizeof(double));
+    else orc_adjoint(B, nx, ny, C, Y, x);
+    memcpy(th, x, V * sizeof(double));
+    for (int t = 0; t < T; ++t) {
+        grad_step(B, nx, ny, C, Y, 1.0 / L, x, r, cr, z);
+        orc_tv_denoise(kind, B, nx, ny, lambda / L, N, accel, 0, 0, z, NULL, th, NULL, NULL);
+        if (t == 0) {
+            memcpy(xp, x, V * sizeof(double));
+            memcpy(x, th, V * sizeof(double));
+        } else {
+            for (size_t k = 0; k < V; ++k) {
+                const double xn = (1.0 - alpha) * xp[k] + (alpha - beta) * x[k] + beta * th[k];
+                xp[k] = x[k];
+                x[k] = xn;
+            }
+        }
+    }
+    memcpy(x_out, x, V * sizeof(double));
+    if (theta_out) memcpy(theta_out, th, V * sizeof(double));
+    free(r); free(cr); free(th); free(z); free(x); free(xp);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Metrics.                                                                 */
 /* ------------------------------------------------------------------------ */

@@ -568,3 +568,79 @@ def test_warm_dual_admm_and_chambolle04_outer():
     xs, _ = orc.gap_tv(Y, C, 0.1, 2, 3000, tv="itv2d")
     xh, _ = orc.gap_tv(Y, C, 0.1, 2, 20000, tv="itv2d", accel=False, chambolle04=True)
     assert np.abs(xs - xh).max() < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# FISTA and TwIST (Sec. 2.2) for 1/2 ||y - Phi x||^2 + lambda TV(x).
+# ---------------------------------------------------------------------------
+
+def objective(Y, C, x, lam, tv):
+    return 0.5 * orc.residual_sq(C, x, Y) + lam * orc.tv_value(x, tv)
+
+
+def test_lipschitz_is_largest_eigenvalue():
+    C, _, _ = small_problem(50, B=3, nx=4, ny=5)
+    Phi = dense_phi(C)
+    assert abs(np.linalg.eigvalsh(Phi.T @ Phi).max() - orc.lipschitz(C)) < 1e-12
+    C = rng(51).uniform(size=(2, 3, 4))
+    Phi = dense_phi(C)
+    assert abs(np.linalg.eigvalsh(Phi.T @ Phi).max() - orc.lipschitz(C)) < 1e-12
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+def test_scaled_identity_sensing_reduces_to_one_prox(tv):
+    """Phi = c I (one frame, every mask entry c): the objective is
+    c^2/2 ||x - y/c||^2 + lambda TV(x), whose minimiser is prox_{lambda/c^2 TV}(y/c).
+    The gradient step lands on y/c from any point, so FISTA and TwIST with
+    alpha = 1 return that prox at every T >= 1 (checks the 1/L step and the
+    lambda/L denoiser weight)."""
+    c, lam = 2.0, 0.3
+    Y = rng(52).uniform(size=(9, 11))
+    C = np.full((1, 9, 11), c)
+    ref = orc.tv_denoise(Y[None] / c, lam / c ** 2, 400, tv)
+    for T in (1, 2, 5):
+        xf, _ = orc.fista_tv(Y, C, lam, T, 400, tv=tv)
+        np.testing.assert_allclose(xf, ref, rtol=0, atol=1e-13)
+        xt, _ = orc.twist_tv(Y, C, lam, T, 400, tv=tv, alpha=1.0, beta=0.7)
+        np.testing.assert_allclose(xt, ref, rtol=0, atol=1e-13)
+
+
+def test_fista_rate_and_fixed_point():
+    """With accurate proximal steps: the Beck-Teboulle bound
+    F(x_k) - F* <= 2 L ||x_0 - x*||^2 / (k+1)^2, and the limit is a fixed point
+    of the proximal-gradient map."""
+    C, X, Y = small_problem(53, B=2, nx=6, ny=6)
+    lam, tv, N = 0.05, "itv2d", 1500
+    L = orc.lipschitz(C)
+    xs, _ = orc.fista_tv(Y, C, lam, 400, N, tv=tv)
+    Fs = objective(Y, C, xs, lam, tv)
+    x0 = orc.adjoint(C, Y)
+    R2 = ((x0 - xs) ** 2).sum()
+    for k in (1, 2, 4, 8, 16, 32):
+        xk, _ = orc.fista_tv(Y, C, lam, k, N, tv=tv)
+        assert objective(Y, C, xk, lam, tv) - Fs <= 2 * L * R2 / (k + 1) ** 2 + 1e-9
+    z = xs + orc.adjoint(C, (Y - orc.forward(C, xs)) / L)
+    assert np.abs(orc.tv_denoise(z, lam / L, N, tv) - xs).max() < 1e-5
+
+
+def test_twist_and_fista_reach_the_same_objective():
+    """Two different iterations on the same convex objective: their limits
+    have the same value (the minimiser need not be unique when Phi has a null
+    space), and that value is below the starting point's."""
+    C, X, Y = small_problem(54, B=2, nx=6, ny=7)
+    lam, tv = 0.05, "atv"
+    xf, _ = orc.fista_tv(Y, C, lam, 600, 800, tv=tv)
+    xt, _ = orc.twist_tv(Y, C, lam, 600, 800, tv=tv)
+    Ff, Ft = objective(Y, C, xf, lam, tv), objective(Y, C, xt, lam, tv)
+    assert abs(Ff - Ft) <= 1e-6 * Ff
+    assert Ff < objective(Y, C, orc.adjoint(C, Y), lam, tv)
+
+
+def test_twist_default_parameters():
+    a, b = orc.twist_default_ab(1e-4, 1.0)
+    rho = (1 - 0.01) / (1 + 0.01)
+    assert abs(a - (1 + rho ** 2)) < 1e-15 and abs(b - 2 * a / 1.0001) < 1e-15
+    assert 0 < a < 2 and 0 < b < 2 * a  # the convergence range of TwIST for spectrum bound 1
+    C = np.zeros((2, 3, 3))
+    with pytest.raises(ValueError):
+        orc.fista_tv(np.zeros((3, 3)), C, 0.1, 2, 2)
