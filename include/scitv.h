@@ -114,6 +114,8 @@ typedef struct {
     int32_t warm_dual;       /* 1 = carry the denoiser's dual from one outer iteration to
                                 the next (momentum restarted), 0 = cold start every call */
     int32_t use_graph;       /* 1 = capture the outer loop once in a HIP graph and replay it */
+    float twist_alpha;       /* TwIST two-step weights; both 0 = the values the spectrum-bound */
+    float twist_beta;        /* formula gives for [0.1, 1] (alpha ~1.27, beta ~2.31) */
 } sci_solver_params;
 
 /* ---- context ----------------------------------------------------------- */
@@ -170,6 +172,28 @@ int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float
  * Arguments as sci_gap_tv; rho from p->rho (rho = 0 reduces to GAP). */
 int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
                 float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
+
+/* FISTA (Sec. 2.2) on 1/2 ||y - Phi x||^2 + lambda TV(x): with L = L(f) =
+ * max_ij sum_k C_kij^2 (the largest eigenvalue of Phi^T Phi),
+ *   theta^(1) = x^(0) = Phi^T y (or X_init), tau^(1) = 1,
+ *   z = theta^(t) + (1/L) Phi^T (y - Phi theta^(t)),
+ *   x^(t) = TVdenoise(z) with weight lambda / L (p->tv otherwise),
+ *   theta^(t+1) = x^(t) + (tau^(t) - 1) / tau^(t+1) (x^(t) - x^(t-1)).
+ * X_out = x^(T); Theta_out (nullable) = theta^(T+1). Runs eagerly (L is read
+ * back, which synchronises `stream` once): p->use_graph and p->warm_dual
+ * must be 0. SCI_ERR_INVALID_ARG when every mask entry is 0. */
+int sci_fista_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
+                 float *Theta_out, const float *X_init, hipStream_t stream);
+
+/* TwIST (Sec. 2.2) on the same objective:
+ *   x^(0) = Phi^T y (or X_init); z = x^(t) + (1/L) Phi^T (y - Phi x^(t));
+ *   theta^(t) = TVdenoise(z) with weight lambda / L;
+ *   x^(1) = theta^(0); x^(t+1) = (1 - alpha) x^(t-1) + (alpha - beta) x^(t) + beta theta^(t).
+ * alpha, beta from p->twist_alpha / twist_beta (0 < alpha < 2, beta > 0).
+ * X_out = x^(T); Theta_out (nullable) = theta^(T-1) (x^(0) when T = 0).
+ * Same restrictions as sci_fista_tv. */
+int sci_twist_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
+                 float *Theta_out, const float *X_init, hipStream_t stream);
 
 /* ---- batched solve --------------------------------------------------------- */
 

@@ -134,6 +134,49 @@ __global__ __launch_bounds__(kRedThreads) void k_final(int nch, const double *__
     }
 }
 
+// Largest S_ij = sum_k C_kij^2 (accumulated as in the weights kernel): one
+// maximum per workgroup, then one workgroup takes the maximum of those.
+__device__ inline float block_max(float v, float *lds)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) lds[threadIdx.x] = fmaxf(lds[threadIdx.x], lds[threadIdx.x + w]);
+        __syncthreads();
+    }
+    float r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_max_s_part(int nx, int ny, int B, const float *__restrict__ C,
+                                                            float *__restrict__ part)
+{
+    __shared__ float lds[kRedThreads];
+    const int64_t npix = (int64_t)nx * ny;
+    float m = 0.0f;
+    for (int64_t c = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; c < npix;
+         c += (int64_t)kRedBlocks * kRedThreads) {
+        float s = 0.0f;
+        for (int k = 0; k < B; ++k) {
+            const float v = C[k * npix + c];
+            s = fmaf(v, v, s);
+        }
+        m = fmaxf(m, s);
+    }
+    const float r = block_max(m, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_max_final(const float *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ float lds[kRedThreads];
+    float m = 0.0f;
+    for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads) m = fmaxf(m, part[b]);
+    const float r = block_max(m, lds);
+    if (threadIdx.x == 0) out[0] = (double)r;
+}
+
 template <int TV>
 void gap_tv_dt(int dual_dtype, int nx, int ny, int B, double lam, const float *x, const void *p, double *part,
                hipStream_t s)
@@ -169,6 +212,12 @@ void launch_residual_sq(int nx, int ny, int B, const float *C, const float *X, c
 {
     hipLaunchKernelGGL(k_resid_part, dim3(kRedBlocks), dim3(kRedThreads), 0, s, nx, ny, B, C, X, Y, partials);
     hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, 1, (const double *)partials, out_dev);
+}
+
+void launch_max_s(int nx, int ny, int B, const float *C, double *partials, double *out_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_max_s_part, dim3(kRedBlocks), dim3(kRedThreads), 0, s, nx, ny, B, C, (float *)partials);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kRedThreads), 0, s, (const float *)partials, out_dev);
 }
 
 int launch_gap_terms(int tv, int dual_dtype, int nx, int ny, int B, float lam, const float *x, const void *p,

@@ -159,7 +159,52 @@ __global__ __launch_bounds__(kBlock) void k_zero1(uint32_t n, uint8_t *__restric
     if (i < n) dst[i] = 0;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill(uint32_t n, float v, float *__restrict__ dst)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+// FISTA extrapolation theta = x + c (x - x_prev).
+__global__ __launch_bounds__(kBlock) void k_extrapolate(uint32_t n, float c, const float *__restrict__ x,
+                                                        const float *__restrict__ xp, float *__restrict__ th)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float xv = x[i];
+    th[i] = fmaf(c, xv - xp[i], xv);
+}
+
+// TwIST two-step update out = a0 x_prev + a1 x + a2 theta.
+__global__ __launch_bounds__(kBlock) void k_two_step(uint32_t n, float a0, float a1, float a2,
+                                                     const float *__restrict__ xp, const float *__restrict__ x,
+                                                     const float *__restrict__ th, float *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    out[i] = fmaf(a2, th[i], fmaf(a1, x[i], a0 * xp[i]));
+}
+
 } // namespace
+
+void launch_fill(float *dst, float v, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t)n, v, dst);
+}
+
+void launch_extrapolate(size_t n, float c, const float *x, const float *xp, float *th, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_extrapolate, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t)n, c, x, xp, th);
+}
+
+void launch_two_step(size_t n, float a0, float a1, float a2, const float *xp, const float *x, const float *th,
+                     float *out, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_two_step, dim3(grid_for(n)), dim3(kBlock), 0, s, (uint32_t)n, a0, a1, a2, xp, x, th, out);
+}
 
 void launch_forward(int nx, int ny, int B, const float *C, const float *X, float *Y, hipStream_t s)
 {

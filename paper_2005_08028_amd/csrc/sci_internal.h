@@ -105,6 +105,12 @@ void launch_gap_project(int nx, int ny, int B, const float *theta, const float *
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
                          const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s);
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+void launch_fill(float *dst, float v, size_t n, hipStream_t s);
+// theta = x + c (x - xp)
+void launch_extrapolate(size_t n, float c, const float *x, const float *xp, float *th, hipStream_t s);
+// out = a0 xp + a1 x + a2 th
+void launch_two_step(size_t n, float a0, float a1, float a2, const float *xp, const float *x, const float *th,
+                     float *out, hipStream_t s);
 void launch_zero(void *dst, size_t bytes, hipStream_t s);
 
 // ---- launchers (k_fgp.hip) ----------------------------------------------------
@@ -149,6 +155,8 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
 // ---- launchers (k_reduce.hip) -------------------------------------------------
 // Deterministic two-stage FP64 reductions into out_dev (device doubles).
 int reduce_partial_blocks();
+// out_dev[0] = max_ij sum_k C_kij^2 (partials: reduce_partial_blocks() entries)
+void launch_max_s(int nx, int ny, int B, const float *C, double *partials, double *out_dev, hipStream_t s);
 void launch_sqdiff(int64_t n, const float *a, const float *b, double *partials, double *out_dev, hipStream_t s);
 void launch_residual_sq(int nx, int ny, int B, const float *C, const float *X, const float *Y, double *partials,
                         double *out_dev, hipStream_t s);

@@ -367,8 +367,9 @@ std::string graph_key(const OuterArgs &a)
     return buf;
 }
 
-int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const float *Y, const float *C,
-              float *X_out, float *Theta_out, const float *X_init, bool admm, hipStream_t s)
+// Argument checks shared by the outer-loop entry points.
+int check_outer_args(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const float *Y, const float *C,
+                     float *X_out, float *Theta_out, const float *X_init)
 {
     if (!ctx) return SCI_ERR_INVALID_ARG;
     int st = check_dims(ctx, d);
@@ -386,8 +387,15 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
         if (overlaps(X_out, vb, ins[k], inb[k]) || overlaps(Theta_out, vb, ins[k], inb[k]))
             return fail(ctx, SCI_ERR_ALIAS, "outputs must not overlap Y, C or X_init");
     if (overlaps(X_out, vb, Theta_out, vb)) return fail(ctx, SCI_ERR_ALIAS, "X_out and Theta_out overlap");
-    st = use_device(ctx);
+    return use_device(ctx);
+}
+
+int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const float *Y, const float *C,
+              float *X_out, float *Theta_out, const float *X_init, bool admm, hipStream_t s)
+{
+    int st = check_outer_args(ctx, d, p, Y, C, X_out, Theta_out, X_init);
     if (st != SCI_OK) return st;
+    const size_t vb = vol_elems(d) * sizeof(float), ib = img_elems(d) * sizeof(float);
 
     // scratch first: a graph must never see a buffer that later grows
     if ((st = ensure_ws(ctx, WS_SINV, ib, s)) != SCI_OK) return st;
@@ -432,6 +440,100 @@ int read_scalars(sci_ctx *ctx, const double *dev, int n, hipStream_t s)
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamSynchronize");
     return SCI_OK;
+}
+
+// L(f) = max_ij S_ij, the largest eigenvalue of Phi^T Phi (read back; synchronises).
+int lipschitz(sci_ctx *ctx, const sci_dims &d, const float *C, double *L, hipStream_t s)
+{
+    const int nb = reduce_partial_blocks();
+    int st = ensure_ws(ctx, WS_PARTIAL, (3 * (size_t)nb + 8) * sizeof(double), s);
+    if (st != SCI_OK) return st;
+    double *part = (double *)ctx->ws[WS_PARTIAL].ptr;
+    double *outd = part + 3 * nb;
+    launch_max_s(d.nx, d.ny, d.B, C, part, outd, s);
+    if ((st = check_launch(ctx, "k_max_s")) != SCI_OK) return st;
+    if ((st = read_scalars(ctx, outd, 1, s)) != SCI_OK) return st;
+    *L = ctx->host_scalars[0];
+    return SCI_OK;
+}
+
+// TwIST's alpha, beta for the spectrum bounds [xi1, 1] of Phi^T Phi / L:
+// rho = (1 - sqrt(xi1)) / (1 + sqrt(xi1)), alpha = 1 + rho^2, beta = 2 alpha / (xi1 + 1).
+constexpr double kTwistXi1 = 0.1;
+void twist_defaults(double *alpha, double *beta)
+{
+    const double k = std::sqrt(kTwistXi1);
+    const double rho = (1.0 - k) / (1.0 + k);
+    *alpha = 1.0 + rho * rho;
+    *beta = 2.0 * *alpha / (kTwistXi1 + 1.0);
+}
+
+// FISTA and TwIST (Sec. 2.2) on 1/2 ||y - Phi x||^2 + lambda TV(x): gradient
+// step z = v + (1/L) Phi^T (y - Phi v) (the GAP projection kernel with the
+// constant weight 1/L), denoiser with weight lambda / L, then the FISTA
+// extrapolation or the TwIST two-step update. Eager only: L is read back.
+int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const float *Y, const float *C,
+                  float *X_out, float *Theta_out, const float *X_init, bool twist, hipStream_t s)
+{
+    int st = check_outer_args(ctx, d, p, Y, C, X_out, Theta_out, X_init);
+    if (st != SCI_OK) return st;
+    if (p->use_graph) return fail(ctx, SCI_ERR_UNSUPPORTED, "FISTA / TwIST run eagerly (L(f) is read back)");
+    if (p->warm_dual) return fail(ctx, SCI_ERR_UNSUPPORTED, "FISTA / TwIST start every denoiser call cold");
+    double alpha = p->twist_alpha, beta = p->twist_beta;
+    if (twist) {
+        if (alpha == 0.0 && beta == 0.0) twist_defaults(&alpha, &beta);
+        if (!(alpha > 0.0 && alpha < 2.0) || !(beta > 0.0) || !std::isfinite(beta))
+            return fail(ctx, SCI_ERR_INVALID_ARG, "TwIST needs 0 < alpha < 2 and beta > 0 (or both 0 for defaults)");
+    }
+    const size_t V = vol_elems(d), vb = V * sizeof(float), ib = img_elems(d) * sizeof(float);
+    if ((st = ensure_ws(ctx, WS_SINV, ib, s)) != SCI_OK) return st;
+    if (!Theta_out && (st = ensure_ws(ctx, WS_THETA, vb, s)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_XTMP, vb, s)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
+    double L = 0.0;
+    if ((st = lipschitz(ctx, d, C, &L, s)) != SCI_OK) return st;
+    if (!(L > 0.0)) return fail(ctx, SCI_ERR_INVALID_ARG, "every mask entry is zero (L(f) = 0)");
+    float *W = (float *)ctx->ws[WS_SINV].ptr;
+    float *theta = Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr;
+    float *z = (float *)ctx->ws[WS_SVOL].ptr;
+    float *xa = X_out, *xb = (float *)ctx->ws[WS_XTMP].ptr;
+    sci_tv_params q = p->tv;
+    q.lambda = (float)((double)p->tv.lambda / L);
+    {
+        ProfScope prof(ctx, PF_SETUP, s);
+        launch_fill(W, (float)(1.0 / L), img_elems(d), s);
+        if (X_init) launch_copy(X_init, xa, vb, s); // x^(0)
+        else launch_adjoint(d.nx, d.ny, d.B, C, Y, xa, s);
+        launch_copy(xa, theta, vb, s);
+    }
+    if ((st = check_launch(ctx, "setup")) != SCI_OK) return st;
+    FgpRun r;
+    bind_duals(ctx, r);
+    double tau = 1.0;
+    for (int t = 0; t < p->outer_iters; ++t) {
+        {
+            ProfScope prof(ctx, PF_PROJECT, s);
+            // FISTA steps from the extrapolated point theta, TwIST from x^(t)
+            launch_gap_project(d.nx, d.ny, d.B, twist ? xa : theta, C, Y, W, z, s);
+        }
+        if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
+        if (!twist) {
+            // x^(t) into the other buffer; x^(t-1) stays in xa
+            if ((st = denoise_fixed(ctx, d, q, z, xb, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
+            const double tau1 = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
+            launch_extrapolate(V, (float)((tau - 1.0) / tau1), xb, xa, theta, s);
+            tau = tau1;
+        } else {
+            if ((st = denoise_fixed(ctx, d, q, z, theta, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
+            if (t == 0) launch_copy(theta, xb, vb, s); // x^(1) = theta^(0)
+            else launch_two_step(V, (float)(1.0 - alpha), (float)(alpha - beta), (float)beta, xb, xa, theta, xb, s);
+        }
+        if ((st = check_launch(ctx, "update")) != SCI_OK) return st;
+        std::swap(xa, xb); // xa = newest iterate, xb = the one before
+    }
+    if (xa != X_out) launch_copy(xa, X_out, vb, s);
+    return check_launch(ctx, "copy");
 }
 
 
@@ -602,6 +704,18 @@ int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const floa
                 float *Theta_out, const float *X_init, hipStream_t stream)
 {
     return run_outer(ctx, d, p, Y, C, X_out, Theta_out, X_init, true, stream);
+}
+
+int sci_fista_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
+                 float *Theta_out, const float *X_init, hipStream_t stream)
+{
+    return run_prox_grad(ctx, d, p, Y, C, X_out, Theta_out, X_init, false, stream);
+}
+
+int sci_twist_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
+                 float *Theta_out, const float *X_init, hipStream_t stream)
+{
+    return run_prox_grad(ctx, d, p, Y, C, X_out, Theta_out, X_init, true, stream);
 }
 
 int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,

@@ -50,7 +50,8 @@ class sci_tv_params(ctypes.Structure):
 
 class sci_solver_params(ctypes.Structure):
     _fields_ = [("tv", sci_tv_params), ("outer_iters", ctypes.c_int32), ("rho", ctypes.c_float),
-                ("warm_dual", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("warm_dual", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("twist_alpha", ctypes.c_float),
+                ("twist_beta", ctypes.c_float)]
 
 
 class sci_problem(ctypes.Structure):
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_tv_denoise": (I, [V, D, P(sci_tv_params), V, V, V, V, P(ctypes.c_double), P(ctypes.c_int32), V]),
         "sci_gap_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
         "sci_admm_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
+        "sci_fista_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
+        "sci_twist_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
         "sci_psnr": (I, [V, ctypes.c_int64, V, V, ctypes.c_double, P(ctypes.c_double), V]),
         "sci_residual_sq": (I, [V, D, V, V, V, P(ctypes.c_double), V]),
         "sci_dual_gap": (I, [V, D, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, V, V, P(ctypes.c_double),
@@ -156,9 +159,10 @@ def tv_params(tv="atv", lam=0.1, n_inner=5, accel=True, dual_dtype="f32", schedu
                          int(bool(chambolle04)))
 
 
-def solver_params(outer_iters=50, rho=0.0, warm_dual=False, use_graph=False, **tv) -> sci_solver_params:
+def solver_params(outer_iters=50, rho=0.0, warm_dual=False, use_graph=False, twist_alpha=0.0, twist_beta=0.0,
+                  **tv) -> sci_solver_params:
     return sci_solver_params(tv_params(**tv), int(outer_iters), float(rho), int(bool(warm_dual)),
-                             int(bool(use_graph)))
+                             int(bool(use_graph)), float(twist_alpha), float(twist_beta))
 
 
 # ---- entry points (same names as the C ABI) ---------------------------------------
@@ -227,6 +231,16 @@ def sci_gap_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None,
 def sci_admm_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None, X_init=None, stream=None):
     """ADMM-TV; returns (X_out, Theta_out)."""
     return _outer(lib.sci_admm_tv, ctx, Y, C, params, X_out, Theta_out, X_init, stream)
+
+
+def sci_fista_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None, X_init=None, stream=None):
+    """FISTA-TV; returns (X_out, Theta_out)."""
+    return _outer(lib.sci_fista_tv, ctx, Y, C, params, X_out, Theta_out, X_init, stream)
+
+
+def sci_twist_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None, X_init=None, stream=None):
+    """TwIST-TV; returns (X_out, Theta_out)."""
+    return _outer(lib.sci_twist_tv, ctx, Y, C, params, X_out, Theta_out, X_init, stream)
 
 
 def _problems(items):
