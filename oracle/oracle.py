@@ -58,8 +58,9 @@ def _load():
         "orc_fgp_beta": (None, [i, P]),
         "orc_tv_denoise": (i, [i, i, i, i, d, i, i, i, i, P, P, P, P, P]),
         "orc_dual_gap": (d, [i, i, i, i, d, P, P, P]),
-        "orc_gap_tv": (i, [i, i, i, i, d, i, i, i, i, i, P, P, P, P, P]),
-        "orc_admm_tv": (i, [i, i, i, i, d, d, i, i, i, i, i, P, P, P, P, P]),
+        "orc_gap_tv": (i, [i, i, i, i, d, i, i, i, i, i, d, P, P, P, P, P]),
+        "orc_admm_tv": (i, [i, i, i, i, d, d, i, i, i, i, i, d, P, P, P, P, P]),
+        "orc_clip_denoise": (i, [i, i, i, d, d, i, P, P, P, P, P]),
         "orc_lipschitz": (d, [i, i, i, P]),
         "orc_fista_tv": (i, [i, i, i, i, d, i, i, i, P, P, P, P, P]),
         "orc_twist_tv": (i, [i, i, i, i, d, d, d, i, i, i, P, P, P, P, P]),
@@ -185,20 +186,31 @@ def dual_gap(x, p, lam, tv):
     return g, prim.value
 
 
-def gap_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None, warm_dual=False, chambolle04=False):
+def _variant(chambolle04, clip, tv):
+    if clip:
+        if _kind(tv) != 0:
+            raise ValueError("ATV-Clip is defined for anisotropic TV only")
+        return 2
+    return 1 if chambolle04 else 0
+
+
+def gap_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None, warm_dual=False, chambolle04=False, clip=False,
+           clip_alpha=4.0):
     """GAP-TV (Eq. (21)-(22), Algorithm 1). Returns (x^(T), theta^(T)).
-    warm_dual: each denoiser call starts from the previous call's final dual."""
+    warm_dual: each denoiser call starts from the previous call's final dual;
+    clip: the ATV-Clip denoiser (step 1/clip_alpha)."""
     Y, C = _d(Y), _d(C)
     B, nx, ny = _dims(C)
     x = np.empty((B, nx, ny))
     th = np.empty((B, nx, ny))
     xi = None if x_init is None else _d(x_init)
     _load().orc_gap_tv(_kind(tv), B, nx, ny, float(lam), int(T), int(N), int(bool(accel)), int(bool(warm_dual)),
-                       int(bool(chambolle04)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
+                       _variant(chambolle04, clip, tv), float(clip_alpha), _p(Y), _p(C), _p(xi), _p(x), _p(th))
     return x, th
 
 
-def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None, warm_dual=False, chambolle04=False):
+def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None, warm_dual=False, chambolle04=False,
+            clip=False, clip_alpha=4.0):
     """ADMM-TV (Eq. (24)-(26)). Returns (x^(T), theta^(T))."""
     Y, C = _d(Y), _d(C)
     B, nx, ny = _dims(C)
@@ -206,8 +218,24 @@ def admm_tv(Y, C, lam, rho, T, N, tv="atv", accel=True, x_init=None, warm_dual=F
     th = np.empty((B, nx, ny))
     xi = None if x_init is None else _d(x_init)
     _load().orc_admm_tv(_kind(tv), B, nx, ny, float(lam), float(rho), int(T), int(N), int(bool(accel)),
-                        int(bool(warm_dual)), int(bool(chambolle04)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
+                        int(bool(warm_dual)), _variant(chambolle04, clip, tv), float(clip_alpha), _p(Y), _p(C),
+                        _p(xi), _p(x), _p(th))
     return x, th
+
+
+def clip_denoise(x, lam, n_iter, alpha=4.0, w_init=None, return_dual=False):
+    """ATV-Clip (Sec. 2.3, Algorithm 1): per-direction iterative clipping at
+    threshold 2 lam, step 1/alpha."""
+    x = _d(x)
+    B, nx, ny = _dims(x)
+    th = np.empty_like(x)
+    wi = None if w_init is None else _d(w_init)
+    wh, wv = np.empty_like(x), np.empty_like(x)
+    _load().orc_clip_denoise(B, nx, ny, float(lam), float(alpha), int(n_iter), _p(x), _p(wi), _p(th), _p(wh),
+                             _p(wv))
+    if return_dual:
+        return th, np.stack([wh, wv])
+    return th
 
 
 def lipschitz(C):

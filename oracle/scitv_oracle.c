@@ -339,6 +339,75 @@ int orc_tv_denoise(int kind, int B, int nx, int ny, double lambda, int n_iter, i
     return 0;
 }
 
+/* ATV-Clip (Sec. 2.3; Algorithm 1, Clip box): iterative clipping with one
+ * dual per difference direction. Threshold T = 2 lambda (as printed), step
+ * 1/alpha; for s = 0 .. n_iter-1:
+ *   theta_h = x - D_h^T w_h,   theta_v = x - D_v^T w_v,
+ *   w_h <- clip(w_h + D_h theta_h / alpha, T),   w_v <- clip(w_v + D_v theta_v / alpha, T),
+ * output theta = theta_h + theta_v - x = x - D_h^T w_h - D_v^T w_v, taken with
+ * the final duals (the convention used for every denoiser here). Each
+ * direction is projected gradient on the dual of
+ * 1/2 ||theta - x||^2 + T ||D_d theta||_1, convergent for alpha > 2 since
+ * ||D_d D_d^T|| < 4. w_init: optional [2][B][nx][ny] start. */
+int orc_clip_denoise(int B, int nx, int ny, double lambda, double alpha, int n_iter, const double *x,
+                     const double *w_init, double *theta_out, double *wh_out, double *wv_out)
+{
+    size_t V = (size_t)B * nx * ny;
+    double *wh = (double *)calloc(V, sizeof(double)), *wv = (double *)calloc(V, sizeof(double));
+    double *zero = (double *)calloc(V, sizeof(double));
+    double *th = (double *)malloc(V * sizeof(double)), *tv = (double *)malloc(V * sizeof(double));
+    double *gh = (double *)malloc(V * sizeof(double)), *gv = (double *)malloc(V * sizeof(double));
+    double *dt = (double *)malloc(V * sizeof(double));
+    if (w_init) {
+        memcpy(wh, w_init, V * sizeof(double));
+        memcpy(wv, w_init + V, V * sizeof(double));
+        zero_padding(B, nx, ny, wh, wv);
+    }
+    const double T = 2.0 * lambda;
+    for (int s = 0; s < n_iter; ++s) {
+        orc_grad_adj(B, nx, ny, wh, zero, dt); /* D_h^T w_h */
+        for (size_t c = 0; c < V; ++c) th[c] = x[c] - dt[c];
+        orc_grad_adj(B, nx, ny, zero, wv, dt); /* D_v^T w_v */
+        for (size_t c = 0; c < V; ++c) tv[c] = x[c] - dt[c];
+        orc_grad(B, nx, ny, th, gh, dt);       /* D_h theta_h (the v part is unused) */
+        orc_grad(B, nx, ny, tv, dt, gv);       /* D_v theta_v */
+        for (size_t c = 0; c < V; ++c) {
+            double a = wh[c] + gh[c] / alpha, b = wv[c] + gv[c] / alpha;
+            wh[c] = a > T ? T : (a < -T ? -T : a);
+            wv[c] = b > T ? T : (b < -T ? -T : b);
+        }
+        zero_padding(B, nx, ny, wh, wv);
+    }
+    orc_grad_adj(B, nx, ny, wh, wv, dt);
+    for (size_t c = 0; c < V; ++c) theta_out[c] = x[c] - dt[c];
+    if (wh_out) {
+        memcpy(wh_out, wh, V * sizeof(double));
+        memcpy(wv_out, wv, V * sizeof(double));
+    }
+    free(wh); free(wv); free(zero); free(th); free(tv); free(gh); free(gv); free(dt);
+    return 0;
+}
+
+/* The denoiser of the outer loops: variant 0 = FGP / projected gradient
+ * (accel), 1 = with Chambolle's 2004 denominator, 2 = ATV-Clip (step
+ * 1/clip_alpha). p (nullable) is the starting dual, p_out [2][V] the final one. */
+static void outer_denoise(int kind, int B, int nx, int ny, double lambda, int N, int accel, int variant,
+                          double clip_alpha, const double *x, const double *p, double *theta, double *p_out)
+{
+    size_t V = (size_t)B * nx * ny;
+    if (variant == 2) {
+        if (lambda == 0.0 || N == 0) {
+            memcpy(theta, x, V * sizeof(double));
+            if (!p) memset(p_out, 0, 2 * V * sizeof(double));
+            else if (p != p_out) memmove(p_out, p, 2 * V * sizeof(double));
+            return;
+        }
+        orc_clip_denoise(B, nx, ny, lambda, clip_alpha, N, x, p, theta, p_out, p_out + V);
+    } else {
+        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, variant == 1, 0, x, p, theta, p_out, p_out + V);
+    }
+}
+
 /* Duality gap of the denoising problem for a feasible dual p, with
  * theta = x - lambda D^T p:
  *   primal  P(theta) = 1/2 ||theta - x||^2 + lambda TV(theta)
@@ -380,9 +449,11 @@ double orc_dual_gap(int kind, int B, int nx, int ny, double lambda, const double
  * warm: each denoiser call starts from the dual the previous call ended with
  *   (Algorithm 1 initialises p before the outer loop; the first call starts
  *   from zero); otherwise every call starts from zero.
- * chambolle04: the denoiser's semi-implicit denominator variant (Sec. 2.3). */
-int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel, int warm, int chambolle04,
-               const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
+ * variant: 0 = FGP / projected gradient, 1 = Chambolle's 2004 denominator,
+ *   2 = ATV-Clip with step 1/clip_alpha (Sec. 2.3, Algorithm 1). */
+int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel, int warm, int variant,
+               double clip_alpha, const double *Y, const double *C, const double *x_init, double *x_out,
+               double *theta_out)
 {
     size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
     double *Sinv = (double *)malloc(n * sizeof(double));
@@ -400,7 +471,7 @@ int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int
         for (size_t c = 0; c < n; ++c) r[c] = (Y[c] - r[c]) * Sinv[c];
         orc_adjoint(B, nx, ny, C, r, cr);                    /* Phi^T (.) */
         for (size_t c = 0; c < V; ++c) x[c] = th[c] + cr[c];
-        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, chambolle04, 0, x, warm ? P : NULL, th, P, P + V);
+        outer_denoise(kind, B, nx, ny, lambda, N, accel, variant, clip_alpha, x, warm ? P : NULL, th, P);
     }
     memcpy(x_out, x, V * sizeof(double));
     if (theta_out) memcpy(theta_out, th, V * sizeof(double));
@@ -415,8 +486,8 @@ int orc_gap_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int
  *   theta^(t+1) = TVdenoise(u^(t) + x^(t+1))  with weight lambda
  *   u^(t+1)     = u^(t) + x^(t+1) - theta^(t+1). */
 int orc_admm_tv(int kind, int B, int nx, int ny, double lambda, double rho, int T, int N, int accel, int warm,
-                int chambolle04, const double *Y, const double *C, const double *x_init, double *x_out,
-                double *theta_out)
+                int variant, double clip_alpha, const double *Y, const double *C, const double *x_init,
+                double *x_out, double *theta_out)
 {
     size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
     double *P = (double *)calloc(2 * V, sizeof(double)); /* carried dual [2][V] (warm, as in GAP) */
@@ -438,7 +509,7 @@ int orc_admm_tv(int kind, int B, int nx, int ny, double lambda, double rho, int 
         orc_adjoint(B, nx, ny, C, r, cr);
         for (size_t c = 0; c < V; ++c) x[c] = v[c] + cr[c];
         for (size_t c = 0; c < V; ++c) v[c] = u[c] + x[c];  /* denoiser input */
-        orc_tv_denoise(kind, B, nx, ny, lambda, N, accel, chambolle04, 0, v, warm ? P : NULL, th, P, P + V);
+        outer_denoise(kind, B, nx, ny, lambda, N, accel, variant, clip_alpha, v, warm ? P : NULL, th, P);
         for (size_t c = 0; c < V; ++c) u[c] = u[c] + x[c] - th[c];
     }
     memcpy(x_out, x, V * sizeof(double));

@@ -644,3 +644,77 @@ def test_twist_default_parameters():
     C = np.zeros((2, 3, 3))
     with pytest.raises(ValueError):
         orc.fista_tv(np.zeros((3, 3)), C, 0.1, 2, 2)
+
+
+# ---------------------------------------------------------------------------
+# ATV-Clip (Sec. 2.3, Algorithm 1): per-direction iterative clipping.
+# ---------------------------------------------------------------------------
+
+def tv1d_prox_rows(X, T):
+    """prox of T ||D x||_1 along the last axis, row by row, through the box-
+    constrained dual min 1/2 ||x - D^T w||^2, |w| <= T, solved by scipy's
+    L-BFGS-B (an independent solver)."""
+    n = X.shape[-1]
+    D = diff_matrix(n)
+    out = np.empty_like(X)
+    for idx in np.ndindex(X.shape[:-1]):
+        x = X[idx]
+        if n == 1:
+            out[idx] = x
+            continue
+
+        def f(w):
+            r = x - D.T @ w
+            return 0.5 * r @ r, -(D @ r)
+        res = scipy.optimize.minimize(f, np.zeros(n - 1), jac=True, method="L-BFGS-B",
+                                      bounds=[(-T, T)] * (n - 1), options={"ftol": 1e-15, "gtol": 1e-12,
+                                                                           "maxiter": 10000})
+        out[idx] = x - D.T @ res.x
+    return out
+
+
+def test_clip_first_step_closed_form():
+    x = rng(60).uniform(size=(2, 5, 6))
+    lam, alpha = 0.02, 4.0
+    g = dense_grad(x)
+    w1 = np.clip(g / alpha, -2 * lam, 2 * lam)
+    th, w = orc.clip_denoise(x, lam, 1, alpha, return_dual=True)
+    np.testing.assert_allclose(w, w1, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(th, x - dense_grad_adj(w1), rtol=0, atol=1e-15)
+
+
+def test_clip_converges_to_sum_of_directional_1d_proxes():
+    """The h and v duals never interact: the limit is
+    prox_{2 lam TV_h}(x) + prox_{2 lam TV_v}(x) - x, each a family of 1-D TV
+    proxes (rows, resp. columns) with weight 2 lam."""
+    x = rng(61).uniform(size=(2, 7, 9))
+    lam = 0.05
+    th = orc.clip_denoise(x, lam, 20000, 4.0)
+    h = tv1d_prox_rows(x, 2 * lam)
+    v = np.swapaxes(tv1d_prox_rows(np.swapaxes(x, 1, 2), 2 * lam), 1, 2)
+    np.testing.assert_allclose(th, h + v - x, rtol=0, atol=1e-6)
+
+
+def test_clip_large_lambda_gives_row_plus_column_means():
+    """A threshold larger than any dual the 1-D problems need: each 1-D prox
+    is the mean of its row (column), so theta = row mean + column mean - x."""
+    x = rng(62).uniform(size=(2, 5, 6))
+    th = orc.clip_denoise(x, 50.0, 5000, 4.0)
+    ref = x.mean(axis=2, keepdims=True) + x.mean(axis=1, keepdims=True) - x
+    np.testing.assert_allclose(th, ref, rtol=0, atol=1e-9)
+
+
+def test_clip_inside_gap():
+    """GAP with the Clip denoiser: the driver passes the denoiser input and
+    carries nothing else (written-out loop), and the measurement holds."""
+    C, X, Y = small_problem(63, B=3, nx=8, ny=9)
+    x, th = orc.gap_tv(Y, C, 0.05, 3, 6, tv="atv", clip=True, clip_alpha=5.0)
+    S = orc.weights(C)
+    t = orc.adjoint(C, Y)
+    for _ in range(3):
+        xe = t + orc.adjoint(C, (Y - orc.forward(C, t)) * S)
+        t = orc.clip_denoise(xe, 0.05, 6, 5.0)
+    np.testing.assert_allclose(x, xe, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(th, t, rtol=0, atol=1e-14)
+    with pytest.raises(ValueError):
+        orc.gap_tv(Y, C, 0.05, 1, 2, tv="itv2d", clip=True)
