@@ -104,6 +104,13 @@ typedef struct {
                                 p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)), z = D theta, |z| per
                                 the TV kind, in place of the projection of w + z/(8 lambda);
                                 float32 duals, streaming schedule only. 0 = projection */
+    int32_t clip;            /* 1 = ATV-Clip (Sec. 2.3, Algorithm 1 Clip box): one dual per
+                                direction, w_d <- clip(w_d + D_d (x - D_d^T w_d) / clip_alpha,
+                                2 lambda), output x - D_h^T w_h - D_v^T w_v; tv must be ATV,
+                                float32 duals, streaming schedule, fixed n_inner (accel and
+                                chambolle04 do not apply). 0 = FGP / projected gradient */
+    float clip_alpha;        /* ATV-Clip step 1/clip_alpha; 0 = 4 (the largest eigenvalue of
+                                D_d D_d^T is below 4; the iteration converges for alpha > 2) */
 } sci_tv_params;
 
 /* Outer framework parameters (Algorithm 1; ADMM of Eq. (24)-(26)). */

@@ -50,7 +50,8 @@ int validate(sci_ctx *ctx, int n, const sci_problem *probs, const sci_solver_par
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p->outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "outer_iters must be >= 0");
     if (p->warm_dual) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: cold-start denoiser only");
-    if (t.chambolle04) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: projection step only (no Chambolle-2004 step)");
+    if (t.chambolle04 || t.clip)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: FGP / projected-gradient denoiser only");
     for (int i = 0; i < n; ++i) {
         const sci_problem &q = probs[i];
         if (q.d.nx < 1 || q.d.ny < 1 || q.d.B < 1 || (int64_t)q.d.nx * q.d.ny * q.d.B >= ((int64_t)1 << 31))

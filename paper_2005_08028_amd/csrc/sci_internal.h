@@ -122,6 +122,10 @@ int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float
 // the projection (float32 duals; every TV kind).
 int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                                   const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
+// One ATV-Clip iteration: w_next = per-direction clip(w + D theta_d / alpha,
+// 2 lambda) with theta_d = x - D_d^T w_d; w nullable = zero (k_clip.hip).
+void launch_clip(int nx, int ny, int B, const float *x, const float *w, float *w_next, float alpha, float lambda,
+                 hipStream_t s);
 // theta = x - lambda D^T p; when u_out is non-null also u_out = x - theta.
 int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const void *p, float lam,
                     float *theta, float *u_out, hipStream_t s);

@@ -54,6 +54,15 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
     if (p.chambolle04 != 0 && p.chambolle04 != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "chambolle04 must be 0 or 1");
     if (p.chambolle04 && (p.dual_dtype != SCI_DUAL_F32 || p.schedule == SCI_SCHED_FUSED))
         return fail(ctx, SCI_ERR_UNSUPPORTED, "the Chambolle-2004 step runs with float32 duals on the streaming schedule");
+    if (p.clip != 0 && p.clip != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "clip must be 0 or 1");
+    if (p.clip) {
+        if (p.tv != SCI_TV_ATV) return fail(ctx, SCI_ERR_INVALID_ARG, "ATV-Clip is defined for anisotropic TV");
+        if (!(p.clip_alpha >= 0.0f) || !std::isfinite(p.clip_alpha))
+            return fail(ctx, SCI_ERR_INVALID_ARG, "clip_alpha must be finite and >= 0 (0 = 4)");
+        if (p.chambolle04 || p.dual_dtype != SCI_DUAL_F32 || p.schedule == SCI_SCHED_FUSED || p.gap_tol > 0.0)
+            return fail(ctx, SCI_ERR_UNSUPPORTED,
+                        "ATV-Clip runs a fixed iteration count with float32 duals on the streaming schedule");
+    }
     return SCI_OK;
 }
 
@@ -227,7 +236,7 @@ void bind_duals(sci_ctx *ctx, FgpRun &r)
 
 bool use_fused(const sci_tv_params &p)
 {
-    if (p.schedule == SCI_SCHED_STREAM || p.chambolle04) return false;
+    if (p.schedule == SCI_SCHED_STREAM || p.chambolle04 || p.clip) return false;
     if (p.schedule == SCI_SCHED_FUSED) return true;
     return tile_supported(p.tv) && p.n_inner >= 2;
 }
@@ -249,6 +258,24 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
         launch_copy(x, theta, vb, s);
         if (u_out) launch_zero(u_out, vb, s);
         return check_launch(ctx, "copy");
+    }
+    if (p.clip) {
+        // ATV-Clip: per-direction duals, output x - D^T w (lambda enters as the threshold)
+        const float alpha = p.clip_alpha > 0.0f ? p.clip_alpha : 4.0f;
+        for (int it = 0; it < p.n_inner; ++it) {
+            float *out = (float *)r.free_buffer();
+            ProfScope prof(ctx, PF_FGP_STREAM, s);
+            launch_clip(d.nx, d.ny, d.B, x, (const float *)r.cur, out, alpha, p.lambda, s);
+            r.prev = r.cur;
+            r.cur = out;
+            ++r.iters;
+        }
+        int st = check_launch(ctx, "k_clip");
+        if (st != SCI_OK) return st;
+        ProfScope prof(ctx, PF_TV_THETA, s);
+        st = launch_tv_theta(SCI_DUAL_F32, d.nx, d.ny, d.B, x, r.cur, 1.0f, theta, u_out, s);
+        if (st != SCI_OK) return fail(ctx, st, "theta pass");
+        return check_launch(ctx, "k_tv_theta");
     }
     if (use_fused(p)) {
         if (!tile_supported(p.tv))
@@ -359,9 +386,9 @@ std::string graph_key(const OuterArgs &a)
 {
     char buf[512];
     const sci_tv_params &t = a.p.tv;
-    snprintf(buf, sizeof buf, "%d|%d,%d,%d|%d,%.9g,%d,%d,%d,%d,%d,%d,%d|%d,%.9g,%d|%p,%p,%p,%p,%p", a.admm ? 1 : 0,
-             a.d.nx, a.d.ny, a.d.B, t.tv, (double)t.lambda, t.n_inner, t.accel, t.dual_dtype, t.schedule,
-             t.chambolle04, t.tile_shape, t.tile_passes, a.p.outer_iters,
+    snprintf(buf, sizeof buf, "%d|%d,%d,%d|%d,%.9g,%d,%d,%d,%d,%d,%d,%d,%d,%.9g|%d,%.9g,%d|%p,%p,%p,%p,%p",
+             a.admm ? 1 : 0, a.d.nx, a.d.ny, a.d.B, t.tv, (double)t.lambda, t.n_inner, t.accel, t.dual_dtype,
+             t.schedule, t.chambolle04, t.tile_shape, t.tile_passes, t.clip, (double)t.clip_alpha, a.p.outer_iters,
              (double)a.p.rho, a.p.warm_dual, (const void *)a.Y, (const void *)a.C, (const void *)a.X_init,
              (void *)a.X_out, (void *)a.theta);
     return buf;
@@ -806,7 +833,8 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     if (st != SCI_OK) return st;
     if (!p || !X) return fail(ctx, SCI_ERR_INVALID_ARG, "null pointer argument");
     if ((st = check_tv(ctx, *p, d)) != SCI_OK) return st;
-    if (!tile_supported(p->tv)) return fail(ctx, SCI_ERR_UNSUPPORTED, "only the fused schedule (ATV, ITV2D) is tuned");
+    if (!tile_supported(p->tv) || p->chambolle04 || p->clip)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "only the tiled FGP / projected-gradient denoiser (ATV, ITV2D) is tuned");
     if (p->lambda == 0.0f || p->n_inner == 0) return fail(ctx, SCI_ERR_INVALID_ARG, "nothing to tune: lambda or n_inner is 0");
     if ((st = use_device(ctx)) != SCI_OK) return st;
     const size_t vb = vol_elems(d) * sizeof(float);

@@ -45,7 +45,8 @@ class sci_tv_params(ctypes.Structure):
     _fields_ = [("tv", ctypes.c_int32), ("lambda_", ctypes.c_float), ("n_inner", ctypes.c_int32),
                 ("accel", ctypes.c_int32), ("dual_dtype", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("gap_tol", ctypes.c_double), ("n_inner_max", ctypes.c_int32), ("gap_check_every", ctypes.c_int32),
-                ("tile_shape", ctypes.c_int32), ("tile_passes", ctypes.c_int32), ("chambolle04", ctypes.c_int32)]
+                ("tile_shape", ctypes.c_int32), ("tile_passes", ctypes.c_int32), ("chambolle04", ctypes.c_int32),
+                ("clip", ctypes.c_int32), ("clip_alpha", ctypes.c_float)]
 
 
 class sci_solver_params(ctypes.Structure):
@@ -151,12 +152,13 @@ def _dims(vol: torch.Tensor) -> sci_dims:
 
 
 def tv_params(tv="atv", lam=0.1, n_inner=5, accel=True, dual_dtype="f32", schedule="auto", gap_tol=0.0,
-              n_inner_max=0, gap_check_every=0, tile_shape=0, tile_passes=0, chambolle04=False) -> sci_tv_params:
+              n_inner_max=0, gap_check_every=0, tile_shape=0, tile_passes=0, chambolle04=False, clip=False,
+              clip_alpha=0.0) -> sci_tv_params:
     return sci_tv_params(TV[tv] if isinstance(tv, str) else int(tv), float(lam), int(n_inner), int(bool(accel)),
                          DUAL[dual_dtype] if isinstance(dual_dtype, str) else int(dual_dtype),
                          SCHED[schedule] if isinstance(schedule, str) else int(schedule), float(gap_tol),
                          int(n_inner_max), int(gap_check_every), int(tile_shape), int(tile_passes),
-                         int(bool(chambolle04)))
+                         int(bool(chambolle04)), int(bool(clip)), float(clip_alpha))
 
 
 def solver_params(outer_iters=50, rho=0.0, warm_dual=False, use_graph=False, twist_alpha=0.0, twist_beta=0.0,

@@ -283,6 +283,53 @@ def test_chambolle04_matches_oracle(sc, ctx, tv, B, nx, ny):
         sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv=tv, n_inner=3, chambolle04=True, dual_dtype="bf16"))
 
 
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (1, 2, 2), (2, 5, 3), (3, 17, 63), (4, 130, 64), (24, 16, 64)])
+def test_clip_matches_oracle(sc, ctx, B, nx, ny):
+    """ATV-Clip: per-direction iterative clipping, threshold 2 lambda."""
+    r = np.random.default_rng(B * 3 + nx * 5 + ny)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    w0 = r.uniform(-0.1, 0.1, size=(2, B, nx, ny)).astype(np.float32)
+    for n, alpha, warm in ((1, 0.0, False), (8, 0.0, False), (8, 3.0, False), (5, 4.5, True)):
+        prm = sc.tv_params(tv="atv", lam=0.05, n_inner=n, clip=True, clip_alpha=alpha)
+        dual = torch.empty((2, B, nx, ny), device="cuda")
+        th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=dev(w0) if warm else None, dual_out=dual)
+        ref, wref = orc.clip_denoise(x, f32(0.05), n, f32(alpha) if alpha else 4.0, w_init=w0 if warm else None,
+                                     return_dual=True)
+        e = rel_l2(host(th), ref)
+        ew = np.abs(host(dual) - wref).max()
+        say(f"clip B={B} {nx}x{ny} N={n} alpha={alpha} warm={warm}: rel-L2 {e:.2e}, dual {ew:.2e}")
+        assert e <= REL_TOL and ew <= 1e-6
+    for bad in (dict(tv="itv2d"), dict(tv="atv", dual_dtype="bf16"), dict(tv="atv", schedule="fused"),
+                dict(tv="atv", gap_tol=1e-3, n_inner_max=10)):
+        with pytest.raises(RuntimeError):
+            sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(lam=0.05, n_inner=3, clip=True, **bad))
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_clip_outer_matches_oracle(sc, ctx, solver):
+    pr = synth.make_problem(96, 130, 8, seed=19, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    cold = None
+    for warm in (False, True):
+        x, th = run_solver(sc, ctx, solver, Y, pr.masks, outer_iters=10, rho=0.05, tv="atv", lam=0.05,
+                           n_inner=6, clip=True, warm_dual=warm)
+        cold = x if not warm else cold
+        if solver == "gap":
+            xr, thr = orc.gap_tv(Y, pr.masks, f32(0.05), 10, 6, tv="atv", clip=True, warm_dual=warm)
+        else:
+            xr, thr = orc.admm_tv(Y, pr.masks, f32(0.05), f32(0.05), 10, 6, tv="atv", clip=True, warm_dual=warm)
+        e = rel_l2(x, xr)
+        say(f"{solver}-ATV-Clip warm={warm}: rel-L2 {e:.2e}, PSNR {orc.psnr(xr, pr.truth):.2f}")
+        assert e <= REL_TOL and rel_l2(th, thr) <= REL_TOL
+    # the captured graph replays the same arithmetic
+    Yd, Cd = dev(Y), dev(pr.masks)
+    fn = sc.sci_gap_tv if solver == "gap" else sc.sci_admm_tv
+    prm = sc.solver_params(outer_iters=10, rho=0.05, tv="atv", lam=0.05, n_inner=6, clip=True, use_graph=True)
+    for _ in range(2):
+        xg, _ = fn(ctx, Yd, Cd, prm)
+        np.testing.assert_array_equal(host(xg), cold)
+
+
 @pytest.mark.parametrize("dt,bound", [("bf16", 2e-2), ("f16", 3e-3)])
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 def test_denoise_16bit_duals(sc, ctx, tv, dt, bound):
