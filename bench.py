@@ -273,6 +273,47 @@ def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, T_eval=20):
     }
 
 
+def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10):
+    """The paper's real-data shape (512x512, B=10, ITV3D-FGP, 150 iterations)
+    on a synthetic scene: time of one GAP-VTV solve, and PSNR against the
+    iteration count for GAP, ADMM, FISTA and TwIST (each run afresh to every
+    checkpoint, so momentum and ADMM multipliers are never reset)."""
+    import torch
+    pr = synth.make_problem(512, 512, 10, 4001, mask="bernoulli", sigma=0.0, texture_sigma=0.02)
+    C = torch.from_numpy(pr.masks).to(dev)
+    Xt = torch.from_numpy(pr.truth).to(dev)
+    Y = scitv.sci_forward(h, C, Xt)
+    V = C.numel()
+    prm = scitv.solver_params(outer_iters=T, tv="vtv", lam=lam, n_inner=N)
+    X = torch.empty_like(C)
+    scitv.sci_gap_tv(h, Y, C, prm, X_out=X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        scitv.sci_gap_tv(h, Y, C, prm, X_out=X)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    curves = {}
+    fns = {"gap": scitv.sci_gap_tv, "admm": scitv.sci_admm_tv, "fista": scitv.sci_fista_tv,
+           "twist": scitv.sci_twist_tv}
+    for name, fn in fns.items():
+        pts = []
+        for t in range(every, T + 1, every):
+            # one lambda for all four (FISTA / TwIST scale it by 1/L inside their denoiser)
+            q = scitv.solver_params(outer_iters=t, tv="vtv", lam=lam, n_inner=N, rho=0.01)
+            x, _ = fn(h, Y, C, q)
+            pts.append((t, round(scitv.sci_psnr(h, x, Xt), 3)))
+        curves[name] = pts
+    return {
+        "workload": f"512x512x10 synthetic scene (Bernoulli(0.5) masks, texture 0.02), ITV3D (VTV) FGP, "
+                    f"{T} outer x {N} inner, lambda={lam}",
+        "gap_vtv_ms_per_solve": round(ms, 2), "voxel_iter_per_s": V * T * N / (ms / 1e3),
+        "paper_context": "the paper reports about 3 minutes for 150 iterations at this shape on a laptop CPU",
+        "psnr_vs_outer_iterations": curves,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +448,7 @@ def main() -> int:
         out["dual_storage_stream_schedule"] = mp
         out["batched"] = measure_batched(scitv, synth, h, dev, max(1, min(steps, 3)))
         out["learned_warm_start"] = measure_learned(scitv, synth, h, dev, Y, C, X_true, lam)
+        out["paper_shaped_vtv_512x512x10"] = measure_paper_shaped(scitv, synth, h, dev)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
