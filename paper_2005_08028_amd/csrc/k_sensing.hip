@@ -122,11 +122,68 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, co
     }
 }
 
+// Two adjacent pixels per thread (8-byte loads and stores), every frame in
+// registers; the same per-pixel arithmetic as k_project_reg.
+template <bool ADMM, int KB>
+__global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_t npix, int B,
+                                                         const float2 *__restrict__ theta,
+                                                         const float2 *__restrict__ u, const float2 *__restrict__ C,
+                                                         const float2 *__restrict__ Y,
+                                                         const float2 *__restrict__ Sinv, float2 *__restrict__ x,
+                                                         float2 *__restrict__ svol)
+{
+    const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= npair) return;
+    const uint32_t fstride = npix / 2; // float2 elements per frame
+    float2 v[KB], c[KB], uu[KB];
+    float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * fstride + q;
+            c[k] = C[o];
+            if (ADMM) {
+                uu[k] = u[o];
+                const float2 t = theta[o];
+                v[k] = make_float2(t.x - uu[k].x, t.y - uu[k].y);
+            } else {
+                v[k] = theta[o];
+            }
+            acc0 = fmaf(c[k].x, v[k].x, acc0);
+            acc1 = fmaf(c[k].y, v[k].y, acc1);
+        }
+    }
+    const float2 yv = Y[q], sv = Sinv[q];
+    const float r0 = (yv.x - acc0) * sv.x, r1 = (yv.y - acc1) * sv.y;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * fstride + q;
+            const float2 xv = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
+            x[o] = xv;
+            if (ADMM) svol[o] = make_float2(uu[k].x + xv.x, uu[k].y + xv.y);
+        }
+    }
+}
+
 template <bool ADMM>
 void launch_project(uint32_t npix, int B, const float *theta, const float *u, const float *C, const float *Y,
                     const float *Sinv, float *x, float *svol, hipStream_t s)
 {
     const dim3 g(grid_for(npix)), b(kBlock);
+    auto al8 = [](const void *p) { return p == nullptr || ((uintptr_t)p & 7u) == 0; };
+    if (npix % 2 == 0 && B <= 32 && al8(theta) && al8(u) && al8(C) && al8(Y) && al8(Sinv) && al8(x) && al8(svol)) {
+        const uint32_t npair = npix / 2;
+        const dim3 g2(grid_for(npair));
+        const float2 *t2 = (const float2 *)theta, *u2 = (const float2 *)u, *C2 = (const float2 *)C;
+        const float2 *Y2 = (const float2 *)Y, *S2 = (const float2 *)Sinv;
+        float2 *x2 = (float2 *)x, *s2 = (float2 *)svol;
+        if (B <= 8) hipLaunchKernelGGL((k_project_reg2<ADMM, 8>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
+        else if (B <= 16) hipLaunchKernelGGL((k_project_reg2<ADMM, 16>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
+        else if (B <= 24) hipLaunchKernelGGL((k_project_reg2<ADMM, 24>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
+        else hipLaunchKernelGGL((k_project_reg2<ADMM, 32>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
+        return;
+    }
     if (B <= 8) hipLaunchKernelGGL((k_project_reg<ADMM, 8>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
     else if (B <= 16) hipLaunchKernelGGL((k_project_reg<ADMM, 16>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
     else if (B <= 32) hipLaunchKernelGGL((k_project_reg<ADMM, 32>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
