@@ -314,6 +314,82 @@ def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10):
     }
 
 
+def measure_kernels(scitv, h, dev, C, Y, X_true):
+    """Every step of the path timed on the 1024x1024x24 volume, against its
+    algorithmic HBM bytes (HBM-bound kernels; the fused denoiser is reported
+    in `roofline`). Single-kernel entry points are timed with events around
+    the call; denoiser passes through the library's per-kernel profiler."""
+    import torch
+    V, npix = C.numel(), Y.numel()
+    out = []
+
+    def row(step, us, nbytes, note=""):
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out.append({"step": step, "us_per_call": round(us, 2), "algorithmic_MB": round(nbytes / 1e6, 1),
+                    "GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / 8000.0, 3), **({"note": note} if note else {})})
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    Yo, Xo = torch.empty_like(Y), torch.empty_like(C)
+    row("a2 forward (sci_forward)", timed(lambda: scitv.sci_forward(h, C, X_true, Y=Yo)), 8 * V + 4 * npix)
+    row("a3 adjoint (sci_adjoint)", timed(lambda: scitv.sci_adjoint(h, C, Y, X=Xo)), 8 * V + 4 * npix)
+    row("a8 PSNR reduction (sci_psnr)", timed(lambda: scitv.sci_psnr(h, Xo, X_true)), 8 * V, "includes the read-back")
+    row("a8 residual reduction (sci_residual_sq)", timed(lambda: scitv.sci_residual_sq(h, C, Xo, Y)),
+        8 * V + 4 * npix, "includes the read-back")
+    p0 = torch.zeros((2,) + tuple(C.shape), device=dev)
+    row("a8 duality-gap reduction (sci_dual_gap)", timed(lambda: scitv.sci_dual_gap(h, Xo, p0, "itv2d", 0.1)),
+        12 * V, "includes the read-back")
+
+    def profiled(fn, fams):
+        fn()
+        torch.cuda.synchronize()
+        scitv.sci_profile_enable(h, True)
+        fn()
+        torch.cuda.synchronize()
+        scitv.sci_profile_enable(h, False)
+        res = {}
+        for f in fams:
+            n, ms = scitv.sci_profile_read(h, f)
+            res[f] = (n, ms)
+        return res
+
+    N = 10
+    per_pass_fgp = (12 + 20 + (N - 2) * 28) / N  # B/voxel: pass 1 reads x, pass 2 adds p, then p and p_prev
+    per_pass_pg = (12 + (N - 1) * 20) / N        # no momentum: x and p
+    cases = [
+        ("a6 FGP pass, ITV2D, streaming schedule (tile kernel, 1 iteration)",
+         dict(tv="itv2d", schedule="stream"), per_pass_fgp),
+        ("a6 FGP pass, VTV (row-streaming kernel, all frames of a pixel)", dict(tv="vtv"), per_pass_fgp),
+        ("f1 Chambolle-2004 pass, ITV2D, projected gradient", dict(tv="itv2d", chambolle04=True, accel=False),
+         per_pass_pg),
+        ("f3 ATV-Clip pass", dict(tv="atv", clip=True), per_pass_pg),
+    ]
+    for name, kw, bpv in cases:
+        prm = scitv.solver_params(outer_iters=2, lam=0.1, n_inner=N, **kw)
+        r = profiled(lambda: scitv.sci_gap_tv(h, Y, C, prm), ("fgp_stream", "tv_theta", "project"))
+        n, ms = r["fgp_stream"]
+        row(name, ms * 1e3 / n, bpv * V)
+        if r["tv_theta"][0]:
+            n, ms = r["tv_theta"]
+            row("a7 theta = x - lambda D^T p (" + kw["tv"] + ")", ms * 1e3 / n, 16 * V)
+        n, ms = r["project"]
+        row("a4 GAP projection", ms * 1e3 / n, 12 * V + 8 * npix)
+    prm = scitv.solver_params(outer_iters=2, lam=0.1, rho=0.01, n_inner=N, tv="itv2d")
+    r = profiled(lambda: scitv.sci_admm_tv(h, Y, C, prm), ("project",))
+    n, ms = r["project"]
+    row("a5 ADMM x-update (+ denoiser input)", ms * 1e3 / n, 20 * V + 8 * npix)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +525,7 @@ def main() -> int:
         out["batched"] = measure_batched(scitv, synth, h, dev, max(1, min(steps, 3)))
         out["learned_warm_start"] = measure_learned(scitv, synth, h, dev, Y, C, X_true, lam)
         out["paper_shaped_vtv_512x512x10"] = measure_paper_shaped(scitv, synth, h, dev)
+        out["kernel_table_1024x1024x24"] = measure_kernels(scitv, h, dev, C, Y, X_true)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as orc

@@ -63,62 +63,107 @@ __global__ __launch_bounds__(kRedThreads) void k_resid_part(int nx, int ny, int 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// theta = x - lambda D^T p at voxel (k, i, j), in double.
-template <int DT>
-__device__ inline double theta64(int nx, int ny, uint32_t V, const float *x, const typename Dual<DT>::T *p,
-                                 double lam, uint32_t fo, int i, int j)
+// Gap terms of voxel o = (k, i, j): adds |D theta| (ATV, ITV2D) or
+// |D theta|^2 (VTV, to s2), <D theta, p> and (theta - x)^2, all in double,
+// with theta = x - lambda D^T p at (i, j), (i, j+1) and (i+1, j). Every load
+// is issued unconditionally from an in-bounds address (o itself stands in
+// for a missing neighbour) and masked afterwards, so a voxel's loads are in
+// flight together instead of one branch at a time.
+template <int TV, int DT>
+__device__ __forceinline__ void gap_voxel(int nx, int ny, uint32_t V, const float *x, const typename Dual<DT>::T *p,
+                                          double lam, uint32_t o, int i, int j, double &tv, double &inner,
+                                          double &fid, double &s2)
 {
     using D = Dual<DT>;
-    const uint32_t o = fo + (uint32_t)i * ny + j;
-    double a = 0.0;
-    if (j >= 1) a += (double)D::ld(p, o - 1);
-    if (j + 1 < ny) a -= (double)D::ld(p, o);
-    if (i >= 1) a += (double)D::ld(p, V + o - ny);
-    if (i + 1 < nx) a -= (double)D::ld(p, V + o);
-    return (double)x[o] - lam * a;
+    const bool l = j >= 1, u = i >= 1, r = j + 1 < ny, dn = i + 1 < nx;
+    const bool ru = r && u, dl = dn && l, r2 = j + 2 < ny, d2 = i + 2 < nx;
+    const uint32_t oR = r ? o + 1 : o, oD = dn ? o + ny : o;
+    // p_h at (i,j-1), (i,j), (i,j+1), (i+1,j-1), (i+1,j); p_v at (i-1,j), (i,j), (i-1,j+1), (i,j+1), (i+1,j)
+    const float h_l = D::ld(p, l ? o - 1 : o), h_c = D::ld(p, o), h_r = D::ld(p, oR);
+    const float h_dl = D::ld(p, dl ? oD - 1 : o), h_d = D::ld(p, oD);
+    const float v_u = D::ld(p, V + (u ? o - ny : o)), v_c = D::ld(p, V + o);
+    const float v_ur = D::ld(p, V + (ru ? oR - ny : o)), v_r = D::ld(p, V + oR), v_d = D::ld(p, V + oD);
+    const float x_c = x[o], x_r = x[oR], x_d = x[oD];
+    // theta = x - lambda ((p_h(j-1) - p_h(j)) + (p_v(i-1) - p_v(i))), terms without a difference are 0
+    auto theta = [&](float xv, bool hl, float a, bool hc, float b, bool vu, float c, bool vc, float d) {
+        double s = 0.0;
+        s += hl ? (double)a : 0.0;
+        s -= hc ? (double)b : 0.0;
+        s += vu ? (double)c : 0.0;
+        s -= vc ? (double)d : 0.0;
+        return (double)xv - lam * s;
+    };
+    const double th = theta(x_c, l, h_l, r, h_c, u, v_u, dn, v_c);
+    const double gh = r ? theta(x_r, true, h_c, r2, h_r, u, v_ur, dn, v_r) - th : 0.0;
+    const double gv = dn ? theta(x_d, l, h_dl, r, h_d, true, v_c, d2, v_d) - th : 0.0;
+    const double ph = r ? (double)h_c : 0.0;
+    const double pv = dn ? (double)v_c : 0.0;
+    inner += gh * ph + gv * pv;
+    const double dx = th - (double)x_c;
+    fid += dx * dx;
+    if (TV == TV_ATV) tv += fabs(gh) + fabs(gv);
+    else if (TV == TV_ITV2D) tv += sqrt(gh * gh + gv * gv);
+    else s2 += gh * gh + gv * gv;
 }
 
-// Partials [3][kRedBlocks]: TV(theta), <D theta, p>, ||theta - x||^2. One
-// thread per pixel, looping over frames (VTV needs the per-pixel norm over
-// all frames).
+// Partials [3][kRedBlocks]: TV(theta), <D theta, p>, ||theta - x||^2. A
+// workgroup covers kRedThreads consecutive columns (blockIdx.x) and every
+// gridDim.y-th row (blockIdx.y); each thread walks its column through those
+// rows and, per row, through all frames (VTV needs the per-pixel norm over
+// them), four frames in flight. No integer division per voxel; neighbours
+// come through the caches.
 template <int TV, int DT>
 __global__ __launch_bounds__(kRedThreads) void k_gap_part(int nx, int ny, int B, double lam,
                                                           const float *__restrict__ x,
                                                           const typename Dual<DT>::T *__restrict__ p,
                                                           double *__restrict__ part)
 {
-    using D = Dual<DT>;
     __shared__ double lds[kRedThreads];
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t V = plane * (uint32_t)B;
+    const int j = (int)blockIdx.x * kRedThreads + (int)threadIdx.x;
     double tv = 0.0, inner = 0.0, fid = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; c < (int64_t)plane;
-         c += (int64_t)kRedBlocks * kRedThreads) {
-        const int i = (int)(c / ny), j = (int)(c % ny);
-        double s2 = 0.0;
-        for (int k = 0; k < B; ++k) {
-            const uint32_t fo = (uint32_t)k * plane;
-            const uint32_t o = fo + (uint32_t)c;
-            const double th = theta64<DT>(nx, ny, V, x, p, lam, fo, i, j);
-            const double gh = (j + 1 < ny) ? theta64<DT>(nx, ny, V, x, p, lam, fo, i, j + 1) - th : 0.0;
-            const double gv = (i + 1 < nx) ? theta64<DT>(nx, ny, V, x, p, lam, fo, i + 1, j) - th : 0.0;
-            const double ph = (j + 1 < ny) ? (double)D::ld(p, o) : 0.0;
-            const double pv = (i + 1 < nx) ? (double)D::ld(p, V + o) : 0.0;
-            inner += gh * ph + gv * pv;
-            const double dx = th - (double)x[o];
-            fid += dx * dx;
-            if (TV == TV_ATV) tv += fabs(gh) + fabs(gv);
-            else if (TV == TV_ITV2D) tv += sqrt(gh * gh + gv * gv);
-            else s2 += gh * gh + gv * gv;
+    if (j < ny) {
+        for (int i = (int)blockIdx.y; i < nx; i += (int)gridDim.y) {
+            const uint32_t pix = (uint32_t)i * ny + (uint32_t)j;
+            double s2 = 0.0;
+#pragma unroll 4
+            for (int k = 0; k < B; ++k)
+                gap_voxel<TV, DT>(nx, ny, V, x, p, lam, (uint32_t)k * plane + pix, i, j, tv, inner, fid, s2);
+            if (TV == TV_VTV) tv += sqrt(s2);
         }
-        if (TV == TV_VTV) tv += sqrt(s2);
     }
+    const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int nb = (int)(gridDim.x * gridDim.y);
     double r = block_sum(tv, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = r;
+    if (threadIdx.x == 0) part[b] = r;
     r = block_sum(inner, lds);
-    if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = r;
+    if (threadIdx.x == 0) part[nb + b] = r;
     r = block_sum(fid, lds);
-    if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = r;
+    if (threadIdx.x == 0) part[2 * nb + b] = r;
+}
+
+// Grid of k_gap_part: column blocks x row strides, about kRedBlocks workgroups.
+dim3 gap_grid(int nx, int ny)
+{
+    const int gx = (ny + kRedThreads - 1) / kRedThreads;
+    int gy = kRedBlocks / gx;
+    if (gy < 1) gy = 1;
+    if (gy > nx) gy = nx;
+    return dim3(gx, gy);
+}
+
+// out[c] = sum of part[c * n .. + n) in a fixed order (one workgroup).
+__global__ __launch_bounds__(kRedThreads) void k_final_n(int nch, int n, const double *__restrict__ part,
+                                                         double *__restrict__ out)
+{
+    __shared__ double lds[kRedThreads];
+    for (int c = 0; c < nch; ++c) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < n; b += kRedThreads) acc += part[(size_t)c * n + b];
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) out[c] = s;
+    }
 }
 
 // out[c] = sum of part[c * kRedBlocks .. + kRedBlocks) in a fixed order.
@@ -181,18 +226,16 @@ template <int TV>
 void gap_tv_dt(int dual_dtype, int nx, int ny, int B, double lam, const float *x, const void *p, double *part,
                hipStream_t s)
 {
+    const dim3 g = gap_grid(nx, ny), b(kRedThreads);
     switch (dual_dtype) {
     case DT_F32:
-        hipLaunchKernelGGL((k_gap_part<TV, DT_F32>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, nx, ny, B, lam, x,
-                           (const float *)p, part);
+        hipLaunchKernelGGL((k_gap_part<TV, DT_F32>), g, b, 0, s, nx, ny, B, lam, x, (const float *)p, part);
         break;
     case DT_BF16:
-        hipLaunchKernelGGL((k_gap_part<TV, DT_BF16>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, nx, ny, B, lam, x,
-                           (const uint16_t *)p, part);
+        hipLaunchKernelGGL((k_gap_part<TV, DT_BF16>), g, b, 0, s, nx, ny, B, lam, x, (const uint16_t *)p, part);
         break;
     default:
-        hipLaunchKernelGGL((k_gap_part<TV, DT_F16>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, nx, ny, B, lam, x,
-                           (const _Float16 *)p, part);
+        hipLaunchKernelGGL((k_gap_part<TV, DT_F16>), g, b, 0, s, nx, ny, B, lam, x, (const _Float16 *)p, part);
         break;
     }
 }
@@ -200,6 +243,12 @@ void gap_tv_dt(int dual_dtype, int nx, int ny, int B, double lam, const float *x
 } // namespace
 
 int reduce_partial_blocks() { return kRedBlocks; }
+
+size_t gap_partial_doubles(int nx, int ny, int, int)
+{
+    const dim3 g = gap_grid(nx, ny);
+    return 3 * (size_t)g.x * g.y;
+}
 
 void launch_sqdiff(int64_t n, const float *a, const float *b, double *partials, double *out_dev, hipStream_t s)
 {
@@ -227,7 +276,9 @@ int launch_gap_terms(int tv, int dual_dtype, int nx, int ny, int B, float lam, c
     if (tv == TV_ATV) gap_tv_dt<TV_ATV>(dual_dtype, nx, ny, B, l, x, p, partials, s);
     else if (tv == TV_ITV2D) gap_tv_dt<TV_ITV2D>(dual_dtype, nx, ny, B, l, x, p, partials, s);
     else gap_tv_dt<TV_VTV>(dual_dtype, nx, ny, B, l, x, p, partials, s);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, 3, (const double *)partials, out_dev);
+    const dim3 g = gap_grid(nx, ny);
+    hipLaunchKernelGGL(k_final_n, dim3(1), dim3(kRedThreads), 0, s, 3, (int)(g.x * g.y), (const double *)partials,
+                       out_dev);
     return SCI_OK;
 }
 

@@ -159,12 +159,14 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
 // ---- launchers (k_reduce.hip) -------------------------------------------------
 // Deterministic two-stage FP64 reductions into out_dev (device doubles).
 int reduce_partial_blocks();
+size_t gap_partial_doubles(int nx, int ny, int B, int tv);
 // out_dev[0] = max_ij sum_k C_kij^2 (partials: reduce_partial_blocks() entries)
 void launch_max_s(int nx, int ny, int B, const float *C, double *partials, double *out_dev, hipStream_t s);
 void launch_sqdiff(int64_t n, const float *a, const float *b, double *partials, double *out_dev, hipStream_t s);
 void launch_residual_sq(int nx, int ny, int B, const float *C, const float *X, const float *Y, double *partials,
                         double *out_dev, hipStream_t s);
-// out_dev[0] = TV(theta), out_dev[1] = <D theta, p>, out_dev[2] = ||theta - x||^2
+// out_dev[0] = TV(theta), out_dev[1] = <D theta, p>, out_dev[2] = ||theta - x||^2;
+// `partials` holds gap_partial_doubles(nx, ny, B, tv) doubles
 int launch_gap_terms(int tv, int dual_dtype, int nx, int ny, int B, float lam, const float *x, const void *p,
                      double *partials, double *out_dev, hipStream_t s);
 

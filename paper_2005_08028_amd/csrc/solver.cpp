@@ -298,11 +298,11 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
 int rel_gap(sci_ctx *ctx, const sci_dims &d, int tv, int dual_dtype, float lam, const float *x, const void *p,
             double *gap, double *primal, hipStream_t s)
 {
-    const int nb = reduce_partial_blocks();
-    int st = ensure_ws(ctx, WS_PARTIAL, (3 * (size_t)nb + 8) * sizeof(double), s);
+    const size_t np = gap_partial_doubles(d.nx, d.ny, d.B, tv);
+    int st = ensure_ws(ctx, WS_PARTIAL, (np + 8) * sizeof(double), s);
     if (st != SCI_OK) return st;
     double *part = (double *)ctx->ws[WS_PARTIAL].ptr;
-    double *outd = part + 3 * nb;
+    double *outd = part + np;
     if (!p) {
         st = ensure_ws(ctx, WS_DUAL2, 2 * vol_elems(d) * dual_elem_bytes(dual_dtype), s);
         if (st != SCI_OK) return st;
