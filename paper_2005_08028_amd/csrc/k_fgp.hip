@@ -10,12 +10,12 @@
 // (64 lanes x 4 bytes), rebuilds w and theta for it on chip, and finishes
 // the current row: z = D theta, q = w + z/(8 lambda), projection, store.
 //
-// Used for VTV, which normalises all 2B dual values of a pixel together: each
-// lane carries every frame of its column in registers (KB >= B) and projects
-// once all frames of the row are done. (The kernel also handles one frame per
-// lane, KB = 1, for the per-voxel projections; ATV and ITV2D stream through
-// the 2D tile kernel with one iteration per pass instead, except in the
-// Chambolle-2004 variant below.)
+// k_fgp_stream handles one frame per lane (KB = 1) for the per-voxel
+// projections; it runs the Chambolle-2004 variant of ATV and ITV2D (their FGP
+// passes stream through the 2D tile kernel instead). VTV, which normalises
+// all 2B dual values of a pixel together, runs k_vtv_groups: the frames of a
+// pixel are split over the wavefronts of a workgroup, which combine their
+// partial norms through LDS once per row.
 //
 // CH = 1 replaces the projection P_K(q) by Chambolle's (2004) semi-implicit
 // step p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)) (Sec. 2.3), with |z|
@@ -31,6 +31,17 @@ namespace {
 
 constexpr int kWaves = 4;  // wavefronts per workgroup
 constexpr int kStrip = 62; // result columns per wavefront
+
+// Workgroup barrier over LDS only: waits for this wavefront's LDS accesses
+// (lgkmcnt), not for its global loads and stores; the signal fences keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // PF = rows of loads kept in flight ahead of the row being finished (0 for
 // VTV, whose B frames per row already give many loads in flight).
@@ -183,6 +194,131 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
     }
 }
 
+// VTV with the frames of a pixel split over the NG wavefronts of a
+// workgroup: all wavefronts walk the same 62-column strip and row segment,
+// wavefront g owning frames [g*fpw, (g+1)*fpw) in registers (KF >= fpw). Per
+// row each wavefront forms q for its frames and the partial squared norm
+// over them; the partials go through LDS (double-buffered by row parity, one
+// barrier per row) and are summed in wavefront order, so every wavefront
+// scales its frames by the same per-pixel factor. PF rows of loads are kept
+// in flight ahead of the row being finished.
+template <int KF, int NG, int DT, int PF, int CH>
+__global__ __launch_bounds__(64 * NG) void k_vtv_groups(int nx, int ny, int B, int fpw, int rows, int nstrips,
+                                                            const float *__restrict__ x,
+                                                            const typename Dual<DT>::T *__restrict__ pc,
+                                                            const typename Dual<DT>::T *__restrict__ pp,
+                                                            typename Dual<DT>::T *__restrict__ pn, int mode,
+                                                            float beta, float lam, float step)
+{
+    using D = Dual<DT>;
+    __shared__ float n2s[2][NG][64];
+    const int lane = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;
+    const int strip = (int)blockIdx.x % nstrips;
+    const int i0 = ((int)blockIdx.x / nstrips) * rows;
+    const int i1 = min(nx, i0 + rows);
+    const int j = strip * kStrip - 1 + lane;
+    const bool jin = j >= 0 && j < ny;
+    const bool hin = j >= 0 && j < ny - 1;
+    const bool outl = lane >= 1 && lane <= kStrip && j < ny;
+    const float step_h = hin ? step : 0.0f;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t V = plane * (uint32_t)B;
+    const int kbase = g * fpw;
+    const int nk = max(0, min(fpw, B - kbase)); // frames of this wavefront (0 for a spare one)
+
+    auto load_row = [&](int kk, int i) -> RowLoad {
+        RowLoad l{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        const uint32_t o = (uint32_t)(kbase + kk) * plane + (uint32_t)i * ny + j;
+        const bool vin = jin && i < nx - 1;
+        if (jin) l.x = x[o];
+        if (mode != 0) {
+            if (hin) l.ph = D::ld(pc, o);
+            if (vin) l.pv = D::ld(pc, V + o);
+            if (mode == 2) {
+                if (hin) l.pph = D::ld(pp, o);
+                if (vin) l.ppv = D::ld(pp, V + o);
+            }
+        }
+        return l;
+    };
+    auto w_of = [&](float p, float ppv) -> float { return mode == 2 ? extrapolate(p, ppv, beta) : p; };
+
+    float wh0[KF], wv0[KF], th0[KF];
+    RowLoad nxt[KF];
+#pragma unroll
+    for (int kk = 0; kk < KF; ++kk) {
+        if (kk < nk) {
+            float wvm = 0.0f;
+            if (i0 >= 1) {
+                const RowLoad u = load_row(kk, i0 - 1);
+                wvm = w_of(u.pv, u.ppv);
+            }
+            const RowLoad c = load_row(kk, i0);
+            if (PF >= 1 && i0 + 1 < nx) nxt[kk] = load_row(kk, i0 + 1);
+            wh0[kk] = w_of(c.ph, c.pph);
+            wv0[kk] = w_of(c.pv, c.ppv);
+            th0[kk] = theta_of(c.x, from_left(wh0[kk]), wh0[kk], wvm, wv0[kk], lam);
+        }
+    }
+
+    int par = 0;
+    for (int i = i0; i < i1; ++i) {
+        const bool has_next = i + 1 < nx;
+        const float step_v = has_next ? step : 0.0f;
+        float qh[KF], qv[KF];
+        float n2 = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < KF; ++kk) {
+            if (kk < nk) {
+                RowLoad r1{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (PF == 0) {
+                    if (has_next) r1 = load_row(kk, i + 1);
+                } else {
+                    r1 = nxt[kk];
+                    if (i + 2 < nx && i + 2 <= i1) nxt[kk] = load_row(kk, i + 2);
+                }
+                float wh1 = 0.0f, wv1 = 0.0f, th1 = 0.0f;
+                if (has_next) {
+                    wh1 = w_of(r1.ph, r1.pph);
+                    wv1 = w_of(r1.pv, r1.ppv);
+                    th1 = theta_of(r1.x, from_left(wh1), wh1, wv0[kk], wv1, lam);
+                }
+                const float zh = from_right(th0[kk]) - th0[kk];
+                const float zv = th1 - th0[kk];
+                if (CH) {
+                    const float sh = step_h * zh, sv = step_v * zv;
+                    qh[kk] = wh0[kk] + sh;
+                    qv[kk] = wv0[kk] + sv;
+                    n2 = norm2_add(n2, sh, sv);
+                } else {
+                    qh[kk] = ascend(wh0[kk], zh, step_h);
+                    qv[kk] = ascend(wv0[kk], zv, step_v);
+                    n2 = norm2_add(n2, qh[kk], qv[kk]);
+                }
+                wh0[kk] = wh1;
+                wv0[kk] = wv1;
+                th0[kk] = th1;
+            }
+        }
+        n2s[par][g][lane] = n2;
+        lds_barrier();
+        float tot = 0.0f;
+#pragma unroll
+        for (int gg = 0; gg < NG; ++gg) tot += n2s[par][gg][lane];
+        const float sc = CH ? semi_implicit_scale(tot) : iso_scale(tot);
+#pragma unroll
+        for (int kk = 0; kk < KF; ++kk) {
+            if (kk < nk && outl) {
+                const uint32_t o = (uint32_t)(kbase + kk) * plane + (uint32_t)i * ny + j;
+                D::st(pn, o, qh[kk] * sc);
+                D::st(pn, V + o, qv[kk] * sc);
+            }
+        }
+        par ^= 1;
+    }
+}
+
 // theta = x - lambda D^T p per voxel; optionally u = x - theta.
 template <int DT>
 __global__ __launch_bounds__(256) void k_tv_theta(int nx, int ny, uint32_t V, const float *__restrict__ x,
@@ -228,22 +364,43 @@ void launch_stream_t(int nx, int ny, int B, const float *x, const void *pc, cons
                        x, (const T *)pc, (const T *)pp, (T *)pn, mode, beta, lam, 1.0f / (8.0f * lam));
 }
 
+constexpr int kVtvWaves = 8; // frame groups (wavefronts) per VTV workgroup
+
+template <int KF, int DT, int CH>
+void launch_vtv_t(int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn, int mode,
+                  float beta, float lam, hipStream_t s)
+{
+    using T = typename Dual<DT>::T;
+    const int nstrips = (ny + kStrip - 1) / kStrip;
+    const int fpw = (B + kVtvWaves - 1) / kVtvWaves;
+    // enough workgroups to fill the chip several times over
+    int rows = 64;
+    while (rows > 4 && (long)nstrips * ((nx + rows - 1) / rows) < 2048) rows >>= 1;
+    const int nwg = nstrips * ((nx + rows - 1) / rows);
+    hipLaunchKernelGGL((k_vtv_groups<KF, kVtvWaves, DT, 1, CH>), dim3(nwg), dim3(64 * kVtvWaves), 0, s, nx, ny, B,
+                       fpw, rows,
+                       nstrips, x, (const T *)pc, (const T *)pp, (T *)pn, mode, beta, lam, 1.0f / (8.0f * lam));
+}
+
+template <int DT, int CH>
+int launch_vtv(int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn, int mode, float beta,
+               float lam, hipStream_t s)
+{
+    const int fpw = (B + kVtvWaves - 1) / kVtvWaves;
+    if (fpw <= 1) launch_vtv_t<1, DT, CH>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    else if (fpw <= 2) launch_vtv_t<2, DT, CH>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    else if (fpw <= 4) launch_vtv_t<4, DT, CH>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    else return SCI_ERR_UNSUPPORTED;
+    return SCI_OK;
+}
+
 template <int DT>
 int launch_stream_dt(int tv, int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn,
                      int mode, float beta, float lam, hipStream_t s)
 {
     // ATV and ITV2D stream through the tile kernel with one iteration per pass
-    if (tv != TV_VTV) return SCI_ERR_UNSUPPORTED;
-    if (B <= 8) {
-        launch_stream_t<TV_VTV, 8, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    } else if (B <= 16) {
-        launch_stream_t<TV_VTV, 16, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    } else if (B <= 32) {
-        launch_stream_t<TV_VTV, 32, DT>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    } else {
-        return SCI_ERR_UNSUPPORTED;
-    }
-    return SCI_OK;
+    if (tv == TV_VTV) return launch_vtv<DT, 0>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    return SCI_ERR_UNSUPPORTED;
 }
 
 // Chambolle-2004 step, float32 duals, every TV kind
@@ -255,12 +412,7 @@ int launch_stream_ch(int tv, int nx, int ny, int B, const float *x, const void *
     case TV_ITV2D:
         launch_stream_t<TV_ITV2D, 1, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
         return SCI_OK;
-    case TV_VTV:
-        if (B <= 8) launch_stream_t<TV_VTV, 8, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-        else if (B <= 16) launch_stream_t<TV_VTV, 16, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-        else if (B <= 32) launch_stream_t<TV_VTV, 32, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-        else return SCI_ERR_UNSUPPORTED;
-        return SCI_OK;
+    case TV_VTV: return launch_vtv<DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
     }
     return SCI_ERR_INVALID_ARG;
 }
