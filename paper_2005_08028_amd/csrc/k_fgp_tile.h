@@ -76,30 +76,66 @@ __device__ __forceinline__ void fgp_tile_body(int nx, int ny, int tx, int ty, ui
     }
 
     float xr[R][C], ph[R][C], pv[R][C], wh[R][C], wv_[R][C];
+    // Loads first, arithmetic after: every load uses an in-bounds address
+    // (the frame's first element stands in for pixels outside the image) and
+    // its value is masked afterwards, so that no load waits behind a branch
+    // and all of a lane's loads are in flight together.
+    uint32_t pixs[R][C];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = ibase + r;
         const bool iin = i >= 0 && i < nx;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const bool hin = hj[c] && iin;                      // horizontal difference exists
-            const bool vin = jin[c] && i >= 0 && i < nx - 1;    // vertical difference exists
-            const uint32_t o = fo + (uint32_t)i * ny + (j0 + c); // dereferenced only inside the image
-            xr[r][c] = (jin[c] && iin) ? x[o] : 0.0f;
-            if (mode == 0) {
-                ph[r][c] = pv[r][c] = wh[r][c] = wv_[r][c] = 0.0f;
-            } else {
-                ph[r][c] = hin ? D::ld(pc, o) : 0.0f;
-                pv[r][c] = vin ? D::ld(pc, V + o) : 0.0f;
+        for (int c = 0; c < C; ++c) pixs[r][c] = (jin[c] && iin) ? (uint32_t)i * ny + (uint32_t)(j0 + c) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) xr[r][c] = x[fo + pixs[r][c]];
+    if (mode == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < C; ++c) ph[r][c] = pv[r][c] = wh[r][c] = wv_[r][c] = 0.0f;
+    } else {
+        // p^(s0) into ph/pv, p^(s0-1) staged in wh/wv_ (mode 2)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const uint32_t o = fo + pixs[r][c];
+                ph[r][c] = D::ld(pc, o);
+                pv[r][c] = D::ld(pc, V + o);
                 if (mode == 2) {
-                    wh[r][c] = hin ? extrapolate(ph[r][c], D::ld(pp, o), bt.b[0]) : 0.0f;
-                    wv_[r][c] = vin ? extrapolate(pv[r][c], D::ld(pp, V + o), bt.b[0]) : 0.0f;
+                    wh[r][c] = D::ld(pp, o);
+                    wv_[r][c] = D::ld(pp, V + o);
+                }
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = ibase + r;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const bool hin = hj[c] && i >= 0 && i < nx;      // horizontal difference exists
+                const bool vin = jin[c] && i >= 0 && i < nx - 1; // vertical difference exists
+                ph[r][c] = hin ? ph[r][c] : 0.0f;
+                pv[r][c] = vin ? pv[r][c] : 0.0f;
+                if (mode == 2) {
+                    wh[r][c] = hin ? extrapolate(ph[r][c], wh[r][c], bt.b[0]) : 0.0f;
+                    wv_[r][c] = vin ? extrapolate(pv[r][c], wv_[r][c], bt.b[0]) : 0.0f;
                 } else {
                     wh[r][c] = ph[r][c];
                     wv_[r][c] = pv[r][c];
                 }
             }
         }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = ibase + r;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (!(jin[c] && i >= 0 && i < nx)) xr[r][c] = 0.0f;
     }
 
     auto interior = [&](int r, int c) {

@@ -103,8 +103,9 @@ struct FgpRun {
     }
 };
 
-// Tile shape used for one-iteration passes (128 x 64 tiles, 2 columns per lane).
-constexpr int kStreamTileShape = 4;
+// Tile shape used for one-iteration passes when none is tuned (64 x 32 tiles, 8 wavefronts per
+// SIMD: the fastest single-iteration shape measured at 1024x1024x24).
+constexpr int kStreamTileShape = 3;
 
 int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
                      float *theta, float *u_out, bool keep_dual, hipStream_t s, int force_shape = -1,
