@@ -3,8 +3,9 @@
 //   theta_h = x - D_h^T w_h,  w_h <- clip(w_h + D_h theta_h / alpha, T)
 // and the same along the vertical direction, T = 2 lambda. The two
 // directions never interact. One pass over HBM per iteration: a thread owns
-// one voxel and reads its row / column neighbours (x and w at j-1, j, j+1
-// and i-1, i, i+1; the neighbours are served by the caches).
+// one column of a frame, every gridDim.y-th row of it, and reads the row /
+// column neighbours (x and w at j-1, j, j+1 and i-1, i, i+1) through the
+// caches.
 #include <hip/hip_runtime.h>
 
 #include "sci_internal.h"
@@ -14,36 +15,46 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ __launch_bounds__(kBlock) void k_clip(int nx, int ny, uint32_t V, const float *__restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_clip(int nx, int ny, int B, const float *__restrict__ x,
                                                  const float *__restrict__ w, float *__restrict__ wn,
                                                  float inv_alpha, float T)
 {
-    const uint32_t o = blockIdx.x * kBlock + threadIdx.x;
-    if (o >= V) return;
+    const int j = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    if (j >= ny) return;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t r = o % plane;
-    const int i = (int)(r / (uint32_t)ny), j = (int)(r % (uint32_t)ny);
-    float nh = 0.0f, nv = 0.0f; // no difference at j = ny-1 (h) / i = nx-1 (v): the dual stays 0
-    if (j < ny - 1) {
-        const float *wh = w;
-        const float wm = (w && j >= 1) ? wh[o - 1] : 0.0f;
-        const float w0 = w ? wh[o] : 0.0f;
-        const float wp = (w && j + 1 < ny - 1) ? wh[o + 1] : 0.0f;
-        const float t0 = x[o] - (wm - w0);     // theta_h at j
-        const float t1 = x[o + 1] - (w0 - wp); // theta_h at j+1
-        nh = fminf(fmaxf(fmaf(t1 - t0, inv_alpha, w0), -T), T);
+    const uint32_t V = plane * (uint32_t)B;
+    const uint32_t fo = (uint32_t)blockIdx.z * plane;
+    for (int i = (int)blockIdx.y; i < nx; i += (int)gridDim.y) {
+        const uint32_t o = fo + (uint32_t)i * ny + (uint32_t)j;
+        const bool hd = j < ny - 1, vd = i < nx - 1; // a difference exists at this voxel
+        // loads from in-bounds addresses (o stands in for a missing neighbour), masked afterwards
+        const uint32_t oR = hd ? o + 1 : o, oD = vd ? o + ny : o;
+        const float x0 = x[o], xr = x[oR], xd = x[oD];
+        float hm = 0.0f, h0 = 0.0f, hp = 0.0f, vm = 0.0f, v0 = 0.0f, vp = 0.0f;
+        if (w) {
+            hm = w[j >= 1 ? o - 1 : o];
+            h0 = w[o];
+            hp = w[oR];
+            vm = w[V + (i >= 1 ? o - ny : o)];
+            v0 = w[V + o];
+            vp = w[V + oD];
+        }
+        float nh = 0.0f, nv = 0.0f; // no difference at j = ny-1 (h) / i = nx-1 (v): the dual stays 0
+        if (hd) {
+            const float wm = j >= 1 ? hm : 0.0f, wp = j + 1 < ny - 1 ? hp : 0.0f;
+            const float t0 = x0 - (wm - h0); // theta_h at j
+            const float t1 = xr - (h0 - wp); // theta_h at j+1
+            nh = fminf(fmaxf(fmaf(t1 - t0, inv_alpha, h0), -T), T);
+        }
+        if (vd) {
+            const float wm = i >= 1 ? vm : 0.0f, wp = i + 1 < nx - 1 ? vp : 0.0f;
+            const float t0 = x0 - (wm - v0);
+            const float t1 = xd - (v0 - wp);
+            nv = fminf(fmaxf(fmaf(t1 - t0, inv_alpha, v0), -T), T);
+        }
+        wn[o] = nh;
+        wn[V + o] = nv;
     }
-    if (i < nx - 1) {
-        const float *wv = w ? w + V : nullptr;
-        const float wm = (wv && i >= 1) ? wv[o - ny] : 0.0f;
-        const float w0 = wv ? wv[o] : 0.0f;
-        const float wp = (wv && i + 1 < nx - 1) ? wv[o + ny] : 0.0f;
-        const float t0 = x[o] - (wm - w0);
-        const float t1 = x[o + ny] - (w0 - wp);
-        nv = fminf(fmaxf(fmaf(t1 - t0, inv_alpha, w0), -T), T);
-    }
-    wn[o] = nh;
-    wn[V + o] = nv;
 }
 
 } // namespace
@@ -51,9 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_clip(int nx, int ny, uint32_t V, con
 void launch_clip(int nx, int ny, int B, const float *x, const float *w, float *w_next, float alpha, float lambda,
                  hipStream_t s)
 {
-    const uint32_t V = (uint32_t)nx * (uint32_t)ny * (uint32_t)B;
-    hipLaunchKernelGGL(k_clip, dim3((V + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nx, ny, V, x, w, w_next,
-                       1.0f / alpha, 2.0f * lambda);
+    const dim3 grid((ny + kBlock - 1) / kBlock, (unsigned)(nx < 65535 ? nx : 65535), (unsigned)B);
+    hipLaunchKernelGGL(k_clip, grid, dim3(kBlock), 0, s, nx, ny, B, x, w, w_next, 1.0f / alpha, 2.0f * lambda);
 }
 
 } // namespace sci

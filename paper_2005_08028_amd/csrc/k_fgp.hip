@@ -23,6 +23,8 @@
 // (VTV); it runs on this kernel for every TV kind.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sci_internal.h"
 #include "sci_math.h"
 
@@ -77,20 +79,28 @@ __global__ __launch_bounds__(64 * kWaves) void k_fgp_stream(int nx, int ny, int 
     const int kbase = (KB == 1) ? (int)blockIdx.y : 0;
     const int nk = (KB == 1) ? 1 : B;
 
-    // row i of frame slot kk (i < nx)
+    // row i of frame slot kk (i < nx). Loads are issued from in-bounds
+    // addresses (the row's first element stands in for columns outside the
+    // image) and masked afterwards, so none waits behind a branch.
     auto load_row = [&](int kk, int i) -> RowLoad {
         RowLoad l{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        const uint32_t o = (uint32_t)(kbase + kk) * plane + (uint32_t)i * ny + j;
+        const uint32_t o = (uint32_t)(kbase + kk) * plane + (uint32_t)i * ny + (jin ? (uint32_t)j : 0u);
         const bool vin = jin && i < nx - 1;
-        if (jin) l.x = x[o];
+        const float xv = x[o];
+        float a = 0.0f, b = 0.0f, c = 0.0f, d = 0.0f;
         if (mode != 0) {
-            if (hin) l.ph = D::ld(pc, o);
-            if (vin) l.pv = D::ld(pc, V + o);
+            a = D::ld(pc, o);
+            b = D::ld(pc, V + o);
             if (mode == 2) {
-                if (hin) l.pph = D::ld(pp, o);
-                if (vin) l.ppv = D::ld(pp, V + o);
+                c = D::ld(pp, o);
+                d = D::ld(pp, V + o);
             }
         }
+        l.x = jin ? xv : 0.0f;
+        l.ph = hin ? a : 0.0f;
+        l.pv = vin ? b : 0.0f;
+        l.pph = hin ? c : 0.0f;
+        l.ppv = vin ? d : 0.0f;
         return l;
     };
     auto w_of = [&](float p, float ppv) -> float { return mode == 2 ? extrapolate(p, ppv, beta) : p; };
@@ -319,26 +329,30 @@ __global__ __launch_bounds__(64 * NG) void k_vtv_groups(int nx, int ny, int B, i
     }
 }
 
-// theta = x - lambda D^T p per voxel; optionally u = x - theta.
+// theta = x - lambda D^T p per voxel; optionally u = x - theta. Grid:
+// column blocks x row strides x frames; loads from in-bounds addresses,
+// masked afterwards.
 template <int DT>
-__global__ __launch_bounds__(256) void k_tv_theta(int nx, int ny, uint32_t V, const float *__restrict__ x,
+__global__ __launch_bounds__(256) void k_tv_theta(int nx, int ny, int B, const float *__restrict__ x,
                                                   const typename Dual<DT>::T *__restrict__ p, float lam,
                                                   float *__restrict__ theta, float *__restrict__ u_out)
 {
     using D = Dual<DT>;
-    const uint32_t o = blockIdx.x * 256u + threadIdx.x;
-    if (o >= V) return;
+    const int j = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (j >= ny) return;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t r = o % plane;
-    const int i = (int)(r / (uint32_t)ny), j = (int)(r % (uint32_t)ny);
-    const float whl = j >= 1 ? D::ld(p, o - 1) : 0.0f;
-    const float wh = j < ny - 1 ? D::ld(p, o) : 0.0f;
-    const float wvu = i >= 1 ? D::ld(p, V + o - ny) : 0.0f;
-    const float wv = i < nx - 1 ? D::ld(p, V + o) : 0.0f;
-    const float xv = x[o];
-    const float th = theta_of(xv, whl, wh, wvu, wv, lam);
-    theta[o] = th;
-    if (u_out) u_out[o] = xv - th;
+    const uint32_t V = plane * (uint32_t)B;
+    const uint32_t fo = (uint32_t)blockIdx.z * plane;
+    for (int i = (int)blockIdx.y; i < nx; i += (int)gridDim.y) {
+        const uint32_t o = fo + (uint32_t)i * ny + (uint32_t)j;
+        const bool l = j >= 1, r = j < ny - 1, u = i >= 1, d = i < nx - 1;
+        const float a = D::ld(p, l ? o - 1 : o), b = D::ld(p, o);
+        const float c = D::ld(p, V + (u ? o - ny : o)), e = D::ld(p, V + o);
+        const float xv = x[o];
+        const float th = theta_of(xv, l ? a : 0.0f, r ? b : 0.0f, u ? c : 0.0f, d ? e : 0.0f, lam);
+        theta[o] = th;
+        if (u_out) u_out[o] = xv - th;
+    }
 }
 
 int pick_rows(int nx, int nstrips, int frames_in_grid)
@@ -440,19 +454,18 @@ int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float
 int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const void *p, float lam, float *theta,
                     float *u_out, hipStream_t s)
 {
-    const uint32_t V = (uint32_t)nx * (uint32_t)ny * (uint32_t)B;
-    const dim3 grid((V + 255u) / 256u);
+    const dim3 grid((ny + 255) / 256, (unsigned)std::min(nx, 65535), (unsigned)B);
     switch (dual_dtype) {
     case DT_F32:
-        hipLaunchKernelGGL(k_tv_theta<DT_F32>, grid, dim3(256), 0, s, nx, ny, V, x, (const float *)p, lam, theta,
+        hipLaunchKernelGGL(k_tv_theta<DT_F32>, grid, dim3(256), 0, s, nx, ny, B, x, (const float *)p, lam, theta,
                            u_out);
         return SCI_OK;
     case DT_BF16:
-        hipLaunchKernelGGL(k_tv_theta<DT_BF16>, grid, dim3(256), 0, s, nx, ny, V, x, (const uint16_t *)p, lam,
+        hipLaunchKernelGGL(k_tv_theta<DT_BF16>, grid, dim3(256), 0, s, nx, ny, B, x, (const uint16_t *)p, lam,
                            theta, u_out);
         return SCI_OK;
     case DT_F16:
-        hipLaunchKernelGGL(k_tv_theta<DT_F16>, grid, dim3(256), 0, s, nx, ny, V, x, (const _Float16 *)p, lam,
+        hipLaunchKernelGGL(k_tv_theta<DT_F16>, grid, dim3(256), 0, s, nx, ny, B, x, (const _Float16 *)p, lam,
                            theta, u_out);
         return SCI_OK;
     }
