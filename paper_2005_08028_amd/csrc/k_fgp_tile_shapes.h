@@ -10,7 +10,7 @@
     X(3, 4, 8, 1, 8)  /* 64 x 32,   512 threads  */                                                                 \
     X(4, 4, 16, 2, 4) /* 128 x 64,  1024 threads */                                                                 \
     X(5, 8, 8, 2, 2)  /* 128 x 64,  512 threads  */                                                                 \
-    X(6, 4, 8, 2, 4)  /* 128 x 32,  512 threads  */                                                                 \
+    X(6, 7, 16, 2, 4) /* 128 x 112, 1024 threads */                                                                 \
     X(7, 6, 16, 2, 4) /* 128 x 96,  1024 threads */
 
 namespace sci {
