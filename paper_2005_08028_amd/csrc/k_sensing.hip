@@ -166,9 +166,81 @@ __global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_
     }
 }
 
+// Binary masks packed one bit per frame into a 32-bit word per pixel
+// (B <= 32): bits[pix] bit k = (C_k(pix) == 1). flag (set to 1 beforehand)
+// is cleared when any entry is neither 0 nor 1; the projection then reads C.
+__global__ __launch_bounds__(kBlock) void k_pack_masks(uint32_t npix, int B, const float *__restrict__ C,
+                                                       uint32_t *__restrict__ bits, int *__restrict__ flag)
+{
+    const uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= npix) return;
+    uint32_t b = 0u;
+    bool ok = true;
+    for (int k = 0; k < B; ++k) {
+        const float c = C[(uint32_t)k * npix + pix];
+        if (c == 1.0f) b |= 1u << k;
+        else if (c != 0.0f) ok = false;
+    }
+    bits[pix] = b;
+    if (!ok) atomicAnd(flag, 0);
+}
+
+__global__ void k_set_flag(int *flag, int v) { *flag = v; }
+
+// The projection with binary masks read from the packed bits: C_k is 0 or
+// 1, so fmaf(C_k, v, acc) and fmaf(C_k, r, v) reduce exactly to a select of
+// acc + v / acc and v + r / v, the same values the float path produces. Two
+// adjacent pixels per thread; when *flag is 0 the float masks are used.
+template <bool ADMM, int KB>
+__global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_t npix, int B,
+                                                         const float2 *__restrict__ theta,
+                                                         const float2 *__restrict__ u, const float2 *__restrict__ C,
+                                                         const uint2 *__restrict__ bits, const int *__restrict__ flag,
+                                                         const float2 *__restrict__ Y, const float2 *__restrict__ Sinv,
+                                                         float2 *__restrict__ x, float2 *__restrict__ svol)
+{
+    const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= npair) return;
+    const uint32_t fstride = npix / 2;
+    const bool packed = *flag != 0;
+    float2 v[KB], uu[KB];
+    uint2 m = packed ? bits[q] : make_uint2(0u, 0u);
+    float2 c[KB];
+    float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * fstride + q;
+            if (packed) c[k] = make_float2((m.x >> k) & 1u ? 1.0f : 0.0f, (m.y >> k) & 1u ? 1.0f : 0.0f);
+            else c[k] = C[o];
+            if (ADMM) {
+                uu[k] = u[o];
+                const float2 t = theta[o];
+                v[k] = make_float2(t.x - uu[k].x, t.y - uu[k].y);
+            } else {
+                v[k] = theta[o];
+            }
+            acc0 = fmaf(c[k].x, v[k].x, acc0);
+            acc1 = fmaf(c[k].y, v[k].y, acc1);
+        }
+    }
+    const float2 yv = Y[q], sv = Sinv[q];
+    const float r0 = (yv.x - acc0) * sv.x, r1 = (yv.y - acc1) * sv.y;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * fstride + q;
+            const float2 xv = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
+            x[o] = xv;
+            if (ADMM) svol[o] = make_float2(uu[k].x + xv.x, uu[k].y + xv.y);
+        }
+    }
+}
+
 template <bool ADMM>
 void launch_project(uint32_t npix, int B, const float *theta, const float *u, const float *C, const float *Y,
-                    const float *Sinv, float *x, float *svol, hipStream_t s)
+                    const float *Sinv, float *x, float *svol, hipStream_t s, const uint32_t *cbits = nullptr,
+                    const int *cflag = nullptr)
 {
     const dim3 g(grid_for(npix)), b(kBlock);
     auto al8 = [](const void *p) { return p == nullptr || ((uintptr_t)p & 7u) == 0; };
@@ -178,6 +250,14 @@ void launch_project(uint32_t npix, int B, const float *theta, const float *u, co
         const float2 *t2 = (const float2 *)theta, *u2 = (const float2 *)u, *C2 = (const float2 *)C;
         const float2 *Y2 = (const float2 *)Y, *S2 = (const float2 *)Sinv;
         float2 *x2 = (float2 *)x, *s2 = (float2 *)svol;
+        if (cbits && cflag && al8(cbits)) {
+            const uint2 *m2 = (const uint2 *)cbits;
+            if (B <= 8) hipLaunchKernelGGL((k_project_bits<ADMM, 8>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else if (B <= 16) hipLaunchKernelGGL((k_project_bits<ADMM, 16>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else if (B <= 24) hipLaunchKernelGGL((k_project_bits<ADMM, 24>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else hipLaunchKernelGGL((k_project_bits<ADMM, 32>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            return;
+        }
         if (B <= 8) hipLaunchKernelGGL((k_project_reg2<ADMM, 8>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
         else if (B <= 16) hipLaunchKernelGGL((k_project_reg2<ADMM, 16>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
         else if (B <= 24) hipLaunchKernelGGL((k_project_reg2<ADMM, 24>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
@@ -282,15 +362,23 @@ void launch_weights(int nx, int ny, int B, const float *C, float rho, float *Sin
 }
 
 void launch_gap_project(int nx, int ny, int B, const float *theta, const float *C, const float *Y,
-                        const float *Sinv, float *x, hipStream_t s)
+                        const float *Sinv, float *x, hipStream_t s, const uint32_t *cbits, const int *cflag)
 {
-    launch_project<false>((uint32_t)nx * (uint32_t)ny, B, theta, nullptr, C, Y, Sinv, x, nullptr, s);
+    launch_project<false>((uint32_t)nx * (uint32_t)ny, B, theta, nullptr, C, Y, Sinv, x, nullptr, s, cbits, cflag);
 }
 
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
-                         const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s)
+                         const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
+                         const uint32_t *cbits, const int *cflag)
 {
-    launch_project<true>((uint32_t)nx * (uint32_t)ny, B, theta, u, C, Y, Sinv, x, svol, s);
+    launch_project<true>((uint32_t)nx * (uint32_t)ny, B, theta, u, C, Y, Sinv, x, svol, s, cbits, cflag);
+}
+
+void launch_pack_masks(int nx, int ny, int B, const float *C, uint32_t *bits, int *flag, hipStream_t s)
+{
+    const uint32_t npix = (uint32_t)nx * (uint32_t)ny;
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, flag, B <= 32 ? 1 : 0);
+    if (B <= 32) hipLaunchKernelGGL(k_pack_masks, dim3(grid_for(npix)), dim3(kBlock), 0, s, npix, B, C, bits, flag);
 }
 
 // Device-to-device copy and zero fill as plain kernels, so that they can be

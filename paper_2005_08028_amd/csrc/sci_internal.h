@@ -30,6 +30,7 @@ enum BufSlot {
     WS_XTMP,                          // denoiser input copy when X_in aliases the output
     WS_BATCH,                         // batched solve: per-problem Sinv and theta
     WS_BDESC,                         // batched solve: device problem table (eager path)
+    WS_CBITS,                         // masks packed one bit per frame (+ a validity flag)
     WS_COUNT
 };
 
@@ -99,11 +100,18 @@ void launch_forward(int nx, int ny, int B, const float *C, const float *X, float
 void launch_adjoint(int nx, int ny, int B, const float *C, const float *Y, float *X, hipStream_t s);
 void launch_weights(int nx, int ny, int B, const float *C, float rho, float *Sinv, hipStream_t s);
 // x = theta + C .* ((Y - sum_k C_k theta_k) .* Sinv)
+// GAP / ADMM projection. cbits / cflag (nullable): masks packed by
+// launch_pack_masks; when *cflag is 1 the kernel reads the bits instead of C.
 void launch_gap_project(int nx, int ny, int B, const float *theta, const float *C, const float *Y,
-                        const float *Sinv, float *x, hipStream_t s);
+                        const float *Sinv, float *x, hipStream_t s, const uint32_t *cbits = nullptr,
+                        const int *cflag = nullptr);
 // v = theta - u; x = v + C .* ((Y - sum_k C_k v_k) .* Sinv); s = u + x
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
-                         const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s);
+                         const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
+                         const uint32_t *cbits = nullptr, const int *cflag = nullptr);
+// bits[pix] bit k = (C_k(pix) == 1); *flag = 1 when every entry of C is 0 or 1
+// and B <= 32, else 0 (all on the device: graph-capturable).
+void launch_pack_masks(int nx, int ny, int B, const float *C, uint32_t *bits, int *flag, hipStream_t s);
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 void launch_fill(float *dst, float v, size_t n, hipStream_t s);
 // theta = x + c (x - xp)

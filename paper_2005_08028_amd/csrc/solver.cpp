@@ -325,6 +325,14 @@ int rel_gap(sci_ctx *ctx, const sci_dims &d, int tv, int dual_dtype, float lam, 
 
 // ---- outer loops ---------------------------------------------------------------
 
+// Scratch for the packed masks: one 32-bit word per pixel, then the flag.
+size_t cbits_bytes(const sci_dims &d) { return ((img_elems(d) * sizeof(uint32_t) + 255) & ~(size_t)255) + 256; }
+uint32_t *cbits_ptr(sci_ctx *ctx) { return (uint32_t *)ctx->ws[WS_CBITS].ptr; }
+int *cflag_ptr(sci_ctx *ctx, const sci_dims &d)
+{
+    return (int *)((char *)ctx->ws[WS_CBITS].ptr + ((img_elems(d) * sizeof(uint32_t) + 255) & ~(size_t)255));
+}
+
 struct OuterArgs {
     sci_dims d;
     sci_solver_params p;
@@ -345,6 +353,7 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
     {
         ProfScope prof(ctx, PF_SETUP, s);
         launch_weights(d.nx, d.ny, d.B, a.C, a.admm ? a.p.rho : 0.0f, Sinv, s);
+        launch_pack_masks(d.nx, d.ny, d.B, a.C, cbits_ptr(ctx), cflag_ptr(ctx, d), s);
         if (a.X_init) launch_copy(a.X_init, theta, vb, s);     // theta^(0) = X_init
         else launch_adjoint(d.nx, d.ny, d.B, a.C, a.Y, theta, s); // theta^(0) = Phi^T y
         if (a.admm) launch_zero(u, vb, s);                     // u^(0) = 0
@@ -362,7 +371,8 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
         if (!a.admm) {
             {
                 ProfScope prof(ctx, PF_PROJECT, s);
-                launch_gap_project(d.nx, d.ny, d.B, theta, a.C, a.Y, Sinv, a.X_out, s);
+                launch_gap_project(d.nx, d.ny, d.B, theta, a.C, a.Y, Sinv, a.X_out, s, cbits_ptr(ctx),
+                                   cflag_ptr(ctx, d));
             }
             st = check_launch(ctx, "k_project");
             if (st != SCI_OK) return st;
@@ -370,7 +380,8 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
         } else {
             {
                 ProfScope prof(ctx, PF_PROJECT, s);
-                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, a.X_out, svol, s);
+                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, a.X_out, svol, s, cbits_ptr(ctx),
+                                    cflag_ptr(ctx, d));
             }
             st = check_launch(ctx, "k_project");
             if (st != SCI_OK) return st;
@@ -431,6 +442,7 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
     if (admm && ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK || (st = ensure_ws(ctx, WS_UVOL, vb, s)) != SCI_OK))
         return st;
     if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), s)) != SCI_OK) return st;
 
     OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm};
     if (!p->use_graph) return enqueue_outer(ctx, a, s);
@@ -519,6 +531,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     if ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_XTMP, vb, s)) != SCI_OK) return st;
     if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
+    if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), s)) != SCI_OK) return st;
     double L = 0.0;
     if ((st = lipschitz(ctx, d, C, &L, s)) != SCI_OK) return st;
     if (!(L > 0.0)) return fail(ctx, SCI_ERR_INVALID_ARG, "every mask entry is zero (L(f) = 0)");
@@ -531,6 +544,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     {
         ProfScope prof(ctx, PF_SETUP, s);
         launch_fill(W, (float)(1.0 / L), img_elems(d), s);
+        launch_pack_masks(d.nx, d.ny, d.B, C, cbits_ptr(ctx), cflag_ptr(ctx, d), s);
         if (X_init) launch_copy(X_init, xa, vb, s); // x^(0)
         else launch_adjoint(d.nx, d.ny, d.B, C, Y, xa, s);
         launch_copy(xa, theta, vb, s);
@@ -543,7 +557,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
         {
             ProfScope prof(ctx, PF_PROJECT, s);
             // FISTA steps from the extrapolated point theta, TwIST from x^(t)
-            launch_gap_project(d.nx, d.ny, d.B, twist ? xa : theta, C, Y, W, z, s);
+            launch_gap_project(d.nx, d.ny, d.B, twist ? xa : theta, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
         }
         if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
         if (!twist) {
@@ -775,7 +789,9 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     float *Sinv = (float *)ctx->ws[WS_SINV].ptr;
     float *pred = (float *)ctx->ws[WS_XTMP].ptr;
     const sci_tv_params &q = t0;
+    if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), stream)) != SCI_OK) return st;
     launch_weights(d.nx, d.ny, d.B, C, 0.0f, Sinv, stream);
+    launch_pack_masks(d.nx, d.ny, d.B, C, cbits_ptr(ctx), cflag_ptr(ctx, d), stream);
     if (X_init) launch_copy(X_init, theta, vb, stream);
     else launch_adjoint(d.nx, d.ny, d.B, C, Y, theta, stream);
     if (p->outer_iters == 0) launch_copy(theta, X_out, vb, stream);
@@ -785,7 +801,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     int inner = 0, fallbacks = 0;
     const void *keep = nullptr;
     for (int t = 0; t < p->outer_iters; ++t) {
-        launch_gap_project(d.nx, d.ny, d.B, theta, C, Y, Sinv, X_out, stream);
+        launch_gap_project(d.nx, d.ny, d.B, theta, C, Y, Sinv, X_out, stream, cbits_ptr(ctx), cflag_ptr(ctx, d));
         if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
         const void *init = nullptr;
         // a correcting network (3 input channels) needs the previous call's final dual,

@@ -449,6 +449,26 @@ def test_warm_dual_schedules_agree(sc, ctx, solver, tv):
 
 
 @pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("kind", ["binary", "graded", "binary_b40"])
+def test_mask_kinds_match_oracle(sc, ctx, solver, kind):
+    """Binary masks (B <= 32) take the packed-bit projection, graded masks
+    (entries in (0, 1]) and more than 32 frames the float path; all match the
+    oracle."""
+    B = 40 if kind == "binary_b40" else 6
+    pr = synth.make_problem(70, 66, B, seed=21, sigma=0.01)
+    C = pr.masks
+    if kind == "graded":
+        C = (C * np.random.default_rng(22).uniform(0.2, 1.0, size=C.shape)).astype(np.float32)
+    Y = orc.measurement(C, pr.truth, pr.noise)
+    tv = "atv" if B > 32 else "vtv"
+    x, th = run_solver(sc, ctx, solver, Y, C, outer_iters=6, rho=0.05, tv=tv, lam=0.1, n_inner=5)
+    xr, thr = oracle_solver(solver, Y, C, 0.1, 0.05, 6, 5, tv)
+    e = rel_l2(x, xr)
+    say(f"{solver} {kind} masks B={B}: rel-L2 {e:.2e}")
+    assert e <= REL_TOL and rel_l2(th, thr) <= REL_TOL
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
 def test_graph_replay_matches_eager(sc, ctx, solver):
     pr = synth.make_problem(96, 80, 8, seed=12, sigma=0.01)
     Y = orc.measurement(pr.masks, pr.truth, pr.noise)
