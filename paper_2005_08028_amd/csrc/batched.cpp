@@ -106,7 +106,7 @@ void plan_batch(const sci_ctx *ctx, int n, const sci_problem *probs, const sci_s
         b.C = q.C;
         b.x = q.X_out;
         b.theta = q.Theta_out;
-        pl.slab_floats += ((size_t)npix + 63) & ~(size_t)63;
+        pl.slab_floats += 2 * (((size_t)npix + 63) & ~(size_t)63) + 64; // Sinv, mask bits, flag
         if (!q.Theta_out) pl.slab_floats += ((size_t)npix * q.d.B + 63) & ~(size_t)63;
         pl.maxB = std::max(pl.maxB, b.B);
         pl.Tmax = std::max(pl.Tmax, b.outer_iters);
@@ -120,6 +120,10 @@ void bind_slab(float *slab, BatchPlan &pl)
         const size_t npix = (size_t)b.nx * b.ny;
         b.Sinv = slab + off;
         off += (npix + 63) & ~(size_t)63;
+        b.cbits = (uint32_t *)(slab + off);
+        off += (npix + 63) & ~(size_t)63;
+        b.cflag = (int *)(slab + off);
+        off += 64;
         if (!b.theta) {
             b.theta = slab + off;
             off += (npix * b.B + 63) & ~(size_t)63;

@@ -30,7 +30,16 @@ __device__ inline int find_problem(int n, int w, F base)
     return lo;
 }
 
-// theta^(0) = Phi^T y and Sinv = 1 / sum_k C_k^2 (0 where the sum is 0).
+// Per problem: mask flag = 1 when it can be packed (B <= 32); cleared by the
+// setup kernel on any entry that is neither 0 nor 1.
+__global__ void k_batch_flags(int n, const BatchProb *__restrict__ tab)
+{
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p < n) *tab[p].cflag = tab[p].B <= 32 ? 1 : 0;
+}
+
+// theta^(0) = Phi^T y, Sinv = 1 / sum_k C_k^2 (0 where the sum is 0) and the
+// masks packed one bit per frame.
 __global__ __launch_bounds__(kPixBlock) void k_batch_setup(int n, const BatchProb *__restrict__ tab)
 {
     const int p = find_problem(n, (int)blockIdx.x, [&](int q) { return tab[q].pb_base; });
@@ -40,14 +49,20 @@ __global__ __launch_bounds__(kPixBlock) void k_batch_setup(int n, const BatchPro
     if (pix >= npix) return;
     const float y = b.Y[pix];
     float s = 0.0f;
+    uint32_t bits = 0u;
+    bool ok = true;
     for (int k = 0; k < b.B; ++k) {
         const uint32_t o = (uint32_t)k * npix + pix;
         const float c = b.C[o];
         s = fmaf(c, c, s);
         b.theta[o] = c * y;
+        if (c == 1.0f) bits |= (k < 32 ? 1u << k : 0u);
+        else if (c != 0.0f) ok = false;
     }
     s = s + 0.0f;
     b.Sinv[pix] = s > 0.0f ? 1.0f / s : 0.0f;
+    b.cbits[pix] = bits;
+    if (!ok) atomicAnd(b.cflag, 0);
 }
 
 // x = theta + C .* ((Y - sum_k C_k theta_k) .* Sinv), frames in registers.
@@ -60,13 +75,15 @@ __global__ __launch_bounds__(kPixBlock) void k_batch_project(int n, const BatchP
     const uint32_t pix = ((uint32_t)blockIdx.x - (uint32_t)b.pb_base) * kPixBlock + threadIdx.x;
     if (pix >= npix) return;
     const int B = b.B;
+    const bool packed = *b.cflag != 0; // binary masks: one word of frame bits instead of B floats
+    const uint32_t m = packed ? b.cbits[pix] : 0u;
     float v[KB], c[KB];
     float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         if (k < B) {
             const uint32_t o = (uint32_t)k * npix + pix;
-            c[k] = b.C[o];
+            c[k] = packed ? ((m >> k) & 1u ? 1.0f : 0.0f) : b.C[o];
             v[k] = b.theta[o];
             acc = fmaf(c[k], v[k], acc);
         }
@@ -146,6 +163,7 @@ void batch_tile_extent(int shape, int m, int *tile_w, int *tile_h)
 
 void launch_batch_setup(int n, int nblocks, const BatchProb *tab, hipStream_t s)
 {
+    hipLaunchKernelGGL(k_batch_flags, dim3((n + 255) / 256), dim3(256), 0, s, n, tab);
     hipLaunchKernelGGL(k_batch_setup, dim3(nblocks), dim3(kPixBlock), 0, s, n, tab);
     hipLaunchKernelGGL(k_batch_copy_theta, dim3(nblocks), dim3(kPixBlock), 0, s, n, tab);
 }

@@ -16,11 +16,14 @@ struct BatchProb {
     int pb_base;     // first 256-pixel block of this problem in setup / projection launches
     const float *Y, *C;
     float *Sinv, *x, *theta;
+    uint32_t *cbits; // masks packed one bit per frame (valid when *cflag != 0)
+    int *cflag;      // 1: every mask entry is 0 or 1 and B <= 32
 };
 
 // Interior extent of a tile of `shape` for pass length m.
 void batch_tile_extent(int shape, int m, int *tile_w, int *tile_h);
-// theta^(0) = Phi^T y and Sinv for the first n problems (x = theta^(0) where outer_iters == 0).
+// theta^(0) = Phi^T y, Sinv and the packed masks for the first n problems
+// (x = theta^(0) where outer_iters == 0).
 void launch_batch_setup(int n, int nblocks, const BatchProb *tab, hipStream_t s);
 // GAP projection of the first n problems.
 int launch_batch_project(int n, int nblocks, int maxB, const BatchProb *tab, hipStream_t s);
