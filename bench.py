@@ -490,6 +490,13 @@ def main() -> int:
                    "nx": nx, "ny": ny, "B": B, "outer_iters": T, "inner_iters": N, "tv": cfg["tv"],
                    "schedule": args.schedule, "dual_dtype": args.dual_dtype, "graph": False, "tiling": tag},
         "roofline": roofline,
+        # the one-pass byte model of an inner iteration (read x, p, p_prev; write p: 28 B per voxel with
+        # float32 duals): the rate a schedule with one HBM pass per iteration could reach at 8 TB/s, and
+        # this run's whole-solve rate against it (above 1 means the temporal blocking beats the model)
+        "one_pass_hbm_model": {"bytes_per_voxel_iter": 28 if args.dual_dtype == "f32" else 16,
+                               "voxel_iter_per_s_at_8TBs": 8e12 / (28 if args.dual_dtype == "f32" else 16),
+                               "value_over_model": V * T * N * steps / elapsed /
+                               (8e12 / (28 if args.dual_dtype == "f32" else 16))},
         "kernel_ms_per_step": {f: round(ms / steps, 3) for f, (n, ms) in fams.items()},
         "psnr_db": round(psnr, 4), "residual_sq": resid, "autotune": tuned,
     }

@@ -9,8 +9,9 @@
 // input channel and the last layer's two output channels. Every convolution
 // is an implicit GEMM on v_mfma_f32_16x16x16bf16_1k: a wavefront produces
 // 16 voxels x 16 output channels, accumulating 27 MFMAs (one per tap, K = 16
-// input channels) in FP32. Zero padding of the volume ("same" convolution)
-// is a zero A operand for neighbours outside the volume.
+// input channels) in FP32. Blocks of the volume are staged in LDS with a
+// zero-filled one-voxel halo, which is the zero padding of the "same"
+// convolution.
 //
 // MFMA operand layout (checked on the hardware): lane l holds A row l%16 and
 // B column l%16, with K elements 4*(l/16) .. 4*(l/16)+3; the result holds
@@ -40,60 +41,80 @@ struct Geom {
     uint32_t V;
 };
 
-// Linear index of the neighbour of voxel v at tap t (sign = +1 forward,
-// -1 for the transposed convolution), or -1 outside the volume.
-__device__ inline int64_t neighbour(const Geom &g, uint32_t v, int t, int sign)
-{
-    const int j = (int)(v % (uint32_t)g.ny);
-    const uint32_t r = v / (uint32_t)g.ny;
-    const int i = (int)(r % (uint32_t)g.nx);
-    const int k = (int)(r / (uint32_t)g.nx);
-    const int dk = t / 9 - 1, di = (t / 3) % 3 - 1, dj = t % 3 - 1;
-    const int kk = k + sign * dk, ii = i + sign * di, jj = j + sign * dj;
-    if (kk < 0 || kk >= g.B || ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) return -1;
-    return ((int64_t)kk * g.nx + ii) * g.ny + jj;
-}
-
-constexpr int kConvWaves = 4;
-
 // out[v][n] = sum_t sum_c Wk[t][n][c] in[nb(v, t)][c] (+ bias[n]); optional
 // ReLU; optional mask by (gate[v][n] > 0) (ReLU derivative); output bf16
-// [V][16] or, for the last layer, fp32 [V][16].
+// [V][16] or, for the last layer, fp32 [V][16]. Computed over LDS tiles: a
+// workgroup owns an output block of
+// kTK frames x kTI rows x kTJ columns; it stages the block plus a one-voxel
+// halo (all 16 channels, bf16, zero outside the volume) in LDS once, and its
+// four wavefronts then run 16-voxel x 16-channel MFMA tiles along j, the A
+// operand of each of the 27 taps read from LDS (8 bytes per lane) and the B
+// operand (the weights of the tap) held in registers for the whole block.
+// Two tiles are accumulated side by side to cover the MFMA latency.
+constexpr int kTK = 4, kTI = 8, kTJ = 32;
+constexpr int kHK = kTK + 2, kHI = kTI + 2, kHJ = kTJ + 2;
+constexpr int kVoxStride = 20; // shorts per staged voxel (16 channels + 4 of padding against bank conflicts)
+
 template <bool RELU, bool OUT_F32>
-__global__ __launch_bounds__(64 * kConvWaves) void k_conv(Geom g, const uint16_t *__restrict__ in,
-                                                          const uint16_t *__restrict__ Wk,
-                                                          const float *__restrict__ bias, int sign,
-                                                          const uint16_t *__restrict__ gate,
-                                                          uint16_t *__restrict__ out16, float *__restrict__ out32)
+__global__ __launch_bounds__(256) void k_conv_tile(Geom g, int ntj, int nti, const uint16_t *__restrict__ in,
+                                                   const uint16_t *__restrict__ Wk, const float *__restrict__ bias,
+                                                   const uint16_t *__restrict__ gate, uint16_t *__restrict__ out16,
+                                                   float *__restrict__ out32)
 {
-    const int lane = threadIdx.x & 63;
-    const uint32_t tile = blockIdx.x * kConvWaves + (threadIdx.x >> 6);
-    const uint32_t v0 = tile * 16u;
-    if (v0 >= g.V) return; // uniform per wavefront
+    __shared__ uint16_t xs[kHK * kHI * kHJ * kVoxStride];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
-    const uint32_t va = v0 + (uint32_t)row; // voxel of this lane's A row
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = 0; t < 27; ++t) {
-        bf16x4 a = {0, 0, 0, 0};
-        if (va < g.V) {
-            const int64_t u = neighbour(g, va, t, sign);
-            if (u >= 0) a = *(const bf16x4 *)(in + (size_t)u * 16 + kq * 4);
-        }
-        const bf16x4 b = *(const bf16x4 *)(Wk + ((size_t)t * 16 + row) * 16 + kq * 4);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    const int bj = (int)blockIdx.x % ntj, bi = ((int)blockIdx.x / ntj) % nti, bk = (int)blockIdx.x / (ntj * nti);
+    const int k0 = bk * kTK, i0 = bi * kTI, j0 = bj * kTJ;
+
+    // stage the block and its halo: 8-byte chunks (4 channels), zero outside
+    for (int e = threadIdx.x; e < kHK * kHI * kHJ * 4; e += 256) {
+        const int q = e & 3, vox = e >> 2;
+        const int jj = vox % kHJ, ii = (vox / kHJ) % kHI, kk = vox / (kHJ * kHI);
+        const int k = k0 + kk - 1, i = i0 + ii - 1, j = j0 + jj - 1;
+        bf16x4 v = {0, 0, 0, 0};
+        if (k >= 0 && k < g.B && i >= 0 && i < g.nx && j >= 0 && j < g.ny)
+            v = *(const bf16x4 *)(in + ((((size_t)k * g.nx + i) * g.ny + j) * 16 + q * 4));
+        *(bf16x4 *)(xs + vox * kVoxStride + q * 4) = v;
     }
-    // result: column n = row (lane & 15), voxels v0 + 4*kq + e
-    const int n = row;
-    const float bn = bias ? bias[n] : 0.0f;
+    // weights of every tap: B[k = input channel 4 kq + e][n = row]
+    bf16x4 wb[27];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const uint32_t v = v0 + 4u * kq + e;
-        if (v >= g.V) continue;
-        float y = acc[e] + bn;
-        if (RELU) y = fmaxf(y, 0.0f);
-        if (gate && !(from_bf16(gate[(size_t)v * 16 + n]) > 0.0f)) y = 0.0f;
-        if (OUT_F32) out32[(size_t)v * 16 + n] = y;
-        else out16[(size_t)v * 16 + n] = to_bf16(y);
+    for (int t = 0; t < 27; ++t) wb[t] = *(const bf16x4 *)(Wk + ((size_t)t * 16 + row) * 16 + kq * 4);
+    const float bn = bias ? bias[row] : 0.0f;
+    __syncthreads();
+
+    // output rows (kl, il) of the block: wavefront wv takes every fourth one;
+    // each row holds kTJ / 16 = 2 MFMA tiles
+    for (int rr = wv; rr < kTK * kTI; rr += 4) {
+        const int kl = rr / kTI, il = rr % kTI;
+        if (k0 + kl >= g.B || i0 + il >= g.nx) continue; // uniform per wavefront
+        f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dk = t / 9, di = (t / 3) % 3, dj = t % 3; // offsets into the haloed block
+            const int base = ((kl + dk) * kHI + (il + di)) * kHJ + dj + row;
+            const bf16x4 a0 = *(const bf16x4 *)(xs + base * kVoxStride + kq * 4);
+            const bf16x4 a1 = *(const bf16x4 *)(xs + (base + 16) * kVoxStride + kq * 4);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, wb[t], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, wb[t], acc1, 0, 0, 0);
+        }
+        // result of tile h: column n = row, voxels j = j0 + 16 h + 4 kq + e
+        const size_t vrow = ((size_t)(k0 + kl) * g.nx + (i0 + il)) * g.ny;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = j0 + 16 * h + 4 * kq + e;
+                if (j >= g.ny) continue;
+                const size_t v = vrow + j;
+                float y = (h == 0 ? acc0[e] : acc1[e]) + bn;
+                if (RELU) y = fmaxf(y, 0.0f);
+                if (gate && !(from_bf16(gate[v * 16 + row]) > 0.0f)) y = 0.0f;
+                if (OUT_F32) out32[v * 16 + row] = y;
+                else out16[v * 16 + row] = to_bf16(y);
+            }
+        }
     }
 }
 
@@ -160,56 +181,79 @@ __global__ __launch_bounds__(256) void k_sum_part(int n, const double *__restric
     if (threadIdx.x == 0) out[0] = lds[0];
 }
 
-// Weight gradient: dW[t][n][c] = sum_v dy[v][n] in[nb(v, t)][c] and
-// dbias[n] = sum_v dy[v][n], as MFMAs with the voxels as K. Each workgroup
-// covers a fixed strided set of 16-voxel chunks and writes its partial sums
-// (28 x 16 x 16 floats, slot 27 = bias in column 0) for a fixed-order second
-// pass. Wavefront w of the group handles taps w, w+4, ...
-constexpr int kWgradGroups = 512;
-__global__ __launch_bounds__(256) void k_wgrad(Geom g, const uint16_t *__restrict__ dy,
-                                               const uint16_t *__restrict__ in, float *__restrict__ part)
+// Weight gradient dW[t][n][c] = sum_v dy[v][n] in[nb(v, t)][c] and
+// dbias[n] = sum_v dy[v][n], as MFMAs with the voxels as K, over LDS blocks
+// (the block shape of the convolution).
+// A workgroup walks a fixed strided set of blocks; per block it stages the
+// input with its halo and dy channel-major ([channel][voxel], bf16) so that
+// the MFMA operands, whose K dimension runs over voxels, are runs of voxels
+// of one channel. Wavefront w accumulates slots w, w+4, ... (27 taps and the
+// bias) over 16-voxel chunks along j:
+//   A[n][v'] = dy[v0 + v'][n]   (8-byte LDS read per lane)
+//   B[v'][c] = in[nb(v0 + v', t)][c]   (four 2-byte LDS reads: a tap shifts
+//   the run by dj, which breaks the 8-byte alignment)
+// and writes its partial sums for the fixed-order reduction.
+constexpr int kWgBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_wgrad_tile(Geom g, int ntj, int nti, int nblocks,
+                                                    const uint16_t *__restrict__ dy, const uint16_t *__restrict__ in,
+                                                    float *__restrict__ part)
 {
+    constexpr int NH = kHK * kHI * kHJ, NB = kTK * kTI * kTJ;
+    __shared__ uint16_t xT[16][NH];
+    __shared__ uint16_t dT[16][NB];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
-    constexpr int kTapsPerWave = 7; // 28 slots over 4 wavefronts
-    f32x4 acc[kTapsPerWave];
+    constexpr int kSlotsPerWave = 7; // 28 slots over 4 wavefronts
+    f32x4 acc[kSlotsPerWave];
 #pragma unroll
-    for (int q = 0; q < kTapsPerWave; ++q) acc[q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    const uint32_t nchunk = (g.V + 15u) / 16u;
-    for (uint32_t ch = blockIdx.x; ch < nchunk; ch += kWgradGroups) {
-        // A[n][v'] = dy[v0 + v'][n]: lane holds n = row, v' = 4 kq + e
-        bf16x4 a;
-        uint32_t vv[4];
+    for (int q = 0; q < kSlotsPerWave; ++q) acc[q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int blk = (int)blockIdx.x; blk < nblocks; blk += (int)gridDim.x) {
+        const int bj = blk % ntj, bi = (blk / ntj) % nti, bk = blk / (ntj * nti);
+        const int k0 = bk * kTK, i0 = bi * kTI, j0 = bj * kTJ;
+        __syncthreads(); // the previous block's operands have been read
+        for (int e = threadIdx.x; e < NH; e += 256) {
+            const int jj = e % kHJ, ii = (e / kHJ) % kHI, kk = e / (kHJ * kHI);
+            const int k = k0 + kk - 1, i = i0 + ii - 1, j = j0 + jj - 1;
+            const bool ok = k >= 0 && k < g.B && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+            const uint16_t *src = in + (ok ? (((size_t)k * g.nx + i) * g.ny + j) * 16 : 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            vv[e] = ch * 16u + 4u * kq + e;
-            a[e] = vv[e] < g.V ? (short)dy[(size_t)vv[e] * 16 + row] : (short)0;
+            for (int c = 0; c < 16; ++c) xT[c][e] = ok ? src[c] : (uint16_t)0;
         }
+        for (int e = threadIdx.x; e < NB; e += 256) {
+            const int jl = e % kTJ, il = (e / kTJ) % kTI, kl = e / (kTJ * kTI);
+            const int k = k0 + kl, i = i0 + il, j = j0 + jl;
+            const bool ok = k < g.B && i < g.nx && j < g.ny; // voxels outside the volume add nothing
+            const uint16_t *src = dy + (ok ? (((size_t)k * g.nx + i) * g.ny + j) * 16 : 0);
 #pragma unroll
-        for (int q = 0; q < kTapsPerWave; ++q) {
-            const int t = wv + 4 * q; // 0..27
-            // B[v'][c] = in[nb(v0 + v', t)][c] (slot 27: 1 in column 0 for the bias)
-            bf16x4 b;
+            for (int n = 0; n < 16; ++n) dT[n][e] = ok ? src[n] : (uint16_t)0;
+        }
+        __syncthreads();
+        for (int ch = 0; ch < NB / 16; ++ch) {
+            const int kl = ch / (kTI * kTJ / 16), il = (ch / (kTJ / 16)) % kTI, jc = (ch % (kTJ / 16)) * 16;
+            const int vb = (kl * kTI + il) * kTJ + jc; // first voxel of the chunk in the block
+            const bf16x4 a = *(const bf16x4 *)(&dT[row][vb + 4 * kq]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                short val = 0;
-                if (vv[e] < g.V) {
-                    if (t == 27) {
-                        val = row == 0 ? (short)0x3f80 : (short)0; // bf16 1.0
-                    } else {
-                        const int64_t u = neighbour(g, vv[e], t, 1);
-                        if (u >= 0) val = (short)in[(size_t)u * 16 + row];
-                    }
+            for (int q = 0; q < kSlotsPerWave; ++q) {
+                const int t = wv + 4 * q; // 0..27
+                bf16x4 b;
+                if (t == 27) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) b[e] = row == 0 ? (short)0x3f80 : (short)0; // bias: 1 in column 0
+                } else {
+                    const int dk = t / 9, di = (t / 3) % 3, dj = t % 3; // offsets into the haloed block
+                    const int hb = ((kl + dk) * kHI + (il + di)) * kHJ + jc + dj + 4 * kq;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) b[e] = (short)xT[row][hb + e];
                 }
-                b[e] = val;
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
             }
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
         }
     }
     // acc[q]: column c = row, rows n = 4 kq + e
     float *p = part + (size_t)blockIdx.x * 28 * 256;
 #pragma unroll
-    for (int q = 0; q < kTapsPerWave; ++q) {
+    for (int q = 0; q < kSlotsPerWave; ++q) {
         const int t = wv + 4 * q;
 #pragma unroll
         for (int e = 0; e < 4; ++e) p[(size_t)t * 256 + (4 * kq + e) * 16 + row] = acc[q][e];
@@ -312,16 +356,15 @@ void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, c
                 const uint16_t *gate, uint16_t *out16, float *out32, hipStream_t s)
 {
     const Geom g = geom(nx, ny, B);
-    const uint32_t tiles = (g.V + 15) / 16;
-    const dim3 grid((tiles + kConvWaves - 1) / kConvWaves), block(64 * kConvWaves);
-    const int sign = 1;
-    if (out32) hipLaunchKernelGGL((k_conv<false, true>), grid, block, 0, s, g, in, Wk, bias, sign, gate, out16, out32);
-    else if (relu) hipLaunchKernelGGL((k_conv<true, false>), grid, block, 0, s, g, in, Wk, bias, sign, gate, out16, out32);
-    else hipLaunchKernelGGL((k_conv<false, false>), grid, block, 0, s, g, in, Wk, bias, sign, gate, out16, out32);
+    const int ntj = (ny + kTJ - 1) / kTJ, nti = (nx + kTI - 1) / kTI, ntk = (B + kTK - 1) / kTK;
+    const dim3 grid(ntj * nti * ntk), block(256);
+    if (out32) hipLaunchKernelGGL((k_conv_tile<false, true>), grid, block, 0, s, g, ntj, nti, in, Wk, bias, gate, out16, out32);
+    else if (relu) hipLaunchKernelGGL((k_conv_tile<true, false>), grid, block, 0, s, g, ntj, nti, in, Wk, bias, gate, out16, out32);
+    else hipLaunchKernelGGL((k_conv_tile<false, false>), grid, block, 0, s, g, ntj, nti, in, Wk, bias, gate, out16, out32);
 }
 
 int wsnet_reduce_blocks() { return kRedBlocks; }
-int wsnet_wgrad_groups() { return kWgradGroups; }
+int wsnet_wgrad_groups() { return kWgBlocks; }
 
 void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *base, const float *target, uint16_t *dy,
                 double *part, double *out, hipStream_t s)
@@ -335,8 +378,11 @@ void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, 
                  hipStream_t s)
 {
     const Geom g = geom(nx, ny, B);
-    hipLaunchKernelGGL(k_wgrad, dim3(kWgradGroups), dim3(256), 0, s, g, dy, in, part);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28), dim3(256), 0, s, kWgradGroups, (const float *)part, grad);
+    const int ntj = (ny + kTJ - 1) / kTJ, nti = (nx + kTI - 1) / kTI, ntk = (B + kTK - 1) / kTK;
+    const int nblocks = ntj * nti * ntk;
+    const int groups = nblocks < kWgBlocks ? nblocks : kWgBlocks;
+    hipLaunchKernelGGL(k_wgrad_tile, dim3(groups), dim3(256), 0, s, g, ntj, nti, nblocks, dy, in, part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28), dim3(256), 0, s, groups, (const float *)part, grad);
 }
 
 void wsnet_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1, float c2, const float *grad,
