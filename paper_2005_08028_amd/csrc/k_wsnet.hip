@@ -53,7 +53,7 @@ struct Geom {
 // Two tiles are accumulated side by side to cover the MFMA latency.
 constexpr int kTK = 4, kTI = 8, kTJ = 32;
 constexpr int kHK = kTK + 2, kHI = kTI + 2, kHJ = kTJ + 2;
-constexpr int kVoxStride = 20; // shorts per staged voxel (16 channels + 4 of padding against bank conflicts)
+constexpr int kVoxStride = 18; // shorts per staged voxel (16 channels + 2 of padding: 36-byte stride, no bank conflicts)
 
 template <bool RELU, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv_tile(Geom g, int ntj, int nti, const uint16_t *__restrict__ in,
