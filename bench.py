@@ -403,6 +403,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations of the oracle sample")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and 16-bit side measurements")
+    ap.add_argument("--kernel-table-only", action="store_true",
+                    help="only time every step of the path on the 1024x1024x24 measurement and print that table "
+                         "(a short run to profile all kernels; not the benchmark line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 1 GiB device copies (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -439,6 +442,12 @@ def main() -> int:
     Th_out = torch.empty_like(C)
     prm = scitv.solver_params(outer_iters=T, tv=cfg["tv"], lam=lam, n_inner=N, schedule=args.schedule,
                               dual_dtype=args.dual_dtype)
+
+    if args.kernel_table_only:
+        table = measure_kernels(scitv, h, dev, C, Y, X_true)
+        ctx.close()
+        print(json.dumps({"kernel_table_1024x1024x24": table}), flush=True)
+        return 0
 
     tuned = None
     tag = "shape1/passes%d" % ((N + 4) // 5)

@@ -30,17 +30,6 @@
 
 namespace sci {
 
-// Workgroups are handed to the 8 XCDs of the chip round-robin by linear id;
-// renumber them so that XCD c gets one contiguous run of tiles (raster order
-// within a frame), and tiles that share halos share that XCD's L2.
-__device__ inline int xcd_contiguous(int wg, int nwg)
-{
-    constexpr int kXcd = 8;
-    const int q = nwg / kXcd, r = nwg % kXcd;
-    const int c = wg % kXcd, idx = wg / kXcd;
-    return c < r ? c * (q + 1) + idx : r * (q + 1) + (c - r) * q + idx;
-}
-
 // One tile of one frame: (tx, ty) tile coordinates, frame offset fo (in
 // elements), V = elements per dual channel of the whole video.
 template <int TV, int M, int DT, int R, int NW, int C>

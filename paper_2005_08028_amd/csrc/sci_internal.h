@@ -124,6 +124,8 @@ void launch_zero(void *dst, size_t bytes, hipStream_t s);
 // ---- launchers (k_fgp.hip) ----------------------------------------------------
 // One FGP iteration over HBM: p_next = P(w + D(x - lambda D^T w) / (8 lambda)),
 // w = 0 (mode 0), w = p_cur (mode 1), w = p_cur + beta (p_cur - p_prev) (mode 2).
+// VTV only (ATV and ITV2D stream through the tile kernel); other kinds
+// return SCI_ERR_UNSUPPORTED.
 int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                       const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
 // The same iteration with Chambolle's (2004) semi-implicit step in place of

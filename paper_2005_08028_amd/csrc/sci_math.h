@@ -1,6 +1,6 @@
-// Per-voxel arithmetic of the TV denoiser, shared by every HIP kernel of the
-// library so that the streaming and the fused schedules evaluate identical
-// expressions (the build disables floating-point contraction; every fused
+// Per-voxel arithmetic of the TV denoiser (and the workgroup numbering),
+// shared by every HIP kernel of the library so that the streaming and the
+// fused schedules evaluate identical expressions (the build disables floating-point contraction; every fused
 // multiply-add below is explicit).
 //
 // Notation follows Algorithm 1 (FGP box) of the paper: w is the extrapolated
@@ -22,6 +22,7 @@ template <int DT> struct Dual;
 
 template <> struct Dual<DT_F32> {
     using T = float;
+    __device__ static inline float cvt(T v) { return v; }
     __device__ static inline float ld(const T *p, uint32_t i) { return p[i]; }
     __device__ static inline void st(T *p, uint32_t i, float v) { p[i] = v; }
 };
@@ -29,7 +30,8 @@ template <> struct Dual<DT_F32> {
 // bfloat16: upper half of a float32; stores round to nearest even.
 template <> struct Dual<DT_BF16> {
     using T = uint16_t;
-    __device__ static inline float ld(const T *p, uint32_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
+    __device__ static inline float cvt(T v) { return __uint_as_float((uint32_t)v << 16); }
+    __device__ static inline float ld(const T *p, uint32_t i) { return cvt(p[i]); }
     __device__ static inline void st(T *p, uint32_t i, float v)
     {
         uint32_t u = __float_as_uint(v);
@@ -42,7 +44,8 @@ template <> struct Dual<DT_BF16> {
 // IEEE binary16: hardware conversion (round to nearest even).
 template <> struct Dual<DT_F16> {
     using T = _Float16;
-    __device__ static inline float ld(const T *p, uint32_t i) { return (float)p[i]; }
+    __device__ static inline float cvt(T v) { return (float)v; }
+    __device__ static inline float ld(const T *p, uint32_t i) { return cvt(p[i]); }
     __device__ static inline void st(T *p, uint32_t i, float v) { p[i] = (_Float16)v; }
 };
 
@@ -81,5 +84,19 @@ __device__ inline float semi_implicit_scale(float n2) { return 1.0f / (1.0f + __
 
 // Squared-norm accumulation (h^2 + v^2 added to acc).
 __device__ inline float norm2_add(float acc, float h, float v) { return fmaf(v, v, fmaf(h, h, acc)); }
+
+// ---- work mapping -----------------------------------------------------------
+
+// Workgroups are handed to the 8 XCDs of the chip round-robin by linear id;
+// renumber them so that XCD c gets one contiguous run of tiles (raster order
+// within a frame), and tiles that share halos or cache lines share that
+// XCD's L2.
+__device__ inline int xcd_contiguous(int wg, int nwg)
+{
+    constexpr int kXcd = 8;
+    const int q = nwg / kXcd, r = nwg % kXcd;
+    const int c = wg % kXcd, idx = wg / kXcd;
+    return c < r ? c * (q + 1) + idx : r * (q + 1) + (c - r) * q + idx;
+}
 
 } // namespace sci

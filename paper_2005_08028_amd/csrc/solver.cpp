@@ -128,7 +128,7 @@ int fgp_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const f
         int st = launch(p.tv, p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, r.prev ? r.prev : r.cur, out, mode,
                         (float)r.beta_prev, p.lambda, s);
         if (st != SCI_OK) return fail(ctx, st, "FGP pass not available for this request");
-        st = check_launch(ctx, "k_fgp_stream");
+        st = check_launch(ctx, p.chambolle04 ? "Chambolle-2004 pass" : "k_fgp_groups");
         if (st != SCI_OK) return st;
         const double b = r.mom.step();
         r.beta_prev = p.accel ? b : 0.0;
