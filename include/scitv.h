@@ -336,7 +336,9 @@ int sci_residual_sq(sci_ctx *ctx, sci_dims d, const float *C, const float *X, co
 /* Duality gap of the denoising problem at the dual p (dual-shaped, storage
  * type dual_dtype): gap = lambda (TV(theta) - <D theta, p>) and primal
  * P(theta) = 1/2 ||theta - x||^2 + lambda TV(theta) with
- * theta = x - lambda D^T p, all in FP64. Either host output may be NULL. */
+ * theta = x - lambda D^T p, all in FP64, summed in a fixed order
+ * (repeated calls return identical values). Either host output may be
+ * NULL. VTV with B > 32: SCI_ERR_UNSUPPORTED (as for the VTV denoiser). */
 int sci_dual_gap(sci_ctx *ctx, sci_dims d, int32_t tv, int32_t dual_dtype, float lambda, const float *X,
                  const void *p, double *gap_host, double *primal_host, hipStream_t stream);
 

@@ -34,17 +34,6 @@ namespace {
 constexpr int kStrip = 62; // result columns per wavefront
 constexpr int kMaxWaves = 8;  // frame groups (wavefronts) per workgroup, at most
 
-// Workgroup barrier over LDS only: waits for this wavefront's LDS accesses
-// (lgkmcnt), not for its global loads and stores; the signal fences keep the
-// compiler from moving memory accesses across it.
-__device__ __forceinline__ void lds_barrier()
-{
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
 // Streaming pass with the frames of a pixel split over the wavefronts of a
 // workgroup (ng = blockDim.x / 64 of them, at most kMaxWaves): all
 // wavefronts walk the same 62-column strip and row segment, wavefront g

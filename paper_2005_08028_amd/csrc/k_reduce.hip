@@ -1,12 +1,14 @@
 // FP64 reductions on the GPU: squared differences (PSNR), the measurement
 // residual ||Y - Phi X||^2, and the terms of the denoiser's duality gap.
 //
-// Deterministic two-stage scheme: a fixed grid of kRedBlocks workgroups,
-// each thread accumulates a grid-stride slice in double, the workgroup folds
-// its 256 values by a fixed LDS tree into one partial; a single workgroup
-// then folds the partials in the same fixed order. No floating-point
-// atomics, so repeated calls return bit-identical results.
+// Deterministic two-stage scheme: a fixed grid of workgroups, each thread
+// accumulates a fixed slice in double, the workgroup folds its values in a
+// fixed order into one partial; a single workgroup then folds the partials
+// in the same fixed order. No floating-point atomics, so repeated calls
+// return bit-identical results.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "sci_internal.h"
 #include "sci_math.h"
@@ -63,94 +65,261 @@ __global__ __launch_bounds__(kRedThreads) void k_resid_part(int nx, int ny, int 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Gap terms of voxel o = (k, i, j): adds |D theta| (ATV, ITV2D) or
-// |D theta|^2 (VTV, to s2), <D theta, p> and (theta - x)^2, all in double,
-// with theta = x - lambda D^T p at (i, j), (i, j+1) and (i+1, j). Every load
-// is issued unconditionally from an in-bounds address (o itself stands in
-// for a missing neighbour) and masked afterwards, so a voxel's loads are in
-// flight together instead of one branch at a time.
-template <int TV, int DT>
-__device__ __forceinline__ void gap_voxel(int nx, int ny, uint32_t V, const float *x, const typename Dual<DT>::T *p,
-                                          double lam, uint32_t o, int i, int j, double &tv, double &inner,
-                                          double &fid, double &s2)
+// ---- duality-gap terms ----------------------------------------------------
+//
+// Partials [3][nwg]: TV(theta), <D theta, p>, ||theta - x||^2 with
+// theta = x - lambda D^T p, all in FP64. Mapping as in the streaming FGP
+// pass: a wavefront owns a strip of 64 columns (62 accumulate, lanes 0 and
+// 63 are halo) and walks down a row segment; theta of each voxel is formed
+// once, its j+1 neighbour comes from the next lane (DPP), its i+1 neighbour
+// from the next row step. The frames of a pixel are split over the
+// wavefronts of a workgroup; for VTV their partial sums of |D theta|^2 meet
+// in LDS once per row (fixed order) before the square root. Loads come in
+// double-buffered 2-row chunks from clamped in-bounds addresses, masked
+// where consumed. Every sum runs in a fixed order, so repeated calls return
+// bit-identical results.
+constexpr int kGapStrip = 62;
+constexpr int kGapMaxWaves = 8;
+constexpr int kGapChunk = 2;
+constexpr int kGapMinRows = 8;
+
+// The value held by lane l+1 (0 in lane 63), for a double.
+__device__ inline double from_right_d(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x130, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wavefront by a fixed butterfly; every lane
+// ends with the same value.
+__device__ inline double wave_sum(double v)
+{
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <int DT> struct GapRow {
+    float x;
+    typename Dual<DT>::T ph, pv;
+};
+
+template <int TV, int KF, int R, int DT>
+__global__ __launch_bounds__(64 * kGapMaxWaves) void k_gap_rows(int nx, int ny, int B, int fpw, int rows,
+                                                                 int nstrips, double lam,
+                                                                 const float *__restrict__ x,
+                                                                 const typename Dual<DT>::T *__restrict__ p,
+                                                                 double *__restrict__ part)
 {
     using D = Dual<DT>;
-    const bool l = j >= 1, u = i >= 1, r = j + 1 < ny, dn = i + 1 < nx;
-    const bool ru = r && u, dl = dn && l, r2 = j + 2 < ny, d2 = i + 2 < nx;
-    const uint32_t oR = r ? o + 1 : o, oD = dn ? o + ny : o;
-    // p_h at (i,j-1), (i,j), (i,j+1), (i+1,j-1), (i+1,j); p_v at (i-1,j), (i,j), (i-1,j+1), (i,j+1), (i+1,j)
-    const float h_l = D::ld(p, l ? o - 1 : o), h_c = D::ld(p, o), h_r = D::ld(p, oR);
-    const float h_dl = D::ld(p, dl ? oD - 1 : o), h_d = D::ld(p, oD);
-    const float v_u = D::ld(p, V + (u ? o - ny : o)), v_c = D::ld(p, V + o);
-    const float v_ur = D::ld(p, V + (ru ? oR - ny : o)), v_r = D::ld(p, V + oR), v_d = D::ld(p, V + oD);
-    const float x_c = x[o], x_r = x[oR], x_d = x[oD];
-    // theta = x - lambda ((p_h(j-1) - p_h(j)) + (p_v(i-1) - p_v(i))), terms without a difference are 0
-    auto theta = [&](float xv, bool hl, float a, bool hc, float b, bool vu, float c, bool vc, float d) {
-        double s = 0.0;
-        s += hl ? (double)a : 0.0;
-        s -= hc ? (double)b : 0.0;
-        s += vu ? (double)c : 0.0;
-        s -= vc ? (double)d : 0.0;
-        return (double)xv - lam * s;
-    };
-    const double th = theta(x_c, l, h_l, r, h_c, u, v_u, dn, v_c);
-    const double gh = r ? theta(x_r, true, h_c, r2, h_r, u, v_ur, dn, v_r) - th : 0.0;
-    const double gv = dn ? theta(x_d, l, h_dl, r, h_d, true, v_c, d2, v_d) - th : 0.0;
-    const double ph = r ? (double)h_c : 0.0;
-    const double pv = dn ? (double)v_c : 0.0;
-    inner += gh * ph + gv * pv;
-    const double dx = th - (double)x_c;
-    fid += dx * dx;
-    if (TV == TV_ATV) tv += fabs(gh) + fabs(gv);
-    else if (TV == TV_ITV2D) tv += sqrt(gh * gh + gv * gv);
-    else s2 += gh * gh + gv * gv;
-}
-
-// Partials [3][kRedBlocks]: TV(theta), <D theta, p>, ||theta - x||^2. A
-// workgroup covers kRedThreads consecutive columns (blockIdx.x) and every
-// gridDim.y-th row (blockIdx.y); each thread walks its column through those
-// rows and, per row, through all frames (VTV needs the per-pixel norm over
-// them), four frames in flight. No integer division per voxel; neighbours
-// come through the caches.
-template <int TV, int DT>
-__global__ __launch_bounds__(kRedThreads) void k_gap_part(int nx, int ny, int B, double lam,
-                                                          const float *__restrict__ x,
-                                                          const typename Dual<DT>::T *__restrict__ p,
-                                                          double *__restrict__ part)
-{
-    __shared__ double lds[kRedThreads];
+    __shared__ double s2s[2][kGapMaxWaves][64];
+    __shared__ double red[3][kGapMaxWaves];
+    const int ng = (int)(blockDim.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;
+    const int t = xcd_contiguous((int)(blockIdx.x + blockIdx.y * gridDim.x), (int)(gridDim.x * gridDim.y));
+    const int fgrp = t / (int)gridDim.x, tile = t % (int)gridDim.x;
+    const int strip = tile % nstrips;
+    const int i0 = (tile / nstrips) * rows;
+    const int i1 = min(nx, i0 + rows);
+    const int j = strip * kGapStrip - 1 + lane;
+    const bool jin = j >= 0 && j < ny;
+    const bool hin = j >= 0 && j < ny - 1; // p_h(i, j) exists; also "j + 1 < ny" for the j-difference
+    const bool outl = lane >= 1 && lane <= kGapStrip && j < ny;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t V = plane * (uint32_t)B;
-    const int j = (int)blockIdx.x * kRedThreads + (int)threadIdx.x;
-    double tv = 0.0, inner = 0.0, fid = 0.0;
-    if (j < ny) {
-        for (int i = (int)blockIdx.y; i < nx; i += (int)gridDim.y) {
-            const uint32_t pix = (uint32_t)i * ny + (uint32_t)j;
-            double s2 = 0.0;
-#pragma unroll 4
-            for (int k = 0; k < B; ++k)
-                gap_voxel<TV, DT>(nx, ny, V, x, p, lam, (uint32_t)k * plane + pix, i, j, tv, inner, fid, s2);
-            if (TV == TV_VTV) tv += sqrt(s2);
+    const int kbase = (fgrp * ng + g) * fpw; // fgrp = 0 for VTV
+    const int nk = max(0, min(fpw, B - kbase));
+    uint32_t fo[KF];
+#pragma unroll
+    for (int kk = 0; kk < KF; ++kk)
+        fo[kk] = (uint32_t)min(kbase + kk, B - 1) * plane + (jin ? (uint32_t)j : 0u);
+
+    auto issue = [&](GapRow<DT> &l, int kk, int i) {
+        const uint32_t o = fo[kk] + (uint32_t)i * (uint32_t)ny;
+        l.x = x[o];
+        l.ph = p[o];
+        l.pv = p[V + o];
+    };
+    // theta of a row from its x, its masked p_h, p_v and the masked p_v of
+    // the row above; the terms are added in the order
+    // ((p_h(j-1) - p_h(j)) + p_v(i-1)) - p_v(i)
+    auto theta = [&](float xv, float ph, float pv_up, float pv) -> double {
+        double s = (double)from_left(ph);
+        s -= (double)ph;
+        s += (double)pv_up;
+        s -= (double)pv;
+        return (double)xv - lam * s;
+    };
+
+    double th0[KF];
+    float ph0[KF], pv0[KF], x0[KF];
+    {
+        GapRow<DT> up[KF], cur[KF];
+#pragma unroll
+        for (int kk = 0; kk < KF; ++kk) {
+            issue(up[kk], kk, max(i0 - 1, 0));
+            issue(cur[kk], kk, i0);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KF; ++kk) {
+            const float pvu = jin && i0 >= 1 ? D::cvt(up[kk].pv) : 0.0f;
+            ph0[kk] = hin ? D::cvt(cur[kk].ph) : 0.0f;
+            pv0[kk] = jin && i0 < nx - 1 ? D::cvt(cur[kk].pv) : 0.0f;
+            x0[kk] = cur[kk].x;
+            th0[kk] = theta(x0[kk], ph0[kk], pvu, pv0[kk]);
         }
     }
-    const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
-    const int nb = (int)(gridDim.x * gridDim.y);
-    double r = block_sum(tv, lds);
-    if (threadIdx.x == 0) part[b] = r;
-    r = block_sum(inner, lds);
-    if (threadIdx.x == 0) part[nb + b] = r;
-    r = block_sum(fid, lds);
-    if (threadIdx.x == 0) part[2 * nb + b] = r;
+
+    double tv = 0.0, inner = 0.0, fid = 0.0;
+    int par = 0;
+    const int ilast = min(i1, nx - 1);
+    auto issue_chunk = [&](GapRow<DT>(&nb)[R][KF], int ic) {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) issue(nb[rr][kk], kk, min(ic + rr + 1, ilast));
+    };
+    // rows ic .. ic+R-1, using the loaded rows ic+1 .. ic+R
+    auto run_chunk = [&](const GapRow<DT>(&nb)[R][KF], int ic) {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int i = ic + rr;
+            const bool has_next = i + 1 < nx;
+            const bool mh = hin && has_next, mv = jin && i + 1 < nx - 1;
+            const bool acc = outl && i < i1;
+            double s2 = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) {
+                const GapRow<DT> &r1 = nb[rr][kk];
+                const float ph1 = mh ? D::cvt(r1.ph) : 0.0f;
+                const float pv1 = mv ? D::cvt(r1.pv) : 0.0f;
+                const double th1 = theta(r1.x, ph1, pv0[kk], pv1);
+                // the lane shift runs on every lane (a disabled source lane
+                // would read as 0); the mask selects afterwards
+                const double thr = from_right_d(th0[kk]);
+                const double gh = hin ? thr - th0[kk] : 0.0;
+                const double gv = has_next ? th1 - th0[kk] : 0.0;
+                if (acc && kk < nk) {
+                    inner += gh * (double)ph0[kk] + gv * (double)pv0[kk];
+                    const double dx = th0[kk] - (double)x0[kk];
+                    fid += dx * dx;
+                    if (TV == TV_ATV) tv += fabs(gh) + fabs(gv);
+                    else if (TV == TV_ITV2D) tv += sqrt(gh * gh + gv * gv);
+                    else s2 += gh * gh + gv * gv;
+                }
+                th0[kk] = th1;
+                ph0[kk] = ph1;
+                pv0[kk] = pv1;
+                x0[kk] = r1.x;
+            }
+            if (TV == TV_VTV) {
+                s2s[par][g][lane] = s2;
+                lds_barrier();
+                if (g == 0 && acc) {
+                    double tot = 0.0;
+                    for (int gg = 0; gg < ng; ++gg) tot += s2s[par][gg][lane];
+                    tv += sqrt(tot);
+                }
+                par ^= 1;
+            }
+        }
+    };
+    GapRow<DT> ba[R][KF], bb[R][KF];
+    issue_chunk(ba, i0);
+    for (int ic = i0; ic < i1; ic += 2 * R) {
+        issue_chunk(bb, ic + R);
+        run_chunk(ba, ic);
+        issue_chunk(ba, ic + 2 * R);
+        run_chunk(bb, ic + R);
+    }
+
+    // fixed-order workgroup sums: lanes by butterfly, wavefronts in order
+    tv = wave_sum(tv);
+    inner = wave_sum(inner);
+    fid = wave_sum(fid);
+    if (lane == 0) {
+        red[0][g] = tv;
+        red[1][g] = inner;
+        red[2][g] = fid;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int b = (int)(blockIdx.x + blockIdx.y * gridDim.x);
+        const int nb = (int)(gridDim.x * gridDim.y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double a = 0.0;
+            for (int gg = 0; gg < ng; ++gg) a += red[c][gg];
+            part[(size_t)c * nb + b] = a;
+        }
+    }
 }
 
-// Grid of k_gap_part: column blocks x row strides, about kRedBlocks workgroups.
-dim3 gap_grid(int nx, int ny)
+// Launch shape of k_gap_rows: frames per wavefront, wavefronts per
+// workgroup, frame groups (grid y), rows per segment, grid x. VTV keeps
+// all frames of a pixel in one workgroup (at most 8 x 4 frames); the
+// per-voxel TVs take one frame per wavefront.
+struct GapShape {
+    int fpw, ng, gy, rows, gx, nstrips;
+};
+
+GapShape gap_shape(int nx, int ny, int B, int tv)
 {
-    const int gx = (ny + kRedThreads - 1) / kRedThreads;
-    int gy = kRedBlocks / gx;
-    if (gy < 1) gy = 1;
-    if (gy > nx) gy = nx;
-    return dim3(gx, gy);
+    GapShape sh;
+    sh.nstrips = (ny + kGapStrip - 1) / kGapStrip;
+    if (tv == TV_VTV) {
+        sh.fpw = (B + kGapMaxWaves - 1) / kGapMaxWaves;
+        sh.ng = (B + sh.fpw - 1) / sh.fpw;
+        sh.gy = 1;
+    } else {
+        sh.fpw = 1;
+        sh.ng = std::min(B, kGapMaxWaves);
+        sh.gy = (B + sh.ng - 1) / sh.ng;
+    }
+    sh.rows = 64;
+    while (sh.rows > kGapMinRows && (long)sh.nstrips * sh.gy * ((nx + sh.rows - 1) / sh.rows) < 4096) sh.rows >>= 1;
+    sh.gx = sh.nstrips * ((nx + sh.rows - 1) / sh.rows);
+    return sh;
+}
+
+template <int TV, int KF, int DT>
+void launch_gap_rows(const GapShape &sh, int nx, int ny, int B, double lam, const float *x, const void *p,
+                     double *part, hipStream_t s)
+{
+    using T = typename Dual<DT>::T;
+    hipLaunchKernelGGL((k_gap_rows<TV, KF, kGapChunk, DT>), dim3(sh.gx, sh.gy), dim3(64 * sh.ng), 0, s, nx, ny, B,
+                       sh.fpw, sh.rows, sh.nstrips, lam, x, (const T *)p, part);
+}
+
+template <int TV, int DT>
+int launch_gap_kf(const GapShape &sh, int nx, int ny, int B, double lam, const float *x, const void *p,
+                  double *part, hipStream_t s)
+{
+    if constexpr (TV != TV_VTV) { // one frame per wavefront
+        launch_gap_rows<TV, 1, DT>(sh, nx, ny, B, lam, x, p, part, s);
+        return SCI_OK;
+    }
+    switch (sh.fpw) {
+    case 1: launch_gap_rows<TV, 1, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
+    case 2: launch_gap_rows<TV, 2, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
+    case 3: launch_gap_rows<TV, 3, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
+    case 4: launch_gap_rows<TV, 4, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
+    }
+    return SCI_ERR_UNSUPPORTED; // VTV with more than 32 frames
+}
+
+template <int TV>
+int launch_gap_dt(int dual_dtype, const GapShape &sh, int nx, int ny, int B, double lam, const float *x,
+                  const void *p, double *part, hipStream_t s)
+{
+    switch (dual_dtype) {
+    case DT_F32: return launch_gap_kf<TV, DT_F32>(sh, nx, ny, B, lam, x, p, part, s);
+    case DT_BF16: return launch_gap_kf<TV, DT_BF16>(sh, nx, ny, B, lam, x, p, part, s);
+    case DT_F16: return launch_gap_kf<TV, DT_F16>(sh, nx, ny, B, lam, x, p, part, s);
+    }
+    return SCI_ERR_INVALID_ARG;
 }
 
 // out[c] = sum of part[c * n .. + n) in a fixed order (one workgroup).
@@ -222,32 +391,14 @@ __global__ __launch_bounds__(kRedThreads) void k_max_final(const float *__restri
     if (threadIdx.x == 0) out[0] = (double)r;
 }
 
-template <int TV>
-void gap_tv_dt(int dual_dtype, int nx, int ny, int B, double lam, const float *x, const void *p, double *part,
-               hipStream_t s)
-{
-    const dim3 g = gap_grid(nx, ny), b(kRedThreads);
-    switch (dual_dtype) {
-    case DT_F32:
-        hipLaunchKernelGGL((k_gap_part<TV, DT_F32>), g, b, 0, s, nx, ny, B, lam, x, (const float *)p, part);
-        break;
-    case DT_BF16:
-        hipLaunchKernelGGL((k_gap_part<TV, DT_BF16>), g, b, 0, s, nx, ny, B, lam, x, (const uint16_t *)p, part);
-        break;
-    default:
-        hipLaunchKernelGGL((k_gap_part<TV, DT_F16>), g, b, 0, s, nx, ny, B, lam, x, (const _Float16 *)p, part);
-        break;
-    }
-}
-
 } // namespace
 
 int reduce_partial_blocks() { return kRedBlocks; }
 
-size_t gap_partial_doubles(int nx, int ny, int, int)
+size_t gap_partial_doubles(int nx, int ny, int B, int tv)
 {
-    const dim3 g = gap_grid(nx, ny);
-    return 3 * (size_t)g.x * g.y;
+    const GapShape sh = gap_shape(nx, ny, B, tv);
+    return 3 * (size_t)sh.gx * sh.gy;
 }
 
 void launch_sqdiff(int64_t n, const float *a, const float *b, double *partials, double *out_dev, hipStream_t s)
@@ -273,11 +424,13 @@ int launch_gap_terms(int tv, int dual_dtype, int nx, int ny, int B, float lam, c
                      double *partials, double *out_dev, hipStream_t s)
 {
     const double l = (double)lam;
-    if (tv == TV_ATV) gap_tv_dt<TV_ATV>(dual_dtype, nx, ny, B, l, x, p, partials, s);
-    else if (tv == TV_ITV2D) gap_tv_dt<TV_ITV2D>(dual_dtype, nx, ny, B, l, x, p, partials, s);
-    else gap_tv_dt<TV_VTV>(dual_dtype, nx, ny, B, l, x, p, partials, s);
-    const dim3 g = gap_grid(nx, ny);
-    hipLaunchKernelGGL(k_final_n, dim3(1), dim3(kRedThreads), 0, s, 3, (int)(g.x * g.y), (const double *)partials,
+    const GapShape sh = gap_shape(nx, ny, B, tv);
+    int st;
+    if (tv == TV_ATV) st = launch_gap_dt<TV_ATV>(dual_dtype, sh, nx, ny, B, l, x, p, partials, s);
+    else if (tv == TV_ITV2D) st = launch_gap_dt<TV_ITV2D>(dual_dtype, sh, nx, ny, B, l, x, p, partials, s);
+    else st = launch_gap_dt<TV_VTV>(dual_dtype, sh, nx, ny, B, l, x, p, partials, s);
+    if (st != SCI_OK) return st;
+    hipLaunchKernelGGL(k_final_n, dim3(1), dim3(kRedThreads), 0, s, 3, sh.gx * sh.gy, (const double *)partials,
                        out_dev);
     return SCI_OK;
 }

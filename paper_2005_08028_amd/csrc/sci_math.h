@@ -99,4 +99,15 @@ __device__ inline int xcd_contiguous(int wg, int nwg)
     return c < r ? c * (q + 1) + idx : r * (q + 1) + (c - r) * q + idx;
 }
 
+// Workgroup barrier over LDS only: waits for this wavefront's LDS accesses
+// (lgkmcnt), not for its global loads and stores; the signal fences keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 } // namespace sci

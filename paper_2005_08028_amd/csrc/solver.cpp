@@ -310,8 +310,9 @@ int rel_gap(sci_ctx *ctx, const sci_dims &d, int tv, int dual_dtype, float lam, 
         launch_zero(ctx->ws[WS_DUAL2].ptr, 2 * vol_elems(d) * dual_elem_bytes(dual_dtype), s);
         p = ctx->ws[WS_DUAL2].ptr;
     }
-    launch_gap_terms(tv, dual_dtype, d.nx, d.ny, d.B, lam, x, p, part, outd, s);
-    st = check_launch(ctx, "k_gap_part");
+    st = launch_gap_terms(tv, dual_dtype, d.nx, d.ny, d.B, lam, x, p, part, outd, s);
+    if (st != SCI_OK) return fail(ctx, st, "duality gap: VTV supports B <= 32 frames");
+    st = check_launch(ctx, "k_gap_rows");
     if (st != SCI_OK) return st;
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, outd, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return fail_hip(ctx, e, "hipMemcpyAsync");

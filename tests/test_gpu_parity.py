@@ -228,6 +228,57 @@ def test_dual_gap_matches_oracle(sc, ctx, tv):
     assert g0 == 0.0 and p0 == 0.0
 
 
+# frames split over wavefronts (1..4 per wavefront for VTV, frame groups
+# along the grid for the per-voxel TVs), several strips and row segments,
+# ragged edges, single-row and single-column images
+GAP_SHAPES = [(1, 9, 9), (8, 70, 130), (24, 33, 200), (10, 130, 64), (32, 20, 63), (3, 300, 17), (12, 17, 1),
+              (5, 1, 40)]
+
+
+@pytest.mark.parametrize("shape", GAP_SHAPES)
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_dual_gap_shapes(sc, ctx, tv, shape):
+    rng = np.random.default_rng(sum(shape))
+    x = rng.uniform(size=shape).astype(np.float32)
+    p = rng.uniform(-1.0, 1.0, size=(2,) + shape).astype(np.float32)
+    g_or, prim_or = orc.dual_gap(x, p, f32(0.1), tv)
+    g1 = sc.sci_dual_gap(ctx, dev(x), dev(p), tv, 0.1)
+    g2 = sc.sci_dual_gap(ctx, dev(x), dev(p), tv, 0.1)
+    assert g1 == g2  # fixed summation order
+    assert abs(g1[0] - g_or) <= 1e-9 * prim_or
+    assert abs(g1[1] - prim_or) <= 1e-10 * prim_or
+    # 16-bit storage: the oracle sees the stored (rounded) values
+    for dt in (torch.bfloat16, torch.float16):
+        pd = dev(p).to(dt)
+        g_or16, prim_or16 = orc.dual_gap(x, host(pd.float()), f32(0.1), tv)
+        g16, prim16 = sc.sci_dual_gap(ctx, dev(x), pd, tv, 0.1)
+        assert abs(g16 - g_or16) <= 1e-9 * prim_or16
+        assert abs(prim16 - prim_or16) <= 1e-10 * prim_or16
+
+
+def test_dual_gap_vtv_frame_limit(sc, ctx):
+    x = torch.zeros((33, 8, 8), device="cuda")
+    with pytest.raises(sc.SciError):
+        sc.sci_dual_gap(ctx, x, torch.zeros((2, 33, 8, 8), device="cuda"), "vtv", 0.1)
+
+
+@pytest.mark.parametrize("tv", ["itv2d", "vtv"])
+def test_dual_gap_full_size(sc, ctx, tv):
+    """The 1024x1024x24 measurement's back-projection and a dual after a few
+    FGP iterations, against the oracle's FP64 gap."""
+    pr = synth.problem_from_config("cacti_1024x24")
+    C = dev(pr.masks)
+    Y = sc.sci_forward(ctx, C, dev(pr.truth))
+    x = sc.sci_adjoint(ctx, C, Y)
+    dual = torch.empty((2,) + tuple(x.shape), device="cuda")
+    sc.sci_tv_denoise(ctx, x, sc.tv_params(tv=tv, lam=0.1, n_inner=5), dual_out=dual)
+    g_or, prim_or = orc.dual_gap(host(x), host(dual), f32(0.1), tv)
+    g, prim = sc.sci_dual_gap(ctx, x, dual, tv, 0.1)
+    say(f"{tv} 1024x1024x24: gap {g:.6e} (oracle {g_or:.6e}), primal {prim:.6e}")
+    assert abs(g - g_or) <= 1e-9 * prim_or
+    assert abs(prim - prim_or) <= 1e-10 * prim_or
+
+
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 def test_gap_controlled_denoise(sc, ctx, tv):
     x = np.random.default_rng(8).uniform(size=(4, 64, 64)).astype(np.float32)
