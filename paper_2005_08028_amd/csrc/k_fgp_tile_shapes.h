@@ -11,8 +11,9 @@
     X(4, 4, 16, 2, 4) /* 128 x 64,  1024 threads */                                                                 \
     X(5, 8, 8, 2, 2)  /* 128 x 64,  512 threads  */                                                                 \
     X(6, 7, 16, 2, 4) /* 128 x 112, 1024 threads */                                                                 \
-    X(7, 6, 16, 2, 4) /* 128 x 96,  1024 threads */
+    X(7, 6, 16, 2, 4) /* 128 x 96,  1024 threads */                                                                 \
+    X(8, 6, 12, 3, 3) /* 192 x 72,  768 threads  */
 
 namespace sci {
-constexpr int kTileShapes = 8;
+constexpr int kTileShapes = 9;
 }
