@@ -109,6 +109,25 @@ def test_denoise_matches_oracle(sc, ctx, tv, schedule, B, nx, ny):
         assert ep <= 1e-4
 
 
+# VTV splits a pixel's frames over up to 8 wavefronts: 3 and 4 frames per
+# wavefront, and splits whose last wavefront holds spare slots (17 = 6 x 3 - 1,
+# 29 = 8 x 4 - 3); several strips and row segments
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("B,nx,ny", [(17, 70, 33), (29, 9, 130), (32, 40, 70), (10, 100, 125)])
+def test_vtv_frame_groups(sc, ctx, B, nx, ny, dt):
+    r = np.random.default_rng(B * 11 + nx + ny)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    for n in (3, 6):
+        prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=n, schedule="stream", dual_dtype=dt)
+        th, _, its, _ = sc.sci_tv_denoise(ctx, dev(x), prm)
+        ref = orc.tv_denoise(x, f32(0.1), n, "vtv")
+        e = rel_l2(host(th), ref)
+        say(f"vtv frame groups B={B} {nx}x{ny} {dt} N={n}: rel-L2 {e:.2e}")
+        assert its == n
+        # 16-bit storage: the per-store rounding bound 4 lambda u per iteration
+        assert e <= (REL_TOL if dt == "f32" else 2e-2)
+
+
 FUSED_SHAPES = [(1, 1, 1), (2, 3, 2), (1, 5, 300), (3, 250, 130), (2, 118, 54), (2, 117, 53), (1, 240, 107)]
 
 
