@@ -242,14 +242,17 @@ def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, T_eval=20):
     res = {}
     prm = scitv.solver_params(outer_iters=T_eval, tv=tv, lam=lam, gap_tol=1e-4, n_inner_max=1000,
                               gap_check_every=5)
-    for name in ("cold", "warm_dual", "learned"):
-        prm.warm_dual = 1 if name == "warm_dual" else 0
-        kw = {"net": net} if name == "learned" else {}
+    # learned: every call starts from the prediction; learned_gap_checked: from the
+    # prediction or the warm dual, whichever has the smaller initial gap
+    for name in ("cold", "warm_dual", "learned", "learned_gap_checked"):
+        prm.warm_dual = 1 if name in ("warm_dual", "learned_gap_checked") else 0
+        kw = {"net": net} if name.startswith("learned") else {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, its, fb = scitv.sci_gap_tv_adaptive(h, Y, C, prm, **kw)
+        x, its, fb, ns = scitv.sci_gap_tv_adaptive(h, Y, C, prm, **kw)
         torch.cuda.synchronize()
-        res[name] = {"inner_iters": its, "fallbacks": fb, "ms": round((time.perf_counter() - t0) * 1e3, 1),
+        res[name] = {"inner_iters": its, "fallbacks": fb, "net_starts": ns,
+                     "ms": round((time.perf_counter() - t0) * 1e3, 1),
                      "psnr_db": round(scitv.sci_psnr(h, x, X_true), 4)}
     fixed = scitv.solver_params(outer_iters=T_eval, tv=tv, lam=lam, n_inner=10)
     x, _ = scitv.sci_gap_tv(h, Y, C, fixed)

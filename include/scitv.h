@@ -288,15 +288,18 @@ int sci_wsnet_train_step(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *
  * p->tv.n_inner_max per outer iteration), each call starting from: the
  * network's projected prediction (net non-null; a network with c_in = 3 gets
  * the previous outer iteration's final dual as P_base and is not used in the
- * first outer iteration, which has none; when the predicted start does not
+ * first outer iteration, which has none; with p->warm_dual = 1 as well, the
+ * call starts from whichever of the prediction and the previous final dual
+ * has the smaller relative duality gap; when a predicted start does not
  * reach the tolerance the call is repeated from a zero dual), else the
  * previous outer iteration's final dual (p->warm_dual = 1), else zero.
- * inner_iters_out / fallbacks_out (nullable, HOST): total inner iterations
- * (fallbacks included) and the number of cold-start fallbacks. float32 duals;
- * synchronises `stream` at every gap check. */
+ * inner_iters_out / fallbacks_out / net_starts_out (nullable, HOST): total
+ * inner iterations (fallbacks included), the number of cold-start
+ * fallbacks, and the number of calls that started from the prediction.
+ * float32 duals; synchronises `stream` at every gap check. */
 int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
                         float *X_out, float *Theta_out, const float *X_init, sci_wsnet *net, int32_t *inner_iters_out,
-                        int32_t *fallbacks_out, hipStream_t stream);
+                        int32_t *fallbacks_out, int32_t *net_starts_out, hipStream_t stream);
 
 /* ---- tile-shape autotuning of the fused schedule -------------------------- */
 

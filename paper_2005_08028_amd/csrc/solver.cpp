@@ -763,7 +763,7 @@ int sci_twist_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const flo
 
 int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
                         float *X_out, float *Theta_out, const float *X_init, sci_wsnet *net, int32_t *inner_iters_out,
-                        int32_t *fallbacks_out, hipStream_t stream)
+                        int32_t *fallbacks_out, int32_t *net_starts_out, hipStream_t stream)
 {
     if (!ctx) return SCI_ERR_INVALID_ARG;
     int st = check_dims(ctx, d);
@@ -799,7 +799,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     if ((st = check_launch(ctx, "adaptive setup")) != SCI_OK) return st;
     FgpRun r;
     bind_duals(ctx, r);
-    int inner = 0, fallbacks = 0;
+    int inner = 0, fallbacks = 0, net_starts = 0;
     const void *keep = nullptr;
     for (int t = 0; t < p->outer_iters; ++t) {
         launch_gap_project(d.nx, d.ny, d.B, theta, C, Y, Sinv, X_out, stream, cbits_ptr(ctx), cflag_ptr(ctx, d));
@@ -813,6 +813,20 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
                 SCI_OK)
                 return st;
             init = pred;
+            if (p->warm_dual && keep) {
+                // gap-checked start: the prediction or the previous final dual,
+                // whichever has the smaller relative duality gap on this input
+                double gp = 0.0, pp = 0.0, gk = 0.0, pk = 0.0;
+                if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_out, pred, &gp, &pp, stream)) != SCI_OK)
+                    return st;
+                if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_out, keep, &gk, &pk, stream)) != SCI_OK)
+                    return st;
+                const double rp = pp > 0.0 ? gp / pp : 0.0, rk = pk > 0.0 ? gk / pk : 0.0;
+                if (rk < rp) init = keep;
+                else ++net_starts;
+            } else {
+                ++net_starts;
+            }
         } else if (p->warm_dual) {
             init = keep;
         }
@@ -828,6 +842,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     }
     if (inner_iters_out) *inner_iters_out = inner;
     if (fallbacks_out) *fallbacks_out = fallbacks;
+    if (net_starts_out) *net_starts_out = net_starts;
     return SCI_OK;
 }
 

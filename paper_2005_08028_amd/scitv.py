@@ -92,7 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_wsnet_grads": (I, [V, V, D, V, V, V, P(ctypes.c_float), P(ctypes.c_double), V]),
         "sci_wsnet_train_step": (I, [V, V, D, V, V, V, ctypes.c_float, P(ctypes.c_double), V]),
         "sci_gap_tv_adaptive": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V, P(ctypes.c_int32),
-                                    P(ctypes.c_int32), V]),
+                                    P(ctypes.c_int32), P(ctypes.c_int32), V]),
         "sci_gap_tv_batched": (I, [V, ctypes.c_int32, P(sci_problem), P(sci_solver_params), V]),
         "sci_autotune_batched": (I, [V, ctypes.c_int32, P(sci_problem), P(sci_solver_params), P(ctypes.c_int32),
                                      P(ctypes.c_double), V]),
@@ -401,17 +401,18 @@ def sci_wsnet_train_step(ctx, net, X, target, lr, base=None, want_loss=True, str
 
 def sci_gap_tv_adaptive(ctx, Y, C, params: sci_solver_params, net=None, X_out=None, Theta_out=None, X_init=None,
                         stream=None):
-    """Gap-controlled GAP-TV; returns (X_out, total inner iterations, fallbacks)."""
+    """Gap-controlled GAP-TV; returns (X_out, total inner iterations, fallbacks,
+    calls started from the network's prediction)."""
     d = _dims(C)
     if X_out is None:
         X_out = torch.empty_like(C)
-    its, fb = ctypes.c_int32(0), ctypes.c_int32(0)
+    its, fb, ns = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     _check(ctx, lib.sci_gap_tv_adaptive(ctx, d, ctypes.byref(params), _dev(Y, shape=(d.nx, d.ny), name="Y"),
                                         _dev(C, name="C"), _dev(X_out, shape=C.shape, name="X_out"),
                                         _dev(Theta_out, shape=C.shape, name="Theta_out"),
                                         _dev(X_init, shape=C.shape, name="X_init"), net, ctypes.byref(its),
-                                        ctypes.byref(fb), _stream(stream)))
-    return X_out, its.value, fb.value
+                                        ctypes.byref(fb), ctypes.byref(ns), _stream(stream)))
+    return X_out, its.value, fb.value, ns.value
 
 
 class Context:

@@ -174,7 +174,7 @@ def test_adaptive_gap_cold_matches_converged_fixed(sc, ctx):
     pr = synth.make_problem(64, 80, 8, seed=5, sigma=0.01)
     Y = orc.measurement(pr.masks, pr.truth, pr.noise)
     prm = sc.solver_params(outer_iters=8, tv="itv2d", lam=0.1, gap_tol=1e-7, n_inner_max=3000, gap_check_every=5)
-    x, its, fb = sc.sci_gap_tv_adaptive(ctx, dev(Y), dev(pr.masks), prm)
+    x, its, fb, _ = sc.sci_gap_tv_adaptive(ctx, dev(Y), dev(pr.masks), prm)
     assert fb == 0 and its > 8 * 5
     ref, _ = orc.gap_tv(Y, pr.masks, float(np.float32(0.1)), 8, 2000, tv="itv2d")
     e = rel(host(x), ref)
@@ -205,23 +205,32 @@ def test_learned_warm_start_gains(sc, ctx, rnet):
         data += warmstart.warm_dual_triples(ctx, Y, C, tv, lam, outer, tol=1e-4, target_tol=1e-6)[1:]
     sc.sci_wsnet_set_params(ctx, rnet, warmstart.init_params(0, c_in=3, last_scale=0.0))
     pr, Y, C, prm = _held_out(sc, ctx, tv, lam, outer)
-    xc, cold, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    xc, cold, _, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
     prm.warm_dual = 1
-    xw, warm, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    xw, warm, _, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    # gap-checked start with the untrained correction: the prediction is the warm
+    # dual re-projected (equal up to rounding at |p| = 1), so either start gives
+    # the warm-dual iteration count
+    _, untrained_gc, _, ns0 = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
     prm.warm_dual = 0
-    _, untrained, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
+    _, untrained, _, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
     hist = warmstart.train(ctx, rnet, data, steps=1500, lr=3e-5, log_every=500)
     print("training loss", hist, flush=True)
-    xl, learned, fb = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
+    xl, learned, fb, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
+    prm.warm_dual = 1
+    xg, gchk, fbg, ns = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
     truth = dev(pr.truth)
     pc, pw, pl = (sc.sci_psnr(ctx, v, truth) for v in (xc, xw, xl))
     print(f"inner iterations to gap 1e-4 over {outer} outer: cold {cold}, warm dual {warm}, untrained net {untrained}, "
           f"trained net {learned} ({fb} fallbacks; {warm / learned:.2f}x vs warm dual); "
           f"PSNR cold {pc:.3f} warm {pw:.3f} learned {pl:.3f}", flush=True)
+    print(f"gap-checked starts: {gchk} inner iterations, {ns} of {outer - 1} calls from the prediction", flush=True)
     assert untrained == warm  # the zero-initialised correction is the warm-dual start
-    assert learned * 2 <= cold
-    assert fb == 0
+    assert untrained_gc == warm and 0 <= ns0 <= outer - 1
+    assert learned * 2 <= cold and gchk * 2 <= cold
+    assert fb == 0 and fbg == 0 and 0 <= ns <= outer - 1
     assert abs(pc - pl) < 0.05 and abs(pw - pl) < 0.05
+    assert abs(pw - sc.sci_psnr(ctx, xg, truth)) < 0.05
 
 
 def test_input_only_network_falls_back(sc, ctx, net):
@@ -239,8 +248,8 @@ def test_input_only_network_falls_back(sc, ctx, net):
     sc.sci_wsnet_set_params(ctx, net, warmstart.init_params(0, last_scale=0.0))
     hist = warmstart.train(ctx, net, pairs, steps=500, lr=1e-4, log_every=250)
     pr, Y, C, prm = _held_out(sc, ctx, tv, lam, outer)
-    xc, cold, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
-    xl, learned, fb = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=net)
+    xc, cold, _, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    xl, learned, fb, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=net)
     truth = dev(pr.truth)
     pc, pl = sc.sci_psnr(ctx, xc, truth), sc.sci_psnr(ctx, xl, truth)
     print(f"x-only network: loss {hist}; inner iterations cold {cold}, learned {learned} ({fb} fallbacks); "
