@@ -78,9 +78,10 @@ KERNEL_SOURCES = {
 
 
 def read_traffic(family: str, tag: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
-    when it is missing or was taken on another kernel source or tile choice."""
+    """HBM bytes per launch of the chosen tiling from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
+    size; one entry per tiling), or None when it is missing, has no entry for
+    this tiling, or was taken on another kernel source."""
     path = os.path.join(PROFILE_DIR, f"hbm_traffic_{family}_cacti_1024x24.txt")
     if not os.path.exists(path):
         return None
@@ -89,10 +90,10 @@ def read_traffic(family: str, tag: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != source_hash(KERNEL_SOURCES[family]) or kv.get("tiling", "") != tag:
+    if kv.get("kernel_source_sha256") != source_hash(KERNEL_SOURCES[family]):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[f"hbm_bytes_per_launch[{tag}]"])
     except (KeyError, ValueError):
         return None
 
