@@ -271,8 +271,20 @@ int sci_wsnet_get_params(sci_ctx *ctx, sci_wsnet *net, float *host, int64_t coun
 int sci_wsnet_forward(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *X, const float *P_base, float *Y_out,
                       int32_t tv, float *dual_out, hipStream_t stream);
 
-/* Loss 1/(c_out V) sum ((P_base +) y - target)^2 (target [c_out][B][nx][ny]
- * fp32) and its gradient for every parameter (HOST, padded layout), without
+/* Training loss of a network (default SCI_WSNET_LOSS_DUAL):
+ *   SCI_WSNET_LOSS_DUAL : 1/(c_out V) sum (r)^2 over the c_out channels,
+ *   SCI_WSNET_LOSS_THETA: 1/V sum (D^T r)^2 over the voxels (c_out = 2),
+ * with r = (P_base +) y - target and, for THETA, r held at 0 on the dual
+ * entries that carry no difference. The denoiser's primal theta = x -
+ * lambda D^T p and its duality gap depend on the dual only through D^T p
+ * (Sec. 2.3, FGP), and the optimal dual is not unique; THETA ignores the
+ * null-space components of D^T in which converged duals differ. Unknown
+ * kind, or THETA with c_out != 2: SCI_ERR_INVALID_ARG. */
+typedef enum { SCI_WSNET_LOSS_DUAL = 0, SCI_WSNET_LOSS_THETA = 1 } sci_wsnet_loss;
+int sci_wsnet_set_loss(sci_ctx *ctx, sci_wsnet *net, int32_t kind);
+
+/* The network's loss (sci_wsnet_set_loss) for target [c_out][B][nx][ny]
+ * fp32 and its gradient for every parameter (HOST, padded layout), without
  * an update. Synchronises `stream`. */
 int sci_wsnet_grads(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *X, const float *P_base, const float *target,
                     float *grad_host, double *loss_host, hipStream_t stream);

@@ -2,8 +2,9 @@
 
 Plain numpy, float64, written from the definitions: a "same" 3x3x3
 cross-correlation over (frame, row, column) as 27 shifted slices, ReLU, mean
-squared error, and the analytic backward pass (the transposed convolution is
-the convolution with the tap-mirrored kernel and the channel roles swapped).
+squared error or the theta-space loss mean((D^T r)^2), and the analytic
+backward pass (the transposed convolution is the convolution with the
+tap-mirrored kernel and the channel roles swapped).
 With ``rounding=True`` the values the GPU stores in bf16 (input, weights,
 hidden activations, loss gradient, hidden gradients) are rounded to bf16
 (round to nearest even) at the same points, so the GPU can be compared
@@ -103,18 +104,52 @@ def forward(x, params, c_out=2, rounding=True, base=None, c_in=1):
     raise AssertionError
 
 
-def loss_and_grads(x, target, params, c_out=2, rounding=True, base=None, c_in=1):
-    """MSE 1/(c_out V) sum ((base +) y - target)^2 and the gradient in the padded layout."""
+def dual_adjoint(r):
+    """D^T r for a dual r [2][B][nx][ny] (forward differences, no wrap; the
+    entries that carry no difference are ignored): per voxel
+    (r_h(j-1) - r_h(j)) + (r_v(i-1) - r_v(i)), missing neighbours 0."""
+    h = np.array(r[0], dtype=np.float64)
+    v = np.array(r[1], dtype=np.float64)
+    h[:, :, -1] = 0.0
+    v[:, -1, :] = 0.0
+    left = np.zeros_like(h)
+    left[:, :, 1:] = h[:, :, :-1]
+    up = np.zeros_like(v)
+    up[:, 1:, :] = v[:, :-1, :]
+    return (left - h) + (up - v)
+
+
+def difference(g):
+    """D g [2][B][nx][ny]: g(j+1) - g(j), g(i+1) - g(i), 0 where the
+    difference does not exist."""
+    g = np.asarray(g, dtype=np.float64)
+    out = np.zeros((2,) + g.shape)
+    out[0, :, :, :-1] = g[:, :, 1:] - g[:, :, :-1]
+    out[1, :, :-1, :] = g[:, 1:, :] - g[:, :-1, :]
+    return out
+
+
+def loss_and_grads(x, target, params, c_out=2, rounding=True, base=None, c_in=1, loss="dual"):
+    """loss="dual": MSE 1/(c_out V) sum ((base +) y - target)^2; loss="theta":
+    1/V sum (D^T r)^2 with r = (base +) y - target (c_out = 2). Returns the
+    loss and the gradient in the padded layout."""
     rd = bf16 if rounding else (lambda v: np.asarray(v, dtype=np.float64))
     layers = unpack(params, c_out, c_in)
     a, y = forward(x, params, c_out, rounding, base, c_in)
     t = np.asarray(target, dtype=np.float64)
-    n = t.size
     diff = y - t
     if c_in == 3 and base is not None:
         diff = diff + np.asarray(base, dtype=np.float64)
-    loss = float((diff ** 2).sum() / n)
-    dy = rd(2.0 * diff / n) if not rounding else bf16((2.0 * diff / n).astype(np.float32))
+    if loss == "theta":
+        g = dual_adjoint(diff)
+        n = g.size
+        value = float((g ** 2).sum() / n)
+        grad_r = 2.0 * difference(g) / n  # d/dr of sum (D^T r)^2 / n
+    else:
+        n = t.size
+        value = float((diff ** 2).sum() / n)
+        grad_r = 2.0 * diff / n
+    dy = rd(grad_r) if not rounding else bf16(grad_r.astype(np.float32))
     grads = []
     for l in range(LAYERS - 1, -1, -1):
         W, _ = layers[l]
@@ -131,7 +166,7 @@ def loss_and_grads(x, target, params, c_out=2, rounding=True, base=None, c_in=1)
             dx = conv3d_transposed(dy, rd(W))
             dy = rd(dx) * (ain > 0)
     grads.reverse()
-    return loss, pack(grads, c_out, c_in)
+    return value, pack(grads, c_out, c_in)
 
 
 def adam_step(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

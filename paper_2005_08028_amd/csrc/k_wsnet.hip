@@ -18,6 +18,8 @@
 // column l%16, rows 4*(l/16) .. 4*(l/16)+3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sci_internal.h"
 #include "sci_wsnet.h"
 
@@ -165,6 +167,79 @@ __global__ __launch_bounds__(256) void k_loss(uint32_t V, int cout, const float 
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+
+// theta-space loss (1/V) sum (D^T r)^2 with r = y + base - target on the two
+// dual channels, entries that carry no difference (j = ny-1 for h, i = nx-1
+// for v) held at 0 as D^T ignores them. The dual enters the denoiser's
+// primal and its duality gap only through D^T p, so this loss ignores the
+// components of the null space of D^T in which converged duals differ.
+// Step 1: g = D^T r (float32 [V]) and FP64 block partials of sum g^2. The
+// grid strides over columns (x), rows (y) and frames (z).
+__device__ inline float r_h(const float *y, const float *base, const float *target, uint32_t V, uint32_t v, bool ex)
+{
+    if (!ex) return 0.0f;
+    const float b = base ? base[v] : 0.0f;
+    return (y[(size_t)v * 16] + b) - target[v];
+}
+__device__ inline float r_v(const float *y, const float *base, const float *target, uint32_t V, uint32_t v, bool ex)
+{
+    if (!ex) return 0.0f;
+    const float b = base ? base[V + v] : 0.0f;
+    return (y[(size_t)v * 16 + 1] + b) - target[V + v];
+}
+
+__global__ __launch_bounds__(256) void k_loss_theta_g(int nx, int ny, int B, const float *__restrict__ y,
+                                                      const float *__restrict__ base,
+                                                      const float *__restrict__ target, float *__restrict__ g,
+                                                      double *__restrict__ part)
+{
+    __shared__ double lds[256];
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t V = plane * (uint32_t)B;
+    double acc = 0.0;
+    for (int k = (int)blockIdx.z; k < B; k += (int)gridDim.z)
+        for (int i = (int)blockIdx.y; i < nx; i += (int)gridDim.y)
+            for (int j = (int)blockIdx.x * 256 + (int)threadIdx.x; j < ny; j += (int)gridDim.x * 256) {
+                const uint32_t v = (uint32_t)k * plane + (uint32_t)i * ny + (uint32_t)j;
+                // (r_h(j-1) - r_h(j)) + (r_v(i-1) - r_v(i)), missing neighbours 0
+                const float a = j >= 1 ? r_h(y, base, target, V, v - 1, true) : 0.0f;
+                const float b = r_h(y, base, target, V, v, j < ny - 1);
+                const float c = i >= 1 ? r_v(y, base, target, V, v - ny, true) : 0.0f;
+                const float d = r_v(y, base, target, V, v, i < nx - 1);
+                const float gv = (a - b) + (c - d);
+                g[v] = gv;
+                acc += (double)gv * (double)gv;
+            }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = lds[0];
+}
+
+// Step 2: d loss / d y = (2/V) D g on the two dual channels (0 where the
+// difference does not exist), as bf16 [V][16] with the other channels 0.
+__global__ __launch_bounds__(256) void k_loss_theta_dy(int nx, int ny, int B, const float *__restrict__ g,
+                                                       uint16_t *__restrict__ dy)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const float scale = (float)(2.0 / ((double)plane * (double)B));
+    for (int k = (int)blockIdx.z; k < B; k += (int)gridDim.z)
+        for (int i = (int)blockIdx.y; i < nx; i += (int)gridDim.y)
+            for (int j = (int)blockIdx.x * 256 + (int)threadIdx.x; j < ny; j += (int)gridDim.x * 256) {
+                const uint32_t v = (uint32_t)k * plane + (uint32_t)i * ny + (uint32_t)j;
+                const float gc = g[v];
+                const float dh = j < ny - 1 ? g[v + 1] - gc : 0.0f;
+                const float dv = i < nx - 1 ? g[v + ny] - gc : 0.0f;
+                uint16_t *o = dy + (size_t)v * 16;
+                o[0] = to_bf16(scale * dh);
+                o[1] = to_bf16(scale * dv);
+#pragma unroll
+                for (int c = 2; c < 16; ++c) o[c] = 0;
+            }
 }
 
 __global__ __launch_bounds__(256) void k_sum_part(int n, const double *__restrict__ part, double *__restrict__ out)
@@ -372,6 +447,27 @@ void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *ba
     const uint32_t V = (uint32_t)nx * ny * B;
     hipLaunchKernelGGL(k_loss, dim3(kRedBlocks), dim3(256), 0, s, V, cout, y, base, target, dy, part);
     hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(256), 0, s, kRedBlocks, (const double *)part, out);
+}
+
+// Grid of the theta-loss kernels: column blocks x row strides x frame
+// strides, at most kRedBlocks workgroups (the loss partials buffer).
+dim3 theta_loss_grid(int nx, int ny, int B)
+{
+    const int gx = std::min((ny + 255) / 256, 16);
+    const int gz = std::min(B, 8);
+    const int gy = std::max(1, std::min(nx, kRedBlocks / (gx * gz)));
+    return dim3(gx, gy, gz);
+}
+
+int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, const float *target, float *g,
+                     uint16_t *dy, double *part, double *out, hipStream_t s)
+{
+    const dim3 grid = theta_loss_grid(nx, ny, B);
+    const int nb = (int)(grid.x * grid.y * grid.z);
+    hipLaunchKernelGGL(k_loss_theta_g, grid, dim3(256), 0, s, nx, ny, B, y, base, target, g, part);
+    hipLaunchKernelGGL(k_loss_theta_dy, grid, dim3(256), 0, s, nx, ny, B, (const float *)g, dy);
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
+    return SCI_OK;
 }
 
 void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,

@@ -17,6 +17,11 @@ int wsnet_reduce_blocks();
 int wsnet_wgrad_groups();
 void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *base, const float *target, uint16_t *dy,
                 double *part, double *out, hipStream_t s);
+// theta-space loss (1/V) sum (D^T (y + base - target))^2 over the two dual
+// channels: g = D^T r into g [V], the bf16 gradient into dy, the sum of g^2
+// into out[0] (part: wsnet_reduce_blocks() doubles).
+int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, const float *target, float *g,
+                     uint16_t *dy, double *part, double *out, hipStream_t s);
 void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,
                  hipStream_t s);
 void wsnet_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1, float c2, const float *grad,

@@ -1,6 +1,7 @@
 // Host side of the warm-start network: parameters, activation scratch,
-// forward, gradients (all layers, MSE loss), Adam steps, and the projected
-// dual field handed to the FGP denoiser as its starting point.
+// forward, gradients (all layers; dual-space MSE or theta-space loss), Adam
+// steps, and the projected dual field handed to the FGP denoiser as its
+// starting point.
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
@@ -15,6 +16,7 @@ using namespace sci;
 struct sci_wsnet {
     int c_in = 1;  // 1: x only; 3: x and a base dual (the prediction is added to it)
     int c_out = 2;
+    int loss = SCI_WSNET_LOSS_DUAL;
     int device = 0;
     int64_t step = 0;
     // per layer: fp32 master params / Adam moments / gradient in [28][16][16]
@@ -27,6 +29,7 @@ struct sci_wsnet {
     uint16_t *act[kNetLayers] = {nullptr, nullptr, nullptr, nullptr}; // layer inputs a0..a3
     uint16_t *dA = nullptr, *dB = nullptr;                            // gradient ping-pong
     float *y = nullptr;                                               // last layer output [V][16]
+    float *gth = nullptr;                                             // theta-loss D^T r [V]
     float *wpart = nullptr;                                           // wgrad partials
     double *lpart = nullptr;                                          // loss partials (+ result)
 };
@@ -47,8 +50,10 @@ void free_acts(sci_wsnet *n)
     if (n->dA) (void)hipFree(n->dA);
     if (n->dB) (void)hipFree(n->dB);
     if (n->y) (void)hipFree(n->y);
+    if (n->gth) (void)hipFree(n->gth);
     n->dA = n->dB = nullptr;
     n->y = nullptr;
+    n->gth = nullptr;
     n->vcap = 0;
 }
 
@@ -62,7 +67,8 @@ int ensure_acts(sci_ctx *ctx, sci_wsnet *n, size_t V, hipStream_t s)
     for (auto &a : n->act)
         if ((e = hipMalloc(&a, ab)) != hipSuccess) return net_fail(ctx, e, "hipMalloc(activations)");
     if ((e = hipMalloc(&n->dA, ab)) != hipSuccess || (e = hipMalloc(&n->dB, ab)) != hipSuccess ||
-        (e = hipMalloc(&n->y, V * 16 * sizeof(float))) != hipSuccess)
+        (e = hipMalloc(&n->y, V * 16 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&n->gth, V * sizeof(float))) != hipSuccess)
         return net_fail(ctx, e, "hipMalloc(activations)");
     n->vcap = V;
     return SCI_OK;
@@ -98,8 +104,11 @@ void forward(sci_wsnet *n, const sci_dims &d, const float *X, const float *base,
 void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, const float *target, hipStream_t s)
 {
     const int nb = wsnet_reduce_blocks();
-    wsnet_loss(d.nx, d.ny, d.B, n->c_out, n->y, n->c_in == 3 ? base : nullptr, target, n->dA, n->lpart,
-               n->lpart + nb, s);
+    const float *b = n->c_in == 3 ? base : nullptr;
+    if (n->loss == SCI_WSNET_LOSS_THETA)
+        wsnet_loss_theta(d.nx, d.ny, d.B, n->y, b, target, n->gth, n->dA, n->lpart, n->lpart + nb, s);
+    else
+        wsnet_loss(d.nx, d.ny, d.B, n->c_out, n->y, b, target, n->dA, n->lpart, n->lpart + nb, s);
     uint16_t *dcur = n->dA, *dnext = n->dB;
     for (int l = kNetLayers - 1; l >= 0; --l) {
         wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], n->wpart, n->g + (size_t)l * kNetSlots, s);
@@ -111,6 +120,13 @@ void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, 
         }
     }
     (void)ctx;
+}
+
+// the summed loss divided by its normaliser: c_out V entries (dual MSE) or
+// V voxels (theta)
+double loss_value(const sci_wsnet *n, double sum, size_t V)
+{
+    return n->loss == SCI_WSNET_LOSS_THETA ? sum / (double)V : sum / ((double)n->c_out * (double)V);
 }
 
 void adam(sci_wsnet *n, float lr, hipStream_t s)
@@ -184,6 +200,17 @@ void sci_wsnet_destroy(sci_wsnet *n)
 
 int64_t sci_wsnet_param_count(void) { return (int64_t)kNetLayers * kNetSlots; }
 
+int sci_wsnet_set_loss(sci_ctx *ctx, sci_wsnet *n, int32_t kind)
+{
+    if (!ctx || !n) return SCI_ERR_INVALID_ARG;
+    if (kind != SCI_WSNET_LOSS_DUAL && kind != SCI_WSNET_LOSS_THETA)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "wsnet: unknown loss kind");
+    if (kind == SCI_WSNET_LOSS_THETA && n->c_out != 2)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "wsnet: the theta loss needs the two dual channels (c_out = 2)");
+    n->loss = kind;
+    return SCI_OK;
+}
+
 int sci_wsnet_set_params(sci_ctx *ctx, sci_wsnet *n, const float *host, int64_t count)
 {
     if (!ctx || !n || !host || count != sci_wsnet_param_count())
@@ -245,7 +272,7 @@ int sci_wsnet_grads(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X, cons
         double se = 0.0;
         if ((e = hipMemcpy(&se, n->lpart + wsnet_reduce_blocks(), sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
             return fail_hip(ctx, e, "hipMemcpy");
-        *loss_host = se / ((double)n->c_out * (double)V);
+        *loss_host = loss_value(n, se, V);
     }
     return SCI_OK;
 }
@@ -270,7 +297,7 @@ int sci_wsnet_train_step(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X,
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return fail_hip(ctx, e, "loss readback");
         se = ctx->host_scalars[0];
-        *loss_host = se / ((double)n->c_out * (double)V);
+        *loss_host = loss_value(n, se, V);
     }
     return SCI_OK;
 }

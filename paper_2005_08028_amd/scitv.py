@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_wsnet_create": (I, [V, ctypes.c_int32, ctypes.c_int32, P(V)]),
         "sci_wsnet_destroy": (None, [V]),
         "sci_wsnet_param_count": (ctypes.c_int64, []),
+        "sci_wsnet_set_loss": (I, [V, V, ctypes.c_int32]),
         "sci_wsnet_set_params": (I, [V, V, P(ctypes.c_float), ctypes.c_int64]),
         "sci_wsnet_get_params": (I, [V, V, P(ctypes.c_float), ctypes.c_int64]),
         "sci_wsnet_forward": (I, [V, V, D, V, V, V, ctypes.c_int32, V, V]),
@@ -350,6 +351,15 @@ def sci_wsnet_destroy(net) -> None:
 
 def sci_wsnet_param_count() -> int:
     return lib.sci_wsnet_param_count()
+
+
+WSNET_LOSS = {"dual": 0, "theta": 1}
+
+
+def sci_wsnet_set_loss(ctx, net, kind) -> None:
+    """Training loss of the network: "dual" (MSE over the dual channels) or
+    "theta" (mean of (D^T r)^2 over the voxels)."""
+    _check(ctx, lib.sci_wsnet_set_loss(ctx, net, WSNET_LOSS[kind] if isinstance(kind, str) else int(kind)))
 
 
 def sci_wsnet_set_params(ctx, net, params) -> None:

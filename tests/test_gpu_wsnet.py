@@ -126,6 +126,34 @@ def test_residual_gradients_match_oracle(sc, ctx, rnet):
         assert e <= 2e-2
 
 
+@pytest.mark.parametrize("B,nx,ny", [(3, 18, 40), (1, 1, 300), (9, 70, 5)])
+def test_theta_loss_gradients_match_oracle(sc, ctx, rnet, B, nx, ny):
+    """The theta-space loss mean((D^T r)^2): loss and every layer's gradient
+    against the FP64 oracle (single rows and columns, several frames); the
+    dual-space loss is restored afterwards."""
+    P = params(23, c_in=3)
+    sc.sci_wsnet_set_params(ctx, rnet, P)
+    sc.sci_wsnet_set_loss(ctx, rnet, "theta")
+    r = np.random.default_rng(B + nx + ny)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    base = r.uniform(-1, 1, size=(2, B, nx, ny)).astype(np.float32)
+    t = r.normal(scale=0.5, size=(2, B, nx, ny)).astype(np.float32)
+    loss, g = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
+    lo, go = wo.loss_and_grads(x, t, P, base=base, c_in=3, loss="theta")
+    print(f"theta loss {loss:.6e} (oracle {lo:.6e})", flush=True)
+    assert abs(loss - lo) <= 2e-3 * lo
+    G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
+    for l in range(4):
+        e = rel(G[l], GO[l])
+        print(f"theta-loss layer {l} gradient rel-L2 {e:.2e}", flush=True)
+        assert e <= 2e-2
+    sc.sci_wsnet_set_loss(ctx, rnet, "dual")
+    loss_d, _ = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
+    assert abs(loss_d - wo.loss_and_grads(x, t, P, base=base, c_in=3)[0]) <= 2e-3 * loss_d
+    with pytest.raises(sc.SciError):
+        sc.sci_wsnet_set_loss(ctx, rnet, 7)
+
+
 def test_gradients_match_oracle(sc, ctx, net):
     P = params(7)
     sc.sci_wsnet_set_params(ctx, net, P)
