@@ -29,6 +29,9 @@
  *     returns a status code; no C++ exception crosses this interface.
  *     Outputs must not overlap inputs (SCI_ERR_ALIAS).
  *   - Sizes: nx, ny, B >= 1, B <= 65535 and B*nx*ny < 2^31.
+ *   - Array values are expected finite; the library does not scan them, and
+ *     a NaN or infinity in an input spreads through the result (it may also
+ *     reach entries a finite input would leave at 0).
  *   - A context may be used from one host thread at a time. Calls that
  *     share a context and overlap on different streams race on its scratch.
  */
