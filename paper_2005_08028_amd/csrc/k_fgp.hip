@@ -41,10 +41,10 @@ constexpr int kMaxWaves = 8;  // frame groups (wavefronts) per workgroup, at mos
 // (KF >= fpw slots; a slot past the last frame reads frame B-1 and neither
 // stores nor enters the norm). VTV keeps all frames of a pixel in one
 // workgroup (fgrp = 0): per row each wavefront forms q for its frames and
-// the partial squared norm over them; the partials go through LDS
-// (double-buffered by row parity, one barrier per row) and are summed in
-// wavefront order, so every wavefront scales its frames by the same
-// per-pixel factor. The per-voxel TVs (ATV, ITV2D) take one frame per
+// the partial squared norm over them; the partials of a chunk's R rows go
+// through LDS together (double-buffered by chunk parity, one barrier per
+// chunk) and are summed in wavefront order, so every wavefront scales its
+// frames by the same per-pixel factor. The per-voxel TVs (ATV, ITV2D) take one frame per
 // wavefront, frame groups along blockIdx.y, and need no exchange and no
 // barrier.
 //
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
                                                                   float lam, float step)
 {
     using D = Dual<DT>;
-    __shared__ float n2s[2][kMaxWaves][64];
+    __shared__ float n2s[2][kMaxWaves][R][64];
     const int ng = (int)(blockDim.x >> 6);
     const int lane = threadIdx.x & 63;
     const int g = threadIdx.x >> 6;
@@ -154,8 +154,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
             for (int kk = 0; kk < KF; ++kk) issue(nb[rr][kk], kk, min(ic + rr + 1, ilast));
     };
     int par = 0;
-    // finish rows ic .. ic+R-1 from the loaded rows ic+1 .. ic+R
+    // finish rows ic .. ic+R-1 from the loaded rows ic+1 .. ic+R: q of all R
+    // rows first (row i+1's theta uses the old w only), then, for VTV, one
+    // exchange of the R rows' partial norms behind one barrier, then the
+    // projections and stores
     auto run_chunk = [&](const RawRow<DT>(&nb)[R][KF], int ic) {
+        float qh[R][KF], qv[R][KF];
+        float sh[R][KF], sv[R][KF]; // z/(8 lambda) where the difference exists (CH only)
+        float n2[R];
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int i = ic + rr;
@@ -164,9 +170,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
             // masks of row i+1 (past the last row every w is 0 there and z_v
             // of row i is multiplied by step_v = 0)
             const bool mh = hin && has_next, mv = jin && i + 1 < nx - 1;
-            float qh[KF], qv[KF];
-            float sh[KF], sv[KF]; // z/(8 lambda) where the difference exists (CH only)
-            float n2 = 0.0f;
+            n2[rr] = 0.0f;
 #pragma unroll
             for (int kk = 0; kk < KF; ++kk) {
                 const RawRow<DT> &r1 = nb[rr][kk];
@@ -176,51 +180,61 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
                 const float zh = from_right(th0[kk]) - th0[kk];
                 const float zv = th1 - th0[kk];
                 if (CH) {
-                    sh[kk] = step_h * zh;
-                    sv[kk] = step_v * zv;
-                    qh[kk] = wh0[kk] + sh[kk];
-                    qv[kk] = wv0[kk] + sv[kk];
-                    if (TV == TV_VTV && kk < nk) n2 = norm2_add(n2, sh[kk], sv[kk]);
+                    sh[rr][kk] = step_h * zh;
+                    sv[rr][kk] = step_v * zv;
+                    qh[rr][kk] = wh0[kk] + sh[rr][kk];
+                    qv[rr][kk] = wv0[kk] + sv[rr][kk];
+                    if (TV == TV_VTV && kk < nk) n2[rr] = norm2_add(n2[rr], sh[rr][kk], sv[rr][kk]);
                 } else {
-                    qh[kk] = ascend(wh0[kk], zh, step_h);
-                    qv[kk] = ascend(wv0[kk], zv, step_v);
-                    if (TV == TV_VTV && kk < nk) n2 = norm2_add(n2, qh[kk], qv[kk]);
+                    qh[rr][kk] = ascend(wh0[kk], zh, step_h);
+                    qv[rr][kk] = ascend(wv0[kk], zv, step_v);
+                    if (TV == TV_VTV && kk < nk) n2[rr] = norm2_add(n2[rr], qh[rr][kk], qv[rr][kk]);
                 }
                 wh0[kk] = wh1;
                 wv0[kk] = wv1;
                 th0[kk] = th1;
             }
-            float sc = 1.0f;
-            if (TV == TV_VTV) {
-                n2s[par][g][lane] = n2;
-                lds_barrier();
+        }
+        float sc[R];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) sc[rr] = 1.0f;
+        if (TV == TV_VTV) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) n2s[par][g][rr][lane] = n2[rr];
+            lds_barrier();
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
                 float tot = 0.0f;
-                for (int gg = 0; gg < ng; ++gg) tot += n2s[par][gg][lane];
-                sc = CH ? semi_implicit_scale(tot) : iso_scale(tot);
-                par ^= 1;
+                for (int gg = 0; gg < ng; ++gg) tot += n2s[par][gg][rr][lane];
+                sc[rr] = CH ? semi_implicit_scale(tot) : iso_scale(tot);
             }
+            par ^= 1;
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int i = ic + rr;
             if (i < i1 && outl) {
 #pragma unroll
                 for (int kk = 0; kk < KF; ++kk) {
                     if (kk < nk) {
                         float ph, pv;
                         if (TV == TV_VTV) {
-                            ph = qh[kk] * sc;
-                            pv = qv[kk] * sc;
+                            ph = qh[rr][kk] * sc[rr];
+                            pv = qv[rr][kk] * sc[rr];
                         } else if (CH && TV == TV_ATV) {
-                            ph = qh[kk] / (1.0f + fabsf(sh[kk]));
-                            pv = qv[kk] / (1.0f + fabsf(sv[kk]));
+                            ph = qh[rr][kk] / (1.0f + fabsf(sh[rr][kk]));
+                            pv = qv[rr][kk] / (1.0f + fabsf(sv[rr][kk]));
                         } else if (CH) {
-                            const float s1 = semi_implicit_scale(norm2_add(0.0f, sh[kk], sv[kk]));
-                            ph = qh[kk] * s1;
-                            pv = qv[kk] * s1;
+                            const float s1 = semi_implicit_scale(norm2_add(0.0f, sh[rr][kk], sv[rr][kk]));
+                            ph = qh[rr][kk] * s1;
+                            pv = qv[rr][kk] * s1;
                         } else if (TV == TV_ATV) {
-                            ph = proj_atv(qh[kk]);
-                            pv = proj_atv(qv[kk]);
+                            ph = proj_atv(qh[rr][kk]);
+                            pv = proj_atv(qv[rr][kk]);
                         } else {
-                            const float s1 = iso_scale(norm2_add(0.0f, qh[kk], qv[kk]));
-                            ph = qh[kk] * s1;
-                            pv = qv[kk] * s1;
+                            const float s1 = iso_scale(norm2_add(0.0f, qh[rr][kk], qv[rr][kk]));
+                            ph = qh[rr][kk] * s1;
+                            pv = qv[rr][kk] * s1;
                         }
                         const uint32_t o = fo[kk] + (uint32_t)i * (uint32_t)ny;
                         D::st(pn, o, ph);
