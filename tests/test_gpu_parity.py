@@ -556,6 +556,38 @@ def test_graph_replay_matches_eager(sc, ctx, solver):
         np.testing.assert_array_equal(host(tg), t0)
 
 
+def test_graph_replay_after_workspace_growth(sc, ctx):
+    """A cached graph holds workspace addresses: a larger solve in between
+    grows (frees and reallocates) the workspace, and the next graph call of
+    the small problem must still match the eager result. A context of its own
+    starts with an empty workspace, so the larger solve does grow it."""
+    own = sc.Context(0)
+    try:
+        _graph_after_growth(sc, own.handle, ctx)
+    finally:
+        own.close()
+
+
+def _graph_after_growth(sc, g, ctx):
+    small = synth.make_problem(96, 80, 8, seed=13, sigma=0.01)
+    big = synth.make_problem(256, 192, 12, seed=14, sigma=0.01)
+    Ys = orc.measurement(small.masks, small.truth, small.noise)
+    Yb = orc.measurement(big.masks, big.truth, big.noise)
+    kw = dict(outer_iters=4, tv="itv2d", lam=0.1, n_inner=5)
+    prm = sc.solver_params(use_graph=True, **kw)
+    Yd, Cd = dev(Ys), dev(small.masks)
+    xg = torch.empty(Cd.shape, device="cuda")
+    sc.sci_gap_tv(g, Yd, Cd, prm, X_out=xg)  # captured with the small workspace
+    first = host(xg)
+    xb, _ = sc.sci_gap_tv(g, dev(Yb), dev(big.masks), sc.solver_params(**kw))  # grows every slot it uses
+    xg.fill_(float("nan"))
+    sc.sci_gap_tv(g, Yd, Cd, prm, X_out=xg)
+    x0, _ = run_solver(sc, ctx, "gap", Ys, small.masks, **kw)
+    np.testing.assert_array_equal(first, x0)
+    np.testing.assert_array_equal(host(xg), x0)
+    assert np.isfinite(host(xb)).all()
+
+
 @pytest.mark.parametrize("solver", ["gap", "admm"])
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 def test_constant_frames_fixed_point(sc, ctx, solver, tv):
