@@ -73,7 +73,7 @@ def source_hash(files) -> str:
 
 KERNEL_SOURCES = {
     "fgp_stream": ("k_fgp.hip", "sci_math.h"),
-    "fgp_fused": ("k_fgp_tile.h", "k_fgp_tile_shapes.h", "sci_math.h"),
+    "fgp_fused": ("k_fgp_tile.h", "k_fgp_rows.h", "k_fgp_tile_shapes.h", "sci_math.h"),
 }
 
 

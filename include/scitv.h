@@ -318,13 +318,25 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
 
 /* ---- tile-shape autotuning of the fused schedule -------------------------- */
 
-/* Number of tile shapes of the fused denoiser kernel. */
+/* Number of shapes of the fused denoiser (tiled, then row-pipelined). */
 int sci_tile_shape_count(void);
 
-/* Shape k (1-based, as in sci_tv_params.tile_shape): a workgroup covers
- * 64 * cols_per_lane columns x (rows_per_wave * waves_per_group) rows of one
- * frame, halo included. Any output pointer may be NULL. */
+/* Shape k (1-based, as in sci_tv_params.tile_shape). Tiled shape: a
+ * workgroup covers 64 * cols_per_lane columns x (rows_per_wave *
+ * waves_per_group) rows of one frame, halo included, and keeps the whole tile
+ * on chip for a pass. Row-pipelined shape (sci_tile_shape_pipelined): one
+ * wavefront (waves_per_group = 1) walks a segment of rows_per_wave rows of a
+ * strip of 64 * cols_per_lane columns, halo columns included, from top to
+ * bottom, every iteration of the pass one row behind the previous one
+ * (temporal wavefront blocking; no rows are recomputed apart from the
+ * pipeline fill of about 2 n rows per segment). Row-pipelined shapes run
+ * float32 dual storage (16-bit storage runs the default shape) and are not
+ * used by the batched solve. Any output pointer may be NULL. */
 int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_per_group, int32_t *cols_per_lane);
+
+/* 1 if shape k (1-based) is row-pipelined, 0 if tiled, SCI_ERR_INVALID_ARG
+ * for a shape out of range. */
+int sci_tile_shape_pipelined(int32_t shape);
 
 /* Time the fused denoiser (p->tv, p->lambda, p->n_inner, p->dual_dtype) on
  * input X (video, device) for every tile shape and for 3 pass counts (the

@@ -1,5 +1,6 @@
 // Fused-schedule FGP passes with 16-bit dual storage (bf16, f16), default tile
-// shape, and the dispatcher over TV kind, storage type and tile shape.
+// shape, and the dispatcher over TV kind, storage type and shape (tiled or
+// row-pipelined).
 #include "k_fgp_tile.h"
 #include "k_fgp_tile_shapes.h"
 
@@ -9,10 +10,14 @@ int launch_tile_atv_f32(int shape, int m, int nx, int ny, int B, const float *x,
                         hipStream_t s);
 int launch_tile_itv_f32(int shape, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
                         hipStream_t s);
+int launch_rows_atv_f32(int H, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
+                        hipStream_t s);
+int launch_rows_itv_f32(int H, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
+                        hipStream_t s);
 
 bool tile_supported(int tv) { return tv == TV_ATV || tv == TV_ITV2D; }
 
-int tile_shape_count() { return kTileShapes; }
+int tile_shape_count() { return kTileShapes + kRowShapes; }
 
 bool tile_shape_info(int shape, int *rows, int *waves, int *cols)
 {
@@ -21,15 +26,27 @@ bool tile_shape_info(int shape, int *rows, int *waves, int *cols)
     case id: *rows = R; *waves = NW; *cols = C; return true;
         SCI_TILE_SHAPES(SCI_CASE)
 #undef SCI_CASE
+#define SCI_CASE(id, H)                                                                                             \
+    case id: *rows = H; *waves = 1; *cols = kRowCols; return true;
+        SCI_ROW_SHAPES(SCI_CASE)
+#undef SCI_CASE
     }
     return false;
 }
 
+bool tile_shape_pipelined(int shape) { return shape >= kTileShapes && shape < kTileShapes + kRowShapes; }
+
 int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,
                     const TilePass &tp, float lam, hipStream_t s)
 {
-    if (m < 1 || m > kTileMaxM || shape < 0 || shape >= kTileShapes) return SCI_ERR_INVALID_ARG;
+    if (m < 1 || m > kTileMaxM || shape < 0 || shape >= tile_shape_count()) return SCI_ERR_INVALID_ARG;
     if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;
+    if (dual_dtype == DT_F32 && tile_shape_pipelined(shape)) {
+        int H = 0, w = 0, c = 0;
+        tile_shape_info(shape, &H, &w, &c);
+        return tv == TV_ATV ? launch_rows_atv_f32(H, m, nx, ny, B, x, tp, lam, s)
+                            : launch_rows_itv_f32(H, m, nx, ny, B, x, tp, lam, s);
+    }
     if (dual_dtype == DT_F32)
         return tv == TV_ATV ? launch_tile_atv_f32(shape, m, nx, ny, B, x, tp, lam, s)
                             : launch_tile_itv_f32(shape, m, nx, ny, B, x, tp, lam, s);

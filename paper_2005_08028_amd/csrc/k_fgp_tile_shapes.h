@@ -14,6 +14,12 @@
     X(7, 6, 16, 2, 4) /* 128 x 96,  1024 threads */                                                                 \
     X(8, 6, 12, 3, 3) /* 192 x 72,  768 threads  */
 
+// Row-pipelined shapes (k_fgp_rows.h), numbered after the tiled ones: one
+// wavefront walks a segment of H rows of a strip of 64 * kRowCols columns.
+#define SCI_ROW_SHAPES(X) X(9, 32) X(10, 64) X(11, 128) X(12, 256)
+
 namespace sci {
-constexpr int kTileShapes = 9;
+constexpr int kTileShapes = 9; // tiled shapes (ids 0 .. kTileShapes-1)
+constexpr int kRowShapes = 4;  // row-pipelined shapes (ids kTileShapes ..)
+constexpr int kRowCols = 2;    // columns per lane of the row-pipelined kernel
 }

@@ -162,7 +162,10 @@ struct TilePass {
 bool tile_supported(int tv);
 int tile_shape_count();
 bool tile_shape_info(int shape, int *rows, int *waves, int *cols);
-// shape: index into the tile-shape table (0 = default)
+// true for the row-pipelined shapes (numbered after the tiled ones)
+bool tile_shape_pipelined(int shape);
+// shape: index into the shape table (0 = default); 16-bit dual storage runs
+// the default shape whatever is asked
 int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,
                     const TilePass &tp, float lam, hipStream_t s);
 

@@ -858,6 +858,13 @@ int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_pe
     return SCI_OK;
 }
 
+int sci_tile_shape_pipelined(int32_t shape)
+{
+    int r = 0, w = 0, c = 0;
+    if (!tile_shape_info(shape - 1, &r, &w, &c)) return SCI_ERR_INVALID_ARG;
+    return tile_shape_pipelined(shape - 1) ? 1 : 0;
+}
+
 int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *X, int32_t *best_shape_out,
                  int32_t *best_passes_out, double *times_ms_out, hipStream_t stream)
 {

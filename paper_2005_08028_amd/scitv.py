@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                      P(ctypes.c_double), V]),
         "sci_tile_shape_count": (I, []),
         "sci_tile_shape_info": (I, [ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]),
+        "sci_tile_shape_pipelined": (I, [ctypes.c_int32]),
         "sci_autotune": (I, [V, D, P(sci_tv_params), V, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_double),
                              V]),
         "sci_profile_read": (I, [V, ctypes.c_char_p, P(ctypes.c_int64), P(ctypes.c_double)]),
@@ -312,6 +313,13 @@ def sci_tile_shape_info(shape: int):
     r, w, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     _check(None, lib.sci_tile_shape_info(int(shape), ctypes.byref(r), ctypes.byref(w), ctypes.byref(c)))
     return r.value, w.value, c.value
+
+
+def sci_tile_shape_pipelined(shape: int) -> bool:
+    """True for a row-pipelined shape, False for a tiled one (1-based)."""
+    v = lib.sci_tile_shape_pipelined(int(shape))
+    _check(None, min(v, 0))
+    return v == 1
 
 
 def sci_autotune(ctx, X: torch.Tensor, params: sci_tv_params, stream=None):

@@ -190,6 +190,64 @@ def test_every_tile_shape_gives_identical_bits(sc, ctx, tv):
         np.testing.assert_array_equal(host(th), ref)
 
 
+def row_shapes(sc):
+    return [k for k in range(1, sc.sci_tile_shape_count() + 1) if sc.sci_tile_shape_pipelined(k)]
+
+
+# several row segments per frame (segment heights 32 .. 256), ragged strips,
+# images narrower than one strip and shorter than the pipeline fill
+ROW_CASES = [(1, 1, 1), (2, 3, 2), (1, 5, 300), (2, 300, 130), (1, 97, 214), (3, 70, 107)]
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+@pytest.mark.parametrize("B,nx,ny", ROW_CASES)
+def test_row_pipelined_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
+    """Row-pipelined shapes against one-pass-per-iteration streaming, float32
+    duals: pass lengths 1..10, one pass and several (the later passes start
+    from the previous pass's p and p_prev), cold and warm starts, momentum on
+    and off, final dual returned: identical bits for theta and the dual."""
+    shapes = row_shapes(sc)
+    assert shapes
+    r = np.random.default_rng(nx * 7 + ny * 3 + B)
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    p0 = dev(orc.project_dual(r.normal(size=(2, B, nx, ny)), tv).astype(np.float32))
+    cases = [(1, 1, True, False), (2, 1, True, True), (3, 1, False, False), (6, 1, True, False),
+             (9, 1, True, True), (10, 1, True, False), (10, 2, True, True), (13, 2, True, False),
+             (20, 3, False, True), (5, 5, True, False)]
+    for n, passes, accel, warm in cases:
+        init = p0 if warm else None
+        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, schedule="stream")
+        dref = torch.empty((2, B, nx, ny), device="cuda")
+        tref, _, _, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=dref)
+        tref, dref = host(tref), host(dref)
+        for k in shapes:
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, schedule="fused", tile_shape=k,
+                               tile_passes=passes)
+            d = torch.empty((2, B, nx, ny), device="cuda")
+            th, _, its, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d)
+            msg = f"shape {k} {sc.sci_tile_shape_info(k)} N={n} passes={passes} accel={accel} warm={warm}"
+            assert its == n, msg
+            np.testing.assert_array_equal(host(th), tref, err_msg="theta " + msg)
+            np.testing.assert_array_equal(host(d), dref, err_msg="dual " + msg)
+    say(f"row-pipelined {tv} B={B} {nx}x{ny}: {len(cases)} cases x {len(shapes)} shapes bit-identical")
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_row_pipelined_solvers_bitwise(sc, ctx, solver):
+    """Whole GAP / ADMM solves (ADMM takes u = s - theta from the kernel),
+    with and without the warm dual across outer iterations: a row-pipelined
+    shape gives the bits of the streaming schedule."""
+    pr = synth.make_problem(150, 90, 6, seed=21, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (False, True):
+        kw = dict(outer_iters=4, rho=0.01, tv="itv2d", lam=0.1, n_inner=7, warm_dual=warm)
+        xs, ts = run_solver(sc, ctx, solver, Y, pr.masks, schedule="stream", **kw)
+        for k in row_shapes(sc):
+            x, t = run_solver(sc, ctx, solver, Y, pr.masks, schedule="fused", tile_shape=k, **kw)
+            np.testing.assert_array_equal(x, xs, err_msg=f"{solver} warm={warm} shape {k}")
+            np.testing.assert_array_equal(t, ts, err_msg=f"{solver} warm={warm} shape {k}")
+
+
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 def test_denoise_default_schedule_matches_oracle(sc, ctx, tv):
     x = np.random.default_rng(3).uniform(size=(6, 70, 150)).astype(np.float32)
