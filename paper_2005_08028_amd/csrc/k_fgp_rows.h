@@ -33,6 +33,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "k_fgp_tile_shapes.h"
 #include "sci_internal.h"
 #include "sci_math.h"
@@ -40,6 +42,16 @@
 namespace sci {
 
 constexpr int kRowChunk = 2; // rows loaded per chunk (one chunk ahead)
+
+// f(integral_constant<int, I>) for I = I0 .. N-1, unrolled at compile time.
+template <int I0, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I0 < N) {
+        f(std::integral_constant<int, I0>{});
+        static_for<I0 + 1, N>(f);
+    }
+}
 
 // MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
 template <int TV, int M, int DT, int C, int MODE>
@@ -127,11 +139,19 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
     // Step k runs level t on row k - t. The first stored row a needs level 0
     // from row a - M, primed two steps earlier (theta_0 and w_0 of the row
     // above); the last stored row a+H-1 leaves level M-1 at step a+H+M-2.
+    //
+    // Relative to k_start, level t first matters at step 2t (it takes in w_t
+    // of the row that primes its theta); the first NPRO chunks, where some
+    // level is still idle, are unrolled with those levels and the theta
+    // stage (whose rows lie above the segment there) left out. Every later
+    // chunk runs all levels.
     const int k_start = a - M - 2;
     const int nsteps = H + 2 * M + 1;
-    const int nchunk = (nsteps + CH - 1) / CH;
+    const int nchunk = (nsteps + CH - 1) / CH; // >= M + 1 > NPRO
+    constexpr int NPRO = (2 * (M - 1) + CH - 1) / CH;
     load_chunk(k_start + 1);
-    for (int b = 0; b < nchunk; ++b) {
+    auto chunk = [&](int b, auto pro) {
+        constexpr int PB = decltype(pro)::value; // prologue chunk index, or -1
         const int k0 = k_start + b * CH;
         // level-0 inputs of the chunk's rows k0+1 .. k0+CH, masked
         float i0h[CH][C], i0v[CH][C], j0h[CH][C], j0v[CH][C];
@@ -180,6 +200,7 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
             float qph[C], qpv[C]; // p^(s0+M-1) of the output row
 #pragma unroll
             for (int t = 0; t < M; ++t) {
+                if (PB >= 0 && PB * CH + s < 2 * t) break; // this level and the later ones are idle
                 const int r = k - t;
                 // theta_t of row r+1 = x - lambda D^T w_t
                 float thn[C];
@@ -226,6 +247,7 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
                     jv[c] = nv[c];
                 }
             }
+            if (PB >= 0) continue; // the theta row is above the segment
             // row r = k - M + 1 now has p^(s0+M) in jh, jv: theta = x - lambda D^T p
             const int r = k - M + 1;
             float th[C], xr[C];
@@ -255,7 +277,9 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
                 }
             }
         }
-    }
+    };
+    static_for<0, NPRO>([&](auto pb) { chunk(decltype(pb)::value, pb); });
+    for (int b = NPRO; b < nchunk; ++b) chunk(b, std::integral_constant<int, -1>{});
 }
 
 // Launch of one pass over every frame: strips of 64*C - 2M - 1 interior

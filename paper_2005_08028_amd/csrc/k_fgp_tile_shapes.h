@@ -16,10 +16,10 @@
 
 // Row-pipelined shapes (k_fgp_rows.h), numbered after the tiled ones: one
 // wavefront walks a segment of H rows of a strip of 64 * kRowCols columns.
-#define SCI_ROW_SHAPES(X) X(9, 32) X(10, 64) X(11, 128) X(12, 256)
+#define SCI_ROW_SHAPES(X) X(9, 32) X(10, 64) X(11, 96) X(12, 128) X(13, 192) X(14, 256)
 
 namespace sci {
 constexpr int kTileShapes = 9; // tiled shapes (ids 0 .. kTileShapes-1)
-constexpr int kRowShapes = 4;  // row-pipelined shapes (ids kTileShapes ..)
+constexpr int kRowShapes = 6;  // row-pipelined shapes (ids kTileShapes ..)
 constexpr int kRowCols = 2;    // columns per lane of the row-pipelined kernel
 }
