@@ -40,6 +40,8 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
                     const TilePass &tp, float lam, hipStream_t s)
 {
     if (m < 1 || m > kTileMaxM || shape < 0 || shape >= tile_shape_count()) return SCI_ERR_INVALID_ARG;
+    if (tv == TV_VTV) // one row-pipelined kernel, whatever the shape
+        return dual_dtype == DT_F32 ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s) : SCI_ERR_UNSUPPORTED;
     if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;
     if (dual_dtype == DT_F32 && tile_shape_pipelined(shape)) {
         int H = 0, w = 0, c = 0;

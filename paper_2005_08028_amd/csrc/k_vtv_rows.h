@@ -1,0 +1,310 @@
+// Row-pipelined fused-schedule denoiser for vectorial TV (ITV3D, Eq. (31)-(32)),
+// instantiated in the k_vtv_rows_kf*.hip translation units.
+//
+// The temporal wavefront blocking of k_fgp_rows.h, for a TV whose projection
+// couples all B frames of a pixel: a workgroup owns a strip of 64 columns
+// (one per lane; a recomputed halo of M+1 columns on the left and M on the
+// right) and a segment of H rows, and its ng wavefronts split the frames of
+// every pixel, wavefront g holding frames [g*fpw, g*fpw + fpw) (KF >= fpw
+// slots; a slot past the last frame reads frame B-1, stays out of the norm and
+// stores nothing). All wavefronts walk the segment together, level t one row
+// behind level t-1. At every level and step each wavefront forms q for its
+// frames and their partial squared norm; the partials meet in LDS (one
+// LDS-only barrier, double-buffered) and are summed in wavefront order, so
+// every wavefront scales its frames by the same per-pixel factor. Frame split
+// and summation order are those of the streaming VTV pass, and the per-voxel
+// arithmetic uses the same helpers in the same order: with float32 duals the
+// results are bit-identical to streaming one iteration per pass.
+//
+// Each level reads x of its own row; x moves down the levels through
+// registers (an LDS ring per frame would not fit next to B frames of state).
+// Levels the pipeline fill has not reached are left out of the first chunks
+// at compile time, as in the 2D kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "k_fgp_rows.h"
+#include "sci_internal.h"
+#include "sci_math.h"
+
+namespace sci {
+
+constexpr int kVtvMaxWaves = 8; // wavefronts (frame groups) per workgroup, at most
+
+// MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
+template <int M, int KF, int MODE>
+__global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, int B, int fpw, int nstrip, int H,
+                                                              const float *__restrict__ x,
+                                                              const float *__restrict__ pc,
+                                                              const float *__restrict__ pp, TileBeta bt, float lam,
+                                                              float step, float *__restrict__ pn_out,
+                                                              float *__restrict__ pp_out,
+                                                              float *__restrict__ theta_out, float *__restrict__ u_out)
+{
+    constexpr int CH = kRowChunk;
+    constexpr int TXO = 64 - 2 * M - 1; // interior columns per strip
+    static_assert(TXO > 0, "strip too narrow for the pass length");
+    __shared__ float n2s[2][kVtvMaxWaves][64];
+
+    const int ng = (int)(blockDim.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;
+    const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    const int seg = lin / nstrip, sx = lin % nstrip;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t V = plane * (uint32_t)B;
+    const int a = seg * H;         // first row of the segment
+    const int hi = min(a + H, nx); // one past its last row
+    const int j = sx * TXO - (M + 1) + lane;
+    const bool jin = j >= 0 && j < ny;
+    const bool hj = j >= 0 && j < ny - 1; // horizontal differences exist for 0 <= j < ny-1
+    const float step_h = hj ? step : 0.0f;
+    const uint32_t jcl = jin ? (uint32_t)j : 0u;
+    const bool outc = lane >= M + 1 && lane <= 63 - M && j < ny;
+    const int kbase = g * fpw;
+    const int nk = max(0, min(fpw, B - kbase)); // real frames of this wavefront
+    uint32_t fo[KF];
+#pragma unroll
+    for (int kk = 0; kk < KF; ++kk) fo[kk] = (uint32_t)min(kbase + kk, B - 1) * plane + jcl;
+
+    // level t's state on its current row r, per frame slot
+    float cth[M][KF], cwh[M][KF], cwv[M][KF], cph[M][KF], cpv[M][KF];
+    float xl[M + 1][KF]; // x of row k+1-t, the row level t reads in step k (t = M: the theta row)
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int kk = 0; kk < KF; ++kk) cth[t][kk] = cwh[t][kk] = cwv[t][kk] = cph[t][kk] = cpv[t][kk] = 0.0f;
+#pragma unroll
+    for (int t = 0; t <= M; ++t)
+#pragma unroll
+        for (int kk = 0; kk < KF; ++kk) xl[t][kk] = 0.0f;
+    float cpm[KF]; // p_v^(s0+M) of the row above the theta row
+#pragma unroll
+    for (int kk = 0; kk < KF; ++kk) cpm[kk] = 0.0f;
+    int par = 0; // LDS buffer of the next exchange
+
+    // Chunk loads of CH rows for every frame slot, from in-bounds addresses,
+    // masked where consumed.
+    float xn[CH][KF], lh[CH][KF], lv[CH][KF], mh[CH][KF], mv[CH][KF];
+    auto load_chunk = [&](int i0) {
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int i = i0 + s;
+            const uint32_t rowo = ((i >= 0 && i < nx) ? (uint32_t)i : 0u) * (uint32_t)ny;
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) {
+                const uint32_t o = fo[kk] + rowo;
+                xn[s][kk] = x[o];
+                if (MODE >= 1) {
+                    lh[s][kk] = pc[o];
+                    lv[s][kk] = pc[V + o];
+                }
+                if (MODE == 2) {
+                    mh[s][kk] = pp[o];
+                    mv[s][kk] = pp[V + o];
+                }
+            }
+        }
+    };
+
+    // Step k runs level t on row k - t (see k_fgp_rows.h for the timing).
+    const int k_start = a - M - 2;
+    const int nsteps = H + 2 * M + 1;
+    const int nchunk = (nsteps + CH - 1) / CH; // >= M + 1 > NPRO
+    constexpr int NPRO = (2 * (M - 1) + CH - 1) / CH;
+    load_chunk(k_start + 1);
+    auto chunk = [&](int b, auto pro) {
+        constexpr int PB = decltype(pro)::value; // prologue chunk index, or -1
+        const int k0 = k_start + b * CH;
+        float i0h[CH][KF], i0v[CH][KF], j0h[CH][KF], j0v[CH][KF], x0[CH][KF];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int i = k0 + s + 1;
+            const bool iin = i >= 0 && i < nx;
+            const bool hin = iin && hj;                      // horizontal difference exists
+            const bool vin = i >= 0 && i < nx - 1 && jin;    // vertical difference exists
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) {
+                x0[s][kk] = (iin && jin) ? xn[s][kk] : 0.0f;
+                if (MODE == 0) {
+                    i0h[s][kk] = i0v[s][kk] = j0h[s][kk] = j0v[s][kk] = 0.0f;
+                } else {
+                    j0h[s][kk] = hin ? lh[s][kk] : 0.0f;
+                    j0v[s][kk] = vin ? lv[s][kk] : 0.0f;
+                    if (MODE == 2) {
+                        i0h[s][kk] = hin ? extrapolate(j0h[s][kk], mh[s][kk], bt.b[0]) : 0.0f;
+                        i0v[s][kk] = vin ? extrapolate(j0v[s][kk], mv[s][kk], bt.b[0]) : 0.0f;
+                    } else {
+                        i0h[s][kk] = j0h[s][kk];
+                        i0v[s][kk] = j0v[s][kk];
+                    }
+                }
+            }
+        }
+        load_chunk(k0 + CH + 1);
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int k = k0 + s;
+#pragma unroll
+            for (int t = M; t > 0; --t)
+#pragma unroll
+                for (int kk = 0; kk < KF; ++kk) xl[t][kk] = xl[t - 1][kk];
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) xl[0][kk] = x0[s][kk];
+            float ih[KF], iv[KF], jh[KF], jv[KF];
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) {
+                ih[kk] = i0h[s][kk];
+                iv[kk] = i0v[s][kk];
+                jh[kk] = j0h[s][kk];
+                jv[kk] = j0v[s][kk];
+            }
+            float qph[KF], qpv[KF]; // p^(s0+M-1) of the output row
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                if (PB >= 0 && PB * CH + s < 2 * t) break; // this level and the later ones are idle
+                const int r = k - t;
+                const float step_v = (r >= 0 && r < nx - 1) ? step : 0.0f; // uniform per row
+                float thn[KF], qh[KF], qv[KF];
+                float n2 = 0.0f;
+#pragma unroll
+                for (int kk = 0; kk < KF; ++kk) {
+                    thn[kk] = theta_of(xl[t][kk], from_left(ih[kk]), ih[kk], cwv[t][kk], iv[kk], lam);
+                    const float zh = from_right(cth[t][kk]) - cth[t][kk];
+                    const float zv = thn[kk] - cth[t][kk];
+                    qh[kk] = ascend(cwh[t][kk], zh, step_h);
+                    qv[kk] = ascend(cwv[t][kk], zv, step_v);
+                    const float n2a = norm2_add(n2, qh[kk], qv[kk]);
+                    n2 = kk < nk ? n2a : n2;
+                }
+                n2s[par][g][lane] = n2;
+                lds_barrier();
+                float tot = 0.0f;
+                for (int gg = 0; gg < ng; ++gg) tot += n2s[par][gg][lane];
+                par ^= 1;
+                const float sc = iso_scale(tot);
+                const float bnext = bt.b[t + 1];
+#pragma unroll
+                for (int kk = 0; kk < KF; ++kk) {
+                    const float nh = qh[kk] * sc, nv = qv[kk] * sc;
+                    const float oh = extrapolate(nh, cph[t][kk], bnext);
+                    const float ov = extrapolate(nv, cpv[t][kk], bnext);
+                    if (t == M - 1) {
+                        qph[kk] = cph[t][kk];
+                        qpv[kk] = cpv[t][kk];
+                    }
+                    cth[t][kk] = thn[kk];
+                    cwh[t][kk] = ih[kk];
+                    cwv[t][kk] = iv[kk];
+                    cph[t][kk] = jh[kk];
+                    cpv[t][kk] = jv[kk];
+                    ih[kk] = oh;
+                    iv[kk] = ov;
+                    jh[kk] = nh;
+                    jv[kk] = nv;
+                }
+            }
+            if (PB >= 0) continue; // the theta row is above the segment
+            // row r = k - M + 1 now has p^(s0+M) in jh, jv: theta = x - lambda D^T p
+            const int r = k - M + 1;
+            float th[KF];
+#pragma unroll
+            for (int kk = 0; kk < KF; ++kk) {
+                th[kk] = theta_of(xl[M][kk], from_left(jh[kk]), jh[kk], cpm[kk], jv[kk], lam);
+                cpm[kk] = jv[kk];
+            }
+            if (r >= a && r < hi && outc) {
+                const uint32_t rowo = (uint32_t)r * (uint32_t)ny;
+#pragma unroll
+                for (int kk = 0; kk < KF; ++kk) {
+                    if (kk >= nk) continue;
+                    const uint32_t o = fo[kk] + rowo;
+                    if (theta_out) theta_out[o] = th[kk];
+                    if (u_out) u_out[o] = xl[M][kk] - th[kk];
+                    if (pn_out) {
+                        pn_out[o] = jh[kk];
+                        pn_out[V + o] = jv[kk];
+                    }
+                    if (pp_out) {
+                        pp_out[o] = qph[kk];
+                        pp_out[V + o] = qpv[kk];
+                    }
+                }
+            }
+        }
+    };
+    static_for<0, NPRO>([&](auto pb) { chunk(decltype(pb)::value, pb); });
+    for (int b = NPRO; b < nchunk; ++b) chunk(b, std::integral_constant<int, -1>{});
+}
+
+} // namespace sci
+
+namespace sci {
+
+// Longest pass (inner iterations) the kernel runs without spilling
+// registers, by frames per wavefront; 0 where it does not run.
+constexpr int vtv_rows_max_m(int kf) { return kf == 1 ? 10 : kf == 2 ? 8 : kf == 3 ? 5 : kf == 4 ? 4 : 0; }
+
+// Segment height: about 8 wavefronts per CU (one or more workgroups, within
+// what registers allow), and with that the tallest segments, which spend the
+// least on the pipeline fill.
+template <typename K>
+int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
+{
+    int dev = 0, ncu = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 64 * ng, 0) != hipSuccess || nb < 1) nb = 1;
+    const int per_cu = std::min(nb, std::max(1, (kVtvMaxWaves + ng - 1) / ng));
+    const long target = (long)per_cu * ncu;
+    const int nseg = (int)std::min<long>(std::max<long>(1, target / nstrip), std::max(1, nx));
+    return (nx + nseg - 1) / nseg;
+}
+
+template <int M, int KF, int MODE>
+void launch_vtv_mode(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
+                     hipStream_t s)
+{
+    constexpr int TXO = 64 - 2 * M - 1;
+    const int nstrip = (ny + TXO - 1) / TXO;
+    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE>, ng, nx, nstrip);
+    const int nseg = (nx + H - 1) / H;
+    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny, B, fpw, nstrip,
+                       H, x, (const float *)tp.pc, (const float *)tp.pp, tp.beta, lam, 1.0f / (8.0f * lam),
+                       (float *)tp.pn_out, (float *)tp.pp_out, tp.theta, tp.u_out);
+}
+
+template <int M, int KF>
+void launch_vtv_m(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
+                  hipStream_t s)
+{
+    if (tp.mode == 0) launch_vtv_mode<M, KF, 0>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    else if (tp.mode == 1) launch_vtv_mode<M, KF, 1>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    else launch_vtv_mode<M, KF, 2>(nx, ny, B, fpw, ng, x, tp, lam, s);
+}
+
+// Dispatch on the pass length m = 1..vtv_rows_max_m(KF).
+template <int KF>
+int launch_vtv_kf(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
+                  hipStream_t s)
+{
+    constexpr int MM = vtv_rows_max_m(KF);
+    if (m < 1 || m > MM) return SCI_ERR_INVALID_ARG;
+    switch (m) {
+#define SCI_VTV_M(mm)                                                                                               \
+    case mm:                                                                                                        \
+        if constexpr (mm <= MM) launch_vtv_m<mm, KF>(nx, ny, B, fpw, ng, x, tp, lam, s);                            \
+        return SCI_OK;
+        SCI_VTV_M(1) SCI_VTV_M(2) SCI_VTV_M(3) SCI_VTV_M(4) SCI_VTV_M(5) SCI_VTV_M(6) SCI_VTV_M(7) SCI_VTV_M(8)
+        SCI_VTV_M(9) SCI_VTV_M(10)
+#undef SCI_VTV_M
+    }
+    return SCI_ERR_INVALID_ARG;
+}
+
+} // namespace sci

@@ -164,6 +164,10 @@ int tile_shape_count();
 bool tile_shape_info(int shape, int *rows, int *waves, int *cols);
 // true for the row-pipelined shapes (numbered after the tiled ones)
 bool tile_shape_pipelined(int shape);
+// Row-pipelined VTV passes (float32 duals): the longest pass for B frames (0
+// when the kernel does not run them), and one pass of m iterations.
+int vtv_rows_max_pass(int B);
+int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s);
 // shape: index into the shape table (0 = default); 16-bit dual storage runs
 // the default shape whatever is asked
 int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,

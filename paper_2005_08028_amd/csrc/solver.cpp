@@ -107,6 +107,8 @@ struct FgpRun {
 // SIMD: the fastest single-iteration shape measured at 1024x1024x24).
 constexpr int kStreamTileShape = 3;
 
+constexpr const char *kFusedScope = "the fused schedule covers ATV, ITV2D, and VTV with float32 duals";
+
 int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
                      float *theta, float *u_out, bool keep_dual, hipStream_t s, int force_shape = -1,
                      int force_passes = -1);
@@ -186,6 +188,11 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
     pick_tiling(ctx, p, d, n, &shape, &npass);
     if (force_shape >= 0) shape = force_shape;
     if (force_passes >= 1) npass = force_passes;
+    if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes the VTV kernel runs, unless more are asked for
+        const int mm = vtv_rows_max_pass(d.B);
+        if (mm < 1) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
+        npass = std::min(n, std::max((n + mm - 1) / mm, p.tile_passes));
+    }
     for (int q = 0; q < npass; ++q) {
         const int m = n / npass + (q < n % npass ? 1 : 0);
         const bool last = q == npass - 1;
@@ -235,12 +242,24 @@ void bind_duals(sci_ctx *ctx, FgpRun &r)
     for (int k = 0; k < 4; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
 }
 
-bool use_fused(const sci_tv_params &p)
+// VTV on the fused schedule: the row-pipelined kernel with float32 duals.
+bool vtv_fused_supported(const sci_tv_params &p, const sci_dims &d)
+{
+    return p.tv == SCI_TV_VTV && p.dual_dtype == SCI_DUAL_F32 && !p.chambolle04 && !p.clip && vtv_rows_max_pass(d.B) > 0;
+}
+
+bool fused_supported(const sci_tv_params &p, const sci_dims &d)
+{
+    return !p.chambolle04 && !p.clip && (tile_supported(p.tv) || vtv_fused_supported(p, d));
+}
+
+bool use_fused(const sci_tv_params &p, const sci_dims &d)
 {
     if (p.schedule == SCI_SCHED_STREAM || p.chambolle04 || p.clip) return false;
     if (p.schedule == SCI_SCHED_FUSED) return true;
-    return tile_supported(p.tv) && p.n_inner >= 2;
+    return fused_supported(p, d) && p.n_inner >= 2;
 }
+
 
 // One denoiser call with a fixed iteration count, as used inside the outer
 // loops: theta = x - lambda D^T p^(N), and u_out = x - theta when non-null.
@@ -278,9 +297,8 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
         if (st != SCI_OK) return fail(ctx, st, "theta pass");
         return check_launch(ctx, "k_tv_theta");
     }
-    if (use_fused(p)) {
-        if (!tile_supported(p.tv))
-            return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule covers ATV and ITV2D (VTV couples all frames)");
+    if (use_fused(p, d)) {
+        if (!fused_supported(p, d)) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
         return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);
     }
     if (tile_supported(p.tv) && !p.chambolle04)
@@ -585,9 +603,8 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
 // pass per iteration. The dual stays in r.cur for the gap check.
 int fgp_chunk(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &q, const float *x, FgpRun &r, int n, hipStream_t s)
 {
-    const bool fused = q.schedule != SCI_SCHED_STREAM && !q.chambolle04 && tile_supported(q.tv);
-    if (q.schedule == SCI_SCHED_FUSED && !fused)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "the fused schedule covers ATV and ITV2D (VTV couples all frames)");
+    const bool fused = q.schedule != SCI_SCHED_STREAM && fused_supported(q, d);
+    if (q.schedule == SCI_SCHED_FUSED && !fused) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
     if (fused)
         return fgp_tile_iterate(ctx, d, q, x, r, n, nullptr, nullptr, true, s, -1, (n + kTileMaxM - 1) / kTileMaxM);
     return fgp_iterate(ctx, d, q, x, r, n, s);

@@ -232,6 +232,59 @@ def test_row_pipelined_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
     say(f"row-pipelined {tv} B={B} {nx}x{ny}: {len(cases)} cases x {len(shapes)} shapes bit-identical")
 
 
+# 1..4 frames per wavefront (B = 8, 10, 24, 32 and splits with spare slots:
+# 3, 17, 29), several row segments, ragged strips, tiny images
+VTV_FUSED_CASES = [(1, 1, 1), (3, 2, 5), (8, 70, 33), (10, 130, 150), (17, 45, 100), (24, 64, 64), (29, 9, 130),
+                   (32, 40, 70)]
+
+
+@pytest.mark.parametrize("B,nx,ny", VTV_FUSED_CASES)
+def test_vtv_fused_bitwise_equals_streaming(sc, ctx, B, nx, ny):
+    """Row-pipelined VTV against one-pass-per-iteration streaming VTV, float32
+    duals: one pass and several (pass lengths up to the kernel's limit for the
+    frames per wavefront), cold and warm starts, momentum on and off, final
+    dual returned: identical bits for theta and the dual."""
+    r = np.random.default_rng(B * 13 + nx + ny)
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    p0 = dev(orc.project_dual(r.normal(size=(2, B, nx, ny)), "vtv").astype(np.float32))
+    cases = [(1, 0, True, False), (2, 0, True, True), (4, 0, False, False), (5, 0, True, False),
+             (7, 0, True, True), (10, 0, True, False), (10, 5, True, True), (13, 0, False, True)]
+    for n, passes, accel, warm in cases:
+        init = p0 if warm else None
+        outs = []
+        for schedule in ("stream", "fused"):
+            prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=n, accel=accel, schedule=schedule, tile_passes=passes)
+            d = torch.empty((2, B, nx, ny), device="cuda")
+            th, _, its, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d)
+            assert its == n
+            outs.append((host(th), host(d)))
+        msg = f"VTV B={B} {nx}x{ny} N={n} passes={passes} accel={accel} warm={warm}"
+        np.testing.assert_array_equal(outs[1][0], outs[0][0], err_msg="theta " + msg)
+        np.testing.assert_array_equal(outs[1][1], outs[0][1], err_msg="dual " + msg)
+    ref = orc.tv_denoise(x.cpu().numpy(), f32(0.1), 10, "vtv")
+    th, _, _, _ = sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=10))
+    assert rel_l2(host(th), ref) <= REL_TOL
+    say(f"VTV fused B={B} {nx}x{ny}: {len(cases)} cases bit-identical to streaming")
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_vtv_fused_solvers_bitwise(sc, ctx, solver):
+    """Whole GAP / ADMM VTV solves, with and without the warm dual, eager and
+    graph-launched: the fused schedule gives the bits of the streaming one."""
+    pr = synth.make_problem(120, 100, 10, seed=31, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (False, True):
+        kw = dict(outer_iters=4, rho=0.01, tv="vtv", lam=0.1, n_inner=6, warm_dual=warm)
+        xs, ts = run_solver(sc, ctx, solver, Y, pr.masks, schedule="stream", **kw)
+        xf, tf = run_solver(sc, ctx, solver, Y, pr.masks, schedule="fused", **kw)
+        np.testing.assert_array_equal(xf, xs, err_msg=f"{solver} warm={warm}")
+        np.testing.assert_array_equal(tf, ts, err_msg=f"{solver} warm={warm}")
+        for rep in range(2):
+            xg, tg = run_solver(sc, ctx, solver, Y, pr.masks, schedule="fused", use_graph=True, **kw)
+            _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+            np.testing.assert_array_equal(xg, xs, err_msg=f"{solver} warm={warm} graph replay {rep}")
+
+
 @pytest.mark.parametrize("solver", ["gap", "admm"])
 def test_row_pipelined_solvers_bitwise(sc, ctx, solver):
     """Whole GAP / ADMM solves (ADMM takes u = s - theta from the kernel),
