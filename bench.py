@@ -289,16 +289,20 @@ def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10):
     Xt = torch.from_numpy(pr.truth).to(dev)
     Y = scitv.sci_forward(h, C, Xt)
     V = C.numel()
-    prm = scitv.solver_params(outer_iters=T, tv="vtv", lam=lam, n_inner=N)
     X = torch.empty_like(C)
-    scitv.sci_gap_tv(h, Y, C, prm, X_out=X)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
+
+    def solve_ms(schedule, reps=3):
+        prm = scitv.solver_params(outer_iters=T, tv="vtv", lam=lam, n_inner=N, schedule=schedule)
         scitv.sci_gap_tv(h, Y, C, prm, X_out=X)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / reps * 1e3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            scitv.sci_gap_tv(h, Y, C, prm, X_out=X)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    ms_stream = solve_ms("stream")
+    ms = solve_ms("auto")  # the fused (row-pipelined) VTV denoiser
     curves = {}
     fns = {"gap": scitv.sci_gap_tv, "admm": scitv.sci_admm_tv, "fista": scitv.sci_fista_tv,
            "twist": scitv.sci_twist_tv}
@@ -314,6 +318,7 @@ def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10):
         "workload": f"512x512x10 synthetic scene (Bernoulli(0.5) masks, texture 0.02), ITV3D (VTV) FGP, "
                     f"{T} outer x {N} inner, lambda={lam}",
         "gap_vtv_ms_per_solve": round(ms, 2), "voxel_iter_per_s": V * T * N / (ms / 1e3),
+        "gap_vtv_ms_per_solve_streaming_schedule": round(ms_stream, 2),
         "paper_context": "the paper reports about 3 minutes for 150 iterations at this shape on a laptop CPU",
         "psnr_vs_outer_iterations": curves,
     }
@@ -370,19 +375,27 @@ def measure_kernels(scitv, h, dev, C, Y, X_true):
     N = 10
     per_pass_fgp = (12 + 20 + (N - 2) * 28) / N  # B/voxel: pass 1 reads x, pass 2 adds p, then p and p_prev
     per_pass_pg = (12 + (N - 1) * 20) / N        # no momentum: x and p
+    # fused VTV at B = 24: two row-pipelined passes of 5 per call; the first reads x and
+    # writes p and p_prev (20 B/voxel), the second reads x, p, p_prev and writes theta (24 B)
+    per_pass_vtv_fused = (20 + 24) / 2
     cases = [
         ("a6 FGP pass, ITV2D, streaming schedule (tile kernel, 1 iteration)",
-         dict(tv="itv2d", schedule="stream"), per_pass_fgp),
-        ("a6 FGP pass, VTV (row-streaming kernel, all frames of a pixel)", dict(tv="vtv"), per_pass_fgp),
+         dict(tv="itv2d", schedule="stream"), per_pass_fgp, "fgp_stream", ""),
+        ("a6 FGP pass, VTV, streaming schedule (row-streaming kernel, all frames of a pixel)",
+         dict(tv="vtv", schedule="stream"), per_pass_fgp, "fgp_stream", ""),
+        ("a6 FGP pass, VTV, fused schedule (row-pipelined kernel, 5 iterations per pass)", dict(tv="vtv"),
+         per_pass_vtv_fused, "fgp_fused", "bound by arithmetic and the per-iteration norm exchange, not HBM"),
         ("f1 Chambolle-2004 pass, ITV2D, projected gradient", dict(tv="itv2d", chambolle04=True, accel=False),
-         per_pass_pg),
-        ("f3 ATV-Clip pass", dict(tv="atv", clip=True), per_pass_pg),
+         per_pass_pg, "fgp_stream", ""),
+        ("f3 ATV-Clip pass", dict(tv="atv", clip=True), per_pass_pg, "fgp_stream", ""),
     ]
-    for name, kw, bpv in cases:
+    for name, kw, bpv, fam, note in cases:
         prm = scitv.solver_params(outer_iters=2, lam=0.1, n_inner=N, **kw)
-        r = profiled(lambda: scitv.sci_gap_tv(h, Y, C, prm), ("fgp_stream", "tv_theta", "project"))
-        n, ms = r["fgp_stream"]
-        row(name, ms * 1e3 / n, bpv * V)
+        r = profiled(lambda: scitv.sci_gap_tv(h, Y, C, prm), (fam, "tv_theta", "project"))
+        n, ms = r[fam]
+        if n == 0:
+            raise RuntimeError(f"kernel table: no {fam} launches recorded for {name}")
+        row(name, ms * 1e3 / n, bpv * V, note)
         if r["tv_theta"][0]:
             n, ms = r["tv_theta"]
             row("a7 theta = x - lambda D^T p (" + kw["tv"] + ")", ms * 1e3 / n, 16 * V)

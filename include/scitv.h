@@ -74,9 +74,11 @@ typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_
 
 /* How the inner denoiser iterations are scheduled on the GPU:
  *   STREAM: one pass over HBM per inner iteration (dual fields in memory);
- *   FUSED : up to 10 inner iterations per on-chip pass over each tile, the
- *           dual fields written back only between passes (ATV and ITV2D;
- *           not the Chambolle-2004 step);
+ *   FUSED : up to 10 inner iterations per on-chip pass, the dual fields
+ *           written back only between passes (ATV and ITV2D with any dual
+ *           type; VTV with float32 duals, passes of at most 10 / 8 / 5 / 4
+ *           iterations for B <= 8 / 16 / 24 / 32; not the Chambolle-2004
+ *           step nor ATV-Clip);
  *   AUTO  : FUSED where it applies, else STREAM.
  * Both schedules evaluate the same per-voxel expressions (bit for bit with
  * float32 duals; 16-bit duals are rounded where they are stored). */
@@ -102,7 +104,8 @@ typedef struct {
                                 default; k >= 1 = tile shape k (see sci_tile_shape_info) */
     int32_t tile_passes;     /* fused schedule: passes over HBM per denoiser call (each runs about
                                 n_inner / tile_passes iterations, at most 10); 0 = autotuned or
-                                default (passes of about 5 iterations) */
+                                default (passes of about 5 iterations; VTV: the fewest passes its
+                                kernel runs) */
     int32_t chambolle04;     /* 1 = Chambolle's (2004) semi-implicit step (Sec. 2.3):
                                 p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)), z = D theta, |z| per
                                 the TV kind, in place of the projection of w + z/(8 lambda);
