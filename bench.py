@@ -278,7 +278,7 @@ def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, T_eval=20):
     }
 
 
-def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10):
+def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10, curves_on=True):
     """The paper's real-data shape (512x512, B=10, ITV3D-FGP, 150 iterations)
     on a synthetic scene: time of one GAP-VTV solve, and PSNR against the
     iteration count for GAP, ADMM, FISTA and TwIST (each run afresh to every
@@ -306,7 +306,7 @@ def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10):
     curves = {}
     fns = {"gap": scitv.sci_gap_tv, "admm": scitv.sci_admm_tv, "fista": scitv.sci_fista_tv,
            "twist": scitv.sci_twist_tv}
-    for name, fn in fns.items():
+    for name, fn in (fns.items() if curves_on else ()):
         pts = []
         for t in range(every, T + 1, every):
             # one lambda for all four (FISTA / TwIST scale it by 1/L inside their denoiser)
@@ -424,6 +424,9 @@ def main() -> int:
     ap.add_argument("--kernel-table-only", action="store_true",
                     help="only time every step of the path on the 1024x1024x24 measurement and print that table "
                          "(a short run to profile all kernels; not the benchmark line)")
+    ap.add_argument("--paper-shaped-only", action="store_true",
+                    help="only time the 512x512x10 GAP-VTV solve on both schedules (a short run to profile the "
+                         "VTV kernels; not the benchmark line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 1 GiB device copies (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -461,6 +464,11 @@ def main() -> int:
     prm = scitv.solver_params(outer_iters=T, tv=cfg["tv"], lam=lam, n_inner=N, schedule=args.schedule,
                               dual_dtype=args.dual_dtype)
 
+    if args.paper_shaped_only:
+        res = measure_paper_shaped(scitv, synth, h, dev, curves_on=False)
+        ctx.close()
+        print(json.dumps({"paper_shaped_vtv_512x512x10": res}), flush=True)
+        return 0
     if args.kernel_table_only:
         table = measure_kernels(scitv, h, dev, C, Y, X_true)
         ctx.close()
