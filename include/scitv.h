@@ -333,8 +333,8 @@ int sci_tile_shape_count(void);
  * bottom, every iteration of the pass one row behind the previous one
  * (temporal wavefront blocking; no rows are recomputed apart from the
  * pipeline fill of about 2 n rows per segment). Row-pipelined shapes run
- * float32 dual storage (16-bit storage runs the default shape) and are not
- * used by the batched solve. Any output pointer may be NULL. */
+ * float32 dual storage (16-bit storage runs the default shape). Any output
+ * pointer may be NULL. */
 int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_per_group, int32_t *cols_per_lane);
 
 /* 1 if shape k (1-based) is row-pipelined, 0 if tiled, SCI_ERR_INVALID_ARG

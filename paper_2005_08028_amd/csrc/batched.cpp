@@ -10,7 +10,6 @@
 #include <string>
 #include <vector>
 
-#include "k_fgp_tile_shapes.h"
 #include "sci_batched.h"
 #include "sci_internal.h"
 
@@ -49,8 +48,6 @@ int validate(sci_ctx *ctx, int n, const sci_problem *probs, const sci_solver_par
     if (t.accel != 0 && t.accel != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "accel must be 0 or 1");
     if (t.tile_shape < 0 || t.tile_shape > tile_shape_count())
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
-    if (t.tile_shape > kTileShapes)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: tiled shapes only (the row-pipelined ones are not batched)");
     if (p->outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "outer_iters must be >= 0");
     if (p->warm_dual) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: cold-start denoiser only");
     if (t.chambolle04 || t.clip)
@@ -291,9 +288,8 @@ int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, cons
     }
     int best = 0;
     double best_ms = 1e300;
-    if (times_ms_out)
-        for (int sh = kTileShapes; sh < tile_shape_count(); ++sh) times_ms_out[sh] = NAN; // not batched
-    for (int sh = 0; sh < kTileShapes && st == SCI_OK; ++sh) {
+    const int nshape = tile_shape_count();
+    for (int sh = 0; sh < nshape && st == SCI_OK; ++sh) {
         plan_batch(ctx, n, probs, *p, sh, pl);
         bind_slab(slab, pl);
         // time the denoise of all problems on their first projection (outer_iters ignored)

@@ -8,6 +8,7 @@
 // problems of outer iteration t are always a prefix of the table).
 #include <hip/hip_runtime.h>
 
+#include "k_fgp_rows.h"
 #include "k_fgp_tile.h"
 #include "k_fgp_tile_shapes.h"
 #include "sci_batched.h"
@@ -124,6 +125,39 @@ __global__ __launch_bounds__(64 * NW, WPE) void k_batch_denoise(int n, const Bat
                                            nullptr, b.theta, nullptr, lds_v, lds_t);
 }
 
+// The same with the row-pipelined kernel: a one-wavefront workgroup per
+// (strip, segment of H rows) of every frame of every active problem.
+template <int TV, int M, int C>
+__global__ __launch_bounds__(64, 2) void k_batch_rows(int n, const BatchProb *__restrict__ tab, TileBeta bt,
+                                                      float lam, float step, int H)
+{
+    __shared__ RowRing<M, C> ring;
+    const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    const int p = find_problem(n, lin, [&](int q) { return tab[q].wg_base; });
+    const BatchProb &b = tab[p];
+    const int local = lin - b.wg_base;
+    const int frame = local / b.ntiles, tile = local % b.ntiles;
+    const uint32_t plane = (uint32_t)b.nx * (uint32_t)b.ny;
+    fgp_rows_body<TV, M, DT_F32, C, 0>(b.nx, b.ny, tile % b.ntx, tile / b.ntx, H, (uint32_t)frame * plane,
+                                       plane * (uint32_t)b.B, b.x, nullptr, nullptr, bt, lam, step, nullptr, nullptr,
+                                       b.theta, nullptr, ring);
+}
+
+template <int TV>
+int launch_rows_batch(int H, int m, int n, int nwg, const BatchProb *tab, const TileBeta &bt, float lam,
+                      hipStream_t s)
+{
+    const dim3 g(nwg), b(64);
+    const float step = 1.0f / (8.0f * lam);
+#define SCI_M(mm)                                                                                                   \
+    case mm: hipLaunchKernelGGL((k_batch_rows<TV, mm, kRowCols>), g, b, 0, s, n, tab, bt, lam, step, H); return SCI_OK;
+    switch (m) {
+        SCI_M(1) SCI_M(2) SCI_M(3) SCI_M(4) SCI_M(5) SCI_M(6) SCI_M(7) SCI_M(8) SCI_M(9) SCI_M(10)
+    }
+#undef SCI_M
+    return SCI_ERR_INVALID_ARG;
+}
+
 template <int TV, int R, int NW, int C, int WPE>
 int launch_denoise_shape(int m, int n, int nwg, const BatchProb *tab, const TileBeta &bt, float lam, hipStream_t s)
 {
@@ -158,7 +192,8 @@ void batch_tile_extent(int shape, int m, int *tile_w, int *tile_h)
     int r = 0, w = 0, c = 0;
     tile_shape_info(shape, &r, &w, &c);
     *tile_w = 64 * c - 2 * m - 1;
-    *tile_h = w * r - 2 * m - 1;
+    // a row-pipelined segment keeps all its rows; a tile loses its halo rows
+    *tile_h = tile_shape_pipelined(shape) ? r : w * r - 2 * m - 1;
 }
 
 void launch_batch_setup(int n, int nblocks, const BatchProb *tab, hipStream_t s)
@@ -182,6 +217,13 @@ int launch_batch_denoise(int tv, int shape, int m, int n, int nwg, const BatchPr
                          float lam, hipStream_t s)
 {
     if (m < 1 || m > kTileMaxM) return SCI_ERR_INVALID_ARG;
+    if (tile_shape_pipelined(shape)) {
+        int H = 0, w = 0, c = 0;
+        tile_shape_info(shape, &H, &w, &c);
+        if (tv == TV_ATV) return launch_rows_batch<TV_ATV>(H, m, n, nwg, tab, bt, lam, s);
+        if (tv == TV_ITV2D) return launch_rows_batch<TV_ITV2D>(H, m, n, nwg, tab, bt, lam, s);
+        return SCI_ERR_UNSUPPORTED;
+    }
     if (tv == TV_ATV) return launch_denoise_tv<TV_ATV>(shape, m, n, nwg, tab, bt, lam, s);
     if (tv == TV_ITV2D) return launch_denoise_tv<TV_ITV2D>(shape, m, n, nwg, tab, bt, lam, s);
     return SCI_ERR_UNSUPPORTED;

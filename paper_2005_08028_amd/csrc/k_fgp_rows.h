@@ -53,15 +53,23 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
-// MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
+// LDS ring of x rows of one wavefront.
+template <int M, int C> struct alignas(16) RowRing {
+    float v[2 * (M + kRowChunk)][64 * C];
+};
+
+// One wavefront's segment: strip sx, segment seg (rows [seg*H, seg*H + H)) of
+// the frame at element offset fo; V = elements per dual channel of the whole
+// video. MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
 template <int TV, int M, int DT, int C, int MODE>
-__global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, int nseg, int H,
-                                                    const float *__restrict__ x,
-                                                    const typename Dual<DT>::T *__restrict__ pc,
-                                                    const typename Dual<DT>::T *__restrict__ pp, TileBeta bt,
-                                                    float lam, float step, typename Dual<DT>::T *__restrict__ pn_out,
-                                                    typename Dual<DT>::T *__restrict__ pp_out,
-                                                    float *__restrict__ theta_out, float *__restrict__ u_out)
+__device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, int H, uint32_t fo, uint32_t V,
+                                              const float *__restrict__ x,
+                                              const typename Dual<DT>::T *__restrict__ pc,
+                                              const typename Dual<DT>::T *__restrict__ pp, const TileBeta &bt,
+                                              float lam, float step, typename Dual<DT>::T *__restrict__ pn_out,
+                                              typename Dual<DT>::T *__restrict__ pp_out,
+                                              float *__restrict__ theta_out, float *__restrict__ u_out,
+                                              RowRing<M, C> &rr)
 {
     using D = Dual<DT>;
     constexpr int CH = kRowChunk;
@@ -69,16 +77,9 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
     constexpr int TXO = TW - 2 * M - 1; // interior columns per strip
     constexpr int P = M + CH;           // ring period: rows k+1-M .. k+1 and the chunk written ahead
     static_assert(TXO > 0, "strip too narrow for the pass length");
-    __shared__ float ring[2 * P][TW];
+    auto &ring = rr.v;
 
     const int lane = threadIdx.x & 63;
-    const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
-    const int per_frame = nstrip * nseg;
-    const int frame = lin / per_frame, rem = lin % per_frame;
-    const int seg = rem / nstrip, sx = rem % nstrip;
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t fo = (uint32_t)frame * plane;
-    const uint32_t V = plane * (gridDim.x / (uint32_t)per_frame);
     const int a = seg * H;               // first row of the segment
     const int hi = min(a + H, nx);       // one past its last row
     const int j0 = sx * TXO - (M + 1) + lane * C;
@@ -280,6 +281,27 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
     };
     static_for<0, NPRO>([&](auto pb) { chunk(decltype(pb)::value, pb); });
     for (int b = NPRO; b < nchunk; ++b) chunk(b, std::integral_constant<int, -1>{});
+}
+
+// One pass over every frame: a one-wavefront workgroup per (frame, segment,
+// strip), numbered XCD-contiguously.
+template <int TV, int M, int DT, int C, int MODE>
+__global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, int nseg, int H,
+                                                    const float *__restrict__ x,
+                                                    const typename Dual<DT>::T *__restrict__ pc,
+                                                    const typename Dual<DT>::T *__restrict__ pp, TileBeta bt,
+                                                    float lam, float step, typename Dual<DT>::T *__restrict__ pn_out,
+                                                    typename Dual<DT>::T *__restrict__ pp_out,
+                                                    float *__restrict__ theta_out, float *__restrict__ u_out)
+{
+    __shared__ RowRing<M, C> ring;
+    const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    const int per_frame = nstrip * nseg;
+    const int frame = lin / per_frame, rem = lin % per_frame;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    fgp_rows_body<TV, M, DT, C, MODE>(nx, ny, rem % nstrip, rem / nstrip, H, (uint32_t)frame * plane,
+                                      plane * (gridDim.x / (uint32_t)per_frame), x, pc, pp, bt, lam, step, pn_out,
+                                      pp_out, theta_out, u_out, ring);
 }
 
 // Launch of one pass over every frame: strips of 64*C - 2M - 1 interior
