@@ -249,9 +249,11 @@ namespace sci {
 // registers, by frames per wavefront; 0 where it does not run.
 constexpr int vtv_rows_max_m(int kf) { return kf == 1 ? 10 : kf == 2 ? 8 : kf == 3 ? 5 : kf == 4 ? 4 : 0; }
 
-// Segment height: about 8 wavefronts per CU (one or more workgroups, within
-// what registers allow), and with that the tallest segments, which spend the
-// least on the pipeline fill.
+// Segment height. A step of the kernel is bound by the latency of its chain
+// of norm exchanges, which a second workgroup on the same CU hides well and a
+// third hardly (measured); so: up to two workgroups per CU, as registers
+// allow, all in one round, and with that the tallest segments, which spend
+// the least on the pipeline fill.
 template <typename K>
 int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
 {
@@ -260,7 +262,7 @@ int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
         ncu = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 64 * ng, 0) != hipSuccess || nb < 1) nb = 1;
-    const int per_cu = std::min(nb, std::max(1, (kVtvMaxWaves + ng - 1) / ng));
+    const int per_cu = std::min(nb, 2);
     const long target = (long)per_cu * ncu;
     const int nseg = (int)std::min<long>(std::max<long>(1, target / nstrip), std::max(1, nx));
     return (nx + nseg - 1) / nseg;
