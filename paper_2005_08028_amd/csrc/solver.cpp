@@ -8,6 +8,7 @@
 #include <cstring>
 #include <string>
 
+#include "k_fgp_tile_shapes.h"
 #include "sci_internal.h"
 #include "sci_wsnet.h"
 
@@ -162,10 +163,42 @@ int stream_tile_shape(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims
 
 constexpr int kDefaultPassLen = 5;
 
+// Untuned choice among the row-pipelined shapes for passes of m iterations:
+// each (frame, strip, segment) is one wavefront and about two run per SIMD,
+// so a launch takes ceil(wavefronts / slots) rounds of (H + 2m + 1) row
+// steps; the segment height with the fewest steps, provided its wavefronts
+// fill at least half of the slots (smaller problems keep the 2D tile, whose
+// workgroups hold many more wavefronts). -1 when no row shape qualifies.
+int default_row_shape(const sci_ctx *ctx, const sci_dims &d, int m)
+{
+    const long slots = 2L * 4 * (ctx->num_cus > 0 ? ctx->num_cus : 256);
+    const int txo = 64 * kRowCols - 2 * m - 1;
+    const long nstrip = (d.ny + txo - 1) / txo;
+    int best = -1;
+    long best_cost = 0, best_waves = 0;
+    for (int sh = 0; sh < tile_shape_count(); ++sh) {
+        int H = 0, w = 0, c = 0;
+        if (!tile_shape_pipelined(sh) || !tile_shape_info(sh, &H, &w, &c)) continue;
+        const long waves = nstrip * ((d.nx + H - 1) / H) * d.B;
+        const long cost = (waves + slots - 1) / slots * (H + 2L * m + 1);
+        if (best < 0 || cost < best_cost) {
+            best = sh;
+            best_cost = cost;
+            best_waves = waves;
+        }
+    }
+    return best >= 0 && 2 * best_waves >= slots ? best : -1;
+}
+
 // Tile shape and number of passes of the fused schedule: explicit
 // (tile_shape / tile_passes >= 1), else the autotuned choice for this
-// problem, else shape 0 and passes of about kDefaultPassLen iterations.
-void pick_tiling(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d, int n, int *shape, int *npass)
+// problem, else, for a cold float32 call of at most kTileMaxM iterations
+// whose dual is not kept (one pass, no dual in or out: where the
+// row-pipelined kernel measured faster than the tiles), a row-pipelined
+// shape when the problem fills the chip, else shape 0 and passes of about
+// kDefaultPassLen iterations.
+void pick_tiling(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d, int n, int *shape, int *npass,
+                 bool single_cold_pass = false)
 {
     *shape = 0;
     *npass = (n + kDefaultPassLen - 1) / kDefaultPassLen;
@@ -173,6 +206,13 @@ void pick_tiling(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d, 
     if (it != ctx->tuned.end()) {
         *shape = it->second.first;
         *npass = it->second.second;
+    } else if (single_cold_pass && p.dual_dtype == SCI_DUAL_F32 && tile_supported(p.tv) && n >= 1 &&
+               n <= kTileMaxM) {
+        const int rs = default_row_shape(ctx, d, n);
+        if (rs >= 0) {
+            *shape = rs;
+            *npass = 1;
+        }
     }
     if (p.tile_shape >= 1) *shape = p.tile_shape - 1;
     if (p.tile_passes >= 1) *npass = p.tile_passes;
@@ -185,7 +225,7 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
                      float *theta, float *u_out, bool keep_dual, hipStream_t s, int force_shape, int force_passes)
 {
     int shape = 0, npass = 1;
-    pick_tiling(ctx, p, d, n, &shape, &npass);
+    pick_tiling(ctx, p, d, n, &shape, &npass, !keep_dual && r.cur == nullptr);
     if (force_shape >= 0) shape = force_shape;
     if (force_passes >= 1) npass = force_passes;
     if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes the VTV kernel runs, unless more are asked for
