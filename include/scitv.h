@@ -101,7 +101,10 @@ typedef struct {
     int32_t n_inner_max;
     int32_t gap_check_every;
     int32_t tile_shape;      /* fused schedule: 0 = autotuned for this problem (sci_autotune) or the
-                                default; k >= 1 = tile shape k (see sci_tile_shape_info) */
+                                default (a cold float32 call of at most 10 iterations whose dual
+                                is not returned: the row-pipelined shape that best fills the GPU
+                                when the problem is large enough; otherwise shape 1); k >= 1 =
+                                shape k (see sci_tile_shape_info) */
     int32_t tile_passes;     /* fused schedule: passes over HBM per denoiser call (each runs about
                                 n_inner / tile_passes iterations, at most 10); 0 = autotuned or
                                 default (passes of about 5 iterations; VTV: the fewest passes its
