@@ -25,6 +25,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "k_fgp_rows.h"
@@ -254,16 +257,32 @@ constexpr int vtv_rows_max_m(int kf) { return kf == 1 ? 10 : kf == 2 ? 8 : kf ==
 // third hardly (measured); so: up to two workgroups per CU, as registers
 // allow, all in one round, and with that the tallest segments, which spend
 // the least on the pipeline fill.
+// Workgroups the launch aims at (CUs x co-resident workgroups, at most two),
+// queried once per (kernel, workgroup size, device).
+template <typename K>
+long vtv_target_groups(K kernel, int ng)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, int>, long> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const auto key = std::make_tuple((const void *)kernel, ng, dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int ncu = 0, nb = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 64 * ng, 0) != hipSuccess || nb < 1) nb = 1;
+    const long target = (long)std::min(nb, 2) * ncu;
+    cache.emplace(key, target);
+    return target;
+}
+
 template <typename K>
 int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
 {
-    int dev = 0, ncu = 0, nb = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
-        ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 64 * ng, 0) != hipSuccess || nb < 1) nb = 1;
-    const int per_cu = std::min(nb, 2);
-    const long target = (long)per_cu * ncu;
+    const long target = vtv_target_groups(kernel, ng);
     const int nseg = (int)std::min<long>(std::max<long>(1, target / nstrip), std::max(1, nx));
     return (nx + nseg - 1) / nseg;
 }
