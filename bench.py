@@ -385,8 +385,10 @@ def measure_kernels(scitv, h, dev, C, Y, X_true):
          dict(tv="vtv", schedule="stream"), per_pass_fgp, "fgp_stream", ""),
         ("a6 FGP pass, VTV, fused schedule (row-pipelined kernel, 5 iterations per pass)", dict(tv="vtv"),
          per_pass_vtv_fused, "fgp_fused", "bound by arithmetic and the per-iteration norm exchange, not HBM"),
-        ("f1 Chambolle-2004 pass, ITV2D, projected gradient", dict(tv="itv2d", chambolle04=True, accel=False),
-         per_pass_pg, "fgp_stream", ""),
+        ("f1 Chambolle-2004 pass, ITV2D, projected gradient, streaming schedule",
+         dict(tv="itv2d", chambolle04=True, accel=False, schedule="stream"), per_pass_pg, "fgp_stream", ""),
+        ("f1 Chambolle-2004, ITV2D, fused schedule (row-pipelined kernel, 10 iterations per pass)",
+         dict(tv="itv2d", chambolle04=True, accel=False), 8.0, "fgp_fused", "bound by arithmetic, not HBM"),
         ("f3 ATV-Clip pass", dict(tv="atv", clip=True), per_pass_pg, "fgp_stream", ""),
     ]
     for name, kw, bpv, fam, note in cases:

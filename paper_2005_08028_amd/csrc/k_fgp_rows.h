@@ -61,7 +61,10 @@ template <int M, int C> struct alignas(16) RowRing {
 // One wavefront's segment: strip sx, segment seg (rows [seg*H, seg*H + H)) of
 // the frame at element offset fo; V = elements per dual channel of the whole
 // video. MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
-template <int TV, int M, int DT, int C, int MODE>
+// CH = 1 replaces the projection of q by Chambolle's (2004) semi-implicit step
+// p = (w + z/(8 lambda)) / (1 + |z/(8 lambda)|), |.| per component (ATV) or
+// per voxel (ITV2D), with the operations of the streaming pass.
+template <int TV, int M, int DT, int C, int MODE, int CH_STEP = 0>
 __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, int H, uint32_t fo, uint32_t V,
                                               const float *__restrict__ x,
                                               const typename Dual<DT>::T *__restrict__ pc,
@@ -218,15 +221,28 @@ __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, i
                     const float thr = c < C - 1 ? cth[t][c + 1] : from_right(cth[t][0]);
                     const float zh = thr - cth[t][c];
                     const float zv = thn[c] - cth[t][c];
-                    const float qh = ascend(cwh[t][c], zh, step_h[c]);
-                    const float qv = ascend(cwv[t][c], zv, step_v);
-                    if (TV == TV_ATV) {
-                        nh[c] = proj_atv(qh);
-                        nv[c] = proj_atv(qv);
+                    if (CH_STEP) {
+                        const float sh = step_h[c] * zh, sv = step_v * zv;
+                        const float qh = cwh[t][c] + sh, qv = cwv[t][c] + sv;
+                        if (TV == TV_ATV) {
+                            nh[c] = qh / (1.0f + fabsf(sh));
+                            nv[c] = qv / (1.0f + fabsf(sv));
+                        } else {
+                            const float s1 = semi_implicit_scale(norm2_add(0.0f, sh, sv));
+                            nh[c] = qh * s1;
+                            nv[c] = qv * s1;
+                        }
                     } else {
-                        const float sc = iso_scale(norm2_add(0.0f, qh, qv));
-                        nh[c] = qh * sc;
-                        nv[c] = qv * sc;
+                        const float qh = ascend(cwh[t][c], zh, step_h[c]);
+                        const float qv = ascend(cwv[t][c], zv, step_v);
+                        if (TV == TV_ATV) {
+                            nh[c] = proj_atv(qh);
+                            nv[c] = proj_atv(qv);
+                        } else {
+                            const float sc = iso_scale(norm2_add(0.0f, qh, qv));
+                            nh[c] = qh * sc;
+                            nv[c] = qv * sc;
+                        }
                     }
                     oh[c] = extrapolate(nh[c], cph[t][c], bnext);
                     ov[c] = extrapolate(nv[c], cpv[t][c], bnext);
@@ -285,7 +301,7 @@ __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, i
 
 // One pass over every frame: a one-wavefront workgroup per (frame, segment,
 // strip), numbered XCD-contiguously.
-template <int TV, int M, int DT, int C, int MODE>
+template <int TV, int M, int DT, int C, int MODE, int CH_STEP>
 __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, int nseg, int H,
                                                     const float *__restrict__ x,
                                                     const typename Dual<DT>::T *__restrict__ pc,
@@ -299,14 +315,14 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
     const int per_frame = nstrip * nseg;
     const int frame = lin / per_frame, rem = lin % per_frame;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    fgp_rows_body<TV, M, DT, C, MODE>(nx, ny, rem % nstrip, rem / nstrip, H, (uint32_t)frame * plane,
+    fgp_rows_body<TV, M, DT, C, MODE, CH_STEP>(nx, ny, rem % nstrip, rem / nstrip, H, (uint32_t)frame * plane,
                                       plane * (gridDim.x / (uint32_t)per_frame), x, pc, pp, bt, lam, step, pn_out,
                                       pp_out, theta_out, u_out, ring);
 }
 
 // Launch of one pass over every frame: strips of 64*C - 2M - 1 interior
 // columns, segments of H rows.
-template <int TV, int M, int DT, int C>
+template <int TV, int M, int DT, int C, int CH_STEP>
 void launch_rows_m(int H, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s)
 {
     using T = typename Dual<DT>::T;
@@ -315,7 +331,7 @@ void launch_rows_m(int H, int nx, int ny, int B, const float *x, const TilePass 
     const dim3 g(nstrip * nseg * B), b(64);
     const float step = 1.0f / (8.0f * lam);
 #define SCI_ROWS_MODE(md)                                                                                           \
-    hipLaunchKernelGGL((k_fgp_rows<TV, M, DT, C, md>), g, b, 0, s, nx, ny, nstrip, nseg, H, x, (const T *)tp.pc,     \
+    hipLaunchKernelGGL((k_fgp_rows<TV, M, DT, C, md, CH_STEP>), g, b, 0, s, nx, ny, nstrip, nseg, H, x, (const T *)tp.pc,     \
                        (const T *)tp.pp, tp.beta, lam, step, (T *)tp.pn_out, (T *)tp.pp_out, tp.theta, tp.u_out)
     if (tp.mode == 0) SCI_ROWS_MODE(0);
     else if (tp.mode == 1) SCI_ROWS_MODE(1);
@@ -324,22 +340,22 @@ void launch_rows_m(int H, int nx, int ny, int B, const float *x, const TilePass 
 }
 
 // Dispatch on the pass length m = 1..kTileMaxM.
-template <int TV, int DT>
+template <int TV, int DT, int CH_STEP = 0>
 int launch_rows(int H, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s)
 {
     static_assert(kTileMaxM == 10, "pass lengths dispatched below");
     constexpr int C = kRowCols;
     switch (m) {
-    case 1: launch_rows_m<TV, 1, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 2: launch_rows_m<TV, 2, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 3: launch_rows_m<TV, 3, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 4: launch_rows_m<TV, 4, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 5: launch_rows_m<TV, 5, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 6: launch_rows_m<TV, 6, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 7: launch_rows_m<TV, 7, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 8: launch_rows_m<TV, 8, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 9: launch_rows_m<TV, 9, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
-    case 10: launch_rows_m<TV, 10, DT, C>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 1: launch_rows_m<TV, 1, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 2: launch_rows_m<TV, 2, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 3: launch_rows_m<TV, 3, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 4: launch_rows_m<TV, 4, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 5: launch_rows_m<TV, 5, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 6: launch_rows_m<TV, 6, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 7: launch_rows_m<TV, 7, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 8: launch_rows_m<TV, 8, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 9: launch_rows_m<TV, 9, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
+    case 10: launch_rows_m<TV, 10, DT, C, CH_STEP>(H, nx, ny, B, x, tp, lam, s); return SCI_OK;
     }
     return SCI_ERR_INVALID_ARG;
 }

@@ -14,6 +14,8 @@ int launch_rows_atv_f32(int H, int m, int nx, int ny, int B, const float *x, con
                         hipStream_t s);
 int launch_rows_itv_f32(int H, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
                         hipStream_t s);
+int launch_rows_ch_f32(int tv, int H, int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam,
+                       hipStream_t s);
 
 bool tile_supported(int tv) { return tv == TV_ATV || tv == TV_ITV2D; }
 
@@ -37,9 +39,15 @@ bool tile_shape_info(int shape, int *rows, int *waves, int *cols)
 bool tile_shape_pipelined(int shape) { return shape >= kTileShapes && shape < kTileShapes + kRowShapes; }
 
 int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,
-                    const TilePass &tp, float lam, hipStream_t s)
+                    const TilePass &tp, float lam, hipStream_t s, bool chambolle04)
 {
     if (m < 1 || m > kTileMaxM || shape < 0 || shape >= tile_shape_count()) return SCI_ERR_INVALID_ARG;
+    if (chambolle04) { // row-pipelined shapes, float32 duals, ATV and ITV2D only
+        int H = 0, w = 0, c = 0;
+        if (dual_dtype != DT_F32 || !tile_supported(tv) || !tile_shape_pipelined(shape)) return SCI_ERR_UNSUPPORTED;
+        tile_shape_info(shape, &H, &w, &c);
+        return launch_rows_ch_f32(tv, H, m, nx, ny, B, x, tp, lam, s);
+    }
     if (tv == TV_VTV) // one row-pipelined kernel, whatever the shape
         return dual_dtype == DT_F32 ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s) : SCI_ERR_UNSUPPORTED;
     if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;

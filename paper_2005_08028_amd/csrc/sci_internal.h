@@ -170,8 +170,10 @@ int vtv_rows_max_pass(int B);
 int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s);
 // shape: index into the shape table (0 = default); 16-bit dual storage runs
 // the default shape whatever is asked
+// chambolle04: Chambolle's (2004) step instead of FGP (row-pipelined shapes,
+// float32 duals, ATV and ITV2D)
 int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, int B, const float *x,
-                    const TilePass &tp, float lam, hipStream_t s);
+                    const TilePass &tp, float lam, hipStream_t s, bool chambolle04 = false);
 
 // ---- launchers (k_reduce.hip) -------------------------------------------------
 // Deterministic two-stage FP64 reductions into out_dev (device doubles).

@@ -53,8 +53,9 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p.tile_passes < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "tile_passes must be >= 0");
     if (p.chambolle04 != 0 && p.chambolle04 != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "chambolle04 must be 0 or 1");
-    if (p.chambolle04 && (p.dual_dtype != SCI_DUAL_F32 || p.schedule == SCI_SCHED_FUSED))
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "the Chambolle-2004 step runs with float32 duals on the streaming schedule");
+    if (p.chambolle04 && (p.dual_dtype != SCI_DUAL_F32 || (p.schedule == SCI_SCHED_FUSED && p.tv == SCI_TV_VTV)))
+        return fail(ctx, SCI_ERR_UNSUPPORTED,
+                    "the Chambolle-2004 step runs with float32 duals (fused schedule: ATV and ITV2D)");
     if (p.clip != 0 && p.clip != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "clip must be 0 or 1");
     if (p.clip) {
         if (p.tv != SCI_TV_ATV) return fail(ctx, SCI_ERR_INVALID_ARG, "ATV-Clip is defined for anisotropic TV");
@@ -228,6 +229,10 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
     pick_tiling(ctx, p, d, n, &shape, &npass, !keep_dual && r.cur == nullptr);
     if (force_shape >= 0) shape = force_shape;
     if (force_passes >= 1) npass = force_passes;
+    if (p.chambolle04 && !tile_shape_pipelined(shape)) { // only the row-pipelined kernel has this step
+        const int rs = default_row_shape(ctx, d, std::min(n, kTileMaxM));
+        shape = rs >= 0 ? rs : kTileShapes + 1;
+    }
     if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes the VTV kernel runs, unless more are asked for
         const int mm = vtv_rows_max_pass(d.B);
         if (mm < 1) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
@@ -255,7 +260,7 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
         tp.theta = last ? theta : nullptr;
         tp.u_out = last ? u_out : nullptr;
         ProfScope prof(ctx, m == 1 ? PF_FGP_STREAM : PF_FGP_FUSED, s);
-        int st = launch_fgp_tile(p.tv, p.dual_dtype, m, shape, d.nx, d.ny, d.B, x, tp, p.lambda, s);
+        int st = launch_fgp_tile(p.tv, p.dual_dtype, m, shape, d.nx, d.ny, d.B, x, tp, p.lambda, s, p.chambolle04 != 0);
         if (st != SCI_OK) return fail(ctx, st, "fused FGP pass not available for this request");
         st = check_launch(ctx, "k_fgp_tile");
         if (st != SCI_OK) return st;
@@ -290,12 +295,14 @@ bool vtv_fused_supported(const sci_tv_params &p, const sci_dims &d)
 
 bool fused_supported(const sci_tv_params &p, const sci_dims &d)
 {
-    return !p.chambolle04 && !p.clip && (tile_supported(p.tv) || vtv_fused_supported(p, d));
+    if (p.clip) return false;
+    if (p.chambolle04) return tile_supported(p.tv) && p.dual_dtype == SCI_DUAL_F32; // row-pipelined kernel
+    return tile_supported(p.tv) || vtv_fused_supported(p, d);
 }
 
 bool use_fused(const sci_tv_params &p, const sci_dims &d)
 {
-    if (p.schedule == SCI_SCHED_STREAM || p.chambolle04 || p.clip) return false;
+    if (p.schedule == SCI_SCHED_STREAM || p.clip) return false;
     if (p.schedule == SCI_SCHED_FUSED) return true;
     return fused_supported(p, d) && p.n_inner >= 2;
 }

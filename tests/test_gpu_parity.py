@@ -464,6 +464,50 @@ def test_chambolle04_matches_oracle(sc, ctx, tv, B, nx, ny):
         sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv=tv, n_inner=3, chambolle04=True, dual_dtype="bf16"))
 
 
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (2, 5, 3), (3, 130, 64), (2, 300, 130), (1, 97, 214)])
+def test_chambolle04_fused_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
+    """Chambolle-2004 step on the row-pipelined shapes against its streaming
+    pass: every row shape, one pass and several, cold and warm starts,
+    momentum off and on, final dual returned: identical bits."""
+    r = np.random.default_rng(B * 9 + nx + ny)
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    p0 = dev(r.uniform(-0.5, 0.5, size=(2, B, nx, ny)).astype(np.float32))
+    for n, passes, accel, warm in ((1, 1, False, False), (6, 1, False, False), (6, 2, False, True),
+                                   (10, 1, True, False), (13, 2, False, True)):
+        init = p0 if warm else None
+        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, chambolle04=True, schedule="stream")
+        dref = torch.empty((2, B, nx, ny), device="cuda")
+        tref, _, _, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=dref)
+        tref, dref = host(tref), host(dref)
+        for k in [0] + row_shapes(sc):
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=n, accel=accel, chambolle04=True, schedule="fused",
+                               tile_shape=k, tile_passes=passes)
+            d = torch.empty((2, B, nx, ny), device="cuda")
+            th, _, its, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d)
+            msg = f"shape {k} N={n} passes={passes} accel={accel} warm={warm}"
+            assert its == n, msg
+            np.testing.assert_array_equal(host(th), tref, err_msg="theta " + msg)
+            np.testing.assert_array_equal(host(d), dref, err_msg="dual " + msg)
+    with pytest.raises(RuntimeError):  # VTV keeps the streaming pass for this step
+        sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", n_inner=3, chambolle04=True, schedule="fused"))
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_chambolle04_fused_solvers_bitwise(sc, ctx, solver):
+    """GAP / ADMM solves with the Chambolle-2004 step, with and without the
+    warm dual: the fused schedule gives the bits of the streaming one."""
+    pr = synth.make_problem(150, 90, 6, seed=41, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (False, True):
+        kw = dict(outer_iters=4, rho=0.01, tv="itv2d", lam=0.1, n_inner=7, warm_dual=warm, chambolle04=True,
+                  accel=False)
+        xs, ts = run_solver(sc, ctx, solver, Y, pr.masks, schedule="stream", **kw)
+        xf, tf = run_solver(sc, ctx, solver, Y, pr.masks, schedule="fused", **kw)
+        np.testing.assert_array_equal(xf, xs, err_msg=f"{solver} warm={warm}")
+        np.testing.assert_array_equal(tf, ts, err_msg=f"{solver} warm={warm}")
+
+
 @pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (1, 2, 2), (2, 5, 3), (3, 17, 63), (4, 130, 64), (24, 16, 64)])
 def test_clip_matches_oracle(sc, ctx, B, nx, ny):
     """ATV-Clip: per-direction iterative clipping, threshold 2 lambda."""
