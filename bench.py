@@ -389,7 +389,10 @@ def measure_kernels(scitv, h, dev, C, Y, X_true):
          dict(tv="itv2d", chambolle04=True, accel=False, schedule="stream"), per_pass_pg, "fgp_stream", ""),
         ("f1 Chambolle-2004, ITV2D, fused schedule (row-pipelined kernel, 10 iterations per pass)",
          dict(tv="itv2d", chambolle04=True, accel=False), 8.0, "fgp_fused", "bound by arithmetic, not HBM"),
-        ("f3 ATV-Clip pass", dict(tv="atv", clip=True), per_pass_pg, "fgp_stream", ""),
+        ("f3 ATV-Clip pass, streaming schedule", dict(tv="atv", clip=True, schedule="stream"), per_pass_pg,
+         "fgp_stream", ""),
+        ("f3 ATV-Clip, fused schedule (row-pipelined kernel, 10 iterations per pass)", dict(tv="atv", clip=True),
+         8.0, "fgp_fused", "bound by arithmetic, not HBM"),
     ]
     for name, kw, bpv, fam, note in cases:
         prm = scitv.solver_params(outer_iters=2, lam=0.1, n_inner=N, **kw)

@@ -134,6 +134,11 @@ int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B,
                                   const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
 // One ATV-Clip iteration: w_next = per-direction clip(w + D theta_d / alpha,
 // 2 lambda) with theta_d = x - D_d^T w_d; w nullable = zero (k_clip.hip).
+// m (1..kTileMaxM) ATV-Clip iterations in one row-pipelined pass (k_clip_rows.hip):
+// segments of H rows, starting duals w_in (nullable = zero), final duals to
+// w_out (nullable), theta = x - D^T w and u = x - theta (nullable).
+int launch_clip_rows(int H, int m, int nx, int ny, int B, const float *x, const float *w_in, float *w_out,
+                     float alpha, float lambda, float *theta, float *u_out, hipStream_t s);
 void launch_clip(int nx, int ny, int B, const float *x, const float *w, float *w_next, float alpha, float lambda,
                  hipStream_t s);
 // theta = x - lambda D^T p; when u_out is non-null also u_out = x - theta.

@@ -61,9 +61,8 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         if (p.tv != SCI_TV_ATV) return fail(ctx, SCI_ERR_INVALID_ARG, "ATV-Clip is defined for anisotropic TV");
         if (!(p.clip_alpha >= 0.0f) || !std::isfinite(p.clip_alpha))
             return fail(ctx, SCI_ERR_INVALID_ARG, "clip_alpha must be finite and >= 0 (0 = 4)");
-        if (p.chambolle04 || p.dual_dtype != SCI_DUAL_F32 || p.schedule == SCI_SCHED_FUSED || p.gap_tol > 0.0)
-            return fail(ctx, SCI_ERR_UNSUPPORTED,
-                        "ATV-Clip runs a fixed iteration count with float32 duals on the streaming schedule");
+        if (p.chambolle04 || p.dual_dtype != SCI_DUAL_F32 || p.gap_tol > 0.0)
+            return fail(ctx, SCI_ERR_UNSUPPORTED, "ATV-Clip runs a fixed iteration count with float32 duals");
     }
     return SCI_OK;
 }
@@ -295,14 +294,14 @@ bool vtv_fused_supported(const sci_tv_params &p, const sci_dims &d)
 
 bool fused_supported(const sci_tv_params &p, const sci_dims &d)
 {
-    if (p.clip) return false;
+    if (p.clip) return p.tv == SCI_TV_ATV && p.dual_dtype == SCI_DUAL_F32; // row-pipelined clip kernel
     if (p.chambolle04) return tile_supported(p.tv) && p.dual_dtype == SCI_DUAL_F32; // row-pipelined kernel
     return tile_supported(p.tv) || vtv_fused_supported(p, d);
 }
 
 bool use_fused(const sci_tv_params &p, const sci_dims &d)
 {
-    if (p.schedule == SCI_SCHED_STREAM || p.clip) return false;
+    if (p.schedule == SCI_SCHED_STREAM) return false;
     if (p.schedule == SCI_SCHED_FUSED) return true;
     return fused_supported(p, d) && p.n_inner >= 2;
 }
@@ -329,6 +328,32 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
     if (p.clip) {
         // ATV-Clip: per-direction duals, output x - D^T w (lambda enters as the threshold)
         const float alpha = p.clip_alpha > 0.0f ? p.clip_alpha : 4.0f;
+        if (use_fused(p, d)) { // row-pipelined passes of up to kTileMaxM iterations
+            const int n = p.n_inner;
+            int npass = std::max((n + kTileMaxM - 1) / kTileMaxM, p.tile_passes);
+            npass = std::min(npass, n);
+            int shape = p.tile_shape >= 1 ? p.tile_shape - 1 : -1;
+            if (shape < 0 || !tile_shape_pipelined(shape)) {
+                const int rs = default_row_shape(ctx, d, (n + npass - 1) / npass);
+                shape = rs >= 0 ? rs : kTileShapes + 1;
+            }
+            int H = 0, w = 0, c = 0;
+            tile_shape_info(shape, &H, &w, &c);
+            for (int q = 0; q < npass; ++q) {
+                const int m = n / npass + (q < n % npass ? 1 : 0);
+                const bool last = q == npass - 1;
+                float *out = (!last || keep_dual) ? (float *)r.free_buffer() : nullptr;
+                ProfScope prof(ctx, PF_FGP_FUSED, s);
+                int st = launch_clip_rows(H, m, d.nx, d.ny, d.B, x, (const float *)r.cur, out, alpha, p.lambda,
+                                          last ? theta : nullptr, last ? u_out : nullptr, s);
+                if (st != SCI_OK) return fail(ctx, st, "fused ATV-Clip pass");
+                if ((st = check_launch(ctx, "k_clip_rows")) != SCI_OK) return st;
+                r.prev = r.cur;
+                r.cur = out;
+                r.iters += m;
+            }
+            return SCI_OK;
+        }
         for (int it = 0; it < p.n_inner; ++it) {
             float *out = (float *)r.free_buffer();
             ProfScope prof(ctx, PF_FGP_STREAM, s);

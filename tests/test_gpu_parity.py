@@ -524,10 +524,49 @@ def test_clip_matches_oracle(sc, ctx, B, nx, ny):
         ew = np.abs(host(dual) - wref).max()
         say(f"clip B={B} {nx}x{ny} N={n} alpha={alpha} warm={warm}: rel-L2 {e:.2e}, dual {ew:.2e}")
         assert e <= REL_TOL and ew <= 1e-6
-    for bad in (dict(tv="itv2d"), dict(tv="atv", dual_dtype="bf16"), dict(tv="atv", schedule="fused"),
-                dict(tv="atv", gap_tol=1e-3, n_inner_max=10)):
+    for bad in (dict(tv="itv2d"), dict(tv="atv", dual_dtype="bf16"), dict(tv="atv", gap_tol=1e-3, n_inner_max=10)):
         with pytest.raises(RuntimeError):
             sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(lam=0.05, n_inner=3, clip=True, **bad))
+
+
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (2, 5, 3), (3, 130, 64), (2, 300, 130), (1, 97, 214)])
+def test_clip_fused_bitwise_equals_streaming(sc, ctx, B, nx, ny):
+    """ATV-Clip on the row-pipelined kernel against one pass per iteration:
+    every row shape, one pass and several, cold and warm starts, final duals
+    returned: identical bits."""
+    r = np.random.default_rng(B * 17 + nx + ny)
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    w0 = dev(r.uniform(-0.1, 0.1, size=(2, B, nx, ny)).astype(np.float32))
+    for n, passes, alpha, warm in ((1, 0, 0.0, False), (4, 0, 3.0, True), (10, 0, 0.0, False), (13, 2, 4.5, True),
+                                   (25, 0, 0.0, False)):
+        init = w0 if warm else None
+        prm = sc.tv_params(tv="atv", lam=0.05, n_inner=n, clip=True, clip_alpha=alpha, schedule="stream")
+        dref = torch.empty((2, B, nx, ny), device="cuda")
+        tref, _, _, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=dref)
+        tref, dref = host(tref), host(dref)
+        for k in [0] + row_shapes(sc):
+            prm = sc.tv_params(tv="atv", lam=0.05, n_inner=n, clip=True, clip_alpha=alpha, schedule="fused",
+                               tile_shape=k, tile_passes=passes)
+            d = torch.empty((2, B, nx, ny), device="cuda")
+            th, _, its, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d)
+            msg = f"shape {k} N={n} passes={passes} alpha={alpha} warm={warm}"
+            assert its == n, msg
+            np.testing.assert_array_equal(host(th), tref, err_msg="theta " + msg)
+            np.testing.assert_array_equal(host(d), dref, err_msg="dual " + msg)
+
+
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_clip_fused_solvers_bitwise(sc, ctx, solver):
+    """GAP / ADMM with ATV-Clip (ADMM takes u = s - theta from the kernel), with
+    and without the warm dual: the fused schedule gives the streaming bits."""
+    pr = synth.make_problem(150, 90, 6, seed=51, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (False, True):
+        kw = dict(outer_iters=4, rho=0.05, tv="atv", lam=0.05, n_inner=6, clip=True, warm_dual=warm)
+        xs, ts = run_solver(sc, ctx, solver, Y, pr.masks, schedule="stream", **kw)
+        xf, tf = run_solver(sc, ctx, solver, Y, pr.masks, schedule="fused", **kw)
+        np.testing.assert_array_equal(xf, xs, err_msg=f"{solver} warm={warm}")
+        np.testing.assert_array_equal(tf, ts, err_msg=f"{solver} warm={warm}")
 
 
 @pytest.mark.parametrize("solver", ["gap", "admm"])
