@@ -77,9 +77,9 @@ typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_
  *   FUSED : up to 10 inner iterations per on-chip pass, the dual fields
  *           written back only between passes (ATV and ITV2D with any dual
  *           type, and their Chambolle-2004 step with float32 duals on the
- *           row-pipelined shapes; VTV with float32 duals, passes of at most
- *           10 / 8 / 5 / 4 iterations for B <= 8 / 16 / 24 / 32; not
- *           ATV-Clip);
+ *           row-pipelined shapes; ATV-Clip with float32 duals; VTV with
+ *           float32 duals, passes of at most 10 / 8 / 5 / 4 iterations for
+ *           B <= 8 / 16 / 24 / 32);
  *   AUTO  : FUSED where it applies, else STREAM.
  * Both schedules evaluate the same per-voxel expressions (bit for bit with
  * float32 duals; 16-bit duals are rounded where they are stored). */
@@ -119,8 +119,9 @@ typedef struct {
     int32_t clip;            /* 1 = ATV-Clip (Sec. 2.3, Algorithm 1 Clip box): one dual per
                                 direction, w_d <- clip(w_d + D_d (x - D_d^T w_d) / clip_alpha,
                                 2 lambda), output x - D_h^T w_h - D_v^T w_v; tv must be ATV,
-                                float32 duals, streaming schedule, fixed n_inner (accel and
-                                chambolle04 do not apply). 0 = FGP / projected gradient */
+                                float32 duals, fixed n_inner (accel and chambolle04 do not
+                                apply); fused schedule: row-pipelined passes (tile_shape a
+                                row-pipelined shape or 0). 0 = FGP / projected gradient */
     float clip_alpha;        /* ATV-Clip step 1/clip_alpha; 0 = 4 (the largest eigenvalue of
                                 D_d D_d^T is below 4; the iteration converges for alpha > 2) */
 } sci_tv_params;
