@@ -52,7 +52,7 @@ extern "C" {
 #define SCI_ERR_ALIAS (-2)      /* an output overlaps an input */
 #define SCI_ERR_NOMEM (-3)      /* device scratch allocation failed */
 #define SCI_ERR_HIP (-4)        /* a HIP runtime call failed; sci_last_error() has the text */
-#define SCI_ERR_UNSUPPORTED (-5)/* valid request this build does not implement (message in sci_last_error) */
+#define SCI_ERR_UNSUPPORTED (-5)/* valid request the library does not implement (message in sci_last_error) */
 
 typedef struct sci_ctx sci_ctx;
 

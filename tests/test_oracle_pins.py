@@ -705,7 +705,7 @@ def test_clip_large_lambda_gives_row_plus_column_means():
 
 
 def test_clip_inside_gap():
-    """GAP with the Clip denoiser: the driver passes the denoiser input and
+    """GAP with the Clip denoiser: the outer loop passes the denoiser input and
     carries nothing else (written-out loop), and the measurement holds."""
     C, X, Y = small_problem(63, B=3, nx=8, ny=9)
     x, th = orc.gap_tv(Y, C, 0.05, 3, 6, tv="atv", clip=True, clip_alpha=5.0)
