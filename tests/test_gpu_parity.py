@@ -285,6 +285,24 @@ def test_vtv_fused_solvers_bitwise(sc, ctx, solver):
             np.testing.assert_array_equal(xg, xs, err_msg=f"{solver} warm={warm} graph replay {rep}")
 
 
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+def test_row_pipelined_matches_oracle(sc, ctx, tv):
+    """Every row-pipelined shape against the FP64 oracle directly (several
+    segments and strips, a ragged last strip), theta and the final dual."""
+    B, nx, ny = 2, 300, 230
+    r = np.random.default_rng(61)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    ref, pref = orc.tv_denoise(x, f32(0.1), 10, tv, return_dual=True)
+    for k in row_shapes(sc):
+        prm = sc.tv_params(tv=tv, lam=0.1, n_inner=10, schedule="fused", tile_shape=k, tile_passes=1)
+        dual = torch.empty((2, B, nx, ny), device="cuda")
+        th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_out=dual)
+        e = rel_l2(host(th), ref)
+        ep = np.abs(host(dual) - pref).max()
+        say(f"row shape {k} {sc.sci_tile_shape_info(k)} {tv}: rel-L2 {e:.2e}, dual max-abs {ep:.2e}")
+        assert e <= REL_TOL and ep <= 1e-4
+
+
 @pytest.mark.parametrize("solver", ["gap", "admm"])
 def test_row_pipelined_solvers_bitwise(sc, ctx, solver):
     """Whole GAP / ADMM solves (ADMM takes u = s - theta from the kernel),
