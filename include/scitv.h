@@ -76,10 +76,10 @@ typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_
  *   STREAM: one pass over HBM per inner iteration (dual fields in memory);
  *   FUSED : up to 10 inner iterations per on-chip pass, the dual fields
  *           written back only between passes (ATV and ITV2D with any dual
- *           type, and their Chambolle-2004 step with float32 duals on the
- *           row-pipelined shapes; ATV-Clip with float32 duals; VTV with
- *           float32 duals, passes of at most 10 / 8 / 5 / 4 iterations for
- *           B <= 8 / 16 / 24 / 32);
+ *           type; VTV with float32 duals, passes of at most 10 / 8 / 5 / 4
+ *           iterations for B <= 8 / 16 / 24 / 32; the Chambolle-2004 step
+ *           with float32 duals on the row-pipelined kernels; ATV-Clip with
+ *           float32 duals);
  *   AUTO  : FUSED where it applies, else STREAM.
  * Both schedules evaluate the same per-voxel expressions (bit for bit with
  * float32 duals; 16-bit duals are rounded where they are stored). */
@@ -113,9 +113,9 @@ typedef struct {
     int32_t chambolle04;     /* 1 = Chambolle's (2004) semi-implicit step (Sec. 2.3):
                                 p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)), z = D theta, |z| per
                                 the TV kind, in place of the projection of w + z/(8 lambda);
-                                float32 duals; ATV and ITV2D run it on the fused schedule too
-                                (row-pipelined shapes; tile_shape is then a row-pipelined shape
-                                or 0), VTV on the streaming schedule only. 0 = projection */
+                                float32 duals; fused schedule: row-pipelined passes (for ATV and
+                                ITV2D tile_shape is then a row-pipelined shape or 0). 0 =
+                                projection */
     int32_t clip;            /* 1 = ATV-Clip (Sec. 2.3, Algorithm 1 Clip box): one dual per
                                 direction, w_d <- clip(w_d + D_d (x - D_d^T w_d) / clip_alpha,
                                 2 lambda), output x - D_h^T w_h - D_v^T w_v; tv must be ATV,

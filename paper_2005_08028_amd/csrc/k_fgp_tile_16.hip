@@ -42,14 +42,14 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
                     const TilePass &tp, float lam, hipStream_t s, bool chambolle04)
 {
     if (m < 1 || m > kTileMaxM || shape < 0 || shape >= tile_shape_count()) return SCI_ERR_INVALID_ARG;
-    if (chambolle04) { // row-pipelined shapes, float32 duals, ATV and ITV2D only
+    if (tv == TV_VTV) // one row-pipelined kernel, whatever the shape
+        return dual_dtype == DT_F32 ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s, chambolle04) : SCI_ERR_UNSUPPORTED;
+    if (chambolle04) { // row-pipelined shapes, float32 duals, ATV and ITV2D
         int H = 0, w = 0, c = 0;
         if (dual_dtype != DT_F32 || !tile_supported(tv) || !tile_shape_pipelined(shape)) return SCI_ERR_UNSUPPORTED;
         tile_shape_info(shape, &H, &w, &c);
         return launch_rows_ch_f32(tv, H, m, nx, ny, B, x, tp, lam, s);
     }
-    if (tv == TV_VTV) // one row-pipelined kernel, whatever the shape
-        return dual_dtype == DT_F32 ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s) : SCI_ERR_UNSUPPORTED;
     if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;
     if (dual_dtype == DT_F32 && tile_shape_pipelined(shape)) {
         int H = 0, w = 0, c = 0;

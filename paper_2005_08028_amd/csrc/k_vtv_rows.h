@@ -39,7 +39,10 @@ namespace sci {
 constexpr int kVtvMaxWaves = 8; // wavefronts (frame groups) per workgroup, at most
 
 // MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
-template <int M, int KF, int MODE>
+// CH_STEP = 1: Chambolle's (2004) semi-implicit step in place of the
+// projection, |z/(8 lambda)| over all frames of the pixel, with the
+// operations of the streaming pass.
+template <int M, int KF, int MODE, int CH_STEP>
 __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, int B, int fpw, int nstrip, int H,
                                                               const float *__restrict__ x,
                                                               const float *__restrict__ pc,
@@ -179,9 +182,17 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                     thn[kk] = theta_of(xl[t][kk], from_left(ih[kk]), ih[kk], cwv[t][kk], iv[kk], lam);
                     const float zh = from_right(cth[t][kk]) - cth[t][kk];
                     const float zv = thn[kk] - cth[t][kk];
-                    qh[kk] = ascend(cwh[t][kk], zh, step_h);
-                    qv[kk] = ascend(cwv[t][kk], zv, step_v);
-                    const float n2a = norm2_add(n2, qh[kk], qv[kk]);
+                    float n2a;
+                    if (CH_STEP) {
+                        const float sh = step_h * zh, sv = step_v * zv;
+                        qh[kk] = cwh[t][kk] + sh;
+                        qv[kk] = cwv[t][kk] + sv;
+                        n2a = norm2_add(n2, sh, sv);
+                    } else {
+                        qh[kk] = ascend(cwh[t][kk], zh, step_h);
+                        qv[kk] = ascend(cwv[t][kk], zv, step_v);
+                        n2a = norm2_add(n2, qh[kk], qv[kk]);
+                    }
                     n2 = kk < nk ? n2a : n2;
                 }
                 n2s[par][g][lane] = n2;
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                 float tot = 0.0f;
                 for (int gg = 0; gg < ng; ++gg) tot += n2s[par][gg][lane];
                 par ^= 1;
-                const float sc = iso_scale(tot);
+                const float sc = CH_STEP ? semi_implicit_scale(tot) : iso_scale(tot);
                 const float bnext = bt.b[t + 1];
 #pragma unroll
                 for (int kk = 0; kk < KF; ++kk) {
@@ -287,30 +298,30 @@ int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
     return (nx + nseg - 1) / nseg;
 }
 
-template <int M, int KF, int MODE>
+template <int M, int KF, int MODE, int CH_STEP>
 void launch_vtv_mode(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                      hipStream_t s)
 {
     constexpr int TXO = 64 - 2 * M - 1;
     const int nstrip = (ny + TXO - 1) / TXO;
-    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE>, ng, nx, nstrip);
+    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE, CH_STEP>, ng, nx, nstrip);
     const int nseg = (nx + H - 1) / H;
-    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny, B, fpw, nstrip,
+    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE, CH_STEP>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny, B, fpw, nstrip,
                        H, x, (const float *)tp.pc, (const float *)tp.pp, tp.beta, lam, 1.0f / (8.0f * lam),
                        (float *)tp.pn_out, (float *)tp.pp_out, tp.theta, tp.u_out);
 }
 
-template <int M, int KF>
+template <int M, int KF, int CH_STEP>
 void launch_vtv_m(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                   hipStream_t s)
 {
-    if (tp.mode == 0) launch_vtv_mode<M, KF, 0>(nx, ny, B, fpw, ng, x, tp, lam, s);
-    else if (tp.mode == 1) launch_vtv_mode<M, KF, 1>(nx, ny, B, fpw, ng, x, tp, lam, s);
-    else launch_vtv_mode<M, KF, 2>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    if (tp.mode == 0) launch_vtv_mode<M, KF, 0, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    else if (tp.mode == 1) launch_vtv_mode<M, KF, 1, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    else launch_vtv_mode<M, KF, 2, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);
 }
 
 // Dispatch on the pass length m = 1..vtv_rows_max_m(KF).
-template <int KF>
+template <int KF, int CH_STEP>
 int launch_vtv_kf(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                   hipStream_t s)
 {
@@ -319,7 +330,7 @@ int launch_vtv_kf(int m, int nx, int ny, int B, int fpw, int ng, const float *x,
     switch (m) {
 #define SCI_VTV_M(mm)                                                                                               \
     case mm:                                                                                                        \
-        if constexpr (mm <= MM) launch_vtv_m<mm, KF>(nx, ny, B, fpw, ng, x, tp, lam, s);                            \
+        if constexpr (mm <= MM) launch_vtv_m<mm, KF, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);                            \
         return SCI_OK;
         SCI_VTV_M(1) SCI_VTV_M(2) SCI_VTV_M(3) SCI_VTV_M(4) SCI_VTV_M(5) SCI_VTV_M(6) SCI_VTV_M(7) SCI_VTV_M(8)
         SCI_VTV_M(9) SCI_VTV_M(10)

@@ -12,16 +12,35 @@ int launch_vtv_rows_kf3(int m, int nx, int ny, int B, int fpw, int ng, const flo
 int launch_vtv_rows_kf4(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
                         float lam, hipStream_t s);
 
+int launch_vtv_rows_ch_kf1(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
+                            float lam, hipStream_t s);
+int launch_vtv_rows_ch_kf2(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
+                            float lam, hipStream_t s);
+int launch_vtv_rows_ch_kf3(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
+                            float lam, hipStream_t s);
+int launch_vtv_rows_ch_kf4(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
+                            float lam, hipStream_t s);
+
 // Frames per wavefront and wavefronts per workgroup: the split of the
 // streaming VTV pass (at most kVtvMaxWaves wavefronts).
 static int vtv_fpw(int B) { return (B + kVtvMaxWaves - 1) / kVtvMaxWaves; }
 
 int vtv_rows_max_pass(int B) { return B >= 1 ? vtv_rows_max_m(vtv_fpw(B)) : 0; }
 
-int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s)
+int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,
+                    bool chambolle04)
 {
     if (B < 1 || m < 1 || m > vtv_rows_max_pass(B)) return SCI_ERR_UNSUPPORTED;
     const int fpw = vtv_fpw(B), ng = (B + fpw - 1) / fpw;
+    if (chambolle04) {
+        switch (fpw) {
+        case 1: return launch_vtv_rows_ch_kf1(m, nx, ny, B, fpw, ng, x, tp, lam, s);
+        case 2: return launch_vtv_rows_ch_kf2(m, nx, ny, B, fpw, ng, x, tp, lam, s);
+        case 3: return launch_vtv_rows_ch_kf3(m, nx, ny, B, fpw, ng, x, tp, lam, s);
+        case 4: return launch_vtv_rows_ch_kf4(m, nx, ny, B, fpw, ng, x, tp, lam, s);
+        }
+        return SCI_ERR_UNSUPPORTED;
+    }
     switch (fpw) {
     case 1: return launch_vtv_rows_kf1(m, nx, ny, B, fpw, ng, x, tp, lam, s);
     case 2: return launch_vtv_rows_kf2(m, nx, ny, B, fpw, ng, x, tp, lam, s);
@@ -34,7 +53,7 @@ int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass
 int launch_vtv_rows_kf1(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
                          float lam, hipStream_t s)
 {
-    return launch_vtv_kf<1>(m, nx, ny, B, fpw, ng, x, tp, lam, s);
+    return launch_vtv_kf<1, 0>(m, nx, ny, B, fpw, ng, x, tp, lam, s);
 }
 
 } // namespace sci

@@ -6,7 +6,7 @@ namespace sci {
 int launch_vtv_rows_kf2(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp,
                          float lam, hipStream_t s)
 {
-    return launch_vtv_kf<2>(m, nx, ny, B, fpw, ng, x, tp, lam, s);
+    return launch_vtv_kf<2, 0>(m, nx, ny, B, fpw, ng, x, tp, lam, s);
 }
 
 } // namespace sci

@@ -172,7 +172,8 @@ bool tile_shape_pipelined(int shape);
 // Row-pipelined VTV passes (float32 duals): the longest pass for B frames (0
 // when the kernel does not run them), and one pass of m iterations.
 int vtv_rows_max_pass(int B);
-int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s);
+int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,
+                    bool chambolle04 = false);
 // shape: index into the shape table (0 = default); 16-bit dual storage runs
 // the default shape whatever is asked
 // chambolle04: Chambolle's (2004) step instead of FGP (row-pipelined shapes,

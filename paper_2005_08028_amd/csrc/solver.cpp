@@ -53,9 +53,8 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p.tile_passes < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "tile_passes must be >= 0");
     if (p.chambolle04 != 0 && p.chambolle04 != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "chambolle04 must be 0 or 1");
-    if (p.chambolle04 && (p.dual_dtype != SCI_DUAL_F32 || (p.schedule == SCI_SCHED_FUSED && p.tv == SCI_TV_VTV)))
-        return fail(ctx, SCI_ERR_UNSUPPORTED,
-                    "the Chambolle-2004 step runs with float32 duals (fused schedule: ATV and ITV2D)");
+    if (p.chambolle04 && p.dual_dtype != SCI_DUAL_F32)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "the Chambolle-2004 step runs with float32 duals");
     if (p.clip != 0 && p.clip != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "clip must be 0 or 1");
     if (p.clip) {
         if (p.tv != SCI_TV_ATV) return fail(ctx, SCI_ERR_INVALID_ARG, "ATV-Clip is defined for anisotropic TV");
@@ -228,7 +227,7 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
     pick_tiling(ctx, p, d, n, &shape, &npass, !keep_dual && r.cur == nullptr);
     if (force_shape >= 0) shape = force_shape;
     if (force_passes >= 1) npass = force_passes;
-    if (p.chambolle04 && !tile_shape_pipelined(shape)) { // only the row-pipelined kernel has this step
+    if (p.chambolle04 && p.tv != SCI_TV_VTV && !tile_shape_pipelined(shape)) { // only the row kernel has this step
         const int rs = default_row_shape(ctx, d, std::min(n, kTileMaxM));
         shape = rs >= 0 ? rs : kTileShapes + 1;
     }
@@ -289,13 +288,14 @@ void bind_duals(sci_ctx *ctx, FgpRun &r)
 // VTV on the fused schedule: the row-pipelined kernel with float32 duals.
 bool vtv_fused_supported(const sci_tv_params &p, const sci_dims &d)
 {
-    return p.tv == SCI_TV_VTV && p.dual_dtype == SCI_DUAL_F32 && !p.chambolle04 && !p.clip && vtv_rows_max_pass(d.B) > 0;
+    return p.tv == SCI_TV_VTV && p.dual_dtype == SCI_DUAL_F32 && !p.clip && vtv_rows_max_pass(d.B) > 0;
 }
 
 bool fused_supported(const sci_tv_params &p, const sci_dims &d)
 {
     if (p.clip) return p.tv == SCI_TV_ATV && p.dual_dtype == SCI_DUAL_F32; // row-pipelined clip kernel
-    if (p.chambolle04) return tile_supported(p.tv) && p.dual_dtype == SCI_DUAL_F32; // row-pipelined kernel
+    if (p.chambolle04) // row-pipelined kernels
+        return p.dual_dtype == SCI_DUAL_F32 && (tile_supported(p.tv) || vtv_fused_supported(p, d));
     return tile_supported(p.tv) || vtv_fused_supported(p, d);
 }
 

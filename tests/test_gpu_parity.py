@@ -507,8 +507,28 @@ def test_chambolle04_fused_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
             assert its == n, msg
             np.testing.assert_array_equal(host(th), tref, err_msg="theta " + msg)
             np.testing.assert_array_equal(host(d), dref, err_msg="dual " + msg)
-    with pytest.raises(RuntimeError):  # VTV keeps the streaming pass for this step
-        sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", n_inner=3, chambolle04=True, schedule="fused"))
+
+
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (3, 2, 5), (10, 130, 150), (24, 64, 64), (29, 9, 130)])
+def test_chambolle04_vtv_fused_bitwise_equals_streaming(sc, ctx, B, nx, ny):
+    """VTV with the Chambolle-2004 step: the fused (row-pipelined) kernel
+    against the streaming pass, one pass and several, cold and warm starts:
+    identical bits."""
+    r = np.random.default_rng(B * 19 + nx + ny)
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    p0 = dev(r.uniform(-0.3, 0.3, size=(2, B, nx, ny)).astype(np.float32))
+    for n, accel, warm in ((1, False, False), (5, False, False), (10, False, True), (7, True, False)):
+        init = p0 if warm else None
+        outs = []
+        for schedule in ("stream", "fused"):
+            prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=n, accel=accel, chambolle04=True, schedule=schedule)
+            d = torch.empty((2, B, nx, ny), device="cuda")
+            th, _, its, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d)
+            assert its == n
+            outs.append((host(th), host(d)))
+        msg = f"VTV Chambolle-2004 B={B} {nx}x{ny} N={n} accel={accel} warm={warm}"
+        np.testing.assert_array_equal(outs[1][0], outs[0][0], err_msg="theta " + msg)
+        np.testing.assert_array_equal(outs[1][1], outs[0][1], err_msg="dual " + msg)
 
 
 @pytest.mark.parametrize("solver", ["gap", "admm"])
