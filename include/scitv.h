@@ -102,10 +102,10 @@ typedef struct {
     int32_t n_inner_max;
     int32_t gap_check_every;
     int32_t tile_shape;      /* fused schedule: 0 = autotuned for this problem (sci_autotune) or the
-                                default (a cold float32 call of at most 10 iterations whose dual
-                                is not returned: the row-pipelined shape that best fills the GPU
-                                when the problem is large enough; otherwise shape 1); k >= 1 =
-                                shape k (see sci_tile_shape_info) */
+                                default (a cold call of at most 10 iterations whose dual is not
+                                returned: the row-pipelined shape that best fills the GPU when
+                                the problem is large enough; otherwise shape 1); k >= 1 = shape k
+                                (see sci_tile_shape_info) */
     int32_t tile_passes;     /* fused schedule: passes over HBM per denoiser call (each runs about
                                 n_inner / tile_passes iterations, at most 10); 0 = autotuned or
                                 default (passes of about 5 iterations; VTV: the fewest passes its
@@ -340,8 +340,10 @@ int sci_tile_shape_count(void);
  * bottom, every iteration of the pass one row behind the previous one
  * (temporal wavefront blocking; no rows are recomputed apart from the
  * pipeline fill of about 2 n rows per segment). Row-pipelined shapes run
- * float32 dual storage (16-bit storage runs the default shape). Any output
- * pointer may be NULL. */
+ * float32 dual storage; with 16-bit storage they serve cold passes that
+ * neither read nor return the dual (the storage is then never touched), and
+ * any other 16-bit pass runs the default shape. Any output pointer may be
+ * NULL. */
 int sci_tile_shape_info(int32_t shape, int32_t *rows_per_wave, int32_t *waves_per_group, int32_t *cols_per_lane);
 
 /* 1 if shape k (1-based) is row-pipelined, 0 if tiled, SCI_ERR_INVALID_ARG

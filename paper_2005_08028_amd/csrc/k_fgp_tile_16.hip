@@ -51,7 +51,11 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
         return launch_rows_ch_f32(tv, H, m, nx, ny, B, x, tp, lam, s);
     }
     if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;
-    if (dual_dtype == DT_F32 && tile_shape_pipelined(shape)) {
+    // A cold pass that neither returns nor keeps the dual never stores it, so
+    // its storage type does not matter: 16-bit requests take the float32 row
+    // kernel too (same bits as their own tiles, whose registers are float32).
+    const bool no_dual_io = tp.mode == 0 && !tp.pn_out && !tp.pp_out;
+    if ((dual_dtype == DT_F32 || no_dual_io) && tile_shape_pipelined(shape)) {
         int H = 0, w = 0, c = 0;
         tile_shape_info(shape, &H, &w, &c);
         return tv == TV_ATV ? launch_rows_atv_f32(H, m, nx, ny, B, x, tp, lam, s)

@@ -191,8 +191,8 @@ int default_row_shape(const sci_ctx *ctx, const sci_dims &d, int m)
 
 // Tile shape and number of passes of the fused schedule: explicit
 // (tile_shape / tile_passes >= 1), else the autotuned choice for this
-// problem, else, for a cold float32 call of at most kTileMaxM iterations
-// whose dual is not kept (one pass, no dual in or out: where the
+// problem, else, for a cold call of at most kTileMaxM iterations whose dual
+// is not kept (one pass, no dual in or out, so any storage type: where the
 // row-pipelined kernel measured faster than the tiles), a row-pipelined
 // shape when the problem fills the chip, else shape 0 and passes of about
 // kDefaultPassLen iterations.
@@ -205,8 +205,7 @@ void pick_tiling(const sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d, 
     if (it != ctx->tuned.end()) {
         *shape = it->second.first;
         *npass = it->second.second;
-    } else if (single_cold_pass && p.dual_dtype == SCI_DUAL_F32 && tile_supported(p.tv) && n >= 1 &&
-               n <= kTileMaxM) {
+    } else if (single_cold_pass && tile_supported(p.tv) && n >= 1 && n <= kTileMaxM) {
         const int rs = default_row_shape(ctx, d, n);
         if (rs >= 0) {
             *shape = rs;

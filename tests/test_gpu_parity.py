@@ -303,6 +303,22 @@ def test_row_pipelined_matches_oracle(sc, ctx, tv):
         assert e <= REL_TOL and ep <= 1e-4
 
 
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+def test_row_pipelined_16bit_cold_pass(sc, ctx, tv):
+    """A cold single pass that does not return the dual never stores it, so
+    with 16-bit storage the row-pipelined shapes give the float32 bits, which
+    are also those of the 16-bit default tile (float32 registers)."""
+    r = np.random.default_rng(71)
+    x = dev(r.uniform(size=(3, 150, 140)).astype(np.float32))
+    ref = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv=tv, lam=0.1, n_inner=10, schedule="fused",
+                                                      tile_shape=1, tile_passes=1, dual_dtype="bf16"))[0])
+    for dt in ("f32", "bf16", "f16"):
+        for k in row_shapes(sc):
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=10, schedule="fused", tile_shape=k, tile_passes=1,
+                               dual_dtype=dt)
+            np.testing.assert_array_equal(host(sc.sci_tv_denoise(ctx, x, prm)[0]), ref, err_msg=f"{dt} shape {k}")
+
+
 @pytest.mark.parametrize("solver", ["gap", "admm"])
 def test_row_pipelined_solvers_bitwise(sc, ctx, solver):
     """Whole GAP / ADMM solves (ADMM takes u = s - theta from the kernel),
