@@ -1,5 +1,6 @@
 // Row-pipelined fused-schedule TV denoiser kernel (template), instantiated in
-// the k_fgp_rows_*.hip translation units.
+// the k_fgp_rows_*.hip translation units; its body also serves the batched
+// launch (k_batched.hip).
 //
 // The same M FGP iterations per pass over HBM as the tiled kernel
 // (Algorithm 1, FGP box; projections of Eq. (29)-(30)), decomposed by
@@ -53,7 +54,7 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
-// LDS ring of x rows of one wavefront.
+// LDS ring of rows (x, or starting duals) private to one wavefront.
 template <int M, int C> struct alignas(16) RowRing {
     float v[2 * (M + kRowChunk)][64 * C];
 };
@@ -61,7 +62,7 @@ template <int M, int C> struct alignas(16) RowRing {
 // One wavefront's segment: strip sx, segment seg (rows [seg*H, seg*H + H)) of
 // the frame at element offset fo; V = elements per dual channel of the whole
 // video. MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
-// CH = 1 replaces the projection of q by Chambolle's (2004) semi-implicit step
+// CH_STEP = 1 replaces the projection of q by Chambolle's (2004) semi-implicit step
 // p = (w + z/(8 lambda)) / (1 + |z/(8 lambda)|), |.| per component (ATV) or
 // per voxel (ITV2D), with the operations of the streaming pass.
 template <int TV, int M, int DT, int C, int MODE, int CH_STEP = 0>
