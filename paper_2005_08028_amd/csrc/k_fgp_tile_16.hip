@@ -42,8 +42,13 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
                     const TilePass &tp, float lam, hipStream_t s, bool chambolle04)
 {
     if (m < 1 || m > kTileMaxM || shape < 0 || shape >= tile_shape_count()) return SCI_ERR_INVALID_ARG;
+    // A cold pass that neither returns nor keeps the dual never stores it, so
+    // its storage type does not matter: 16-bit requests take the float32 row
+    // kernels too (same bits as a float32 pass; registers are float32).
+    const bool no_dual_io = tp.mode == 0 && !tp.pn_out && !tp.pp_out;
     if (tv == TV_VTV) // one row-pipelined kernel, whatever the shape
-        return dual_dtype == DT_F32 ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s, chambolle04) : SCI_ERR_UNSUPPORTED;
+        return dual_dtype == DT_F32 || no_dual_io ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s, chambolle04)
+                                                  : SCI_ERR_UNSUPPORTED;
     if (chambolle04) { // row-pipelined shapes, float32 duals, ATV and ITV2D
         int H = 0, w = 0, c = 0;
         if (dual_dtype != DT_F32 || !tile_supported(tv) || !tile_shape_pipelined(shape)) return SCI_ERR_UNSUPPORTED;
@@ -51,10 +56,6 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
         return launch_rows_ch_f32(tv, H, m, nx, ny, B, x, tp, lam, s);
     }
     if (!tile_supported(tv)) return SCI_ERR_UNSUPPORTED;
-    // A cold pass that neither returns nor keeps the dual never stores it, so
-    // its storage type does not matter: 16-bit requests take the float32 row
-    // kernel too (same bits as their own tiles, whose registers are float32).
-    const bool no_dual_io = tp.mode == 0 && !tp.pn_out && !tp.pp_out;
     if ((dual_dtype == DT_F32 || no_dual_io) && tile_shape_pipelined(shape)) {
         int H = 0, w = 0, c = 0;
         tile_shape_info(shape, &H, &w, &c);

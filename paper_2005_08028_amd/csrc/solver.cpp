@@ -368,6 +368,12 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
         if (st != SCI_OK) return fail(ctx, st, "theta pass");
         return check_launch(ctx, "k_tv_theta");
     }
+    // 16-bit VTV in one cold pass that keeps no dual: the storage is never
+    // touched, so the fused float32 kernel gives the answer (as for 2D TVs)
+    const bool vtv16_single = p.tv == SCI_TV_VTV && p.dual_dtype != SCI_DUAL_F32 &&
+                              p.schedule != SCI_SCHED_STREAM && !p.chambolle04 && warm == nullptr && !keep_dual &&
+                              p.n_inner >= 2 && p.n_inner <= vtv_rows_max_pass(d.B) && p.tile_passes <= 1;
+    if (vtv16_single) return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);
     if (use_fused(p, d)) {
         if (!fused_supported(p, d)) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
         return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);

@@ -267,6 +267,26 @@ def test_vtv_fused_bitwise_equals_streaming(sc, ctx, B, nx, ny):
     say(f"VTV fused B={B} {nx}x{ny}: {len(cases)} cases bit-identical to streaming")
 
 
+@pytest.mark.parametrize("B", [3, 10, 24])
+def test_vtv_16bit_cold_single_pass(sc, ctx, B):
+    """16-bit VTV storage in one cold pass that returns no dual never stores
+    the dual: the default schedule gives the float32 fused bits. Asked for
+    the dual, the call keeps the 16-bit streaming pass (its own bits)."""
+    r = np.random.default_rng(B * 23)
+    x = dev(r.uniform(size=(B, 90, 140)).astype(np.float32))
+    n = 4
+    ref = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, schedule="fused"))[0])
+    for dt in ("bf16", "f16"):
+        th = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, dual_dtype=dt))[0])
+        np.testing.assert_array_equal(th, ref, err_msg=dt)
+        ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
+        d = torch.empty((2, B, 90, 140), device="cuda", dtype=ddt)
+        th_d = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, dual_dtype=dt), dual_out=d)[0])
+        th_s = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, dual_dtype=dt,
+                                                           schedule="stream"))[0])
+        np.testing.assert_array_equal(th_d, th_s, err_msg=dt + " with the dual returned")
+
+
 @pytest.mark.parametrize("solver", ["gap", "admm"])
 def test_vtv_fused_solvers_bitwise(sc, ctx, solver):
     """Whole GAP / ADMM VTV solves, with and without the warm dual, eager and
