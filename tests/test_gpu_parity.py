@@ -267,6 +267,26 @@ def test_vtv_fused_bitwise_equals_streaming(sc, ctx, B, nx, ny):
     say(f"VTV fused B={B} {nx}x{ny}: {len(cases)} cases bit-identical to streaming")
 
 
+def test_vtv_fused_every_frame_split(sc, ctx):
+    """Frame counts across every split of the fused VTV kernel (1..4 frames
+    per wavefront, last wavefront full or with spare slots): the fused bits
+    equal the streaming ones for a single pass and for a warm two-pass call."""
+    r = np.random.default_rng(81)
+    for B in (1, 2, 5, 7, 8, 9, 11, 15, 16, 17, 20, 23, 24, 25, 28, 31, 32):
+        x = dev(r.uniform(size=(B, 21, 70)).astype(np.float32))
+        p0 = dev(orc.project_dual(r.normal(size=(2, B, 21, 70)), "vtv").astype(np.float32))
+        for n, warm in ((3, False), (7, True)):
+            init = p0 if warm else None
+            outs = []
+            for schedule in ("stream", "fused"):
+                prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=n, schedule=schedule)
+                d = torch.empty((2, B, 21, 70), device="cuda")
+                th, _, _, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d)
+                outs.append((host(th), host(d)))
+            np.testing.assert_array_equal(outs[1][0], outs[0][0], err_msg=f"theta B={B} N={n} warm={warm}")
+            np.testing.assert_array_equal(outs[1][1], outs[0][1], err_msg=f"dual B={B} N={n} warm={warm}")
+
+
 @pytest.mark.parametrize("B", [3, 10, 24])
 def test_vtv_16bit_cold_single_pass(sc, ctx, B):
     """16-bit VTV storage in one cold pass that returns no dual never stores
