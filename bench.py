@@ -418,10 +418,12 @@ def measure_kernels(scitv, h, dev, C, Y, X_true):
         n, ms = r["project"]
         # binary masks travel as one 32-bit word of frame bits per pixel
         row("a4 GAP projection (packed binary masks)", ms * 1e3 / n, 8 * V + 12 * npix)
-    prm = scitv.solver_params(outer_iters=2, lam=0.1, rho=0.01, n_inner=N, tv="itv2d")
+    T = 4
+    prm = scitv.solver_params(outer_iters=T, lam=0.1, rho=0.01, n_inner=N, tv="itv2d")
     r = profiled(lambda: scitv.sci_admm_tv(h, Y, C, prm), ("project",))
     n, ms = r["project"]
-    row("a5 ADMM x-update (+ denoiser input, packed binary masks)", ms * 1e3 / n, 16 * V + 12 * npix)
+    # reads theta, u and writes s = u + x each pass; x itself only on the last
+    row("a5 ADMM x-update (+ denoiser input, packed binary masks)", ms * 1e3 / n, (12 + 4 / T) * V + 12 * npix)
     return out
 
 

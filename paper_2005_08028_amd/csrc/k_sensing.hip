@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kBlock) void k_weights(uint32_t npix, int B, const 
 }
 
 // x_k = v_k + C_k r with r = (Y - sum_k C_k v_k) Sinv, v = theta (GAP) or
-// theta - u (ADMM); ADMM also writes the denoiser input s = u + x.
+// theta - u (ADMM); ADMM also writes the denoiser input s = u + x, and x only
+// when x is non-null.
 template <bool ADMM>
 __global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, const float *__restrict__ theta,
                                                     const float *__restrict__ u, const float *__restrict__ C,
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, const 
         uint32_t o = (uint32_t)k * npix + pix;
         float v = ADMM ? theta[o] - u[o] : theta[o];
         float xv = fmaf(C[o], r, v);
-        x[o] = xv;
+        if (!ADMM || x) x[o] = xv;
         if (ADMM) svol[o] = u[o] + xv;
     }
 }
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, co
         if (k < B) {
             const uint32_t o = (uint32_t)k * npix + pix;
             const float xv = fmaf(c[k], r, v[k]);
-            x[o] = xv;
+            if (!ADMM || x) x[o] = xv;
             if (ADMM) svol[o] = uu[k] + xv;
         }
     }
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_
         if (k < B) {
             const uint32_t o = (uint32_t)k * fstride + q;
             const float2 xv = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
-            x[o] = xv;
+            if (!ADMM || x) x[o] = xv;
             if (ADMM) svol[o] = make_float2(uu[k].x + xv.x, uu[k].y + xv.y);
         }
     }
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
         if (k < B) {
             const uint32_t o = (uint32_t)k * fstride + q;
             const float2 xv = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
-            x[o] = xv;
+            if (!ADMM || x) x[o] = xv;
             if (ADMM) svol[o] = make_float2(uu[k].x + xv.x, uu[k].y + xv.y);
         }
     }

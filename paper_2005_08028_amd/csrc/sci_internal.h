@@ -106,6 +106,7 @@ void launch_gap_project(int nx, int ny, int B, const float *theta, const float *
                         const float *Sinv, float *x, hipStream_t s, const uint32_t *cbits = nullptr,
                         const int *cflag = nullptr);
 // v = theta - u; x = v + C .* ((Y - sum_k C_k v_k) .* Sinv); s = u + x
+// (x nullable: then only s is stored)
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
                          const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
                          const uint32_t *cbits = nullptr, const int *cflag = nullptr);

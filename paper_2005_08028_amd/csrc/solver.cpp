@@ -475,8 +475,11 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
             st = denoise_fixed(ctx, d, a.p.tv, a.X_out, theta, nullptr, warm, a.p.warm_dual != 0, r, s);
         } else {
             {
+                // x^(t) feeds only the output: the denoiser reads s = u + x and
+                // forms u = s - theta itself, so x is stored on the last pass only
+                float *x = t + 1 == a.p.outer_iters ? a.X_out : nullptr;
                 ProfScope prof(ctx, PF_PROJECT, s);
-                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, a.X_out, svol, s, cbits_ptr(ctx),
+                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, x, svol, s, cbits_ptr(ctx),
                                     cflag_ptr(ctx, d));
             }
             st = check_launch(ctx, "k_project");

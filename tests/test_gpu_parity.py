@@ -899,6 +899,30 @@ def test_gap_iterates_satisfy_measurement(sc, ctx):
         assert np.abs(f - Y)[S > 0].max() < 1e-5
 
 
+@pytest.mark.parametrize("B,nx,ny,binary", [(8, 40, 70, True), (24, 33, 35, True), (10, 64, 64, False),
+                                             (40, 32, 32, False)])
+def test_admm_x_stored_on_last_pass(sc, ctx, B, nx, ny, binary):
+    """ADMM stores x only on its last outer pass (the denoiser reads u + x and
+    forms the new u itself). x^(T) must still be the whole projection of Eq. (24):
+    with rho = 0 it meets Phi x = y wherever a mask is non-zero, whatever X_out
+    held before. The cases reach packed bits, an odd pixel count, real-valued
+    masks and B > 32."""
+    r = np.random.default_rng(16)
+    C = synth.masks_bernoulli(r, nx, ny, B) if binary else r.uniform(size=(B, nx, ny)).astype(np.float32)
+    truth = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    Y = orc.measurement(C, truth)
+    S = (C.astype(np.float64) ** 2).sum(axis=0)
+    prm = sc.solver_params(outer_iters=3, rho=0.0, tv="itv2d", n_inner=5)
+    outs = []
+    for fill in (float("nan"), 0.0):
+        xo = torch.full((B, nx, ny), fill, device="cuda")
+        sc.sci_admm_tv(ctx, dev(Y), dev(C), prm, X_out=xo)
+        outs.append(host(xo))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    f = orc.forward(C, outs[0])
+    assert np.abs(f - Y)[S > 0].max() <= 1e-6 * B * max(1.0, float(np.abs(Y).max()))
+
+
 def test_metrics_match_oracle(sc, ctx):
     r = np.random.default_rng(15)
     a = r.uniform(size=(6, 33, 71)).astype(np.float32)
