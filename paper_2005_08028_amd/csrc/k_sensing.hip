@@ -58,27 +58,37 @@ __global__ __launch_bounds__(kBlock) void k_weights(uint32_t npix, int B, const 
     Sinv[pix] = s > 0.0f ? 1.0f / s : 0.0f;
 }
 
-// x_k = v_k + C_k r with r = (Y - sum_k C_k v_k) Sinv, v = theta (GAP) or
-// theta - u (ADMM); ADMM also writes the denoiser input s = u + x, and x only
-// when x is non-null.
-template <bool ADMM>
-__global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, const float *__restrict__ theta,
+// Projection modes: what the kernels take as v, the point they project.
+//   kProjGap    v = theta (Eq. (21))
+//   kProjAdmm   v = theta - u (Eq. (24)); the kernel also writes the denoiser
+//               input s = u + x, and x only when x is non-null
+//   kProjFista  v = theta + ex (theta - u), FISTA's extrapolated point formed
+//               on load from the newest iterate (theta) and the one before (u),
+//               the same expression as k_extrapolate (Sec. 2.2)
+constexpr int kProjGap = 0, kProjAdmm = 1, kProjFista = 2;
+
+__device__ inline float fista_point(float x, float xp, float ex) { return fmaf(ex, x - xp, x); }
+
+// x_k = v_k + C_k r with r = (Y - sum_k C_k v_k) Sinv.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, float ex, const float *__restrict__ theta,
                                                     const float *__restrict__ u, const float *__restrict__ C,
                                                     const float *__restrict__ Y, const float *__restrict__ Sinv,
                                                     float *__restrict__ x, float *__restrict__ svol)
 {
     uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
     if (pix >= npix) return;
+    constexpr bool ADMM = MODE == kProjAdmm;
     float acc = 0.0f;
     for (int k = 0; k < B; ++k) {
         uint32_t o = (uint32_t)k * npix + pix;
-        float v = ADMM ? theta[o] - u[o] : theta[o];
+        float v = MODE == kProjGap ? theta[o] : ADMM ? theta[o] - u[o] : fista_point(theta[o], u[o], ex);
         acc = fmaf(C[o], v, acc);
     }
     float r = (Y[pix] - acc) * Sinv[pix];
     for (int k = 0; k < B; ++k) {
         uint32_t o = (uint32_t)k * npix + pix;
-        float v = ADMM ? theta[o] - u[o] : theta[o];
+        float v = MODE == kProjGap ? theta[o] : ADMM ? theta[o] - u[o] : fista_point(theta[o], u[o], ex);
         float xv = fmaf(C[o], r, v);
         if (!ADMM || x) x[o] = xv;
         if (ADMM) svol[o] = u[o] + xv;
@@ -87,14 +97,15 @@ __global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, const 
 
 // Same projection with every frame of the pixel held in registers (KB >= B),
 // so theta, u and C are read from memory once.
-template <bool ADMM, int KB>
-__global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, const float *__restrict__ theta,
+template <int MODE, int KB>
+__global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, float ex, const float *__restrict__ theta,
                                                         const float *__restrict__ u, const float *__restrict__ C,
                                                         const float *__restrict__ Y, const float *__restrict__ Sinv,
                                                         float *__restrict__ x, float *__restrict__ svol)
 {
     uint32_t pix = blockIdx.x * kBlock + threadIdx.x;
     if (pix >= npix) return;
+    constexpr bool ADMM = MODE == kProjAdmm;
     float v[KB], c[KB], uu[KB];
     float acc = 0.0f;
 #pragma unroll
@@ -105,6 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, co
             if (ADMM) {
                 uu[k] = u[o];
                 v[k] = theta[o] - uu[k];
+            } else if (MODE == kProjFista) {
+                v[k] = fista_point(theta[o], u[o], ex);
             } else {
                 v[k] = theta[o];
             }
@@ -125,8 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, co
 
 // Two adjacent pixels per thread (8-byte loads and stores), every frame in
 // registers; the same per-pixel arithmetic as k_project_reg.
-template <bool ADMM, int KB>
-__global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_t npix, int B,
+template <int MODE, int KB>
+__global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_t npix, int B, float ex,
                                                          const float2 *__restrict__ theta,
                                                          const float2 *__restrict__ u, const float2 *__restrict__ C,
                                                          const float2 *__restrict__ Y,
@@ -135,6 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_
 {
     const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
     if (q >= npair) return;
+    constexpr bool ADMM = MODE == kProjAdmm;
     const uint32_t fstride = npix / 2; // float2 elements per frame
     float2 v[KB], c[KB], uu[KB];
     float acc0 = 0.0f, acc1 = 0.0f;
@@ -147,6 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_
                 uu[k] = u[o];
                 const float2 t = theta[o];
                 v[k] = make_float2(t.x - uu[k].x, t.y - uu[k].y);
+            } else if (MODE == kProjFista) {
+                const float2 t = theta[o], tp = u[o];
+                v[k] = make_float2(fista_point(t.x, tp.x, ex), fista_point(t.y, tp.y, ex));
             } else {
                 v[k] = theta[o];
             }
@@ -192,8 +209,8 @@ __global__ void k_set_flag(int *flag, int v) { *flag = v; }
 // 1, so fmaf(C_k, v, acc) and fmaf(C_k, r, v) reduce exactly to a select of
 // acc + v / acc and v + r / v, the same values the float path produces. Two
 // adjacent pixels per thread; when *flag is 0 the float masks are used.
-template <bool ADMM, int KB>
-__global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_t npix, int B,
+template <int MODE, int KB>
+__global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_t npix, int B, float ex,
                                                          const float2 *__restrict__ theta,
                                                          const float2 *__restrict__ u, const float2 *__restrict__ C,
                                                          const uint2 *__restrict__ bits, const int *__restrict__ flag,
@@ -202,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
 {
     const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
     if (q >= npair) return;
+    constexpr bool ADMM = MODE == kProjAdmm;
     const uint32_t fstride = npix / 2;
     const bool packed = *flag != 0;
     float2 v[KB], uu[KB];
@@ -218,6 +236,9 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
                 uu[k] = u[o];
                 const float2 t = theta[o];
                 v[k] = make_float2(t.x - uu[k].x, t.y - uu[k].y);
+            } else if (MODE == kProjFista) {
+                const float2 t = theta[o], tp = u[o];
+                v[k] = make_float2(fista_point(t.x, tp.x, ex), fista_point(t.y, tp.y, ex));
             } else {
                 v[k] = theta[o];
             }
@@ -238,10 +259,10 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
     }
 }
 
-template <bool ADMM>
-void launch_project(uint32_t npix, int B, const float *theta, const float *u, const float *C, const float *Y,
-                    const float *Sinv, float *x, float *svol, hipStream_t s, const uint32_t *cbits = nullptr,
-                    const int *cflag = nullptr)
+template <int MODE>
+void launch_project(uint32_t npix, int B, float ex, const float *theta, const float *u, const float *C,
+                    const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
+                    const uint32_t *cbits = nullptr, const int *cflag = nullptr)
 {
     const dim3 g(grid_for(npix)), b(kBlock);
     auto al8 = [](const void *p) { return p == nullptr || ((uintptr_t)p & 7u) == 0; };
@@ -253,22 +274,22 @@ void launch_project(uint32_t npix, int B, const float *theta, const float *u, co
         float2 *x2 = (float2 *)x, *s2 = (float2 *)svol;
         if (cbits && cflag && al8(cbits)) {
             const uint2 *m2 = (const uint2 *)cbits;
-            if (B <= 8) hipLaunchKernelGGL((k_project_bits<ADMM, 8>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
-            else if (B <= 16) hipLaunchKernelGGL((k_project_bits<ADMM, 16>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
-            else if (B <= 24) hipLaunchKernelGGL((k_project_bits<ADMM, 24>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
-            else hipLaunchKernelGGL((k_project_bits<ADMM, 32>), g2, b, 0, s, npair, npix, B, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            if (B <= 8) hipLaunchKernelGGL((k_project_bits<MODE, 8>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else if (B <= 16) hipLaunchKernelGGL((k_project_bits<MODE, 16>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else if (B <= 24) hipLaunchKernelGGL((k_project_bits<MODE, 24>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else hipLaunchKernelGGL((k_project_bits<MODE, 32>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
             return;
         }
-        if (B <= 8) hipLaunchKernelGGL((k_project_reg2<ADMM, 8>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
-        else if (B <= 16) hipLaunchKernelGGL((k_project_reg2<ADMM, 16>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
-        else if (B <= 24) hipLaunchKernelGGL((k_project_reg2<ADMM, 24>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
-        else hipLaunchKernelGGL((k_project_reg2<ADMM, 32>), g2, b, 0, s, npair, npix, B, t2, u2, C2, Y2, S2, x2, s2);
+        if (B <= 8) hipLaunchKernelGGL((k_project_reg2<MODE, 8>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
+        else if (B <= 16) hipLaunchKernelGGL((k_project_reg2<MODE, 16>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
+        else if (B <= 24) hipLaunchKernelGGL((k_project_reg2<MODE, 24>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
+        else hipLaunchKernelGGL((k_project_reg2<MODE, 32>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
         return;
     }
-    if (B <= 8) hipLaunchKernelGGL((k_project_reg<ADMM, 8>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
-    else if (B <= 16) hipLaunchKernelGGL((k_project_reg<ADMM, 16>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
-    else if (B <= 32) hipLaunchKernelGGL((k_project_reg<ADMM, 32>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
-    else hipLaunchKernelGGL((k_project<ADMM>), g, b, 0, s, npix, B, theta, u, C, Y, Sinv, x, svol);
+    if (B <= 8) hipLaunchKernelGGL((k_project_reg<MODE, 8>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
+    else if (B <= 16) hipLaunchKernelGGL((k_project_reg<MODE, 16>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
+    else if (B <= 32) hipLaunchKernelGGL((k_project_reg<MODE, 32>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
+    else hipLaunchKernelGGL((k_project<MODE>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy4(uint32_t n4, const uint32_t *__restrict__ src,
@@ -365,14 +386,22 @@ void launch_weights(int nx, int ny, int B, const float *C, float rho, float *Sin
 void launch_gap_project(int nx, int ny, int B, const float *theta, const float *C, const float *Y,
                         const float *Sinv, float *x, hipStream_t s, const uint32_t *cbits, const int *cflag)
 {
-    launch_project<false>((uint32_t)nx * (uint32_t)ny, B, theta, nullptr, C, Y, Sinv, x, nullptr, s, cbits, cflag);
+    launch_project<kProjGap>((uint32_t)nx * (uint32_t)ny, B, 0.0f, theta, nullptr, C, Y, Sinv, x, nullptr, s, cbits,
+                             cflag);
 }
 
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
                          const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
                          const uint32_t *cbits, const int *cflag)
 {
-    launch_project<true>((uint32_t)nx * (uint32_t)ny, B, theta, u, C, Y, Sinv, x, svol, s, cbits, cflag);
+    launch_project<kProjAdmm>((uint32_t)nx * (uint32_t)ny, B, 0.0f, theta, u, C, Y, Sinv, x, svol, s, cbits, cflag);
+}
+
+void launch_fista_project(int nx, int ny, int B, const float *x, const float *x_prev, float ex, const float *C,
+                          const float *Y, const float *W, float *z, hipStream_t s, const uint32_t *cbits,
+                          const int *cflag)
+{
+    launch_project<kProjFista>((uint32_t)nx * (uint32_t)ny, B, ex, x, x_prev, C, Y, W, z, nullptr, s, cbits, cflag);
 }
 
 void launch_pack_masks(int nx, int ny, int B, const float *C, uint32_t *bits, int *flag, hipStream_t s)

@@ -110,6 +110,11 @@ void launch_gap_project(int nx, int ny, int B, const float *theta, const float *
 void launch_admm_project(int nx, int ny, int B, const float *theta, const float *u, const float *C,
                          const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
                          const uint32_t *cbits = nullptr, const int *cflag = nullptr);
+// FISTA gradient step from the extrapolated point formed on load:
+// v = x + ex (x - x_prev), z = v + C .* ((Y - sum_k C_k v_k) .* W)
+void launch_fista_project(int nx, int ny, int B, const float *x, const float *x_prev, float ex, const float *C,
+                          const float *Y, const float *W, float *z, hipStream_t s, const uint32_t *cbits = nullptr,
+                          const int *cflag = nullptr);
 // bits[pix] bit k = (C_k(pix) == 1); *flag = 1 when every entry of C is 0 or 1
 // and B <= 32, else 0 (all on the device: graph-capturable).
 void launch_pack_masks(int nx, int ny, int B, const float *C, uint32_t *bits, int *flag, hipStream_t s);

@@ -652,18 +652,23 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     FgpRun r;
     bind_duals(ctx, r);
     double tau = 1.0;
+    float ex = 0.0f; // FISTA: theta = xa + ex (xa - xb), formed by the projection as it loads
     for (int t = 0; t < p->outer_iters; ++t) {
         {
             ProfScope prof(ctx, PF_PROJECT, s);
-            // FISTA steps from the extrapolated point theta, TwIST from x^(t)
-            launch_gap_project(d.nx, d.ny, d.B, twist ? xa : theta, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
+            // FISTA steps from the extrapolated point (x^(0) itself at first),
+            // TwIST from x^(t)
+            if (!twist && t > 0)
+                launch_fista_project(d.nx, d.ny, d.B, xa, xb, ex, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
+            else
+                launch_gap_project(d.nx, d.ny, d.B, xa, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
         }
         if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
         if (!twist) {
             // x^(t) into the other buffer; x^(t-1) stays in xa
             if ((st = denoise_fixed(ctx, d, q, z, xb, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
             const double tau1 = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
-            launch_extrapolate(V, (float)((tau - 1.0) / tau1), xb, xa, theta, s);
+            ex = (float)((tau - 1.0) / tau1);
             tau = tau1;
         } else {
             if ((st = denoise_fixed(ctx, d, q, z, theta, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
@@ -673,6 +678,8 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
         if ((st = check_launch(ctx, "update")) != SCI_OK) return st;
         std::swap(xa, xb); // xa = newest iterate, xb = the one before
     }
+    // FISTA's last extrapolated point is stored only for the caller
+    if (!twist && p->outer_iters > 0 && Theta_out) launch_extrapolate(V, ex, xa, xb, theta, s);
     if (xa != X_out) launch_copy(xa, X_out, vb, s);
     return check_launch(ctx, "copy");
 }
