@@ -65,13 +65,21 @@ __global__ __launch_bounds__(kBlock) void k_weights(uint32_t npix, int B, const 
 //   kProjFista  v = theta + ex (theta - u), FISTA's extrapolated point formed
 //               on load from the newest iterate (theta) and the one before (u),
 //               the same expression as k_extrapolate (Sec. 2.2)
-constexpr int kProjGap = 0, kProjAdmm = 1, kProjFista = 2;
+//   kProjTwist  v = a2 w + a1 theta + ex u, TwIST's two-step update from the
+//               denoised point (w), the newest iterate (theta) and the one
+//               before (u), the same expression as k_two_step (Sec. 2.2); the
+//               kernel also stores v, the new iterate, to svol
+constexpr int kProjGap = 0, kProjAdmm = 1, kProjFista = 2, kProjTwist = 3;
 
 __device__ inline float fista_point(float x, float xp, float ex) { return fmaf(ex, x - xp, x); }
+__device__ inline float twist_point(float xp, float x, float th, float a0, float a1, float a2)
+{
+    return fmaf(a2, th, fmaf(a1, x, a0 * xp));
+}
 
 // x_k = v_k + C_k r with r = (Y - sum_k C_k v_k) Sinv.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, float ex, const float *__restrict__ theta,
+__global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, float ex, float a1, float a2, const float *__restrict__ w, const float *__restrict__ theta,
                                                     const float *__restrict__ u, const float *__restrict__ C,
                                                     const float *__restrict__ Y, const float *__restrict__ Sinv,
                                                     float *__restrict__ x, float *__restrict__ svol)
@@ -82,23 +90,30 @@ __global__ __launch_bounds__(kBlock) void k_project(uint32_t npix, int B, float 
     float acc = 0.0f;
     for (int k = 0; k < B; ++k) {
         uint32_t o = (uint32_t)k * npix + pix;
-        float v = MODE == kProjGap ? theta[o] : ADMM ? theta[o] - u[o] : fista_point(theta[o], u[o], ex);
+        float v = MODE == kProjGap    ? theta[o]
+                : ADMM                ? theta[o] - u[o]
+                : MODE == kProjFista ? fista_point(theta[o], u[o], ex)
+                                     : twist_point(u[o], theta[o], w[o], ex, a1, a2);
         acc = fmaf(C[o], v, acc);
     }
     float r = (Y[pix] - acc) * Sinv[pix];
     for (int k = 0; k < B; ++k) {
         uint32_t o = (uint32_t)k * npix + pix;
-        float v = MODE == kProjGap ? theta[o] : ADMM ? theta[o] - u[o] : fista_point(theta[o], u[o], ex);
+        float v = MODE == kProjGap    ? theta[o]
+                : ADMM                ? theta[o] - u[o]
+                : MODE == kProjFista ? fista_point(theta[o], u[o], ex)
+                                     : twist_point(u[o], theta[o], w[o], ex, a1, a2);
         float xv = fmaf(C[o], r, v);
         if (!ADMM || x) x[o] = xv;
         if (ADMM) svol[o] = u[o] + xv;
+        if (MODE == kProjTwist) svol[o] = v;
     }
 }
 
 // Same projection with every frame of the pixel held in registers (KB >= B),
 // so theta, u and C are read from memory once.
 template <int MODE, int KB>
-__global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, float ex, const float *__restrict__ theta,
+__global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, float ex, float a1, float a2, const float *__restrict__ w, const float *__restrict__ theta,
                                                         const float *__restrict__ u, const float *__restrict__ C,
                                                         const float *__restrict__ Y, const float *__restrict__ Sinv,
                                                         float *__restrict__ x, float *__restrict__ svol)
@@ -118,6 +133,8 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, fl
                 v[k] = theta[o] - uu[k];
             } else if (MODE == kProjFista) {
                 v[k] = fista_point(theta[o], u[o], ex);
+            } else if (MODE == kProjTwist) {
+                v[k] = twist_point(u[o], theta[o], w[o], ex, a1, a2);
             } else {
                 v[k] = theta[o];
             }
@@ -132,6 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, fl
             const float xv = fmaf(c[k], r, v[k]);
             if (!ADMM || x) x[o] = xv;
             if (ADMM) svol[o] = uu[k] + xv;
+            if (MODE == kProjTwist) svol[o] = v[k];
         }
     }
 }
@@ -139,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_project_reg(uint32_t npix, int B, fl
 // Two adjacent pixels per thread (8-byte loads and stores), every frame in
 // registers; the same per-pixel arithmetic as k_project_reg.
 template <int MODE, int KB>
-__global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_t npix, int B, float ex,
+__global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_t npix, int B, float ex, float a1, float a2, const float2 *__restrict__ w,
                                                          const float2 *__restrict__ theta,
                                                          const float2 *__restrict__ u, const float2 *__restrict__ C,
                                                          const float2 *__restrict__ Y,
@@ -164,6 +182,9 @@ __global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_
             } else if (MODE == kProjFista) {
                 const float2 t = theta[o], tp = u[o];
                 v[k] = make_float2(fista_point(t.x, tp.x, ex), fista_point(t.y, tp.y, ex));
+            } else if (MODE == kProjTwist) {
+                const float2 t = theta[o], tp = u[o], tw = w[o];
+                v[k] = make_float2(twist_point(tp.x, t.x, tw.x, ex, a1, a2), twist_point(tp.y, t.y, tw.y, ex, a1, a2));
             } else {
                 v[k] = theta[o];
             }
@@ -180,6 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_project_reg2(uint32_t npair, uint32_
             const float2 xv = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
             if (!ADMM || x) x[o] = xv;
             if (ADMM) svol[o] = make_float2(uu[k].x + xv.x, uu[k].y + xv.y);
+            if (MODE == kProjTwist) svol[o] = v[k];
         }
     }
 }
@@ -210,7 +232,7 @@ __global__ void k_set_flag(int *flag, int v) { *flag = v; }
 // acc + v / acc and v + r / v, the same values the float path produces. Two
 // adjacent pixels per thread; when *flag is 0 the float masks are used.
 template <int MODE, int KB>
-__global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_t npix, int B, float ex,
+__global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_t npix, int B, float ex, float a1, float a2, const float2 *__restrict__ w,
                                                          const float2 *__restrict__ theta,
                                                          const float2 *__restrict__ u, const float2 *__restrict__ C,
                                                          const uint2 *__restrict__ bits, const int *__restrict__ flag,
@@ -239,6 +261,9 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
             } else if (MODE == kProjFista) {
                 const float2 t = theta[o], tp = u[o];
                 v[k] = make_float2(fista_point(t.x, tp.x, ex), fista_point(t.y, tp.y, ex));
+            } else if (MODE == kProjTwist) {
+                const float2 t = theta[o], tp = u[o], tw = w[o];
+                v[k] = make_float2(twist_point(tp.x, t.x, tw.x, ex, a1, a2), twist_point(tp.y, t.y, tw.y, ex, a1, a2));
             } else {
                 v[k] = theta[o];
             }
@@ -255,6 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
             const float2 xv = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
             if (!ADMM || x) x[o] = xv;
             if (ADMM) svol[o] = make_float2(uu[k].x + xv.x, uu[k].y + xv.y);
+            if (MODE == kProjTwist) svol[o] = v[k];
         }
     }
 }
@@ -262,11 +288,12 @@ __global__ __launch_bounds__(kBlock) void k_project_bits(uint32_t npair, uint32_
 template <int MODE>
 void launch_project(uint32_t npix, int B, float ex, const float *theta, const float *u, const float *C,
                     const float *Y, const float *Sinv, float *x, float *svol, hipStream_t s,
-                    const uint32_t *cbits = nullptr, const int *cflag = nullptr)
+                    const uint32_t *cbits = nullptr, const int *cflag = nullptr, float a1 = 0.0f, float a2 = 0.0f,
+                    const float *w = nullptr)
 {
     const dim3 g(grid_for(npix)), b(kBlock);
     auto al8 = [](const void *p) { return p == nullptr || ((uintptr_t)p & 7u) == 0; };
-    if (npix % 2 == 0 && B <= 32 && al8(theta) && al8(u) && al8(C) && al8(Y) && al8(Sinv) && al8(x) && al8(svol)) {
+    if (npix % 2 == 0 && B <= 32 && al8(theta) && al8(u) && al8(C) && al8(Y) && al8(Sinv) && al8(x) && al8(svol) && al8(w)) {
         const uint32_t npair = npix / 2;
         const dim3 g2(grid_for(npair));
         const float2 *t2 = (const float2 *)theta, *u2 = (const float2 *)u, *C2 = (const float2 *)C;
@@ -274,22 +301,22 @@ void launch_project(uint32_t npix, int B, float ex, const float *theta, const fl
         float2 *x2 = (float2 *)x, *s2 = (float2 *)svol;
         if (cbits && cflag && al8(cbits)) {
             const uint2 *m2 = (const uint2 *)cbits;
-            if (B <= 8) hipLaunchKernelGGL((k_project_bits<MODE, 8>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
-            else if (B <= 16) hipLaunchKernelGGL((k_project_bits<MODE, 16>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
-            else if (B <= 24) hipLaunchKernelGGL((k_project_bits<MODE, 24>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
-            else hipLaunchKernelGGL((k_project_bits<MODE, 32>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            if (B <= 8) hipLaunchKernelGGL((k_project_bits<MODE, 8>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else if (B <= 16) hipLaunchKernelGGL((k_project_bits<MODE, 16>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else if (B <= 24) hipLaunchKernelGGL((k_project_bits<MODE, 24>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
+            else hipLaunchKernelGGL((k_project_bits<MODE, 32>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, m2, cflag, Y2, S2, x2, s2);
             return;
         }
-        if (B <= 8) hipLaunchKernelGGL((k_project_reg2<MODE, 8>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
-        else if (B <= 16) hipLaunchKernelGGL((k_project_reg2<MODE, 16>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
-        else if (B <= 24) hipLaunchKernelGGL((k_project_reg2<MODE, 24>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
-        else hipLaunchKernelGGL((k_project_reg2<MODE, 32>), g2, b, 0, s, npair, npix, B, ex, t2, u2, C2, Y2, S2, x2, s2);
+        if (B <= 8) hipLaunchKernelGGL((k_project_reg2<MODE, 8>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, Y2, S2, x2, s2);
+        else if (B <= 16) hipLaunchKernelGGL((k_project_reg2<MODE, 16>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, Y2, S2, x2, s2);
+        else if (B <= 24) hipLaunchKernelGGL((k_project_reg2<MODE, 24>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, Y2, S2, x2, s2);
+        else hipLaunchKernelGGL((k_project_reg2<MODE, 32>), g2, b, 0, s, npair, npix, B, ex, a1, a2, (const float2 *)w, t2, u2, C2, Y2, S2, x2, s2);
         return;
     }
-    if (B <= 8) hipLaunchKernelGGL((k_project_reg<MODE, 8>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
-    else if (B <= 16) hipLaunchKernelGGL((k_project_reg<MODE, 16>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
-    else if (B <= 32) hipLaunchKernelGGL((k_project_reg<MODE, 32>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
-    else hipLaunchKernelGGL((k_project<MODE>), g, b, 0, s, npix, B, ex, theta, u, C, Y, Sinv, x, svol);
+    if (B <= 8) hipLaunchKernelGGL((k_project_reg<MODE, 8>), g, b, 0, s, npix, B, ex, a1, a2, w, theta, u, C, Y, Sinv, x, svol);
+    else if (B <= 16) hipLaunchKernelGGL((k_project_reg<MODE, 16>), g, b, 0, s, npix, B, ex, a1, a2, w, theta, u, C, Y, Sinv, x, svol);
+    else if (B <= 32) hipLaunchKernelGGL((k_project_reg<MODE, 32>), g, b, 0, s, npix, B, ex, a1, a2, w, theta, u, C, Y, Sinv, x, svol);
+    else hipLaunchKernelGGL((k_project<MODE>), g, b, 0, s, npix, B, ex, a1, a2, w, theta, u, C, Y, Sinv, x, svol);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy4(uint32_t n4, const uint32_t *__restrict__ src,
@@ -402,6 +429,14 @@ void launch_fista_project(int nx, int ny, int B, const float *x, const float *x_
                           const int *cflag)
 {
     launch_project<kProjFista>((uint32_t)nx * (uint32_t)ny, B, ex, x, x_prev, C, Y, W, z, nullptr, s, cbits, cflag);
+}
+
+void launch_twist_project(int nx, int ny, int B, const float *x, const float *x_prev, const float *theta, float a0,
+                          float a1, float a2, const float *C, const float *Y, const float *W, float *z, float *x_next,
+                          hipStream_t s, const uint32_t *cbits, const int *cflag)
+{
+    launch_project<kProjTwist>((uint32_t)nx * (uint32_t)ny, B, a0, x, x_prev, C, Y, W, z, x_next, s, cbits, cflag, a1,
+                               a2, theta);
 }
 
 void launch_pack_masks(int nx, int ny, int B, const float *C, uint32_t *bits, int *flag, hipStream_t s)

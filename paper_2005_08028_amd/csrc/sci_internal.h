@@ -115,6 +115,12 @@ void launch_admm_project(int nx, int ny, int B, const float *theta, const float 
 void launch_fista_project(int nx, int ny, int B, const float *x, const float *x_prev, float ex, const float *C,
                           const float *Y, const float *W, float *z, hipStream_t s, const uint32_t *cbits = nullptr,
                           const int *cflag = nullptr);
+// TwIST: the two-step update x_next = a0 x_prev + a1 x + a2 theta formed on
+// load and stored (x_next may be x_prev: each element is read before it is
+// written, by the same thread), then z = x_next + C .* ((Y - sum_k C_k x_next_k) .* W)
+void launch_twist_project(int nx, int ny, int B, const float *x, const float *x_prev, const float *theta, float a0,
+                          float a1, float a2, const float *C, const float *Y, const float *W, float *z, float *x_next,
+                          hipStream_t s, const uint32_t *cbits = nullptr, const int *cflag = nullptr);
 // bits[pix] bit k = (C_k(pix) == 1); *flag = 1 when every entry of C is 0 or 1
 // and B <= 32, else 0 (all on the device: graph-capturable).
 void launch_pack_masks(int nx, int ny, int B, const float *C, uint32_t *bits, int *flag, hipStream_t s);

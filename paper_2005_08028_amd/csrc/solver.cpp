@@ -653,15 +653,23 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     bind_duals(ctx, r);
     double tau = 1.0;
     float ex = 0.0f; // FISTA: theta = xa + ex (xa - xb), formed by the projection as it loads
+    const float a0 = (float)(1.0 - alpha), a1 = (float)(alpha - beta), a2 = (float)beta;
+    bool pend = false; // TwIST: x^(t+1) = a0 xb + a1 xa + a2 theta not formed yet
     for (int t = 0; t < p->outer_iters; ++t) {
         {
             ProfScope prof(ctx, PF_PROJECT, s);
             // FISTA steps from the extrapolated point (x^(0) itself at first),
-            // TwIST from x^(t)
-            if (!twist && t > 0)
+            // TwIST from x^(t), formed here (over x^(t-2)) once t >= 2
+            if (!twist && t > 0) {
                 launch_fista_project(d.nx, d.ny, d.B, xa, xb, ex, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
-            else
+            } else if (pend) {
+                launch_twist_project(d.nx, d.ny, d.B, xa, xb, theta, a0, a1, a2, C, Y, W, z, xb, s, cbits_ptr(ctx),
+                                     cflag_ptr(ctx, d));
+                std::swap(xa, xb);
+                pend = false;
+            } else {
                 launch_gap_project(d.nx, d.ny, d.B, xa, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
+            }
         }
         if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
         if (!twist) {
@@ -672,11 +680,19 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
             tau = tau1;
         } else {
             if ((st = denoise_fixed(ctx, d, q, z, theta, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
-            if (t == 0) launch_copy(theta, xb, vb, s); // x^(1) = theta^(0)
-            else launch_two_step(V, (float)(1.0 - alpha), (float)(alpha - beta), (float)beta, xb, xa, theta, xb, s);
+            if (t == 0) {
+                launch_copy(theta, xb, vb, s); // x^(1) = theta^(0)
+                std::swap(xa, xb);
+            } else {
+                pend = true; // the next projection (or the end of the loop) forms x^(t+1)
+            }
         }
         if ((st = check_launch(ctx, "update")) != SCI_OK) return st;
-        std::swap(xa, xb); // xa = newest iterate, xb = the one before
+        if (!twist) std::swap(xa, xb); // xa = newest iterate, xb = the one before
+    }
+    if (pend) {
+        launch_two_step(V, a0, a1, a2, xb, xa, theta, xb, s);
+        std::swap(xa, xb);
     }
     // FISTA's last extrapolated point is stored only for the caller
     if (!twist && p->outer_iters > 0 && Theta_out) launch_extrapolate(V, ex, xa, xb, theta, s);
