@@ -116,3 +116,19 @@ def test_fista_beats_gap_objective(sc, ctx):
         return 0.5 * orc.residual_sq(pr.masks, v, Y) + f32(0.05) * orc.tv_value(v, "atv")
     assert abs(F(x) - F(xr)) <= 1e-5 * F(xr)
     assert F(x) < F(orc.adjoint(pr.masks, Y))
+
+
+@pytest.mark.parametrize("which", ["fista", "twist"])
+def test_theta_out_does_not_change_x(sc, ctx, which):
+    """FISTA's extrapolated point and TwIST's two-step update are formed inside
+    the projection, and theta is stored only when the caller asks for it: x
+    must not depend on whether it does (odd pixel count and packed masks)."""
+    fn = sc.sci_fista_tv if which == "fista" else sc.sci_twist_tv
+    prm = sc.solver_params(outer_iters=5, tv="itv2d", lam=0.05, n_inner=4)
+    for nx, ny in ((40, 66), (33, 35)):
+        pr = synth.make_problem(nx, ny, 8, seed=64)
+        Y = orc.measurement(pr.masks, pr.truth)
+        th = torch.empty(pr.masks.shape, device="cuda")
+        x1, _ = fn(ctx, dev(Y), dev(pr.masks), prm, Theta_out=th)
+        x2, _ = fn(ctx, dev(Y), dev(pr.masks), prm)
+        np.testing.assert_array_equal(host(x1), host(x2))
