@@ -43,7 +43,9 @@
  * Parity status: every function below is pinned by the CPU tests (adjoint
  * identities, dense-matrix formulations built from Eq. (2) and Eq. (7),
  * closed-form TV values and prox solutions, an independent bound-constrained
- * dual solve, fixed points and normal equations).
+ * dual solve, fixed points and normal equations; ADMM, FISTA and TwIST by
+ * hand-worked three-iteration examples, and ADMM's limit by an independent
+ * constrained solve of the penalised least-squares problem it minimises).
  */
 #include <math.h>
 #include <stdlib.h>

@@ -718,3 +718,113 @@ def test_clip_inside_gap():
     np.testing.assert_allclose(th, t, rtol=0, atol=1e-14)
     with pytest.raises(ValueError):
         orc.gap_tv(Y, C, 0.05, 1, 2, tv="itv2d", clip=True)
+
+
+# ---------------------------------------------------------------------------
+# Outer frameworks on hand-worked examples (ADMM Eq. (24)-(26), FISTA
+# Eq. (14)-(17), TwIST Eq. (18)-(20)) and the ADMM fixed point.
+# ---------------------------------------------------------------------------
+
+FRAMEWORKS = os.path.join(os.path.dirname(__file__), "golden", "framework_worked_examples.json")
+
+
+def framework_case(name):
+    return next(c for c in json.load(open(FRAMEWORKS))["cases"] if c["name"] == name)
+
+
+def exact(values):
+    """Golden entries are exact rationals written as strings, or decimals."""
+    from fractions import Fraction
+    return np.array([float(Fraction(v)) if isinstance(v, str) else float(v) for v in values])
+
+
+def test_golden_admm_three_iterations():
+    """Pins the multiplier update u <- u + x - theta and the denoiser input
+    u + x: u is nonzero from the first iteration on and changes x^(2), x^(3)."""
+    g = framework_case("admm_atv_1x3_three_iterations")
+    C, Y = np.array(g["C"]), np.array(g["Y"])
+    for T, ref in g["by_T"].items():
+        x, th = orc.admm_tv(Y, C, g["lam"], g["rho"], int(T), g["n_inner"], tv=g["tv"])
+        np.testing.assert_allclose(x[0, 0], exact(ref["x"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(th[0, 0], exact(ref["theta"]), rtol=0, atol=1e-15)
+
+
+def test_golden_fista_three_iterations():
+    """Pins the tau sequence and the direction of the extrapolation (a pixel
+    with c^2 = L/4 keeps moving, so the momentum shows in theta^(3))."""
+    g = framework_case("fista_identity_denoiser_1x2")
+    C, Y = np.array(g["C"]), np.array(g["Y"])
+    for T, ref in g["by_T"].items():
+        x, th = orc.fista_tv(Y, C, g["lam"], int(T), g["n_inner"], tv=g["tv"])
+        np.testing.assert_allclose(x[0, 0], exact(ref["x"]), rtol=0, atol=2e-15)
+        np.testing.assert_allclose(th[0, 0], exact(ref["theta_next"]), rtol=0, atol=2e-15)
+
+
+def test_golden_twist_three_iterations():
+    """Pins the two-step weights (1 - alpha) on x^(t-1), (alpha - beta) on
+    x^(t) with alpha != 1, and the start x^(1) = theta^(0)."""
+    g = framework_case("twist_identity_denoiser_1x2")
+    C, Y = np.array(g["C"]), np.array(g["Y"])
+    for T, ref in g["by_T"].items():
+        x, th = orc.twist_tv(Y, C, g["lam"], int(T), g["n_inner"], tv=g["tv"], alpha=g["alpha"], beta=g["beta"])
+        np.testing.assert_allclose(x[0, 0], exact(ref["x"]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(th[0, 0], exact(ref["theta"]), rtol=0, atol=1e-15)
+
+
+def dense_difference_rows(B, nx, ny):
+    """Every difference of Eq. (7) as a row acting on vec_video (one +1, one -1)."""
+    rows = []
+    for k in range(B):
+        for i in range(nx):
+            for j in range(ny):
+                for di, dj in ((0, 1), (1, 0)):
+                    if i + di < nx and j + dj < ny:
+                        e = np.zeros((B, nx, ny))
+                        e[k, i + di, j + dj] = 1.0
+                        e[k, i, j] = -1.0
+                        rows.append(vec_video(e))
+    return np.array(rows)
+
+
+def test_admm_converges_to_penalised_least_squares_minimiser():
+    """Scaled ADMM for min f(x) + g(theta), x = theta, alternates
+    x = argmin f + rho/2 ||x - theta + u||^2, theta = prox_{g/rho}(x + u),
+    u += x - theta. The denoiser solves prox_{lambda TV}, so g = rho lambda TV
+    and the limit minimises 1/2 ||y - Phi x||^2 + rho lambda ATV(x). That
+    minimum is computed independently by scipy's SLSQP on the epigraph form
+    (variables x, t; -t <= D x <= t; objective 1/2 ||y - Phi x||^2 +
+    rho lambda sum t) with dense Phi and D, and compared by value (Phi has a
+    null space, so the minimiser itself need not be unique)."""
+    r = rng(7)
+    B, nx, ny = 2, 3, 3
+    C = (r.random((B, nx, ny)) < 0.6).astype(float)
+    Y = orc.forward(C, r.random((B, nx, ny))) + 0.05 * r.standard_normal((nx, ny))
+    lam, rho = 0.05, 2.0
+    mu = rho * lam
+    x, th = orc.admm_tv(Y, C, lam, rho, 500, 300, tv="atv")
+    assert np.abs(x - th).max() < 1e-10  # consensus x = theta at the limit
+
+    V = B * nx * ny
+    Phi, Dm, yv = dense_phi(C), dense_difference_rows(B, nx, ny), Y.ravel(order="F")
+    m = Dm.shape[0]
+
+    def f(zv):
+        res = yv - Phi @ zv[:V]
+        return 0.5 * res @ res + mu * zv[V:].sum()
+
+    def fgrad(zv):
+        return np.concatenate([-Phi.T @ (yv - Phi @ zv[:V]), mu * np.ones(m)])
+
+    A = np.block([[Dm, np.eye(m)], [-Dm, np.eye(m)]])
+    x0 = vec_video(orc.adjoint(C, Y))
+    res = scipy.optimize.minimize(f, np.concatenate([x0, np.abs(Dm @ x0)]), jac=fgrad, method="SLSQP",
+                                  constraints=[{"type": "ineq", "fun": lambda z: A @ z, "jac": lambda z: A}],
+                                  options={"ftol": 1e-15, "maxiter": 2000})
+    assert res.success
+
+    def F(vol):
+        xv = vec_video(vol)
+        rr = yv - Phi @ xv
+        return 0.5 * rr @ rr + mu * np.abs(Dm @ xv).sum()
+
+    assert abs(F(x) - res.fun) <= 1e-9 * res.fun
