@@ -169,7 +169,10 @@ int sci_adjoint(sci_ctx *ctx, sci_dims d, const float *C, const float *Y, float 
  * X_in - lambda D^T p^(N). rel_gap_out (nullable, HOST pointer) receives
  * the relative duality gap lambda (TV(theta) - <D theta, p>) / P(theta)
  * computed in FP64; iters_out (nullable, HOST) the iterations run.
- * Returns SCI_NOT_CONVERGED when gap_tol > 0 was not met at n_inner_max. */
+ * Returns SCI_NOT_CONVERGED when gap_tol > 0 was not met at n_inner_max,
+ * or at the first check whose gap or primal value is not finite (a NaN or
+ * infinity in dual_init or X_in): a non-finite gap never meets a tolerance,
+ * the loop stops there and *rel_gap_out is NaN. */
 int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *X_in, float *Theta_out,
                    const void *dual_init, void *dual_out, double *rel_gap_out, int32_t *iters_out,
                    hipStream_t stream);
@@ -316,9 +319,12 @@ int sci_wsnet_train_step(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *
  * the previous outer iteration's final dual as P_base and is not used in the
  * first outer iteration, which has none; with p->warm_dual = 1 as well, the
  * call starts from whichever of the prediction and the previous final dual
- * has the smaller relative duality gap; when a predicted start does not
- * reach the tolerance the call is repeated from a zero dual), else the
+ * has the smaller relative duality gap, a non-finite gap losing; when a
+ * call that started from the prediction does not reach the tolerance, or
+ * meets a non-finite gap, it is repeated from a zero dual), else the
  * previous outer iteration's final dual (p->warm_dual = 1), else zero.
+ * A call started from the previous final dual is not repeated (as without
+ * a network).
  * inner_iters_out / fallbacks_out / net_starts_out (nullable, HOST): total
  * inner iterations (fallbacks included), the number of cold-start
  * fallbacks, and the number of calls that started from the prediction.

@@ -31,6 +31,7 @@ enum BufSlot {
     WS_BATCH,                         // batched solve: per-problem Sinv and theta
     WS_BDESC,                         // batched solve: device problem table (eager path)
     WS_CBITS,                         // masks packed one bit per frame (+ a validity flag)
+    WS_XNEXT,                         // TwIST: the third iterate buffer
     WS_COUNT
 };
 
@@ -116,8 +117,8 @@ void launch_fista_project(int nx, int ny, int B, const float *x, const float *x_
                           const float *Y, const float *W, float *z, hipStream_t s, const uint32_t *cbits = nullptr,
                           const int *cflag = nullptr);
 // TwIST: the two-step update x_next = a0 x_prev + a1 x + a2 theta formed on
-// load and stored (x_next may be x_prev: each element is read before it is
-// written, by the same thread), then z = x_next + C .* ((Y - sum_k C_k x_next_k) .* W)
+// load and stored (x_next must not overlap any input), then
+// z = x_next + C .* ((Y - sum_k C_k x_next_k) .* W)
 void launch_twist_project(int nx, int ny, int B, const float *x, const float *x_prev, const float *theta, float a0,
                           float a1, float a2, const float *C, const float *Y, const float *W, float *z, float *x_next,
                           hipStream_t s, const uint32_t *cbits = nullptr, const int *cflag = nullptr);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 
 #include "k_fgp_tile_shapes.h"
@@ -78,6 +79,18 @@ struct Momentum {
         return b;
     }
 };
+
+// Relative duality gap gap / P(theta) of one check. A non-finite gap or
+// primal (a NaN or infinity in the dual or the input) gives NaN, never a
+// small number: primal > 0 is false for NaN, which must not read as 0.
+double relative_gap(double gap, double primal)
+{
+    if (!std::isfinite(gap) || !std::isfinite(primal)) return std::numeric_limits<double>::quiet_NaN();
+    return primal > 0.0 ? gap / primal : 0.0;
+}
+
+// Stopping test of the gap-controlled denoiser: NaN never meets a tolerance.
+bool gap_met(double rel, double tol) { return std::isfinite(rel) && rel <= tol; }
 
 // Dual-field bookkeeping of one denoiser call: four rotating scratch
 // buffers, so that a pass never writes a buffer it (or another tile of it)
@@ -429,27 +442,37 @@ int *cflag_ptr(sci_ctx *ctx, const sci_dims &d)
     return (int *)((char *)ctx->ws[WS_CBITS].ptr + ((img_elems(d) * sizeof(uint32_t) + 255) & ~(size_t)255));
 }
 
+// One outer solve: its inputs, outputs and the device scratch it runs on
+// (the context's growable buffers, or the fixed array of the allocation-free
+// entry point).
 struct OuterArgs {
     sci_dims d;
     sci_solver_params p;
     const float *Y, *C, *X_init;
     float *X_out, *theta;
     bool admm;
+    float *Sinv;               // 1 / (S + rho) image
+    uint32_t *cbits;           // packed masks, one word per pixel
+    int *cflag;                // 1 when the packed masks apply
+    float *svol, *u;           // ADMM only
+    void *duals[4];            // dual fields (nullptr: none needed)
 };
 
 int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
 {
     const sci_dims &d = a.d;
     const size_t vb = vol_elems(d) * sizeof(float);
-    float *Sinv = (float *)ctx->ws[WS_SINV].ptr;
+    float *Sinv = a.Sinv;
     float *theta = a.theta;
-    float *svol = a.admm ? (float *)ctx->ws[WS_SVOL].ptr : nullptr;
-    float *u = a.admm ? (float *)ctx->ws[WS_UVOL].ptr : nullptr;
+    float *svol = a.admm ? a.svol : nullptr;
+    float *u = a.admm ? a.u : nullptr;
+    uint32_t *cbits = a.cbits;
+    int *cflag = a.cflag;
 
     {
         ProfScope prof(ctx, PF_SETUP, s);
         launch_weights(d.nx, d.ny, d.B, a.C, a.admm ? a.p.rho : 0.0f, Sinv, s);
-        launch_pack_masks(d.nx, d.ny, d.B, a.C, cbits_ptr(ctx), cflag_ptr(ctx, d), s);
+        launch_pack_masks(d.nx, d.ny, d.B, a.C, cbits, cflag, s);
         if (a.X_init) launch_copy(a.X_init, theta, vb, s);     // theta^(0) = X_init
         else launch_adjoint(d.nx, d.ny, d.B, a.C, a.Y, theta, s); // theta^(0) = Phi^T y
         if (a.admm) launch_zero(u, vb, s);                     // u^(0) = 0
@@ -461,14 +484,13 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
         return check_launch(ctx, "copy");
     }
     FgpRun r;
-    bind_duals(ctx, r);
+    for (int k = 0; k < 4; ++k) r.buf[k] = a.duals[k];
     const void *warm = nullptr;
     for (int t = 0; t < a.p.outer_iters; ++t) {
         if (!a.admm) {
             {
                 ProfScope prof(ctx, PF_PROJECT, s);
-                launch_gap_project(d.nx, d.ny, d.B, theta, a.C, a.Y, Sinv, a.X_out, s, cbits_ptr(ctx),
-                                   cflag_ptr(ctx, d));
+                launch_gap_project(d.nx, d.ny, d.B, theta, a.C, a.Y, Sinv, a.X_out, s, cbits, cflag);
             }
             st = check_launch(ctx, "k_project");
             if (st != SCI_OK) return st;
@@ -479,8 +501,7 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
                 // forms u = s - theta itself, so x is stored on the last pass only
                 float *x = t + 1 == a.p.outer_iters ? a.X_out : nullptr;
                 ProfScope prof(ctx, PF_PROJECT, s);
-                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, x, svol, s, cbits_ptr(ctx),
-                                    cflag_ptr(ctx, d));
+                launch_admm_project(d.nx, d.ny, d.B, theta, u, a.C, a.Y, Sinv, x, svol, s, cbits, cflag);
             }
             st = check_launch(ctx, "k_project");
             if (st != SCI_OK) return st;
@@ -543,7 +564,11 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
     if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), s)) != SCI_OK) return st;
 
-    OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm};
+    OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm,
+                (float *)ctx->ws[WS_SINV].ptr, cbits_ptr(ctx), cflag_ptr(ctx, d),
+                admm ? (float *)ctx->ws[WS_SVOL].ptr : nullptr, admm ? (float *)ctx->ws[WS_UVOL].ptr : nullptr,
+                {nullptr, nullptr, nullptr, nullptr}};
+    for (int k = 0; k < 4; ++k) a.duals[k] = ctx->ws[WS_DUAL0 + k].ptr;
     if (!p->use_graph) return enqueue_outer(ctx, a, s);
 
     const std::string key = graph_key(a);
@@ -629,6 +654,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     if (!Theta_out && (st = ensure_ws(ctx, WS_THETA, vb, s)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_XTMP, vb, s)) != SCI_OK) return st;
+    if (twist && (st = ensure_ws(ctx, WS_XNEXT, vb, s)) != SCI_OK) return st;
     if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), s)) != SCI_OK) return st;
     double L = 0.0;
@@ -637,7 +663,15 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     float *W = (float *)ctx->ws[WS_SINV].ptr;
     float *theta = Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr;
     float *z = (float *)ctx->ws[WS_SVOL].ptr;
-    float *xa = X_out, *xb = (float *)ctx->ws[WS_XTMP].ptr;
+    // TwIST rotates three iterate buffers: the new iterate never overwrites
+    // one that the same kernel reads
+    float *xa = X_out, *xb = (float *)ctx->ws[WS_XTMP].ptr, *xc = twist ? (float *)ctx->ws[WS_XNEXT].ptr : nullptr;
+    auto rotate = [&]() { // x^(t+1) was written to xc
+        float *old_b = xb;
+        xb = xa;
+        xa = xc;
+        xc = old_b;
+    };
     sci_tv_params q = p->tv;
     q.lambda = (float)((double)p->tv.lambda / L);
     {
@@ -659,13 +693,13 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
         {
             ProfScope prof(ctx, PF_PROJECT, s);
             // FISTA steps from the extrapolated point (x^(0) itself at first),
-            // TwIST from x^(t), formed here (over x^(t-2)) once t >= 2
+            // TwIST from x^(t), formed here (into the third buffer) once t >= 2
             if (!twist && t > 0) {
                 launch_fista_project(d.nx, d.ny, d.B, xa, xb, ex, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
             } else if (pend) {
-                launch_twist_project(d.nx, d.ny, d.B, xa, xb, theta, a0, a1, a2, C, Y, W, z, xb, s, cbits_ptr(ctx),
+                launch_twist_project(d.nx, d.ny, d.B, xa, xb, theta, a0, a1, a2, C, Y, W, z, xc, s, cbits_ptr(ctx),
                                      cflag_ptr(ctx, d));
-                std::swap(xa, xb);
+                rotate();
                 pend = false;
             } else {
                 launch_gap_project(d.nx, d.ny, d.B, xa, C, Y, W, z, s, cbits_ptr(ctx), cflag_ptr(ctx, d));
@@ -691,8 +725,8 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
         if (!twist) std::swap(xa, xb); // xa = newest iterate, xb = the one before
     }
     if (pend) {
-        launch_two_step(V, a0, a1, a2, xb, xa, theta, xb, s);
-        std::swap(xa, xb);
+        launch_two_step(V, a0, a1, a2, xb, xa, theta, xc, s);
+        rotate();
     }
     // FISTA's last extrapolated point is stored only for the caller
     if (!twist && p->outer_iters > 0 && Theta_out) launch_extrapolate(V, ex, xa, xb, theta, s);
@@ -733,10 +767,12 @@ int denoise_adaptive(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &q, co
         const int n = std::min(every, q.n_inner_max - r.iters);
         if ((st = fgp_chunk(ctx, d, q, x, r, n, s)) != SCI_OK) return st;
         if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, x, r.cur, &gap, &primal, s)) != SCI_OK) return st;
-        if ((primal > 0.0 ? gap / primal : 0.0) <= q.gap_tol) {
+        const double rel = relative_gap(gap, primal);
+        if (gap_met(rel, q.gap_tol)) {
             *converged = true;
             break;
         }
+        if (std::isnan(rel)) break; // a non-finite start does not recover: stop and report it
     }
     *iters += r.iters;
     st = launch_tv_theta(q.dual_dtype, d.nx, d.ny, d.B, x, r.cur, q.lambda, theta, u_out, s);
@@ -837,11 +873,12 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
             if ((st = fgp_chunk(ctx, d, q, X_in, r, n, stream)) != SCI_OK) return st;
             if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_in, r.cur, &gap, &primal, stream)) != SCI_OK)
                 return st;
-            const double rel = primal > 0.0 ? gap / primal : 0.0;
-            if (rel <= q.gap_tol) {
+            const double rel = relative_gap(gap, primal);
+            if (gap_met(rel, q.gap_tol)) {
                 status = SCI_OK;
                 break;
             }
+            if (std::isnan(rel)) break; // non-finite gap: SCI_NOT_CONVERGED without running to the cap
         }
         st = launch_tv_theta(q.dual_dtype, d.nx, d.ny, d.B, X_in, r.cur, q.lambda, Theta_out, nullptr, stream);
         if (st == SCI_OK) st = check_launch(ctx, "k_tv_theta");
@@ -852,7 +889,7 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
         else launch_zero(dual_out, db, stream);
         if ((st = check_launch(ctx, "copy")) != SCI_OK) return st;
     }
-    if (rel_gap_out) *rel_gap_out = primal > 0.0 ? gap / primal : 0.0;
+    if (rel_gap_out) *rel_gap_out = relative_gap(gap, primal);
     if (iters_out) *iters_out = (q.n_inner == 0 && !adaptive) ? 0 : (adaptive ? r.iters : q.n_inner);
     return status;
 }
@@ -941,9 +978,11 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
                     return st;
                 if ((st = rel_gap(ctx, d, q.tv, q.dual_dtype, q.lambda, X_out, keep, &gk, &pk, stream)) != SCI_OK)
                     return st;
-                const double rp = pp > 0.0 ? gp / pp : 0.0, rk = pk > 0.0 ? gk / pk : 0.0;
-                if (rk < rp) init = keep;
-                else ++net_starts;
+                // a non-finite gap loses: the prediction is taken only when its
+                // gap is finite and no larger than the previous dual's
+                const double rp = relative_gap(gp, pp), rk = relative_gap(gk, pk);
+                if (std::isfinite(rp) && !(rk < rp)) ++net_starts;
+                else init = keep;
             } else {
                 ++net_starts;
             }
@@ -953,7 +992,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
         bool ok = false;
         if ((st = denoise_adaptive(ctx, d, q, X_out, theta, nullptr, init, r, &inner, &ok, stream)) != SCI_OK)
             return st;
-        if (!ok && use_net) { // the predicted start did not reach the tolerance: cold start
+        if (!ok && init == pred) { // the predicted start did not reach the tolerance: cold start
             ++fallbacks;
             if ((st = denoise_adaptive(ctx, d, q, X_out, theta, nullptr, nullptr, r, &inner, &ok, stream)) != SCI_OK)
                 return st;

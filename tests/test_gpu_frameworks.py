@@ -132,3 +132,57 @@ def test_theta_out_does_not_change_x(sc, ctx, which):
         x1, _ = fn(ctx, dev(Y), dev(pr.masks), prm, Theta_out=th)
         x2, _ = fn(ctx, dev(Y), dev(pr.masks), prm)
         np.testing.assert_array_equal(host(x1), host(x2))
+
+
+def graded(masks, seed):
+    """Graded (non-binary) masks: the projection reads float masks instead of packed bits."""
+    return (masks * np.random.default_rng(seed).uniform(0.2, 1.0, size=masks.shape)).astype(np.float32)
+
+
+# Shapes that reach every projection kernel the FISTA and TwIST modes
+# launch: two pixels per thread with packed binary masks (B = 24) or with
+# float masks when a mask is graded; one pixel per thread with every frame in
+# registers (odd pixel count, B = 10 and B = 24); and the generic kernel that
+# loops over the frames (B > 32, ATV and ITV2D only).
+PROJ_CASES = [
+    ("pairs_bits_b24", 24, 48, 66, "binary"),
+    ("pairs_float_masks_b24", 24, 40, 66, "graded"),
+    ("reg_odd_b10", 10, 33, 35, "graded"),
+    ("reg_odd_b24", 24, 33, 35, "binary"),
+    ("generic_b40", 40, 20, 34, "binary"),
+    ("generic_graded_b40", 40, 21, 33, "graded"),
+]
+
+
+@pytest.mark.parametrize("which", ["fista", "twist"])
+@pytest.mark.parametrize("case,B,nx,ny,mk", PROJ_CASES, ids=[c[0] for c in PROJ_CASES])
+def test_every_projection_kernel_matches_oracle(sc, ctx, which, case, B, nx, ny, mk):
+    pr = synth.make_problem(nx, ny, B, seed=nx + 3 * ny + B, sigma=0.01, radius=(2.0, 12.0))
+    C = graded(pr.masks, B) if mk == "graded" else pr.masks
+    Y = orc.measurement(C, pr.truth, pr.noise)
+    tv = "atv" if B > 32 else "itv2d"
+    x, th = run(sc, ctx, which, Y, C, outer_iters=7, tv=tv, lam=0.1, n_inner=4)
+    xr, thr = oracle(which, Y, C, 0.1, 7, 4, tv)
+    say = f"{which} {case}: rel-L2 x {rel(x, xr):.2e}, theta {rel(th, thr):.2e}"
+    print(say, flush=True)
+    assert rel(x, xr) <= REL_TOL and rel(th, thr) <= REL_TOL
+    # x does not depend on whether theta is requested (theta is formed only for the caller)
+    fn = sc.sci_fista_tv if which == "fista" else sc.sci_twist_tv
+    x2, _ = fn(ctx, dev(Y), dev(C), sc.solver_params(outer_iters=7, tv=tv, lam=0.1, n_inner=4))
+    np.testing.assert_array_equal(host(x2), x)
+
+
+@pytest.mark.parametrize("which", ["fista", "twist"])
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_short_runs_x_and_theta_match_oracle(sc, ctx, which, T):
+    """T = 1: TwIST has no pending two-step update and FISTA's last
+    extrapolation coefficient is 0; T = 2, 3: the update after the loop
+    (k_two_step / k_extrapolate) is the only one of its kind. Both x and theta
+    are compared with the oracle."""
+    pr = synth.make_problem(40, 66, 8, seed=70 + T, sigma=0.01, radius=(2.0, 12.0))
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for tv in ("atv", "vtv"):
+        x, th = run(sc, ctx, which, Y, pr.masks, outer_iters=T, tv=tv, lam=0.1, n_inner=5)
+        xr, thr = oracle(which, Y, pr.masks, 0.1, T, 5, tv)
+        print(f"{which} T={T} {tv}: rel-L2 x {rel(x, xr):.2e}, theta {rel(th, thr):.2e}", flush=True)
+        assert rel(x, xr) <= REL_TOL and rel(th, thr) <= REL_TOL

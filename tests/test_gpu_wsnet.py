@@ -284,3 +284,71 @@ def test_input_only_network_falls_back(sc, ctx, net):
           f"PSNR cold {pc:.3f} learned {pl:.3f}", flush=True)
     assert abs(pc - pl) < 0.05
     assert 0 <= fb <= outer
+
+
+# ---------------------------------------------------------------------------
+# Non-finite gaps: never "converged", never the better start.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("schedule", ["fused", "stream"])
+def test_nan_dual_init_is_not_converged(sc, ctx, schedule):
+    """A NaN in the starting dual makes every later gap NaN (the isotropic
+    projection keeps it); the gap-controlled denoiser must report
+    SCI_NOT_CONVERGED at the first check, with a NaN relative gap, rather than
+    read NaN as 0."""
+    r = np.random.default_rng(21)
+    x = dev(r.uniform(size=(4, 40, 48)))
+    init = torch.zeros((2, 4, 40, 48), device="cuda")
+    init[0, 1, 5, 7] = float("nan")
+    prm = sc.tv_params(tv="itv2d", lam=0.1, n_inner=0, gap_tol=1e-4, n_inner_max=3000, gap_check_every=5,
+                       schedule=schedule)
+    _, gap, its, st = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, want_gap=True)
+    print(f"NaN start ({schedule}): status {st}, {its} iterations, rel gap {gap}", flush=True)
+    assert st == sc.SCI_NOT_CONVERGED and its == 5 and np.isnan(gap)
+    # the same call from a finite start converges
+    _, gap, its, st = sc.sci_tv_denoise(ctx, x, prm, want_gap=True)
+    assert st == sc.SCI_OK and gap <= 1e-4
+
+
+def nan_params():
+    from paper_2005_08028_amd import warmstart
+    P = warmstart.init_params(3, last_scale=1.0, c_in=1)
+    P[:] = np.nan
+    return P
+
+
+def test_nan_network_falls_back_to_cold_start(sc, ctx, net):
+    """A network whose output is NaN (all weights NaN): every predicted start
+    fails the gap check and is redone from a zero dual, so x is bit-equal to
+    the cold-start run."""
+    sc.sci_wsnet_set_params(ctx, net, nan_params())
+    pr, Y, C, prm = _held_out(sc, ctx, "itv2d", 0.1, 6)
+    xc, cold, fbc, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    xl, its, fb, ns = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=net)
+    print(f"NaN network: {its} inner iterations (cold {cold}), {fb} fallbacks, {ns} net starts", flush=True)
+    assert fbc == 0 and fb == 6 and ns == 6
+    np.testing.assert_array_equal(host(xl), host(xc))
+    assert its == cold + 6  # one failed check per predicted start (gap_check_every = 1)
+
+
+def test_nan_network_loses_gap_checked_selection(sc, ctx, rnet):
+    """With warm duals the prediction competes with the previous final dual;
+    a NaN prediction must lose. A start from the previous dual that misses the
+    tolerance is kept as it is (no cold repeat, as without a network): with a
+    tight tolerance and a small cap every call misses, the fallback count
+    stays 0 and x is bit-equal to the warm-dual run without the network."""
+    from paper_2005_08028_amd import warmstart
+    P = warmstart.init_params(3, last_scale=1.0, c_in=3)
+    P[:] = np.nan
+    sc.sci_wsnet_set_params(ctx, rnet, P)
+    pr, Y, C, prm = _held_out(sc, ctx, "itv2d", 0.1, 5)
+    prm.tv.gap_tol = 1e-9
+    prm.tv.n_inner_max = 8
+    prm.tv.gap_check_every = 4
+    prm.warm_dual = 1
+    xw, warm, fbw, _ = sc.sci_gap_tv_adaptive(ctx, Y, C, prm)
+    xl, its, fb, ns = sc.sci_gap_tv_adaptive(ctx, Y, C, prm, net=rnet)
+    print(f"NaN correcting network, warm duals: {its} inner iterations (warm {warm}), {fb} fallbacks, "
+          f"{ns} net starts", flush=True)
+    assert fb == 0 and ns == 0 and its == warm == 5 * 8
+    np.testing.assert_array_equal(host(xl), host(xw))
