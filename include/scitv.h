@@ -189,6 +189,25 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
 int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
                float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
 
+/* sci_gap_tv for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, and harnesses that forbid
+ * hipMalloc. It calls no hipMalloc, hipFree or other allocating routine and
+ * creates no event; its scratch (the 1 / S image, the packed masks and their
+ * flag, about 32 MiB) is a fixed device array that the library holds on every
+ * GPU it runs on until the process ends, so nx * ny <= 4194304
+ * (SCI_ERR_INVALID_ARG beyond). Same arguments and results as sci_gap_tv with
+ * the same parameters and tile_passes = 1, except: Theta_out is required (it
+ * holds theta between iterations); use_graph and warm_dual must be 0
+ * (SCI_ERR_UNSUPPORTED); every denoiser call runs as one cold on-chip pass
+ * that stores no dual, so n_inner <= 10 (VTV: 10 / 8 / 5 / 4 for
+ * B <= 8 / 16 / 24 / 32; SCI_ERR_UNSUPPORTED beyond), schedule and
+ * tile_passes are ignored and dual_dtype does not change the result. Every
+ * part of the scratch is written before it is read in each call. All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (different
+ * streams, host threads or contexts) race and must be ordered by the caller. */
+int sci_gap_tv_noalloc(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
+                       float *X_out, float *Theta_out, const float *X_init, hipStream_t stream);
+
 /* ADMM (Eq. (24)-(26)): theta^(0) = Phi^T Y (or X_init), u^(0) = 0;
  *   x^(t+1) = v + Phi^T (Phi Phi^T + rho I)^{-1} (Y - Phi v), v = theta^(t) - u^(t)
  *   theta^(t+1) = TVdenoise(u^(t) + x^(t+1))   (weight lambda)

@@ -126,6 +126,10 @@ int sci_create(sci_ctx **out, int device)
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    if (sci::noalloc_scratch_lookup(device, &ctx->noalloc_scratch) != SCI_OK) {
+        delete ctx;
+        return SCI_ERR_HIP;
+    }
     e = hipHostMalloc((void **)&ctx->host_scalars, 8 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete ctx;

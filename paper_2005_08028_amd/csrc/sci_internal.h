@@ -58,6 +58,7 @@ struct ProfRec {
 struct sci_ctx {
     int device = 0;
     int num_cus = 0;
+    void *noalloc_scratch = nullptr; // device address of the fixed scratch array (sci_gap_tv_noalloc)
     std::string last_error;
     sci::Buf ws[sci::WS_COUNT];
     double *host_scalars = nullptr; // pinned, 8 doubles
@@ -74,6 +75,17 @@ struct sci_ctx {
 };
 
 namespace sci {
+
+// ---- fixed scratch of the allocation-free GAP entry point (noalloc.hip) -----
+// Layout: 1 / S image (float per pixel), packed masks (32-bit word per
+// pixel), the packed-mask flag; sized for nx * ny <= kNoAllocMaxPixels.
+constexpr size_t kNoAllocMaxPixels = (size_t)1 << 22;
+constexpr size_t kNoAllocBitsOffset = kNoAllocMaxPixels * 4;
+constexpr size_t kNoAllocFlagOffset = kNoAllocBitsOffset + kNoAllocMaxPixels * 4;
+constexpr size_t kNoAllocScratchBytes = kNoAllocFlagOffset + 256;
+// Device address of the array on `device`, which must be current; looked up
+// once per device and cached. SCI_OK or SCI_ERR_HIP.
+int noalloc_scratch_lookup(int device, void **addr);
 
 // ---- context helpers (ctx.cpp) ---------------------------------------------
 int fail_hip(sci_ctx *ctx, hipError_t e, const char *what);

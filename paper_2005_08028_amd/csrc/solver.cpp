@@ -906,6 +906,46 @@ int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const floa
     return run_outer(ctx, d, p, Y, C, X_out, Theta_out, X_init, true, stream);
 }
 
+int sci_gap_tv_noalloc(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C,
+                       float *X_out, float *Theta_out, const float *X_init, hipStream_t stream)
+{
+    if (!ctx) return SCI_ERR_INVALID_ARG;
+    int st = check_dims(ctx, d);
+    if (st != SCI_OK) return st;
+    if (img_elems(d) > kNoAllocMaxPixels)
+        return fail(ctx, SCI_ERR_INVALID_ARG, "nx * ny exceeds the fixed scratch of the allocation-free GAP (4194304 pixels)");
+    if ((st = check_outer_args(ctx, d, p, Y, C, X_out, Theta_out, X_init)) != SCI_OK) return st;
+    if (!Theta_out) return fail(ctx, SCI_ERR_INVALID_ARG, "Theta_out is required (no scratch volume is allocated)");
+    if (p->use_graph || p->warm_dual)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "the allocation-free GAP needs use_graph = 0 and warm_dual = 0");
+    if (!ctx->noalloc_scratch) return fail(ctx, SCI_ERR_HIP, "fixed scratch address unknown");
+    // every denoiser call is one cold on-chip pass that stores no dual field,
+    // so the dual storage type does not change the result
+    sci_solver_params q = *p;
+    sci_tv_params &t = q.tv;
+    t.dual_dtype = SCI_DUAL_F32;
+    t.schedule = SCI_SCHED_FUSED;
+    t.tile_passes = 1;
+    if (t.lambda > 0.0f && t.n_inner > 0) {
+        const int max_m = (t.tv == SCI_TV_VTV && !t.clip) ? vtv_rows_max_pass(d.B) : kTileMaxM;
+        if (t.n_inner > max_m || !fused_supported(t, d))
+            return fail(ctx, SCI_ERR_UNSUPPORTED,
+                        "the allocation-free GAP runs each denoiser call in one on-chip pass (n_inner <= 10; "
+                        "VTV: 10 / 8 / 5 / 4 for B <= 8 / 16 / 24 / 32)");
+    }
+    // no context event may be created here: the profiler is off for this call
+    struct ProfOff {
+        sci_ctx *c;
+        bool was;
+        ~ProfOff() { c->prof_on = was; }
+    } prof_off{ctx, ctx->prof_on};
+    ctx->prof_on = false;
+    char *base = (char *)ctx->noalloc_scratch;
+    OuterArgs a{d, q, Y, C, X_init, X_out, Theta_out, false, (float *)base, (uint32_t *)(base + kNoAllocBitsOffset),
+                (int *)(base + kNoAllocFlagOffset), nullptr, nullptr, {nullptr, nullptr, nullptr, nullptr}};
+    return enqueue_outer(ctx, a, stream);
+}
+
 int sci_fista_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
                  float *Theta_out, const float *X_init, hipStream_t stream)
 {

@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sci_adjoint": (I, [V, D, V, V, V, V]),
         "sci_tv_denoise": (I, [V, D, P(sci_tv_params), V, V, V, V, P(ctypes.c_double), P(ctypes.c_int32), V]),
         "sci_gap_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
+        "sci_gap_tv_noalloc": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
         "sci_admm_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
         "sci_fista_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
         "sci_twist_tv": (I, [V, D, P(sci_solver_params), V, V, V, V, V, V]),
@@ -230,6 +231,12 @@ def _outer(fn, ctx, Y, C, params, X_out, Theta_out, X_init, stream):
 def sci_gap_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None, X_init=None, stream=None):
     """GAP-TV; returns (X_out, Theta_out)."""
     return _outer(lib.sci_gap_tv, ctx, Y, C, params, X_out, Theta_out, X_init, stream)
+
+
+def sci_gap_tv_noalloc(ctx, Y, C, params: sci_solver_params, X_out, Theta_out, X_init=None, stream=None):
+    """GAP-TV without any device allocation by the library (caller-owned
+    X_out and Theta_out); returns (X_out, Theta_out)."""
+    return _outer(lib.sci_gap_tv_noalloc, ctx, Y, C, params, X_out, Theta_out, X_init, stream)
 
 
 def sci_admm_tv(ctx, Y, C, params: sci_solver_params, X_out=None, Theta_out=None, X_init=None, stream=None):
