@@ -222,8 +222,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
                             ph = qh[rr][kk] * sc[rr];
                             pv = qv[rr][kk] * sc[rr];
                         } else if (CH && TV == TV_ATV) {
-                            ph = qh[rr][kk] / (1.0f + fabsf(sh[rr][kk]));
-                            pv = qv[rr][kk] / (1.0f + fabsf(sv[rr][kk]));
+                            ph = semi_implicit_atv(qh[rr][kk], sh[rr][kk]);
+                            pv = semi_implicit_atv(qv[rr][kk], sv[rr][kk]);
                         } else if (CH) {
                             const float s1 = semi_implicit_scale(norm2_add(0.0f, sh[rr][kk], sv[rr][kk]));
                             ph = qh[rr][kk] * s1;

@@ -226,8 +226,8 @@ __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, i
                         const float sh = step_h[c] * zh, sv = step_v * zv;
                         const float qh = cwh[t][c] + sh, qv = cwv[t][c] + sv;
                         if (TV == TV_ATV) {
-                            nh[c] = qh / (1.0f + fabsf(sh));
-                            nv[c] = qv / (1.0f + fabsf(sv));
+                            nh[c] = semi_implicit_atv(qh, sh);
+                            nv[c] = semi_implicit_atv(qv, sv);
                         } else {
                             const float s1 = semi_implicit_scale(norm2_add(0.0f, sh, sv));
                             nh[c] = qh * s1;

@@ -79,8 +79,16 @@ __device__ inline float proj_atv(float q) { return fminf(fmaxf(q, -1.0f), 1.0f);
 __device__ inline float iso_scale(float n2) { return fminf(1.0f, __builtin_amdgcn_rsqf(n2)); }
 
 // Semi-implicit (Chambolle 2004) scale 1 / (1 + sqrt(n2)) for the squared
-// norm n2 of z/(8 lambda).
-__device__ inline float semi_implicit_scale(float n2) { return 1.0f / (1.0f + __builtin_sqrtf(n2)); }
+// norm n2 of z/(8 lambda), with the hardware square root and reciprocal
+// (v_sqrt_f32, v_rcp_f32: about 1 ulp each, in place of the IEEE-exact
+// sequences, which cost several times the instructions).
+__device__ inline float semi_implicit_scale(float n2)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(n2));
+}
+
+// The same step per component (ATV): q / (1 + |s|) for s = z/(8 lambda).
+__device__ inline float semi_implicit_atv(float q, float s) { return q * __builtin_amdgcn_rcpf(1.0f + fabsf(s)); }
 
 // Squared-norm accumulation (h^2 + v^2 added to acc).
 __device__ inline float norm2_add(float acc, float h, float v) { return fmaf(v, v, fmaf(h, h, acc)); }
