@@ -76,14 +76,14 @@ typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_
  *   STREAM: one pass over HBM per inner iteration (dual fields in memory);
  *   FUSED : up to 10 inner iterations per on-chip pass, the dual fields
  *           written back only between passes (ATV and ITV2D with any dual
- *           type; VTV with float32 duals (16-bit: a cold single pass
- *           that returns no dual), passes of at most 10 / 8 / 5 / 4
+ *           type; VTV with any dual type, passes of at most 10 / 8 / 5 / 4
  *           iterations for B <= 8 / 16 / 24 / 32; the Chambolle-2004 step
  *           with float32 duals on the row-pipelined kernels; ATV-Clip with
  *           float32 duals);
  *   AUTO  : FUSED where it applies, else STREAM.
  * Both schedules evaluate the same per-voxel expressions (bit for bit with
- * float32 duals; 16-bit duals are rounded where they are stored). */
+ * float32 duals; 16-bit duals are rounded where they are stored: after every
+ * iteration on STREAM, between passes on FUSED). */
 typedef enum { SCI_SCHED_AUTO = 0, SCI_SCHED_STREAM = 1, SCI_SCHED_FUSED = 2 } sci_schedule;
 
 /* TV denoiser parameters: theta = argmin 1/2 ||theta - x||^2 + lambda TV(theta)

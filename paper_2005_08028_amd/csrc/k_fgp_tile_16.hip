@@ -47,8 +47,7 @@ int launch_fgp_tile(int tv, int dual_dtype, int m, int shape, int nx, int ny, in
     // kernels too (same bits as a float32 pass; registers are float32).
     const bool no_dual_io = tp.mode == 0 && !tp.pn_out && !tp.pp_out;
     if (tv == TV_VTV) // one row-pipelined kernel, whatever the shape
-        return dual_dtype == DT_F32 || no_dual_io ? launch_vtv_rows(m, nx, ny, B, x, tp, lam, s, chambolle04)
-                                                  : SCI_ERR_UNSUPPORTED;
+        return launch_vtv_rows(m, nx, ny, B, x, tp, lam, s, chambolle04, no_dual_io ? DT_F32 : dual_dtype);
     if (chambolle04) { // row-pipelined shapes, float32 duals, ATV and ITV2D
         int H = 0, w = 0, c = 0;
         if (dual_dtype != DT_F32 || !tile_supported(tv) || !tile_shape_pipelined(shape)) return SCI_ERR_UNSUPPORTED;

@@ -41,16 +41,20 @@ constexpr int kVtvMaxWaves = 8; // wavefronts (frame groups) per workgroup, at m
 // MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
 // CH_STEP = 1: Chambolle's (2004) semi-implicit step in place of the
 // projection, |z/(8 lambda)| over all frames of the pixel, with the
-// operations of the streaming pass.
-template <int M, int KF, int MODE, int CH_STEP>
+// operations of the streaming pass. DT: storage type of the duals read and
+// written between passes (arithmetic stays float32; 16-bit values are
+// rounded to nearest even where they are stored).
+template <int M, int KF, int MODE, int CH_STEP, int DT = DT_F32>
 __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, int B, int fpw, int nstrip, int H,
                                                               const float *__restrict__ x,
-                                                              const float *__restrict__ pc,
-                                                              const float *__restrict__ pp, TileBeta bt, float lam,
-                                                              float step, float *__restrict__ pn_out,
-                                                              float *__restrict__ pp_out,
+                                                              const typename Dual<DT>::T *__restrict__ pc,
+                                                              const typename Dual<DT>::T *__restrict__ pp,
+                                                              TileBeta bt, float lam, float step,
+                                                              typename Dual<DT>::T *__restrict__ pn_out,
+                                                              typename Dual<DT>::T *__restrict__ pp_out,
                                                               float *__restrict__ theta_out, float *__restrict__ u_out)
 {
+    using D = Dual<DT>;
     constexpr int CH = kRowChunk;
     constexpr int TXO = 64 - 2 * M - 1; // interior columns per strip
     static_assert(TXO > 0, "strip too narrow for the pass length");
@@ -106,12 +110,12 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                 const uint32_t o = fo[kk] + rowo;
                 xn[s][kk] = x[o];
                 if (MODE >= 1) {
-                    lh[s][kk] = pc[o];
-                    lv[s][kk] = pc[V + o];
+                    lh[s][kk] = D::ld(pc, o);
+                    lv[s][kk] = D::ld(pc, V + o);
                 }
                 if (MODE == 2) {
-                    mh[s][kk] = pp[o];
-                    mv[s][kk] = pp[V + o];
+                    mh[s][kk] = D::ld(pp, o);
+                    mv[s][kk] = D::ld(pp, V + o);
                 }
             }
         }
@@ -240,12 +244,12 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                     if (theta_out) theta_out[o] = th[kk];
                     if (u_out) u_out[o] = xl[M][kk] - th[kk];
                     if (pn_out) {
-                        pn_out[o] = jh[kk];
-                        pn_out[V + o] = jv[kk];
+                        D::st(pn_out, o, jh[kk]);
+                        D::st(pn_out, V + o, jv[kk]);
                     }
                     if (pp_out) {
-                        pp_out[o] = qph[kk];
-                        pp_out[V + o] = qpv[kk];
+                        D::st(pp_out, o, qph[kk]);
+                        D::st(pp_out, V + o, qpv[kk]);
                     }
                 }
             }
@@ -298,30 +302,31 @@ int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
     return (nx + nseg - 1) / nseg;
 }
 
-template <int M, int KF, int MODE, int CH_STEP>
+template <int M, int KF, int MODE, int CH_STEP, int DT>
 void launch_vtv_mode(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                      hipStream_t s)
 {
+    using T = typename Dual<DT>::T;
     constexpr int TXO = 64 - 2 * M - 1;
     const int nstrip = (ny + TXO - 1) / TXO;
-    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE, CH_STEP>, ng, nx, nstrip);
+    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE, CH_STEP, DT>, ng, nx, nstrip);
     const int nseg = (nx + H - 1) / H;
-    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE, CH_STEP>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny, B, fpw, nstrip,
-                       H, x, (const float *)tp.pc, (const float *)tp.pp, tp.beta, lam, 1.0f / (8.0f * lam),
-                       (float *)tp.pn_out, (float *)tp.pp_out, tp.theta, tp.u_out);
+    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE, CH_STEP, DT>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny, B, fpw,
+                       nstrip, H, x, (const T *)tp.pc, (const T *)tp.pp, tp.beta, lam, 1.0f / (8.0f * lam),
+                       (T *)tp.pn_out, (T *)tp.pp_out, tp.theta, tp.u_out);
 }
 
-template <int M, int KF, int CH_STEP>
+template <int M, int KF, int CH_STEP, int DT>
 void launch_vtv_m(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                   hipStream_t s)
 {
-    if (tp.mode == 0) launch_vtv_mode<M, KF, 0, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);
-    else if (tp.mode == 1) launch_vtv_mode<M, KF, 1, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);
-    else launch_vtv_mode<M, KF, 2, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    if (tp.mode == 0) launch_vtv_mode<M, KF, 0, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    else if (tp.mode == 1) launch_vtv_mode<M, KF, 1, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    else launch_vtv_mode<M, KF, 2, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
 }
 
 // Dispatch on the pass length m = 1..vtv_rows_max_m(KF).
-template <int KF, int CH_STEP>
+template <int KF, int CH_STEP, int DT = DT_F32>
 int launch_vtv_kf(int m, int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                   hipStream_t s)
 {
@@ -330,7 +335,7 @@ int launch_vtv_kf(int m, int nx, int ny, int B, int fpw, int ng, const float *x,
     switch (m) {
 #define SCI_VTV_M(mm)                                                                                               \
     case mm:                                                                                                        \
-        if constexpr (mm <= MM) launch_vtv_m<mm, KF, CH_STEP>(nx, ny, B, fpw, ng, x, tp, lam, s);                            \
+        if constexpr (mm <= MM) launch_vtv_m<mm, KF, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);                        \
         return SCI_OK;
         SCI_VTV_M(1) SCI_VTV_M(2) SCI_VTV_M(3) SCI_VTV_M(4) SCI_VTV_M(5) SCI_VTV_M(6) SCI_VTV_M(7) SCI_VTV_M(8)
         SCI_VTV_M(9) SCI_VTV_M(10)

@@ -194,11 +194,12 @@ int tile_shape_count();
 bool tile_shape_info(int shape, int *rows, int *waves, int *cols);
 // true for the row-pipelined shapes (numbered after the tiled ones)
 bool tile_shape_pipelined(int shape);
-// Row-pipelined VTV passes (float32 duals): the longest pass for B frames (0
-// when the kernel does not run them), and one pass of m iterations.
+// Row-pipelined VTV passes: the longest pass for B frames (0 when the kernel
+// does not run them), and one pass of m iterations with the duals read and
+// written between passes in dual_dtype (16-bit: projection step only).
 int vtv_rows_max_pass(int B);
 int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,
-                    bool chambolle04 = false);
+                    bool chambolle04 = false, int dual_dtype = 0);
 // shape: index into the shape table (0 = default); 16-bit dual storage runs
 // the default shape whatever is asked
 // chambolle04: Chambolle's (2004) step instead of FGP (row-pipelined shapes,

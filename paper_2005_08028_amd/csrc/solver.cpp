@@ -120,7 +120,8 @@ struct FgpRun {
 // SIMD: the fastest single-iteration shape measured at 1024x1024x24).
 constexpr int kStreamTileShape = 3;
 
-constexpr const char *kFusedScope = "the fused schedule covers ATV, ITV2D, and VTV with float32 duals";
+constexpr const char *kFusedScope =
+    "the fused schedule covers ATV, ITV2D, and VTV with B <= 32 (the Chambolle-2004 step with float32 duals)";
 
 int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const float *x, FgpRun &r, int n,
                      float *theta, float *u_out, bool keep_dual, hipStream_t s, int force_shape = -1,
@@ -297,10 +298,12 @@ void bind_duals(sci_ctx *ctx, FgpRun &r)
     for (int k = 0; k < 4; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
 }
 
-// VTV on the fused schedule: the row-pipelined kernel with float32 duals.
+// VTV on the fused schedule: the row-pipelined kernel (16-bit dual storage
+// for the projection step, float32 for the Chambolle-2004 step).
 bool vtv_fused_supported(const sci_tv_params &p, const sci_dims &d)
 {
-    return p.tv == SCI_TV_VTV && p.dual_dtype == SCI_DUAL_F32 && !p.clip && vtv_rows_max_pass(d.B) > 0;
+    return p.tv == SCI_TV_VTV && (p.dual_dtype == SCI_DUAL_F32 || !p.chambolle04) && !p.clip &&
+           vtv_rows_max_pass(d.B) > 0;
 }
 
 bool fused_supported(const sci_tv_params &p, const sci_dims &d)
@@ -381,12 +384,6 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
         if (st != SCI_OK) return fail(ctx, st, "theta pass");
         return check_launch(ctx, "k_tv_theta");
     }
-    // 16-bit VTV in one cold pass that keeps no dual: the storage is never
-    // touched, so the fused float32 kernel gives the answer (as for 2D TVs)
-    const bool vtv16_single = p.tv == SCI_TV_VTV && p.dual_dtype != SCI_DUAL_F32 &&
-                              p.schedule != SCI_SCHED_STREAM && !p.chambolle04 && warm == nullptr && !keep_dual &&
-                              p.n_inner >= 2 && p.n_inner <= vtv_rows_max_pass(d.B) && p.tile_passes <= 1;
-    if (vtv16_single) return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);
     if (use_fused(p, d)) {
         if (!fused_supported(p, d)) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
         return fgp_tile_iterate(ctx, d, p, x, r, p.n_inner, theta, u_out, keep_dual, s);

@@ -289,22 +289,24 @@ def test_vtv_fused_every_frame_split(sc, ctx):
 
 @pytest.mark.parametrize("B", [3, 10, 24])
 def test_vtv_16bit_cold_single_pass(sc, ctx, B):
-    """16-bit VTV storage in one cold pass that returns no dual never stores
-    the dual: the default schedule gives the float32 fused bits. Asked for
-    the dual, the call keeps the 16-bit streaming pass (its own bits)."""
+    """16-bit VTV storage in one cold pass: the dual is held in float32
+    registers for the whole pass, so theta is the float32 fused result bit
+    for bit, and the dual returned in 16 bits is the float32 dual rounded to
+    nearest even (torch's conversion), also bit for bit."""
     r = np.random.default_rng(B * 23)
     x = dev(r.uniform(size=(B, 90, 140)).astype(np.float32))
     n = 4
-    ref = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, schedule="fused"))[0])
+    d32 = torch.empty((2, B, 90, 140), device="cuda")
+    ref = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, schedule="fused"),
+                                 dual_out=d32)[0])
     for dt in ("bf16", "f16"):
         th = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, dual_dtype=dt))[0])
         np.testing.assert_array_equal(th, ref, err_msg=dt)
         ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
         d = torch.empty((2, B, 90, 140), device="cuda", dtype=ddt)
         th_d = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, dual_dtype=dt), dual_out=d)[0])
-        th_s = host(sc.sci_tv_denoise(ctx, x, sc.tv_params(tv="vtv", lam=0.1, n_inner=n, dual_dtype=dt,
-                                                           schedule="stream"))[0])
-        np.testing.assert_array_equal(th_d, th_s, err_msg=dt + " with the dual returned")
+        np.testing.assert_array_equal(th_d, ref, err_msg=dt + " with the dual returned")
+        assert torch.equal(d.view(torch.int16), d32.to(ddt).view(torch.int16)), dt + " dual rounding"
 
 
 @pytest.mark.parametrize("solver", ["gap", "admm"])
@@ -706,6 +708,40 @@ def test_denoise_16bit_duals(sc, ctx, tv, dt, bound):
     assert amax <= 10 * 4 * 0.1 * u
 
 
+@pytest.mark.parametrize("dt,bound", [("bf16", 2e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("B,maxpass", [(8, 10), (16, 8), (24, 5), (32, 4)])
+def test_vtv_fused_16bit_duals_between_passes(sc, ctx, B, maxpass, dt, bound):
+    """VTV on the fused schedule with 16-bit dual storage: a call longer than
+    one pass (at most 10 / 8 / 5 / 4 iterations for B <= 8 / 16 / 24 / 32)
+    stores the dual between passes in 16 bits and keeps it in float32
+    registers inside a pass. Against the FP64 oracle within the 16-bit bound,
+    cold and from a 16-bit starting dual, with the returned dual checked
+    through the duality gap it certifies; beside it the streaming schedule,
+    which rounds after every iteration."""
+    r = np.random.default_rng(B)
+    nx, ny = 37, 70
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    n = 2 * maxpass + 1  # three passes
+    ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
+    p0 = orc.project_dual(0.3 * r.normal(size=(2, B, nx, ny)), "vtv")
+    p0_16 = dev(p0.astype(np.float32), ddt)
+    for init in (None, p0_16):
+        errs = {}
+        for schedule in ("fused", "stream"):
+            prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=n, schedule=schedule, dual_dtype=dt)
+            dual = torch.empty((2, B, nx, ny), device="cuda", dtype=ddt)
+            th, gap, its, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=init, dual_out=dual, want_gap=True)
+            assert its == n
+            ref = orc.tv_denoise(x, f32(0.1), n, "vtv", p_init=None if init is None else host(init))
+            errs[schedule] = rel_l2(host(th), ref)
+            # the returned dual is feasible and certifies theta through the FP64 gap
+            g, prim = orc.dual_gap(x, host(dual), f32(0.1), "vtv")
+            assert np.isfinite(gap) and abs(gap - g / prim) <= 1e-3 * max(g / prim, 1e-6) + 1e-6
+        say(f"vtv B={B} {dt} N={n} ({'warm' if init is not None else 'cold'}): rel-L2 fused {errs['fused']:.2e}, "
+            f"streaming {errs['stream']:.2e}")
+        assert errs["fused"] <= bound and errs["stream"] <= bound
+
+
 # ---------------------------------------------------------------------------
 # GAP / ADMM.
 # ---------------------------------------------------------------------------
@@ -1000,3 +1036,41 @@ def test_cacti_full_solve_properties(sc, ctx, cacti):
     p_0 = orc.psnr(orc.adjoint(pr.masks, Y) / np.maximum(S, 1)[None], pr.truth)
     say(f"GAP-ITV2D 1024x1024x24 200x10: PSNR {p_x:.2f} dB (back-projection {p_0:.2f})")
     assert p_x > p_0 + 5.0
+
+
+@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+@pytest.mark.parametrize("B,nx,ny,masks", [(8, 70, 96, "binary"), (24, 33, 130, "binary"), (6, 45, 61, "graded"),
+                                           (40, 21, 100, "binary")])
+def test_gap_row_and_tiled_shapes_bitwise(sc, ctx, tv, B, nx, ny, masks):
+    """Whole GAP solves with the row-pipelined and with a tiled denoiser
+    shape give the same bits (the same per-voxel arithmetic): several
+    outer-iteration counts, X_init given or not, Theta_out requested or not,
+    eager and graph-launched; packed bits (binary masks, B <= 32) and float
+    masks (graded, or B > 32) in the projection."""
+    pr = synth.make_problem(nx, ny, B, seed=nx + ny + B, sigma=0.01, radius=(3.0, 15.0))
+    C = pr.masks
+    if masks == "graded":
+        C = (C * np.random.default_rng(B).uniform(0.2, 1.0, size=C.shape)).astype(np.float32)
+    Y, Cd = dev(orc.measurement(C, pr.truth, pr.noise)), dev(C)
+    shapes = range(1, sc.sci_tile_shape_count() + 1)
+    row = next(k for k in shapes if sc.sci_tile_shape_pipelined(k))
+    tiled = next(k for k in shapes if not sc.sci_tile_shape_pipelined(k))
+    x0 = dev(np.random.default_rng(3).uniform(size=C.shape).astype(np.float32))
+    for T in (1, 2, 3, 6):
+        for x_init in (None, x0):
+            for graph in (False, True):
+                outs = []
+                for shape in (row, tiled):
+                    prm = sc.solver_params(outer_iters=T, tv=tv, lam=0.1, n_inner=7, tile_shape=shape,
+                                           tile_passes=1, use_graph=graph)
+                    th = torch.empty_like(Cd)
+                    x, _ = sc.sci_gap_tv(ctx, Y, Cd, prm, Theta_out=th, X_init=x_init)
+                    x2, _ = sc.sci_gap_tv(ctx, Y, Cd, prm, X_init=x_init)  # no theta requested
+                    outs.append((host(x), host(th), host(x2)))
+                tag = f"T={T} init={x_init is not None} graph={graph}"
+                np.testing.assert_array_equal(outs[0][0], outs[1][0], err_msg="x " + tag)
+                np.testing.assert_array_equal(outs[0][1], outs[1][1], err_msg="theta " + tag)
+                np.testing.assert_array_equal(outs[0][2], outs[0][0], err_msg="x without theta " + tag)
+    e = rel_l2(outs[0][0], orc.gap_tv(host(Y), C, f32(0.1), 6, 7, tv=tv, x_init=host(x0))[0])
+    say(f"GAP-{tv} B={B} {nx}x{ny} {masks}: row and tiled shapes bit-equal; rel-L2 vs oracle {e:.2e}")
+    assert e <= REL_TOL
