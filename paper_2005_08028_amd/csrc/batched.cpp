@@ -23,6 +23,7 @@ struct BatchPlan {
     std::vector<int> order;     // tab[k] is problem order[k]
     std::vector<int> wg_end;    // wg_end[k] = workgroups of problems 0..k-1 (prefix)
     std::vector<int> pb_end;
+    std::vector<int> pj_end;
     int maxB = 0, Tmax = 0, shape = 0, m = 0;
     size_t slab_floats = 0;
 };
@@ -85,6 +86,7 @@ void plan_batch(const sci_ctx *ctx, int n, const sci_problem *probs, const sci_s
     pl.tab.assign(n, BatchProb{});
     pl.wg_end.assign(n + 1, 0);
     pl.pb_end.assign(n + 1, 0);
+    pl.pj_end.assign(n + 1, 0);
     pl.slab_floats = 0;
     pl.maxB = 0;
     pl.Tmax = 0;
@@ -102,6 +104,11 @@ void plan_batch(const sci_ctx *ctx, int n, const sci_problem *probs, const sci_s
         pl.wg_end[k + 1] = b.wg_base + b.ntiles * b.B;
         const int npix = q.d.nx * q.d.ny;
         pl.pb_end[k + 1] = b.pb_base + (npix + kPixBlock - 1) / kPixBlock;
+        auto al8 = [](const void *ptr) { return ptr == nullptr || ((uintptr_t)ptr & 7u) == 0; };
+        b.pairs = npix % 2 == 0 && al8(q.Y) && al8(q.C) && al8(q.X_out) && al8(q.Theta_out) ? 1 : 0;
+        b.pj_base = pl.pj_end[k];
+        const int units = b.pairs ? npix / 2 : npix;
+        pl.pj_end[k + 1] = b.pj_base + (units + kPixBlock - 1) / kPixBlock;
         b.Y = q.Y;
         b.C = q.C;
         b.x = q.X_out;
@@ -159,7 +166,7 @@ int enqueue_batch(sci_ctx *ctx, const BatchPlan &pl, const BatchProb *tab_dev, c
         const int na = active_count(pl, t);
         {
             ProfScope prof(ctx, PF_PROJECT, s);
-            st = launch_batch_project(na, pl.pb_end[na], pl.maxB, tab_dev, s);
+            st = launch_batch_project(na, pl.pj_end[na], pl.maxB, tab_dev, s);
         }
         if (st != SCI_OK) return fail(ctx, st, "batched projection");
         if ((st = check_launch(ctx, "k_batch_project")) != SCI_OK) return st;
@@ -297,7 +304,7 @@ int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, cons
         const int nb = (int)pl.tab.size();
         if ((st = upload_table(ctx, pl, tab, stream)) != SCI_OK) break;
         launch_batch_setup(nb, pl.pb_end[nb], tab, stream);
-        if ((st = launch_batch_project(nb, pl.pb_end[nb], pl.maxB, tab, stream)) != SCI_OK) break;
+        if ((st = launch_batch_project(nb, pl.pj_end[nb], pl.maxB, tab, stream)) != SCI_OK) break;
         const int reps = 3;
         for (int r = 0; r <= reps && st == SCI_OK; ++r) {
             if (r == 1 && hipEventRecord(e0, stream) != hipSuccess) st = fail(ctx, SCI_ERR_HIP, "hipEventRecord");

@@ -67,13 +67,51 @@ __global__ __launch_bounds__(kPixBlock) void k_batch_setup(int n, const BatchPro
 }
 
 // x = theta + C .* ((Y - sum_k C_k theta_k) .* Sinv), frames in registers.
+// Problems flagged `pairs` take two adjacent pixels per thread (8-byte
+// accesses, as the single-problem projection); the others one. The per-pixel
+// arithmetic is the same either way.
+template <int KB>
+__device__ inline void batch_project_pair(const BatchProb &b, uint32_t q)
+{
+    const uint32_t npix = (uint32_t)b.nx * (uint32_t)b.ny;
+    const uint32_t half = npix / 2; // float2 elements per frame
+    if (q >= half) return;
+    const int B = b.B;
+    const bool packed = *b.cflag != 0;
+    const uint2 m = packed ? ((const uint2 *)b.cbits)[q] : make_uint2(0u, 0u);
+    const float2 *th = (const float2 *)b.theta, *C = (const float2 *)b.C;
+    float2 v[KB], c[KB];
+    float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < B) {
+            const uint32_t o = (uint32_t)k * half + q;
+            c[k] = packed ? make_float2((m.x >> k) & 1u ? 1.0f : 0.0f, (m.y >> k) & 1u ? 1.0f : 0.0f) : C[o];
+            v[k] = th[o];
+            acc0 = fmaf(c[k].x, v[k].x, acc0);
+            acc1 = fmaf(c[k].y, v[k].y, acc1);
+        }
+    }
+    const float2 yv = ((const float2 *)b.Y)[q], sv = ((const float2 *)b.Sinv)[q];
+    const float r0 = (yv.x - acc0) * sv.x, r1 = (yv.y - acc1) * sv.y;
+    float2 *x = (float2 *)b.x;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (k < B) x[(uint32_t)k * half + q] = make_float2(fmaf(c[k].x, r0, v[k].x), fmaf(c[k].y, r1, v[k].y));
+}
+
 template <int KB>
 __global__ __launch_bounds__(kPixBlock) void k_batch_project(int n, const BatchProb *__restrict__ tab)
 {
-    const int p = find_problem(n, (int)blockIdx.x, [&](int q) { return tab[q].pb_base; });
+    const int p = find_problem(n, (int)blockIdx.x, [&](int q) { return tab[q].pj_base; });
     const BatchProb &b = tab[p];
+    const uint32_t unit = ((uint32_t)blockIdx.x - (uint32_t)b.pj_base) * kPixBlock + threadIdx.x;
+    if (b.pairs) { // uniform per workgroup
+        batch_project_pair<KB>(b, unit);
+        return;
+    }
     const uint32_t npix = (uint32_t)b.nx * (uint32_t)b.ny;
-    const uint32_t pix = ((uint32_t)blockIdx.x - (uint32_t)b.pb_base) * kPixBlock + threadIdx.x;
+    const uint32_t pix = unit;
     if (pix >= npix) return;
     const int B = b.B;
     const bool packed = *b.cflag != 0; // binary masks: one word of frame bits instead of B floats
