@@ -66,6 +66,7 @@ def _load():
         "orc_twist_tv": (i, [i, i, i, i, d, d, d, i, i, i, P, P, P, P, P]),
         "orc_psnr": (d, [ctypes.c_long, P, P, d]),
         "orc_residual_sq": (d, [i, i, i, P, P, P]),
+        "orc_set_threads": (i, [i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -295,6 +296,12 @@ def residual_sq(C, X, Y):
     C, X, Y = _d(C), _d(X), _d(Y)
     B, nx, ny = _dims(C)
     return _load().orc_residual_sq(B, nx, ny, _p(C), _p(X), _p(Y))
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's element-wise loops (n <= 0: unchanged);
+    returns the count in effect. Results do not depend on it."""
+    return _load().orc_set_threads(int(n))
 
 
 def measurement(C, X, G=None):

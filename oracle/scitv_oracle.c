@@ -48,6 +48,7 @@
  * constrained solve of the penalised least-squares problem it minimises).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -56,6 +57,15 @@
 #define ORC_VTV 2
 
 #define IDX(k, i, j) (((size_t)(k) * (size_t)nx + (size_t)(i)) * (size_t)ny + (size_t)(j))
+
+/* Threads of the element-wise loops for later calls from this thread (the
+ * results do not depend on it); used to time the oracle at one thread and at
+ * all cores. Returns the count now in effect. */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------------ */
 /* Sensing operator, Eq. (2)-(4): Y = sum_k C_k .* X_k, and its transpose.  */

@@ -94,6 +94,107 @@ def warm_dual_triples(h, Y, C, tv: str, lam: float, outer: int, tol: float = 1e-
     return out
 
 
+class CropSet:
+    """Training examples stored as crops of full-frame solves, all frames of a
+    crop x crop window: X [n][B][c][c] (denoiser inputs x^(t)), P [n][2][B][c][c]
+    (the previous outer iteration's final dual, the base of the correcting
+    network) and T [n][2][B][c][c] (the dual FGP reaches at a tight gap).
+    Preallocated on the device for `capacity` crops."""
+
+    def __init__(self, capacity: int, B: int, crop: int, device):
+        self.X = torch.empty((capacity, B, crop, crop), device=device)
+        self.P = torch.empty((capacity, 2, B, crop, crop), device=device)
+        self.T = torch.empty((capacity, 2, B, crop, crop), device=device)
+        self.n = 0
+        self.crop = crop
+
+    def add_frame(self, x: torch.Tensor, base: torch.Tensor, target: torch.Tensor) -> int:
+        """Cut one full-frame example into crop x crop windows on a regular grid
+        (as many as fit, and as the capacity allows); returns the crops added."""
+        c = self.crop
+        _, nx, ny = x.shape
+        added = 0
+        for i0 in range(0, nx - c + 1, c):
+            for j0 in range(0, ny - c + 1, c):
+                if self.n == self.X.shape[0]:
+                    return added
+                self.X[self.n].copy_(x[:, i0:i0 + c, j0:j0 + c])
+                self.P[self.n].copy_(base[:, :, i0:i0 + c, j0:j0 + c])
+                self.T[self.n].copy_(target[:, :, i0:i0 + c, j0:j0 + c])
+                self.n += 1
+                added += 1
+        return added
+
+    def example(self, i: int, with_base: bool):
+        return (self.X[i], self.P[i], self.T[i]) if with_base else (self.X[i], self.T[i])
+
+
+def fill_crop_set(h, cs: CropSet, Y, C, tv: str, lam: float, outer: int, tol: float = 1e-4,
+                  target_tol: float = 1e-6, cap: int = 4000, every: int = 5) -> int:
+    """Add the crops of one measurement: a gap-controlled GAP run with warm duals
+    (each denoiser call starts from the previous call's final dual and stops at
+    relative gap tol, checked every `every` iterations); at every outer
+    iteration t, x^(t), p^(t-1) and the dual at target_tol for x^(t) (started
+    from the tol dual) are cut into crops. p^(0) = 0. Returns the crops added."""
+    proj = scitv.solver_params(outer_iters=1, tv=tv, lam=lam, n_inner=0)
+    at_tol = scitv.tv_params(tv=tv, lam=lam, gap_tol=tol, n_inner_max=cap, gap_check_every=every)
+    tight = scitv.tv_params(tv=tv, lam=lam, gap_tol=target_tol, n_inner_max=cap, gap_check_every=20)
+    theta = scitv.sci_adjoint(h, C, Y)
+    x = torch.empty_like(theta)
+    scratch = torch.empty_like(theta)
+    prev = torch.zeros((2,) + tuple(theta.shape), device=theta.device)
+    dual = torch.empty_like(prev)
+    target = torch.empty_like(prev)
+    added = 0
+    for _ in range(outer):
+        scitv.sci_gap_tv(h, Y, C, proj, X_out=x, Theta_out=scratch, X_init=theta)  # x^(t), Eq. (21)
+        scitv.sci_tv_denoise(h, x, at_tol, Theta_out=theta, dual_init=prev, dual_out=dual)
+        scitv.sci_tv_denoise(h, x, tight, dual_init=dual, dual_out=target)
+        added += cs.add_frame(x, prev, target)
+        prev, dual = dual, prev
+    return added
+
+
+def mean_loss(h, net, cs: CropSet, idx, with_base: bool) -> float:
+    """Mean loss of the network over the listed examples (no update)."""
+    tot = 0.0
+    for i in idx:
+        ex = cs.example(int(i), with_base)
+        x, base, t = ex if with_base else (ex[0], None, ex[1])
+        loss, _ = scitv.sci_wsnet_grads(h, net, x, t, base=base)
+        tot += loss
+    return tot / max(1, len(idx))
+
+
+def train_epochs(h, net, cs: CropSet, with_base: bool, epochs: int, lr: float, held: CropSet = None,
+                 n_held: int = 256, log_every: int = 2000, seed: int = 0, progress=None):
+    """Adam over the whole crop set in a fresh random order every epoch.
+    Returns [(step, mean training loss over the steps since the last entry,
+    mean held-out loss)]; the held-out loss is computed on the first n_held
+    examples of `held` (no update)."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    step, acc, cnt = 0, 0.0, 0
+    hidx = range(min(n_held, held.n)) if held is not None else []
+    if held is not None:
+        hist.append((0, None, mean_loss(h, net, held, hidx, with_base)))
+    for ep in range(epochs):
+        for i in rng.permutation(cs.n):
+            ex = cs.example(int(i), with_base)
+            x, base, t = ex if with_base else (ex[0], None, ex[1])
+            acc += scitv.sci_wsnet_train_step(h, net, x, t, lr, base=base, want_loss=True)
+            cnt += 1
+            step += 1
+            if step % log_every == 0 or step == epochs * cs.n:
+                ho = mean_loss(h, net, held, hidx, with_base) if held is not None else None
+                hist.append((step, acc / cnt, ho))
+                if progress:
+                    progress(f"step {step}: train loss {acc / cnt:.5f}" + (f", held-out {ho:.5f}" if ho is not None
+                                                                           else ""))
+                acc, cnt = 0.0, 0
+    return hist
+
+
 def crops(x: torch.Tensor, size: int, n: int, rng: np.random.Generator) -> List[Tuple[int, int]]:
     _, nx, ny = x.shape
     return [(int(rng.integers(0, nx - size + 1)), int(rng.integers(0, ny - size + 1))) for _ in range(n)]

@@ -72,7 +72,7 @@ def test_forward_matches_oracle(sc, ctx, net, B, nx, ny):
     got = np.moveaxis(raw[..., :2], -1, 0)
     e = rel(got, y)
     print(f"forward {B}x{nx}x{ny}: rel-L2 {e:.2e}", flush=True)
-    assert e <= 5e-3
+    assert e <= 1e-3
     assert np.all(raw[..., 2:] == 0)
     np.testing.assert_allclose(host(dual), wo.project_dual(got, "itv2d"), rtol=0, atol=2e-6)
 
@@ -91,12 +91,12 @@ def test_residual_forward_matches_oracle(sc, ctx, rnet, B, nx, ny):
     got = np.moveaxis(raw[..., :2], -1, 0)
     e = rel(got, y)
     print(f"residual forward {B}x{nx}x{ny}: rel-L2 {e:.2e}", flush=True)
-    assert e <= 5e-3
+    assert e <= 1e-3
     np.testing.assert_allclose(host(dual), wo.project_dual(got + base, "vtv"), rtol=0, atol=2e-6)
     # no base given: the base channels read as zero
     _, dual0 = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="vtv")
     _, y0 = wo.forward(x, P, base=None, c_in=3)
-    assert rel(host(dual0), wo.project_dual(y0, "vtv")) <= 5e-3
+    assert rel(host(dual0), wo.project_dual(y0, "vtv")) <= 1e-3
 
 
 def test_residual_zero_net_is_the_base(sc, ctx, rnet):
@@ -118,12 +118,12 @@ def test_residual_gradients_match_oracle(sc, ctx, rnet):
     t = r.normal(scale=0.5, size=(2, 3, 18, 40)).astype(np.float32)
     loss, g = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
     lo, go = wo.loss_and_grads(x, t, P, base=base, c_in=3)
-    assert abs(loss - lo) <= 2e-3 * lo
+    assert abs(loss - lo) <= 1e-4 * lo
     G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
     for l in range(4):
         e = rel(G[l], GO[l])
         print(f"residual layer {l} gradient rel-L2 {e:.2e}", flush=True)
-        assert e <= 2e-2
+        assert e <= 5e-3
 
 
 @pytest.mark.parametrize("B,nx,ny", [(3, 18, 40), (1, 1, 300), (9, 70, 5)])
@@ -141,15 +141,15 @@ def test_theta_loss_gradients_match_oracle(sc, ctx, rnet, B, nx, ny):
     loss, g = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
     lo, go = wo.loss_and_grads(x, t, P, base=base, c_in=3, loss="theta")
     print(f"theta loss {loss:.6e} (oracle {lo:.6e})", flush=True)
-    assert abs(loss - lo) <= 2e-3 * lo
+    assert abs(loss - lo) <= 1e-4 * lo
     G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
     for l in range(4):
         e = rel(G[l], GO[l])
         print(f"theta-loss layer {l} gradient rel-L2 {e:.2e}", flush=True)
-        assert e <= 2e-2
+        assert e <= 5e-3
     sc.sci_wsnet_set_loss(ctx, rnet, "dual")
     loss_d, _ = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
-    assert abs(loss_d - wo.loss_and_grads(x, t, P, base=base, c_in=3)[0]) <= 2e-3 * loss_d
+    assert abs(loss_d - wo.loss_and_grads(x, t, P, base=base, c_in=3)[0]) <= 1e-4 * loss_d
     with pytest.raises(sc.SciError):
         sc.sci_wsnet_set_loss(ctx, rnet, 7)
 
@@ -162,12 +162,12 @@ def test_gradients_match_oracle(sc, ctx, net):
     t = r.normal(scale=0.5, size=(2, 3, 18, 40)).astype(np.float32)
     loss, g = sc.sci_wsnet_grads(ctx, net, dev(x), dev(t))
     lo, go = wo.loss_and_grads(x, t, P)
-    assert abs(loss - lo) <= 2e-3 * lo
+    assert abs(loss - lo) <= 1e-4 * lo
     G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
     for l in range(4):
         e = rel(G[l], GO[l])
         print(f"layer {l} gradient rel-L2 {e:.2e}", flush=True)
-        assert e <= 2e-2
+        assert e <= 5e-3
 
 
 def test_adam_step_matches_oracle(sc, ctx, net):
@@ -219,11 +219,12 @@ def _held_out(sc, ctx, tv, lam, outer):
 
 def test_learned_warm_start_gains(sc, ctx, rnet):
     """The correcting network (input x^(t) and the previous outer iteration's
-    final dual, output added to that dual) trained on GPU-FGP duals: against a
-    cold start it needs far fewer inner iterations to reach relative gap 1e-4,
-    at the same PSNR. Most of that gain is the previous dual itself: the test
-    reports the trained correction against the plain warm-dual start as well
-    (on this scene family the correction does not beat it)."""
+    final dual, output added to that dual) trained on GPU-FGP duals, measured
+    against both baselines: a cold start, which it beats by more than 2x in
+    inner iterations to relative gap 1e-4 at the same PSNR, and the plain
+    warm-dual start (the previous final dual without the network), which is
+    where that gain comes from: on this scene family the trained correction
+    does not beat it, and the gap-checked start keeps it within 10 % of it."""
     from paper_2005_08028_amd import warmstart
     tv, lam, outer = "itv2d", 0.1, 30
     data = []
@@ -250,12 +251,14 @@ def test_learned_warm_start_gains(sc, ctx, rnet):
     truth = dev(pr.truth)
     pc, pw, pl = (sc.sci_psnr(ctx, v, truth) for v in (xc, xw, xl))
     print(f"inner iterations to gap 1e-4 over {outer} outer: cold {cold}, warm dual {warm}, untrained net {untrained}, "
-          f"trained net {learned} ({fb} fallbacks; {warm / learned:.2f}x vs warm dual); "
+          f"trained net {learned} ({fb} fallbacks; warm dual / trained net {warm / learned:.2f}, "
+          f"warm dual / gap-checked {warm / gchk:.2f}); "
           f"PSNR cold {pc:.3f} warm {pw:.3f} learned {pl:.3f}", flush=True)
     print(f"gap-checked starts: {gchk} inner iterations, {ns} of {outer - 1} calls from the prediction", flush=True)
     assert untrained == warm  # the zero-initialised correction is the warm-dual start
     assert untrained_gc == warm and 0 <= ns0 <= outer - 1
     assert learned * 2 <= cold and gchk * 2 <= cold
+    assert gchk <= 1.1 * warm  # against its real baseline: no gain, and no more than a 10 % loss
     assert fb == 0 and fbg == 0 and 0 <= ns <= outer - 1
     assert abs(pc - pl) < 0.05 and abs(pw - pl) < 0.05
     assert abs(pw - sc.sci_psnr(ctx, xg, truth)) < 0.05
