@@ -301,26 +301,39 @@ def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, n_crops=20000, n_he
     targets = {"cold_final": res["cold"]["psnr_db"] - 0.1, "plain_final": p_plain - 0.1}
     target = targets["cold_final"]
 
-    def first_reaching(psnr_at, label=""):
-        t, step = 0, 5
+    def first_reaching(psnr_at, label="", hint=8):
+        """First outer iteration t <= T_eval whose PSNR reaches the target
+        (None if none does): bracket around `hint` by doubling steps, then
+        bisect (the PSNR rises with t on these runs)."""
+        cache = {}
 
-        def probe(tt):
-            v = psnr_at(tt)
-            say(f"learned: {label} PSNR after {tt} outer iterations {v:.4f} (target {target:.4f})")
-            return v
+        def ok(tt):
+            if tt not in cache:
+                cache[tt] = psnr_at(tt)
+                say(f"learned: {label} PSNR after {tt} outer iterations {cache[tt]:.4f} (target {target:.4f})")
+            return cache[tt] >= target
 
-        while t < T_eval:
-            t = min(T_eval, t + step)
-            if probe(t) >= target:
-                lo, hi = t - step, t
-                while hi - lo > 1:
-                    mid = (lo + hi) // 2
-                    if probe(mid) >= target:
-                        hi = mid
-                    else:
-                        lo = mid
-                return hi
-        return None
+        hint = max(1, min(T_eval, hint))
+        step = 1
+        if ok(hint):
+            hi, lo = hint, hint - 1
+            while lo >= 1 and ok(lo):
+                hi, step = lo, step * 2
+                lo = max(0, hi - step)
+        else:
+            lo, hi = hint, min(T_eval, hint + 1)
+            while not ok(hi):
+                if hi == T_eval:
+                    return None
+                lo, step = hi, step * 2
+                hi = min(T_eval, lo + step)
+        while hi - lo > 1:  # ok(hi) holds; lo == 0 or not ok(lo)
+            mid = (lo + hi) // 2
+            if ok(mid):
+                hi = mid
+            else:
+                lo = mid
+        return hi
 
     def plain_ms(T):
         scitv.sci_gap_tv(h, Y, C, fixed(T))
@@ -333,13 +346,17 @@ def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, n_crops=20000, n_he
     res["plain_fixed_10"] = {"inner_iters": 10 * T_eval, "psnr_db": round(p_plain, 4)}
     for tname, tval in targets.items():
         target = tval
-        for name in variants:
-            ts = first_reaching(lambda t: scitv.sci_psnr(h, run(name, t, every_timed)[0], X_true), name)
+        hint = 8
+        # the warm-dual start first (the cheapest); its t* is the others' starting guess
+        for name in ["warm_dual"] + [v for v in variants if v != "warm_dual"]:
+            ts = first_reaching(lambda t: scitv.sci_psnr(h, run(name, t, every_timed)[0], X_true), name, hint)
             res[name][f"t_star_{tname}"] = ts
             if ts:
+                hint = ts if name == "warm_dual" else hint
                 run(name, ts, every_timed)
                 res[name][f"ms_to_{tname}"] = round(run(name, ts, every_timed)[4], 1)
-        ts = first_reaching(lambda t: scitv.sci_psnr(h, scitv.sci_gap_tv(h, Y, C, fixed(t))[0], X_true), "plain")
+        ts = first_reaching(lambda t: scitv.sci_psnr(h, scitv.sci_gap_tv(h, Y, C, fixed(t))[0], X_true), "plain",
+                            hint)
         res["plain_fixed_10"][f"t_star_{tname}"] = ts
         if ts:
             res["plain_fixed_10"][f"ms_to_{tname}"] = round(plain_ms(ts), 1)
@@ -371,6 +388,46 @@ def measure_learned(scitv, synth, h, dev, Y, C, X_true, lam, n_crops=20000, n_he
         "target_speedup_vs_plain": 2.0,
         **res,
     }
+
+
+def measure_net(scitv, h, dev, C, Y, reps):
+    """Throughput of the warm-start network's MFMA kernels: the forward pass of
+    the correcting network (3 input channels) at 1024x1024x24 and training
+    steps (forward, loss, data and weight gradients, Adam) at 512x512x16,
+    against the algorithmic FLOPs of the four 3x3x3 layers
+    (2 * 27 * (3*16 + 16*16 + 16*16 + 16*2) per voxel forward; about 3x that
+    per training step)."""
+    import numpy as np
+    import torch
+    from paper_2005_08028_amd import warmstart
+    net = scitv.sci_wsnet_create(h, c_in=3, c_out=2)
+    scitv.sci_wsnet_set_params(h, net, warmstart.init_params(0, c_in=3, last_scale=0.1))
+    x0 = scitv.sci_adjoint(h, C, Y)
+    base = torch.zeros((2,) + tuple(x0.shape), device=dev)
+    flop_fwd = 2 * 27 * (3 * 16 + 16 * 16 + 16 * 16 + 16 * 2)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    fwd_ms = timed(lambda: scitv.sci_wsnet_forward(h, net, x0, tv="itv2d", base=base))
+    r = np.random.default_rng(0)
+    xs = torch.from_numpy(r.uniform(size=(16, 512, 512)).astype(np.float32)).to(dev)
+    bs = torch.from_numpy(r.uniform(-1, 1, size=(2, 16, 512, 512)).astype(np.float32)).to(dev)
+    ts = torch.from_numpy(r.uniform(-1, 1, size=(2, 16, 512, 512)).astype(np.float32)).to(dev)
+    step_ms = timed(lambda: scitv.sci_wsnet_train_step(h, net, xs, ts, 1e-5, base=bs, want_loss=False))
+    scitv.sci_wsnet_destroy(net)
+    V, Vt = x0.numel(), xs.numel()
+    return {"forward_ms_1024x1024x24": round(fwd_ms, 3),
+            "forward_tflops_algorithmic": round(flop_fwd * V / (fwd_ms / 1e3) / 1e12, 2),
+            "train_step_ms_512x512x16": round(step_ms, 3),
+            "train_step_tflops_algorithmic": round(3 * flop_fwd * Vt / (step_ms / 1e3) / 1e12, 2),
+            "bf16_mfma_peak_tflops": 2500.0}
 
 
 def measure_paper_shaped(scitv, synth, h, dev, T=150, N=5, lam=0.1, every=10, curves_on=True):
@@ -608,6 +665,10 @@ def main() -> int:
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched-solve measurement (64 measurements) and print its JSON (a short run "
                          "to profile the batched graph; not the benchmark line)")
+    ap.add_argument("--net-only", action="store_true",
+                    help="only time the warm-start network's kernels (forward at 1024x1024x24, training steps at "
+                         "512x512x16) and print their JSON (a short run to profile the MFMA kernels; not the "
+                         "benchmark line)")
     ap.add_argument("--learned-only", action="store_true",
                     help="only run the learned warm start's full protocol (20000 training crops, 200 outer "
                          "iterations) and print its JSON (minutes; not the benchmark line)")
@@ -657,6 +718,11 @@ def main() -> int:
         res = measure_batched(scitv, synth, h, dev, max(1, min(args.steps, 3)))
         ctx.close()
         print(json.dumps({"batched": res}), flush=True)
+        return 0
+    if args.net_only:
+        res = measure_net(scitv, h, dev, C, Y, max(3, args.steps))
+        ctx.close()
+        print(json.dumps({"network": res}), flush=True)
         return 0
     if args.learned_only:
         res = measure_learned(scitv, synth, h, dev, Y, C, X_true, lam)

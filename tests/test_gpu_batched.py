@@ -121,3 +121,35 @@ def test_batched_rejects_unsupported(sc, ctx):
         args.update(kw)
         with pytest.raises(sc.SciError):
             sc.sci_gap_tv_batched(ctx, items, sc.solver_params(**args))
+
+
+def test_batched_workload_full_count_psnr_matches_oracle(sc, ctx):
+    """The 64-measurement batched workload (GAP-ATV, 50 outer x 5 inner) at
+    its full count: every problem's PSNR against its truth agrees with the
+    FP64 oracle's, stored by tests/golden/make_batched_reference.py, within
+    0.01 dB. The benchmark's time-to-PSNR target (full-count PSNR - 0.1 dB)
+    is taken from this solve."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_64_gap_atv_50x5_psnr.json")
+    with open(path) as f:
+        ref = json.load(f)
+    specs = synth.batched_specs(64, seed=4000)
+    assert len(ref["problems"]) == len(specs)
+    items, truths = [], []
+    for sp, rp in zip(specs, ref["problems"]):
+        assert (sp["nx"], sp["ny"], sp["B"], sp["seed"]) == (rp["nx"], rp["ny"], rp["B"], rp["seed"])
+        pr = synth.make_problem(sp["nx"], sp["ny"], sp["B"], sp["seed"], mask=sp["mask"], mask_p=sp["mask_p"],
+                                sigma=sp["sigma"])
+        Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+        items.append(dict(Y=dev(Y), C=dev(pr.masks), X_out=torch.empty(pr.masks.shape, device="cuda"),
+                          Theta_out=None, outer_iters=ref["T"]))
+        truths.append(dev(pr.truth))
+    prm = sc.solver_params(outer_iters=ref["T"], tv=ref["tv"], lam=0.1, n_inner=ref["N"], use_graph=True)
+    sc.sci_gap_tv_batched(ctx, items, prm)
+    worst = 0.0
+    for it, xt, rp in zip(items, truths, ref["problems"]):
+        d = sc.sci_psnr(ctx, it["X_out"], xt) - rp["psnr_x"]
+        worst = max(worst, abs(d))
+    print(f"batched 64-measurement workload, 50x5: max |dPSNR| vs oracle {worst:.2e} dB", flush=True)
+    assert worst <= 0.01
