@@ -301,9 +301,9 @@ int sci_wsnet_get_params(sci_ctx *ctx, sci_wsnet *net, float *host, int64_t coun
 
 /* Network output for input X (video) and, when c_in = 3, P_base (dual
  * [2][B][nx][ny] fp32; NULL = zero; ignored when c_in = 1): Y_out (nullable)
- * [V][16] fp32 raw output (channels >= c_out are 0), dual_out (nullable)
- * [2][B][nx][ny] fp32 = (P_base +) output projected onto the dual ball of TV
- * kind tv with the entries that carry no difference set to 0 (c_out = 2). */
+ * [c_out][B][nx][ny] fp32 raw output, dual_out (nullable) [2][B][nx][ny]
+ * fp32 = (P_base +) output projected onto the dual ball of TV kind tv with
+ * the entries that carry no difference set to 0 (c_out = 2). */
 int sci_wsnet_forward(sci_ctx *ctx, sci_wsnet *net, sci_dims d, const float *X, const float *P_base, float *Y_out,
                       int32_t tv, float *dual_out, hipStream_t stream);
 

@@ -5,22 +5,24 @@
 // Activations are channels-last bf16, [V][16] (V = B*nx*ny voxels, voxel
 // v = (k*nx + i)*ny + j, 16 channels, unused channels zero). Weights are
 // packed per layer as Wk[27][16 out][16 in] bf16 (tap t = (dk*3 + di)*3 + dj,
-// offset (dk-1, di-1, dj-1)), with zero padding for the first layer's single
-// input channel and the last layer's two output channels. Every convolution
-// is an implicit GEMM on v_mfma_f32_16x16x16bf16_1k: a wavefront produces
-// 16 voxels x 16 output channels, accumulating 27 MFMAs (one per tap, K = 16
-// input channels) in FP32. Blocks of the volume are staged in LDS with a
-// zero-filled one-voxel halo, which is the zero padding of the "same"
-// convolution.
+// offset (dk-1, di-1, dj-1)), with zero padding for the first layer's input
+// channels and the last layer's output channels. The convolutions are
+// implicit GEMMs on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the
+// weights as the A operand, the staged input voxels as B; the mapping is
+// described at the convolution kernel). The weight gradient runs on
+// v_mfma_f32_16x16x16bf16_1k with the voxels as K.
 //
-// MFMA operand layout (checked on the hardware): lane l holds A row l%16 and
-// B column l%16, with K elements 4*(l/16) .. 4*(l/16)+3; the result holds
-// column l%16, rows 4*(l/16) .. 4*(l/16)+3.
+// MFMA operand layouts (checked on the hardware): 16x16x16 - lane l holds A
+// row l%16 and B column l%16 with K = 4*(l/16) .. +3; 16x16x32 - the same
+// with K = 8*(l/16) .. +7; the result holds column l%16, rows
+// 4*(l/16) .. +3.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sci_internal.h"
+#include "sci_math.h"
 #include "sci_wsnet.h"
 
 namespace sci {
@@ -43,80 +45,347 @@ struct Geom {
     uint32_t V;
 };
 
-// out[v][n] = sum_t sum_c Wk[t][n][c] in[nb(v, t)][c] (+ bias[n]); optional
-// ReLU; optional mask by (gate[v][n] > 0) (ReLU derivative); output bf16
-// [V][16] or, for the last layer, fp32 [V][16]. Computed over LDS tiles: a
-// workgroup owns an output block of
-// kTK frames x kTI rows x kTJ columns; it stages the block plus a one-voxel
-// halo (all 16 channels, bf16, zero outside the volume) in LDS once, and its
-// four wavefronts then run 16-voxel x 16-channel MFMA tiles along j, the A
-// operand of each of the 27 taps read from LDS (8 bytes per lane) and the B
-// operand (the weights of the tap) held in registers for the whole block.
-// Two tiles are accumulated side by side to cover the MFMA latency.
-constexpr int kTK = 4, kTI = 8, kTJ = 32;
-constexpr int kHK = kTK + 2, kHI = kTI + 2, kHJ = kTJ + 2;
-constexpr int kVoxStride = 18; // shorts per staged voxel (16 channels + 2 of padding: 36-byte stride, no bank conflicts)
+// ---- 3x3x3 convolution ------------------------------------------------------
+//
+// out[v][n] = sum_t sum_c Wk[t][n][c] in[nb(v, t)][c] + bias[n] over the
+// volume, zero outside it ("same" padding). A workgroup owns a tile of
+// kCI rows x kCJ columns and walks it through a run of frames; for output
+// frame k it needs the input slabs (tile plus one-voxel halo) of frames
+// k-1, k, k+1. Slabs sit in a ring of four in LDS: while frame k is computed
+// from three of them, the fourth is free, and the global loads of the slab
+// two frames ahead are in flight in registers. One barrier per frame.
+//
+// MFMA mapping (v_mfma_f32_16x16x32_bf16: A 16x32, B 32x16; lane l holds A
+// row l%16 and B column l%16 with K = 8 (l/16) .. +7, and the result column
+// l%16, rows 4 (l/16) .. +3). A row is an output voxel (16 consecutive
+// columns of one output row), a result column an output channel. The K = 32
+// of one instruction covers either two taps x 16 input channels or, for an
+// input with at most 8 channels, four taps x 8 channels; taps are grouped by
+// their (frame, column) offset (dk, dj), nine of them, so one operand read
+// from staged row s serves output rows s, s-1, s-2 (di = 0, 1, 2) with the
+// weights of (dk, di, dj): each wavefront computes four consecutive output
+// rows from six staged rows and reads every operand once.
+//
+// The nine (dk, dj) offsets fill 5 (or 3) MFMAs with one (or three) K slots
+// to spare; lanes of a spare slot read the last offset's data again and meet
+// zero weights, so they add exact zeros, except that a non-finite staged
+// value, which already turns the output it reaches into NaN or +-Inf through
+// the real slot, makes it NaN.
+//
+// LDS layout: a staged voxel v (slab row si, column sj; v = si*kSJ + sj) is
+// two 16-byte chunks (channels 0-7, 8-15); chunk h sits at slot
+// 2v + (h xor (sj>>2 & 1)). Eight lanes reading chunk h of eight consecutive
+// columns, or eight threads writing both chunks of four consecutive voxels,
+// touch 32 distinct banks. An input with at most 8 channels stages one chunk
+// per voxel, at slot v.
+constexpr int kCI = 16, kCJ = 32;                     // output tile
+constexpr int kSI = kCI + 2, kSJ = kCJ + 2;           // staged slab
+constexpr int kSlabVox = kSI * kSJ;                   // 612 voxels
+constexpr int kSlabChunks = 2 * kSlabVox;             // 1224 chunks, 19584 bytes
+constexpr int kRing = 4;
+constexpr int kChunkLoads = (kSlabChunks + 255) / 256; // per thread and slab, bf16 input
+constexpr int kVoxLoads = (kSlabVox + 255) / 256;      // per thread and slab, fp32 input
+constexpr int kRowsPerWave = kCI / 4;                  // 4 wavefronts
 
-template <bool RELU, bool OUT_F32>
-__global__ __launch_bounds__(256) void k_conv_tile(Geom g, int ntj, int nti, const uint16_t *__restrict__ in,
-                                                   const uint16_t *__restrict__ Wk, const float *__restrict__ bias,
-                                                   const uint16_t *__restrict__ gate, uint16_t *__restrict__ out16,
-                                                   float *__restrict__ out32)
+static_assert(kCJ == 32 && kRowsPerWave == 4, "the compute loop is written for 4 rows x 2 tiles per wavefront");
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+enum { CIN_BF16 = 0, CIN_F32 = 1 };          // input: bf16 [V][16], or fp32 planes x [V] (+ base [2][V])
+enum { COUT_BF16 = 0, COUT_F32 = 1, COUT_DUAL = 2 };
+
+struct ConvArgs {
+    Geom g;
+    int ntj, ntiles, F, nitems;  // tiles per row band, tiles per frame, frames per item, items
+    const uint16_t *in;          // CIN_BF16
+    const float *x, *xb0, *xb1;  // CIN_F32: x and the base planes (x itself when there is no base)
+    int xb_live;                 // 0: channels 1, 2 are zero
+    const uint16_t *Wk;
+    const float *bias;           // nullable
+    const uint16_t *gate;        // GATE: output zeroed where gate[v][n] <= 0
+    uint16_t *out16;             // COUT_BF16: [V][16]
+    float *out32;                // COUT_F32: [cout][V] raw; COUT_DUAL: [2][V] projected dual
+    const float *obase;          // COUT_DUAL: base dual added before the projection (nullable)
+    int cout, tv;                // COUT_F32 channels; COUT_DUAL: 0 ATV (clamp), 1 ITV2D (disc)
+};
+
+// two floats to bf16 (round to nearest even; v_cvt_pk_bf16_f32), packed low | high << 16
+__device__ inline uint32_t pack2_bf16(float lo, float hi)
 {
-    __shared__ uint16_t xs[kHK * kHI * kHJ * kVoxStride];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 p = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, p);
+}
+
+// Workgroups per CU: LDS holds two rings of 16-channel slabs, three of 8-channel ones.
+template <int CIN> constexpr int conv_wgs_per_cu() { return CIN == CIN_F32 ? 3 : 2; }
+
+template <int CIN, int COUT, bool RELU, bool GATE>
+__global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const ConvArgs a)
+{
+    constexpr int CPT = CIN == CIN_F32 ? 1 : 2;   // chunks of a tap in one MFMA operand
+    constexpr int TPM = 4 / CPT;                  // (dk, dj) offsets per MFMA
+    constexpr int G = (9 + TPM - 1) / TPM;        // MFMAs per (staged row, di)
+    constexpr int NL = CIN == CIN_F32 ? kVoxLoads : kChunkLoads;
+    // LDS slot of chunk h of staged voxel v (slab column sj): one chunk per
+    // voxel when only channels 0-7 are staged, else two, swizzled
+    auto chunk_slot = [](int v, int sj, int h) { return CPT == 1 ? v : 2 * v + (h ^ ((sj >> 2) & 1)); };
+    constexpr int SLAB = CPT == 1 ? kSlabVox : kSlabChunks; // 16-byte slots per slab
+    __shared__ uint4 ring[kRing * SLAB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
-    const int bj = (int)blockIdx.x % ntj, bi = ((int)blockIdx.x / ntj) % nti, bk = (int)blockIdx.x / (ntj * nti);
-    const int k0 = bk * kTK, i0 = bi * kTI, j0 = bj * kTJ;
+    const int hsel = CPT == 2 ? (kq & 1) : 0;
+    const int nx = a.g.nx, ny = a.g.ny, B = a.g.B;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny, V = a.g.V;
 
-    // stage the block and its halo: 8-byte chunks (4 channels), zero outside
-    for (int e = threadIdx.x; e < kHK * kHI * kHJ * 4; e += 256) {
-        const int q = e & 3, vox = e >> 2;
-        const int jj = vox % kHJ, ii = (vox / kHJ) % kHI, kk = vox / (kHJ * kHI);
-        const int k = k0 + kk - 1, i = i0 + ii - 1, j = j0 + jj - 1;
-        bf16x4 v = {0, 0, 0, 0};
-        if (k >= 0 && k < g.B && i >= 0 && i < g.nx && j >= 0 && j < g.ny)
-            v = *(const bf16x4 *)(in + ((((size_t)k * g.nx + i) * g.ny + j) * 16 + q * 4));
-        *(bf16x4 *)(xs + vox * kVoxStride + q * 4) = v;
+    // B operands: weights of tap (dk, di, dj) for the lane's (dk, dj) in group gi
+    bf16x8 wb[3][G];
+    int coff[G][2], cdk[G];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        const int c = TPM * gi + kq / CPT;
+        const int cc = c < 9 ? c : 8, dk = cc / 3, dj = cc % 3;
+#pragma unroll
+        for (int di = 0; di < 3; ++di) {
+            if (c < 9) wb[di][gi] = *(const bf16x8 *)(a.Wk + ((size_t)(dk * 9 + di * 3 + dj) * 16 + row) * 16 + 8 * hsel);
+            else wb[di][gi] = bf16x8{};
+        }
+        cdk[gi] = dk;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int col = 16 * tt + row + dj;
+            coff[gi][tt] = chunk_slot(kRowsPerWave * wv * kSJ + col, col, hsel);
+        }
     }
-    // weights of every tap: B[k = input channel 4 kq + e][n = row]
-    bf16x4 wb[27];
+    float bn[4];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) wb[t] = *(const bf16x4 *)(Wk + ((size_t)t * 16 + row) * 16 + kq * 4);
-    const float bn = bias ? bias[row] : 0.0f;
-    __syncthreads();
+    for (int e = 0; e < 4; ++e) bn[e] = a.bias ? a.bias[4 * kq + e] : 0.0f;
 
-    // output rows (kl, il) of the block: wavefront wv takes every fourth one;
-    // each row holds kTJ / 16 = 2 MFMA tiles
-    for (int rr = wv; rr < kTK * kTI; rr += 4) {
-        const int kl = rr / kTI, il = rr % kTI;
-        if (k0 + kl >= g.B || i0 + il >= g.nx) continue; // uniform per wavefront
-        f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+    // staging: this thread's chunks (bf16 input) or voxels (fp32 input) of a slab
+    int pslot[NL];
+    uint32_t poff[NL];
+    uint32_t pok = 0;
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dk = t / 9, di = (t / 3) % 3, dj = t % 3; // offsets into the haloed block
-            const int base = ((kl + dk) * kHI + (il + di)) * kHJ + dj + row;
-            const bf16x4 a0 = *(const bf16x4 *)(xs + base * kVoxStride + kq * 4);
-            const bf16x4 a1 = *(const bf16x4 *)(xs + (base + 16) * kVoxStride + kq * 4);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, wb[t], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, wb[t], acc1, 0, 0, 0);
-        }
-        // result of tile h: column n = row, voxels j = j0 + 16 h + 4 kq + e
-        const size_t vrow = ((size_t)(k0 + kl) * g.nx + (i0 + il)) * g.ny;
+    for (int q = 0; q < NL; ++q) {
+        const int e = tid + 256 * q;
+        const int v = CIN == CIN_F32 ? e : (e >> 1), hh = CIN == CIN_F32 ? 0 : (e & 1);
+        pslot[q] = chunk_slot(v, v % kSJ, hh);
+    }
+    uint4 pre[2][CIN == CIN_F32 ? 1 : NL];
+    float px[2][CIN == CIN_F32 ? NL : 1], pb0[2][CIN == CIN_F32 ? NL : 1], pb1[2][CIN == CIN_F32 ? NL : 1];
+    bool fval[2] = {false, false};
+
+    auto q_live = [&](int q) { return q < NL - 1 || tid + 256 * q < (CIN == CIN_F32 ? kSlabVox : kSlabChunks); };
+
+    // Every load is issued unconditionally (frames outside the volume read
+    // the nearest frame, dead slots read offset 0) and the zeros are applied
+    // when the slab is stored: with a fixed count of loads per slab the
+    // wait for one slab's data lets the next slab's loads stay in flight.
+    auto load_slab = [&](auto setc, int k0, int r) {
+        constexpr int S = decltype(setc)::value;
+        const int f = k0 - 1 + r;
+        fval[S] = f >= 0 && f < B;
+        const int fc = min(max(f, 0), B - 1);
+        if constexpr (CIN == CIN_F32) {
+            const size_t fb = (size_t)fc * plane;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = j0 + 16 * h + 4 * kq + e;
-                if (j >= g.ny) continue;
-                const size_t v = vrow + j;
-                float y = (h == 0 ? acc0[e] : acc1[e]) + bn;
-                if (RELU) y = fmaxf(y, 0.0f);
-                if (gate && !(from_bf16(gate[v * 16 + row]) > 0.0f)) y = 0.0f;
-                if (OUT_F32) out32[v * 16 + row] = y;
-                else out16[v * 16 + row] = to_bf16(y);
+            for (int q = 0; q < NL; ++q) {
+                px[S][q] = a.x[fb + poff[q]];
+                pb0[S][q] = a.xb0[fb + poff[q]];
+                pb1[S][q] = a.xb1[fb + poff[q]];
             }
+        } else {
+            const uint16_t *src = a.in + (size_t)fc * plane * 16;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) pre[S][q] = *(const uint4 *)(src + poff[q]);
         }
+    };
+    auto store_slab = [&](auto setc, int r) {
+        constexpr int S = decltype(setc)::value;
+        uint4 *slab = ring + (r & (kRing - 1)) * SLAB;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            if (!q_live(q)) continue;
+            const bool ok = fval[S] && ((pok >> q) & 1u);
+            uint4 val;
+            if constexpr (CIN == CIN_F32)
+                val = a.xb_live ? make_uint4(pack2_bf16(px[S][q], pb0[S][q]), pack2_bf16(pb1[S][q], 0.0f), 0u, 0u)
+                                : make_uint4(pack2_bf16(px[S][q], 0.0f), 0u, 0u, 0u);
+            else val = pre[S][q];
+            slab[pslot[q]] = ok ? val : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+
+    const int nwg = (int)gridDim.x;
+    for (int it = xcd_contiguous((int)blockIdx.x, nwg); it < a.nitems; it += nwg) {
+        const int chunk = it / a.ntiles, tile = it % a.ntiles;
+        const int i0 = (tile / a.ntj) * kCI, j0 = (tile % a.ntj) * kCJ, k0 = chunk * a.F;
+        const int nf = min(a.F, B - k0);
+        pok = 0;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = tid + 256 * q;
+            const int v = CIN == CIN_F32 ? e : (e >> 1), hh = CIN == CIN_F32 ? 0 : (e & 1);
+            const int i = i0 - 1 + v / kSJ, j = j0 - 1 + v % kSJ;
+            const bool ok = q_live(q) && i >= 0 && i < nx && j >= 0 && j < ny;
+            poff[q] = ok ? (CIN == CIN_F32 ? (uint32_t)(i * ny + j) : (uint32_t)(i * ny + j) * 16u + 8u * hh) : 0u;
+            pok |= (uint32_t)ok << q;
+        }
+        __syncthreads(); // every wavefront is done with the previous item's slabs
+        load_slab(std::integral_constant<int, 0>{}, k0, 0);
+        load_slab(std::integral_constant<int, 1>{}, k0, 1);
+        store_slab(std::integral_constant<int, 0>{}, 0);
+        store_slab(std::integral_constant<int, 1>{}, 1);
+        load_slab(std::integral_constant<int, 0>{}, k0, 2);
+        load_slab(std::integral_constant<int, 1>{}, k0, 3);
+
+        auto step = [&](auto setc, int s) {
+            store_slab(setc, s + 2);
+            __syncthreads();
+            const int k = k0 + s;
+            const bool rows_live = i0 + kRowsPerWave * wv < nx; // uniform per wavefront
+            // Loads complete in issue order: a kernel whose epilogue reads
+            // memory (gate, base) requests those reads first and issues the
+            // prefetch after the epilogue, so that waiting for them does not
+            // wait for the prefetch.
+            // Epilogue operands. The gate (GATE) is read before the compute
+            // and the prefetch is issued after the epilogue: loads complete in
+            // issue order, so waiting for the gate must not wait for a
+            // prefetch. The base dual (COUT_DUAL) is read before the prefetch:
+            // lane (row, kq) reads it for its own voxel of output row kq, and
+            // the epilogue gathers it across lanes.
+            uint2 eg[GATE ? 4 : 1][2];
+            float eb[COUT == COUT_DUAL ? 2 : 1][2];
+            if constexpr (GATE) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int tt = 0; tt < 2; ++tt) {
+                        const int i = i0 + kRowsPerWave * wv + r, j = j0 + 16 * tt + row;
+                        const size_t v = ((size_t)k * nx + i) * ny + j;
+                        eg[r][tt] = i < nx && j < ny ? *(const uint2 *)(a.gate + v * 16 + 4 * kq) : make_uint2(0u, 0u);
+                    }
+            }
+            if constexpr (COUT == COUT_DUAL) {
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) {
+                    const int i = i0 + kRowsPerWave * wv + kq, j = j0 + 16 * tt + row;
+                    const size_t v = ((size_t)k * nx + i) * ny + j;
+                    const bool in = a.obase && i < nx && j < ny;
+                    eb[tt][0] = in ? a.obase[v] : 0.0f;
+                    eb[tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
+                }
+            }
+            if constexpr (!GATE) load_slab(setc, k0, s + 4); // past the run's last slab: loaded, never stored
+            if (rows_live) {
+                // D[n][voxel] = sum_K W[n][K] X[K][voxel]: the weights are the
+                // A operand, the staged voxels the B operand
+                f32x4 acc[4][2];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int tt = 0; tt < 2; ++tt) acc[r][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                const uint4 *slab[G];
+#pragma unroll
+                for (int gi = 0; gi < G; ++gi) slab[gi] = ring + ((s + cdk[gi]) & (kRing - 1)) * SLAB;
+                // (staged row u, group gi) in sequence; the operands of the
+                // entry two ahead are read while the current one's MFMAs run
+                constexpr int NP = (kRowsPerWave + 2) * G;
+                bf16x8 X[3][2];
+                auto rd = [&](int p, bf16x8(&b)[2]) {
+                    const int u = p / G, gi = p % G;
+#pragma unroll
+                    for (int tt = 0; tt < 2; ++tt) b[tt] = __builtin_bit_cast(bf16x8, slab[gi][coff[gi][tt] + u * CPT * kSJ]);
+                };
+                rd(0, X[0]);
+                rd(1, X[1]);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (p + 2 < NP) rd(p + 2, X[(p + 2) % 3]);
+                    const int u = p / G, gi = p % G;
+#pragma unroll
+                    for (int di = 0; di < 3; ++di) {
+                        const int r = u - di;
+                        if (r < 0 || r >= kRowsPerWave) continue;
+#pragma unroll
+                        for (int tt = 0; tt < 2; ++tt)
+                            acc[r][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[di][gi], X[p % 3][tt], acc[r][tt], 0, 0, 0);
+                    }
+                }
+
+                // result: voxel j = j0 + 16 tt + row, output channels 4 kq + e
+                float gb[COUT == COUT_DUAL ? 4 : 1][2][2];
+                if constexpr (COUT == COUT_DUAL) {
+                    // base of output row r: held by lane (row, r); every lane takes part
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                gb[r][tt][c] = __int_as_float(
+                                    __builtin_amdgcn_ds_bpermute(4 * (row + 16 * r), __float_as_int(eb[tt][c])));
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + kRowsPerWave * wv + r;
+                    if (i >= nx) break; // uniform per wavefront
+                    const size_t vrow = ((size_t)k * nx + i) * ny;
+#pragma unroll
+                    for (int tt = 0; tt < 2; ++tt) {
+                        const int j = j0 + 16 * tt + row;
+                        if (j >= ny) continue;
+                        const size_t v = vrow + j;
+                        float y[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) y[e] = acc[r][tt][e] + bn[e];
+                        if constexpr (COUT == COUT_DUAL) {
+                            if (kq == 0) {
+                                // (base +) output, entries with no difference 0, projected
+                                float h = j < ny - 1 ? y[0] + gb[r][tt][0] : 0.0f;
+                                float w = i < nx - 1 ? y[1] + gb[r][tt][1] : 0.0f;
+                                if (a.tv == 0) {
+                                    h = fminf(fmaxf(h, -1.0f), 1.0f);
+                                    w = fminf(fmaxf(w, -1.0f), 1.0f);
+                                } else {
+                                    const float sc = fminf(1.0f, __builtin_amdgcn_rsqf(fmaf(w, w, h * h)));
+                                    h *= sc;
+                                    w *= sc;
+                                }
+                                a.out32[v] = h;
+                                a.out32[(size_t)V + v] = w;
+                            }
+                        } else if constexpr (COUT == COUT_F32) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (4 * kq + e < a.cout) a.out32[(size_t)(4 * kq + e) * V + v] = y[e];
+                        } else {
+                            if (RELU)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) y[e] = fmaxf(y[e], 0.0f);
+                            if constexpr (GATE) {
+                                const uint2 gv = eg[r][tt];
+                                if (!(__uint_as_float(gv.x << 16) > 0.0f)) y[0] = 0.0f;
+                                if (!(__uint_as_float(gv.x & 0xffff0000u) > 0.0f)) y[1] = 0.0f;
+                                if (!(__uint_as_float(gv.y << 16) > 0.0f)) y[2] = 0.0f;
+                                if (!(__uint_as_float(gv.y & 0xffff0000u) > 0.0f)) y[3] = 0.0f;
+                            }
+                            *(uint2 *)(a.out16 + v * 16 + 4 * kq) = make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
+                        }
+                    }
+                }
+            }
+            if constexpr (GATE) load_slab(setc, k0, s + 4);
+        };
+        // frames in pairs (both register sets on every trip, so the compiler
+        // can count the loads in flight), then an odd last frame
+        int s = 0;
+        for (; s + 1 < nf; s += 2) {
+            step(std::integral_constant<int, 0>{}, s);
+            step(std::integral_constant<int, 1>{}, s + 1);
+        }
+        if (s < nf) step(std::integral_constant<int, 0>{}, s);
     }
 }
 
@@ -153,7 +422,7 @@ __global__ __launch_bounds__(256) void k_loss(uint32_t V, int cout, const float 
             float gval = 0.0f;
             if (c < cout) {
                 const double b = base ? (double)base[(size_t)c * V + v] : 0.0;
-                const double d = ((double)y[(size_t)v * 16 + c] + b) - (double)target[(size_t)c * V + v];
+                const double d = ((double)y[(size_t)c * V + v] + b) - (double)target[(size_t)c * V + v];
                 acc += d * d;
                 gval = (float)(scale * d);
             }
@@ -180,13 +449,13 @@ __device__ inline float r_h(const float *y, const float *base, const float *targ
 {
     if (!ex) return 0.0f;
     const float b = base ? base[v] : 0.0f;
-    return (y[(size_t)v * 16] + b) - target[v];
+    return (y[v] + b) - target[v];
 }
 __device__ inline float r_v(const float *y, const float *base, const float *target, uint32_t V, uint32_t v, bool ex)
 {
     if (!ex) return 0.0f;
     const float b = base ? base[V + v] : 0.0f;
-    return (y[(size_t)v * 16 + 1] + b) - target[V + v];
+    return (y[V + v] + b) - target[V + v];
 }
 
 __global__ __launch_bounds__(256) void k_loss_theta_g(int nx, int ny, int B, const float *__restrict__ y,
@@ -269,6 +538,8 @@ __global__ __launch_bounds__(256) void k_sum_part(int n, const double *__restric
 //   the run by dj, which breaks the 8-byte alignment)
 // and writes its partial sums for the fixed-order reduction.
 constexpr int kWgBlocks = 512;
+constexpr int kTK = 4, kTI = 8, kTJ = 32;           // block of output voxels
+constexpr int kHK = kTK + 2, kHI = kTI + 2, kHJ = kTJ + 2; // with its halo
 
 __global__ __launch_bounds__(256) void k_wgrad_tile(Geom g, int ntj, int nti, int nblocks,
                                                     const uint16_t *__restrict__ dy, const uint16_t *__restrict__ in,
@@ -392,16 +663,16 @@ __global__ __launch_bounds__(256) void k_dual_from_net(Geom g, int tv, const flo
     if (tv == 2) {
         for (int k = 0; k < g.B; ++k) {
             const uint32_t v = (uint32_t)k * plane + pix;
-            const float h = hin ? y[(size_t)v * 16] + (base ? base[v] : 0.0f) : 0.0f;
-            const float w = vin ? y[(size_t)v * 16 + 1] + (base ? base[g.V + v] : 0.0f) : 0.0f;
+            const float h = hin ? y[v] + (base ? base[v] : 0.0f) : 0.0f;
+            const float w = vin ? y[g.V + v] + (base ? base[g.V + v] : 0.0f) : 0.0f;
             n2 = fmaf(w, w, fmaf(h, h, n2));
         }
     }
     const float svtv = fminf(1.0f, __builtin_amdgcn_rsqf(n2));
     for (int k = 0; k < g.B; ++k) {
         const uint32_t v = (uint32_t)k * plane + pix;
-        float h = hin ? y[(size_t)v * 16] + (base ? base[v] : 0.0f) : 0.0f;
-        float w = vin ? y[(size_t)v * 16 + 1] + (base ? base[g.V + v] : 0.0f) : 0.0f;
+        float h = hin ? y[v] + (base ? base[v] : 0.0f) : 0.0f;
+        float w = vin ? y[g.V + v] + (base ? base[g.V + v] : 0.0f) : 0.0f;
         if (tv == 0) {
             h = fminf(fmaxf(h, -1.0f), 1.0f);
             w = fminf(fmaxf(w, -1.0f), 1.0f);
@@ -425,17 +696,94 @@ void wsnet_pack_input(int nx, int ny, int B, const float *x, const float *dual, 
     hipLaunchKernelGGL(k_pack_input, dim3((V + 255) / 256), dim3(256), 0, s, V, x, dual, a);
 }
 
-// The transposed convolution (data gradient) is this same convolution with
-// the tap-mirrored, in/out-swapped weight pack WkT[26 - t][c][n] = W[t][n][c].
-void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
-                const uint16_t *gate, uint16_t *out16, float *out32, hipStream_t s)
+namespace {
+
+int device_cus()
 {
-    const Geom g = geom(nx, ny, B);
-    const int ntj = (ny + kTJ - 1) / kTJ, nti = (nx + kTI - 1) / kTI, ntk = (B + kTK - 1) / kTK;
-    const dim3 grid(ntj * nti * ntk), block(256);
-    if (out32) hipLaunchKernelGGL((k_conv_tile<false, true>), grid, block, 0, s, g, ntj, nti, in, Wk, bias, gate, out16, out32);
-    else if (relu) hipLaunchKernelGGL((k_conv_tile<true, false>), grid, block, 0, s, g, ntj, nti, in, Wk, bias, gate, out16, out32);
-    else hipLaunchKernelGGL((k_conv_tile<false, false>), grid, block, 0, s, g, ntj, nti, in, Wk, bias, gate, out16, out32);
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            ncu = n;
+        else
+            ncu = 256;
+    }
+    return ncu;
+}
+
+// Work split: tiles of kCI x kCJ, each walked through runs of F frames; the
+// frames are cut into runs only when there are fewer tiles than resident
+// workgroups (conv_wgs_per_cu per CU). Persistent grid of at most that many
+// workgroups, each taking every gridDim-th item.
+template <int CIN, int COUT, bool RELU, bool GATE>
+void launch_conv(ConvArgs a, hipStream_t s)
+{
+    const int nti = (a.g.nx + kCI - 1) / kCI;
+    a.ntj = (a.g.ny + kCJ - 1) / kCJ;
+    a.ntiles = nti * a.ntj;
+    const int slots = conv_wgs_per_cu<CIN>() * device_cus();
+    const int runs = std::max(1, std::min(a.g.B, (slots + a.ntiles - 1) / a.ntiles));
+    a.F = (a.g.B + runs - 1) / runs;
+    a.nitems = a.ntiles * ((a.g.B + a.F - 1) / a.F);
+    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE>), dim3(std::min(a.nitems, slots)), dim3(256), 0, s, a);
+}
+
+ConvArgs conv_args(int nx, int ny, int B, const uint16_t *Wk, const float *bias)
+{
+    ConvArgs a{};
+    a.g = geom(nx, ny, B);
+    a.Wk = Wk;
+    a.bias = bias;
+    return a;
+}
+
+} // namespace
+
+void wsnet_conv_input(int nx, int ny, int B, const float *x, const float *base, const uint16_t *Wk, const float *bias,
+                      uint16_t *out16, hipStream_t s)
+{
+    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
+    const size_t V = (size_t)nx * ny * B;
+    a.x = x;
+    a.xb0 = base ? base : x;
+    a.xb1 = base ? base + V : x;
+    a.xb_live = base != nullptr;
+    a.out16 = out16;
+    launch_conv<CIN_F32, COUT_BF16, true, false>(a, s);
+}
+
+void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
+                const uint16_t *gate, uint16_t *out16, hipStream_t s)
+{
+    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
+    a.in = in;
+    a.gate = gate;
+    a.out16 = out16;
+    if (gate) launch_conv<CIN_BF16, COUT_BF16, false, true>(a, s);
+    else if (relu) launch_conv<CIN_BF16, COUT_BF16, true, false>(a, s);
+    else launch_conv<CIN_BF16, COUT_BF16, false, false>(a, s);
+}
+
+void wsnet_conv_out(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int cout,
+                    float *y, hipStream_t s)
+{
+    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
+    a.in = in;
+    a.out32 = y;
+    a.cout = cout;
+    launch_conv<CIN_BF16, COUT_F32, false, false>(a, s);
+}
+
+void wsnet_conv_dual(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int tv,
+                     const float *base, float *dual, hipStream_t s)
+{
+    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
+    a.in = in;
+    a.out32 = dual;
+    a.obase = base;
+    a.tv = tv;
+    launch_conv<CIN_BF16, COUT_DUAL, false, false>(a, s);
 }
 
 int wsnet_reduce_blocks() { return kRedBlocks; }

@@ -11,8 +11,19 @@ constexpr int kNetHidden = 16;
 constexpr int kNetSlots = 28 * 256; // per layer: [27 taps + bias][16 out][16 in] fp32 master layout
 
 void wsnet_pack_input(int nx, int ny, int B, const float *x, const float *dual, uint16_t *a, hipStream_t s);
+// 3x3x3 convolutions (Wk[27][16 out][16 in] bf16, bias nullable):
+// first layer from fp32 planes x [V] and base [2][V] (nullable) with ReLU, to bf16 [V][16];
+void wsnet_conv_input(int nx, int ny, int B, const float *x, const float *base, const uint16_t *Wk, const float *bias,
+                      uint16_t *out16, hipStream_t s);
+// bf16 [V][16] to bf16 [V][16], with ReLU, or masked by gate > 0 (gate non-null, no ReLU);
 void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
-                const uint16_t *gate, uint16_t *out16, float *out32, hipStream_t s);
+                const uint16_t *gate, uint16_t *out16, hipStream_t s);
+// bf16 [V][16] to the raw output planes y [cout][V] fp32;
+void wsnet_conv_out(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int cout,
+                    float *y, hipStream_t s);
+// bf16 [V][16] to the dual [2][V] = (base +) output projected for tv 0 (ATV) or 1 (ITV2D).
+void wsnet_conv_dual(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int tv,
+                     const float *base, float *dual, hipStream_t s);
 int wsnet_reduce_blocks();
 int wsnet_wgrad_groups();
 void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *base, const float *target, uint16_t *dy,

@@ -28,7 +28,7 @@ struct sci_wsnet {
     size_t vcap = 0;
     uint16_t *act[kNetLayers] = {nullptr, nullptr, nullptr, nullptr}; // layer inputs a0..a3
     uint16_t *dA = nullptr, *dB = nullptr;                            // gradient ping-pong
-    float *y = nullptr;                                               // last layer output [V][16]
+    float *y = nullptr;                                               // last layer output [c_out][V]
     float *gth = nullptr;                                             // theta-loss D^T r [V]
     float *wpart = nullptr;                                           // wgrad partials
     double *lpart = nullptr;                                          // loss partials (+ result)
@@ -67,7 +67,7 @@ int ensure_acts(sci_ctx *ctx, sci_wsnet *n, size_t V, hipStream_t s)
     for (auto &a : n->act)
         if ((e = hipMalloc(&a, ab)) != hipSuccess) return net_fail(ctx, e, "hipMalloc(activations)");
     if ((e = hipMalloc(&n->dA, ab)) != hipSuccess || (e = hipMalloc(&n->dB, ab)) != hipSuccess ||
-        (e = hipMalloc(&n->y, V * 16 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&n->y, V * (size_t)n->c_out * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&n->gth, V * sizeof(float))) != hipSuccess)
         return net_fail(ctx, e, "hipMalloc(activations)");
     n->vcap = V;
@@ -88,16 +88,24 @@ int check_net_args(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *X
     return SCI_OK;
 }
 
-// a0 = pack(X [, base]); a_{l+1} = relu(conv_l(a_l)); y = conv_3(a_3)
-void forward(sci_wsnet *n, const sci_dims &d, const float *X, const float *base, hipStream_t s)
+// a1 = relu(conv_0(X [, base])), read from the fp32 planes; a_{l+1} =
+// relu(conv_l(a_l)); the last layer writes the raw output planes y or, when
+// `dual` is given (a pointwise projection: ATV, ITV2D), the projected
+// (base +) output straight into it. The packed input a0 (bf16 [V][16]) is
+// written only for the gradients, whose first weight gradient reads it.
+void forward(sci_wsnet *n, const sci_dims &d, const float *X, const float *P_base, bool for_grads, float *dual,
+             int tv, hipStream_t s)
 {
-    wsnet_pack_input(d.nx, d.ny, d.B, X, n->c_in == 3 ? base : nullptr, n->act[0], s);
-    for (int l = 0; l < kNetLayers; ++l) {
-        const uint16_t *Wk = n->Wk + (size_t)l * 27 * 256;
-        const float *b = n->bias + l * 16;
-        if (l < kNetLayers - 1) wsnet_conv(d.nx, d.ny, d.B, n->act[l], Wk, b, true, nullptr, n->act[l + 1], nullptr, s);
-        else wsnet_conv(d.nx, d.ny, d.B, n->act[l], Wk, b, false, nullptr, nullptr, n->y, s);
-    }
+    const float *base = n->c_in == 3 ? P_base : nullptr;
+    if (for_grads) wsnet_pack_input(d.nx, d.ny, d.B, X, base, n->act[0], s);
+    wsnet_conv_input(d.nx, d.ny, d.B, X, base, n->Wk, n->bias, n->act[1], s);
+    for (int l = 1; l < kNetLayers - 1; ++l)
+        wsnet_conv(d.nx, d.ny, d.B, n->act[l], n->Wk + (size_t)l * 27 * 256, n->bias + l * 16, true, nullptr,
+                   n->act[l + 1], s);
+    const int l = kNetLayers - 1;
+    const uint16_t *Wk = n->Wk + (size_t)l * 27 * 256;
+    if (dual) wsnet_conv_dual(d.nx, d.ny, d.B, n->act[l], Wk, n->bias + l * 16, tv, base, dual, s);
+    else wsnet_conv_out(d.nx, d.ny, d.B, n->act[l], Wk, n->bias + l * 16, n->c_out, n->y, s);
 }
 
 // loss and gradients of every layer into n->g
@@ -114,8 +122,7 @@ void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, 
         wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], n->wpart, n->g + (size_t)l * kNetSlots, s);
         if (l > 0) {
             // d a_l = conv^T(d y_l), masked by the ReLU of a_l
-            wsnet_conv(d.nx, d.ny, d.B, dcur, n->WkT + (size_t)l * 27 * 256, nullptr, false, n->act[l], dnext,
-                       nullptr, s);
+            wsnet_conv(d.nx, d.ny, d.B, dcur, n->WkT + (size_t)l * 27 * 256, nullptr, false, n->act[l], dnext, s);
             std::swap(dcur, dnext);
         }
     }
@@ -245,9 +252,11 @@ int sci_wsnet_forward(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X, co
     const size_t V = (size_t)d.nx * d.ny * d.B;
     if ((st = ensure_acts(ctx, n, V, stream)) != SCI_OK) return st;
     const float *base = n->c_in == 3 ? P_base : nullptr;
-    forward(n, d, X, base, stream);
-    if (Y_out) launch_copy(n->y, Y_out, V * 16 * sizeof(float), stream);
-    if (dual_out) wsnet_dual_from_net(d.nx, d.ny, d.B, tv, n->y, base, dual_out, stream);
+    // ATV and ITV2D project pointwise: the last layer writes the dual itself
+    const bool fused = dual_out && !Y_out && tv != SCI_TV_VTV;
+    forward(n, d, X, base, false, fused ? dual_out : nullptr, tv, stream);
+    if (Y_out) launch_copy(n->y, Y_out, V * (size_t)n->c_out * sizeof(float), stream);
+    if (dual_out && !fused) wsnet_dual_from_net(d.nx, d.ny, d.B, tv, n->y, base, dual_out, stream);
     return check_launch(ctx, "wsnet forward");
 }
 
@@ -259,7 +268,7 @@ int sci_wsnet_grads(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X, cons
     if (!target) return fail(ctx, SCI_ERR_INVALID_ARG, "wsnet: null target");
     const size_t V = (size_t)d.nx * d.ny * d.B;
     if ((st = ensure_acts(ctx, n, V, stream)) != SCI_OK) return st;
-    forward(n, d, X, P_base, stream);
+    forward(n, d, X, P_base, true, nullptr, 0, stream);
     backward(ctx, n, d, P_base, target, stream);
     if ((st = check_launch(ctx, "wsnet grads")) != SCI_OK) return st;
     hipError_t e = hipStreamSynchronize(stream);
@@ -285,7 +294,7 @@ int sci_wsnet_train_step(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X,
     if (!target || !std::isfinite(lr) || lr < 0.0f) return fail(ctx, SCI_ERR_INVALID_ARG, "wsnet: bad target or lr");
     const size_t V = (size_t)d.nx * d.ny * d.B;
     if ((st = ensure_acts(ctx, n, V, stream)) != SCI_OK) return st;
-    forward(n, d, X, P_base, stream);
+    forward(n, d, X, P_base, true, nullptr, 0, stream);
     backward(ctx, n, d, P_base, target, stream);
     ++n->step;
     adam(n, lr, stream);

@@ -390,10 +390,11 @@ def sci_wsnet_get_params(ctx, net):
     return a
 
 
-def sci_wsnet_forward(ctx, net, X, tv="itv2d", base=None, want_raw=False, want_dual=True, stream=None):
-    """(raw [V][16] output or None, projected dual [2][B][nx][ny] or None)."""
+def sci_wsnet_forward(ctx, net, X, tv="itv2d", base=None, want_raw=False, want_dual=True, stream=None, c_out=2):
+    """(raw output [c_out][B][nx][ny] or None, projected dual [2][B][nx][ny] or
+    None); c_out is the network's output channel count."""
     d = _dims(X)
-    raw = torch.empty((X.numel(), 16), device=X.device) if want_raw else None
+    raw = torch.empty((c_out,) + tuple(X.shape), device=X.device) if want_raw else None
     dual = torch.empty((2,) + tuple(X.shape), device=X.device) if want_dual else None
     _check(ctx, lib.sci_wsnet_forward(ctx, net, d, _dev(X, name="X"), _dev(base, shape=(2,) + tuple(X.shape), name="base"),
                                       _dev(raw, name="raw"),

@@ -67,13 +67,11 @@ def test_forward_matches_oracle(sc, ctx, net, B, nx, ny):
     np.testing.assert_array_equal(sc.sci_wsnet_get_params(ctx, net), wo.pack(wo.unpack(P)))
     x = np.random.default_rng(1).uniform(size=(B, nx, ny)).astype(np.float32)
     raw, dual = sc.sci_wsnet_forward(ctx, net, dev(x), tv="itv2d", want_raw=True)
-    raw = host(raw).reshape(B, nx, ny, 16)
+    got = host(raw)
     _, y = wo.forward(x, P)
-    got = np.moveaxis(raw[..., :2], -1, 0)
     e = rel(got, y)
     print(f"forward {B}x{nx}x{ny}: rel-L2 {e:.2e}", flush=True)
     assert e <= 1e-3
-    assert np.all(raw[..., 2:] == 0)
     np.testing.assert_allclose(host(dual), wo.project_dual(got, "itv2d"), rtol=0, atol=2e-6)
 
 
@@ -86,9 +84,8 @@ def test_residual_forward_matches_oracle(sc, ctx, rnet, B, nx, ny):
     x = r.uniform(size=(B, nx, ny)).astype(np.float32)
     base = r.uniform(-1, 1, size=(2, B, nx, ny)).astype(np.float32)
     raw, dual = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="vtv", base=dev(base), want_raw=True)
-    raw = host(raw).reshape(B, nx, ny, 16)
+    got = host(raw)
     _, y = wo.forward(x, P, base=base, c_in=3)
-    got = np.moveaxis(raw[..., :2], -1, 0)
     e = rel(got, y)
     print(f"residual forward {B}x{nx}x{ny}: rel-L2 {e:.2e}", flush=True)
     assert e <= 1e-3
@@ -97,6 +94,81 @@ def test_residual_forward_matches_oracle(sc, ctx, rnet, B, nx, ny):
     _, dual0 = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="vtv")
     _, y0 = wo.forward(x, P, base=None, c_in=3)
     assert rel(host(dual0), wo.project_dual(y0, "vtv")) <= 1e-3
+
+
+@pytest.mark.parametrize("c_in", [1, 3])
+@pytest.mark.parametrize("B,nx,ny", [(3, 20, 37), (2, 33, 65), (1, 1, 1)])
+def test_fused_dual_equals_projected_raw_output(sc, ctx, net, rnet, c_in, B, nx, ny):
+    """ATV and ITV2D project pointwise, so the last layer writes the projected
+    dual itself when no raw output is asked for; it must equal, bit for bit,
+    the projection of the raw output by the separate pass."""
+    n = net if c_in == 1 else rnet
+    P = params(B + 2 * nx + ny, c_in=c_in)
+    sc.sci_wsnet_set_params(ctx, n, P)
+    r = np.random.default_rng(nx + ny)
+    x = dev(r.uniform(size=(B, nx, ny)))
+    base = dev(r.uniform(-1, 1, size=(2, B, nx, ny))) if c_in == 3 else None
+    for tv in ("atv", "itv2d"):
+        _, fused = sc.sci_wsnet_forward(ctx, n, x, tv=tv, base=base)
+        raw, split = sc.sci_wsnet_forward(ctx, n, x, tv=tv, base=base, want_raw=True)
+        np.testing.assert_array_equal(host(fused), host(split))
+        b = host(base) if c_in == 3 else 0.0
+        np.testing.assert_allclose(host(fused), wo.project_dual(host(raw) + b, tv), rtol=0, atol=2e-6)
+
+
+def test_forward_frame_walk_matches_oracle(sc, ctx, rnet):
+    """250 x 1000 frames hold 16 x 16 = 512 output tiles of 16 x 32 voxels,
+    ragged in both directions (the last tile row holds 10 rows, the last tile
+    column 8 columns): on a 256-CU device every tile is walked through all
+    five frames (a pair, a pair and an odd last frame, slabs recycled through
+    the four-slab ring). The oracle is run on crops of the volume: four
+    layers of 3x3x3 see 4 voxels away, so outputs 4 or more voxels inside a
+    crop's cut edges (a crop edge on the volume edge is no cut) are exact;
+    the crops take the two volume corners and tile corners in between."""
+    B, nx, ny = 5, 250, 1000
+    P = params(31, c_in=3)
+    sc.sci_wsnet_set_params(ctx, rnet, P)
+    r = np.random.default_rng(8)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    base = r.uniform(-1, 1, size=(2, B, nx, ny)).astype(np.float32)
+    raw, dual_vtv = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="vtv", base=dev(base), want_raw=True)
+    _, dual_itv = sc.sci_wsnet_forward(ctx, rnet, dev(x), tv="itv2d", base=dev(base))
+    got = host(raw)
+    m = 4
+    for (i0, i1), (j0, j1) in [((0, 40), (0, 72)), ((210, 250), (940, 1000)), ((100, 140), (300, 360))]:
+        _, y = wo.forward(x[:, i0:i1, j0:j1], P, base=base[:, :, i0:i1, j0:j1], c_in=3)
+        a0, a1 = (0 if i0 == 0 else m), (i1 - i0) - (0 if i1 == nx else m)
+        b0, b1 = (0 if j0 == 0 else m), (j1 - j0) - (0 if j1 == ny else m)
+        ref = y[:, :, a0:a1, b0:b1]
+        g = got[:, :, i0 + a0:i0 + a1, j0 + b0:j0 + b1]
+        e = rel(g, ref)
+        print(f"residual forward {B}x{nx}x{ny}, rows {i0 + a0}-{i0 + a1} cols {j0 + b0}-{j0 + b1}: rel-L2 {e:.2e}",
+              flush=True)
+        assert e <= 1e-3
+    np.testing.assert_allclose(host(dual_vtv), wo.project_dual(got + base, "vtv"), rtol=0, atol=2e-6)
+    np.testing.assert_allclose(host(dual_itv), wo.project_dual(got + base, "itv2d"), rtol=0, atol=2e-6)
+
+
+def test_gradients_frame_walk_match_oracle(sc, ctx, rnet):
+    """Gradients of a 520-frame volume of 3 x 40 pixels: two tiles (the
+    second holds 8 columns, both 3 rows), so on a 256-CU device the frames
+    are cut into runs of three (a pair and an odd frame) and a last run of
+    one, walked by the forward and the transposed convolutions."""
+    B, nx, ny = 520, 3, 40
+    P = params(37, c_in=3)
+    sc.sci_wsnet_set_params(ctx, rnet, P)
+    r = np.random.default_rng(13)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    base = r.uniform(-1, 1, size=(2, B, nx, ny)).astype(np.float32)
+    t = r.normal(scale=0.5, size=(2, B, nx, ny)).astype(np.float32)
+    loss, g = sc.sci_wsnet_grads(ctx, rnet, dev(x), dev(t), base=dev(base))
+    lo, go = wo.loss_and_grads(x, t, P, base=base, c_in=3)
+    assert abs(loss - lo) <= 1e-4 * lo
+    G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
+    for l in range(4):
+        e = rel(G[l], GO[l])
+        print(f"{B}x{nx}x{ny} layer {l} gradient rel-L2 {e:.2e}", flush=True)
+        assert e <= 5e-3
 
 
 def test_residual_zero_net_is_the_base(sc, ctx, rnet):
