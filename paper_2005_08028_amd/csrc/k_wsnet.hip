@@ -94,12 +94,22 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 enum { CIN_BF16 = 0, CIN_F32 = 1 };          // input: bf16 [V][16], or fp32 planes x [V] (+ base [2][V])
 enum { COUT_BF16 = 0, COUT_F32 = 1, COUT_DUAL = 2 };
 
-struct ConvArgs {
-    Geom g;
-    int ntj, ntiles, F, nitems;  // tiles per row band, tiles per frame, frames per item, items
-    const uint16_t *in;          // CIN_BF16
+// Where a frame walk takes its input from.
+struct SlabSrc {
+    const uint16_t *in;          // CIN_BF16: [V][16]
     const float *x, *xb0, *xb1;  // CIN_F32: x and the base planes (x itself when there is no base)
     int xb_live;                 // 0: channels 1, 2 are zero
+};
+
+// Tiles, frame runs and items of a frame walk.
+struct WalkGeom {
+    Geom g;
+    int ntj, ntiles, F, nitems;  // tiles per row band, tiles per frame, frames per run, items
+};
+
+struct ConvArgs {
+    WalkGeom w;
+    SlabSrc src;
     const uint16_t *Wk;
     const float *bias;           // nullable
     const uint16_t *gate;        // GATE: output zeroed where gate[v][n] <= 0
@@ -117,29 +127,160 @@ __device__ inline uint32_t pack2_bf16(float lo, float hi)
     return __builtin_bit_cast(uint32_t, p);
 }
 
+// Staging of input slabs (tile plus halo, one frame) through registers into
+// the LDS ring. Each thread owns NL fixed slots of a slab; two register sets
+// hold the slabs in flight.
+template <int CIN> struct SlabStage {
+    static constexpr int CPT = CIN == CIN_F32 ? 1 : 2;                  // 16-byte chunks per staged voxel
+    static constexpr int NL = CIN == CIN_F32 ? kVoxLoads : kChunkLoads; // slots per thread
+    static constexpr int SLAB = CPT == 1 ? kSlabVox : kSlabChunks;      // 16-byte slots per slab
+    static constexpr int NSLOT = CPT == 1 ? kSlabVox : kSlabChunks;     // live slots per slab
+
+    // LDS slot of chunk h of staged voxel v (slab column sj): one chunk per
+    // voxel when only channels 0-7 are staged, else two, swizzled
+    __device__ static int chunk_slot(int v, int sj, int h) { return CPT == 1 ? v : 2 * v + (h ^ ((sj >> 2) & 1)); }
+
+    int pslot[NL];
+    uint32_t poff[NL];
+    uint32_t pok;
+    uint4 pre[2][CIN == CIN_F32 ? 1 : NL];
+    float px[2][CIN == CIN_F32 ? NL : 1], pb0[2][CIN == CIN_F32 ? NL : 1], pb1[2][CIN == CIN_F32 ? NL : 1];
+    bool fval[2];
+
+    __device__ static bool live(int tid, int q) { return q < NL - 1 || tid + 256 * q < NSLOT; }
+    __device__ static void split(int e, int &v, int &hh)
+    {
+        v = CIN == CIN_F32 ? e : (e >> 1);
+        hh = CIN == CIN_F32 ? 0 : (e & 1);
+    }
+
+    __device__ void init(int tid)
+    {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            int v, hh;
+            split(tid + 256 * q, v, hh);
+            pslot[q] = chunk_slot(v, v % kSJ, hh);
+        }
+        fval[0] = fval[1] = false;
+    }
+    // source offsets within a frame for the tile at (i0, j0); zero outside the frame
+    __device__ void begin(int tid, int i0, int j0, int nx, int ny)
+    {
+        pok = 0;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            int v, hh;
+            split(tid + 256 * q, v, hh);
+            const int i = i0 - 1 + v / kSJ, j = j0 - 1 + v % kSJ;
+            const bool ok = live(tid, q) && i >= 0 && i < nx && j >= 0 && j < ny;
+            poff[q] = ok ? (CIN == CIN_F32 ? (uint32_t)(i * ny + j) : (uint32_t)(i * ny + j) * 16u + 8u * hh) : 0u;
+            pok |= (uint32_t)ok << q;
+        }
+    }
+    // Every load is issued unconditionally (a frame outside the volume reads
+    // the nearest frame, dead slots read offset 0) and the zeros are applied
+    // when the slab is stored: with a fixed count of loads per slab, the wait
+    // for one slab's data lets the next slab's loads stay in flight.
+    template <int S> __device__ void load(const SlabSrc &src, const Geom &g, int f)
+    {
+        fval[S] = f >= 0 && f < g.B;
+        const int fc = min(max(f, 0), g.B - 1);
+        const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
+        if constexpr (CIN == CIN_F32) {
+            const size_t fb = (size_t)fc * plane;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                px[S][q] = src.x[fb + poff[q]];
+                pb0[S][q] = src.xb0[fb + poff[q]];
+                pb1[S][q] = src.xb1[fb + poff[q]];
+            }
+        } else {
+            const uint16_t *p = src.in + (size_t)fc * plane * 16;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) pre[S][q] = *(const uint4 *)(p + poff[q]);
+        }
+    }
+    template <int S> __device__ void store(const SlabSrc &src, uint4 *slab, int tid)
+    {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            if (!live(tid, q)) continue;
+            const bool ok = fval[S] && ((pok >> q) & 1u);
+            uint4 val;
+            if constexpr (CIN == CIN_F32)
+                val = src.xb_live ? make_uint4(pack2_bf16(px[S][q], pb0[S][q]), pack2_bf16(pb1[S][q], 0.0f), 0u, 0u)
+                                  : make_uint4(pack2_bf16(px[S][q], 0.0f), 0u, 0u, 0u);
+            else val = pre[S][q];
+            slab[pslot[q]] = ok ? val : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+};
+
+// The frame walk: this workgroup's items (tile, run of frames), every
+// gridDim-th item after an XCD-contiguous renumbering. For output frame k0 + s
+// of an item, slabs r = s, s+1, s+2 (frames k0-1+r) are in LDS ring slots
+// r mod 4; step(setc, s, i0, j0, k, prefetch) computes it and must call
+// prefetch() exactly once (uniformly), which issues the loads of slab s + 4.
+// begin(i0, j0, k0) runs once per item, after the first slabs are requested.
+template <int CIN, typename Step, typename Begin>
+__device__ __forceinline__ void frame_walk(const WalkGeom &w, const SlabSrc &src, uint4 *ring, SlabStage<CIN> &st,
+                                           Step &&step, Begin &&begin)
+{
+    using St = SlabStage<CIN>;
+    const int tid = threadIdx.x, nwg = (int)gridDim.x;
+    auto slab = [&](int r) { return ring + (r & (kRing - 1)) * St::SLAB; };
+    for (int it = xcd_contiguous((int)blockIdx.x, nwg); it < w.nitems; it += nwg) {
+        const int run = it / w.ntiles, tile = it % w.ntiles;
+        const int i0 = (tile / w.ntj) * kCI, j0 = (tile % w.ntj) * kCJ, k0 = run * w.F;
+        const int nf = min(w.F, w.g.B - k0);
+        st.begin(tid, i0, j0, w.g.nx, w.g.ny);
+        __syncthreads(); // every wavefront is done with the previous item's slabs
+        st.template load<0>(src, w.g, k0 - 1);
+        st.template load<1>(src, w.g, k0);
+        st.template store<0>(src, slab(0), tid);
+        st.template store<1>(src, slab(1), tid);
+        st.template load<0>(src, w.g, k0 + 1);
+        st.template load<1>(src, w.g, k0 + 2);
+        begin(i0, j0, k0);
+        auto one = [&](auto setc, int s) {
+            constexpr int S = decltype(setc)::value;
+            st.template store<S>(src, slab(s + 2), tid);
+            __syncthreads();
+            // past the run's last slab: loaded, never stored
+            auto prefetch = [&] { st.template load<S>(src, w.g, k0 + s + 3); };
+            step(setc, s, i0, j0, k0 + s, prefetch);
+        };
+        // frames in pairs (both register sets on every trip, so the compiler
+        // can count the loads in flight), then an odd last frame
+        int s = 0;
+        for (; s + 1 < nf; s += 2) {
+            one(std::integral_constant<int, 0>{}, s);
+            one(std::integral_constant<int, 1>{}, s + 1);
+        }
+        if (s < nf) one(std::integral_constant<int, 0>{}, s);
+    }
+}
+
 // Workgroups per CU: LDS holds two rings of 16-channel slabs, three of 8-channel ones.
 template <int CIN> constexpr int conv_wgs_per_cu() { return CIN == CIN_F32 ? 3 : 2; }
 
 template <int CIN, int COUT, bool RELU, bool GATE>
 __global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const ConvArgs a)
 {
-    constexpr int CPT = CIN == CIN_F32 ? 1 : 2;   // chunks of a tap in one MFMA operand
+    using St = SlabStage<CIN>;
+    constexpr int CPT = St::CPT;                  // chunks of a tap in one MFMA operand
     constexpr int TPM = 4 / CPT;                  // (dk, dj) offsets per MFMA
     constexpr int G = (9 + TPM - 1) / TPM;        // MFMAs per (staged row, di)
-    constexpr int NL = CIN == CIN_F32 ? kVoxLoads : kChunkLoads;
-    // LDS slot of chunk h of staged voxel v (slab column sj): one chunk per
-    // voxel when only channels 0-7 are staged, else two, swizzled
-    auto chunk_slot = [](int v, int sj, int h) { return CPT == 1 ? v : 2 * v + (h ^ ((sj >> 2) & 1)); };
-    constexpr int SLAB = CPT == 1 ? kSlabVox : kSlabChunks; // 16-byte slots per slab
-    __shared__ uint4 ring[kRing * SLAB];
+    __shared__ uint4 ring[kRing * St::SLAB];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int hsel = CPT == 2 ? (kq & 1) : 0;
-    const int nx = a.g.nx, ny = a.g.ny, B = a.g.B;
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny, V = a.g.V;
+    const int nx = a.w.g.nx, ny = a.w.g.ny;
+    const uint32_t V = a.w.g.V;
 
-    // B operands: weights of tap (dk, di, dj) for the lane's (dk, dj) in group gi
+    // A operands: weights of tap (dk, di, dj) for the lane's (dk, dj) in group gi
     bf16x8 wb[3][G];
     int coff[G][2], cdk[G];
 #pragma unroll
@@ -155,238 +296,147 @@ __global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const Conv
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt) {
             const int col = 16 * tt + row + dj;
-            coff[gi][tt] = chunk_slot(kRowsPerWave * wv * kSJ + col, col, hsel);
+            coff[gi][tt] = St::chunk_slot(kRowsPerWave * wv * kSJ + col, col, hsel);
         }
     }
     float bn[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) bn[e] = a.bias ? a.bias[4 * kq + e] : 0.0f;
 
-    // staging: this thread's chunks (bf16 input) or voxels (fp32 input) of a slab
-    int pslot[NL];
-    uint32_t poff[NL];
-    uint32_t pok = 0;
+    SlabStage<CIN> st;
+    st.init(tid);
+    frame_walk<CIN>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
+        (void)setc;
+        const bool rows_live = i0 + kRowsPerWave * wv < nx; // uniform per wavefront
+        // Vector memory operations complete in issue order, and the
+        // epilogue's stores are conditional, so the compiler cannot count
+        // them: the prefetch is issued after the epilogue, and the wait for
+        // a slab (two steps later) then leaves the next slab's loads in
+        // flight. The epilogue's operands (the gate; the base dual, which
+        // lane (row, kq) reads for its own voxel of output row kq and the
+        // epilogue gathers across lanes) are read before the compute.
+        uint2 eg[GATE ? 4 : 1][2];
+        float eb[COUT == COUT_DUAL ? 2 : 1][2];
+        if constexpr (GATE) {
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-        const int e = tid + 256 * q;
-        const int v = CIN == CIN_F32 ? e : (e >> 1), hh = CIN == CIN_F32 ? 0 : (e & 1);
-        pslot[q] = chunk_slot(v, v % kSJ, hh);
-    }
-    uint4 pre[2][CIN == CIN_F32 ? 1 : NL];
-    float px[2][CIN == CIN_F32 ? NL : 1], pb0[2][CIN == CIN_F32 ? NL : 1], pb1[2][CIN == CIN_F32 ? NL : 1];
-    bool fval[2] = {false, false};
-
-    auto q_live = [&](int q) { return q < NL - 1 || tid + 256 * q < (CIN == CIN_F32 ? kSlabVox : kSlabChunks); };
-
-    // Every load is issued unconditionally (frames outside the volume read
-    // the nearest frame, dead slots read offset 0) and the zeros are applied
-    // when the slab is stored: with a fixed count of loads per slab the
-    // wait for one slab's data lets the next slab's loads stay in flight.
-    auto load_slab = [&](auto setc, int k0, int r) {
-        constexpr int S = decltype(setc)::value;
-        const int f = k0 - 1 + r;
-        fval[S] = f >= 0 && f < B;
-        const int fc = min(max(f, 0), B - 1);
-        if constexpr (CIN == CIN_F32) {
-            const size_t fb = (size_t)fc * plane;
-#pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                px[S][q] = a.x[fb + poff[q]];
-                pb0[S][q] = a.xb0[fb + poff[q]];
-                pb1[S][q] = a.xb1[fb + poff[q]];
-            }
-        } else {
-            const uint16_t *src = a.in + (size_t)fc * plane * 16;
-#pragma unroll
-            for (int q = 0; q < NL; ++q) pre[S][q] = *(const uint4 *)(src + poff[q]);
-        }
-    };
-    auto store_slab = [&](auto setc, int r) {
-        constexpr int S = decltype(setc)::value;
-        uint4 *slab = ring + (r & (kRing - 1)) * SLAB;
-#pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            if (!q_live(q)) continue;
-            const bool ok = fval[S] && ((pok >> q) & 1u);
-            uint4 val;
-            if constexpr (CIN == CIN_F32)
-                val = a.xb_live ? make_uint4(pack2_bf16(px[S][q], pb0[S][q]), pack2_bf16(pb1[S][q], 0.0f), 0u, 0u)
-                                : make_uint4(pack2_bf16(px[S][q], 0.0f), 0u, 0u, 0u);
-            else val = pre[S][q];
-            slab[pslot[q]] = ok ? val : make_uint4(0u, 0u, 0u, 0u);
-        }
-    };
-
-    const int nwg = (int)gridDim.x;
-    for (int it = xcd_contiguous((int)blockIdx.x, nwg); it < a.nitems; it += nwg) {
-        const int chunk = it / a.ntiles, tile = it % a.ntiles;
-        const int i0 = (tile / a.ntj) * kCI, j0 = (tile % a.ntj) * kCJ, k0 = chunk * a.F;
-        const int nf = min(a.F, B - k0);
-        pok = 0;
-#pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            const int e = tid + 256 * q;
-            const int v = CIN == CIN_F32 ? e : (e >> 1), hh = CIN == CIN_F32 ? 0 : (e & 1);
-            const int i = i0 - 1 + v / kSJ, j = j0 - 1 + v % kSJ;
-            const bool ok = q_live(q) && i >= 0 && i < nx && j >= 0 && j < ny;
-            poff[q] = ok ? (CIN == CIN_F32 ? (uint32_t)(i * ny + j) : (uint32_t)(i * ny + j) * 16u + 8u * hh) : 0u;
-            pok |= (uint32_t)ok << q;
-        }
-        __syncthreads(); // every wavefront is done with the previous item's slabs
-        load_slab(std::integral_constant<int, 0>{}, k0, 0);
-        load_slab(std::integral_constant<int, 1>{}, k0, 1);
-        store_slab(std::integral_constant<int, 0>{}, 0);
-        store_slab(std::integral_constant<int, 1>{}, 1);
-        load_slab(std::integral_constant<int, 0>{}, k0, 2);
-        load_slab(std::integral_constant<int, 1>{}, k0, 3);
-
-        auto step = [&](auto setc, int s) {
-            store_slab(setc, s + 2);
-            __syncthreads();
-            const int k = k0 + s;
-            const bool rows_live = i0 + kRowsPerWave * wv < nx; // uniform per wavefront
-            // Loads complete in issue order: a kernel whose epilogue reads
-            // memory (gate, base) requests those reads first and issues the
-            // prefetch after the epilogue, so that waiting for them does not
-            // wait for the prefetch.
-            // Epilogue operands. The gate (GATE) is read before the compute
-            // and the prefetch is issued after the epilogue: loads complete in
-            // issue order, so waiting for the gate must not wait for a
-            // prefetch. The base dual (COUT_DUAL) is read before the prefetch:
-            // lane (row, kq) reads it for its own voxel of output row kq, and
-            // the epilogue gathers it across lanes.
-            uint2 eg[GATE ? 4 : 1][2];
-            float eb[COUT == COUT_DUAL ? 2 : 1][2];
-            if constexpr (GATE) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int tt = 0; tt < 2; ++tt) {
-                        const int i = i0 + kRowsPerWave * wv + r, j = j0 + 16 * tt + row;
-                        const size_t v = ((size_t)k * nx + i) * ny + j;
-                        eg[r][tt] = i < nx && j < ny ? *(const uint2 *)(a.gate + v * 16 + 4 * kq) : make_uint2(0u, 0u);
-                    }
-            }
-            if constexpr (COUT == COUT_DUAL) {
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) {
-                    const int i = i0 + kRowsPerWave * wv + kq, j = j0 + 16 * tt + row;
+                    const int i = i0 + kRowsPerWave * wv + r, j = j0 + 16 * tt + row;
                     const size_t v = ((size_t)k * nx + i) * ny + j;
-                    const bool in = a.obase && i < nx && j < ny;
-                    eb[tt][0] = in ? a.obase[v] : 0.0f;
-                    eb[tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
+                    eg[r][tt] = i < nx && j < ny ? *(const uint2 *)(a.gate + v * 16 + 4 * kq) : make_uint2(0u, 0u);
+                }
+        }
+        if constexpr (COUT == COUT_DUAL) {
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const int i = i0 + kRowsPerWave * wv + kq, j = j0 + 16 * tt + row;
+                const size_t v = ((size_t)k * nx + i) * ny + j;
+                const bool in = a.obase && i < nx && j < ny;
+                eb[tt][0] = in ? a.obase[v] : 0.0f;
+                eb[tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
+            }
+        }
+        if (rows_live) {
+            // D[n][voxel] = sum_K W[n][K] X[K][voxel]: the weights are the
+            // A operand, the staged voxels the B operand
+            f32x4 acc[4][2];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) acc[r][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const uint4 *slab[G];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) slab[gi] = ring + ((s + cdk[gi]) & (kRing - 1)) * St::SLAB;
+            // (staged row u, group gi) in sequence; the operands of the
+            // entry two ahead are read while the current one's MFMAs run
+            constexpr int NP = (kRowsPerWave + 2) * G;
+            bf16x8 X[3][2];
+            auto rd = [&](int p, bf16x8(&b)[2]) {
+                const int u = p / G, gi = p % G;
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) b[tt] = __builtin_bit_cast(bf16x8, slab[gi][coff[gi][tt] + u * CPT * kSJ]);
+            };
+            rd(0, X[0]);
+            rd(1, X[1]);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                if (p + 2 < NP) rd(p + 2, X[(p + 2) % 3]);
+                const int u = p / G, gi = p % G;
+#pragma unroll
+                for (int di = 0; di < 3; ++di) {
+                    const int r = u - di;
+                    if (r < 0 || r >= kRowsPerWave) continue;
+#pragma unroll
+                    for (int tt = 0; tt < 2; ++tt)
+                        acc[r][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[di][gi], X[p % 3][tt], acc[r][tt], 0, 0, 0);
                 }
             }
-            if constexpr (!GATE) load_slab(setc, k0, s + 4); // past the run's last slab: loaded, never stored
-            if (rows_live) {
-                // D[n][voxel] = sum_K W[n][K] X[K][voxel]: the weights are the
-                // A operand, the staged voxels the B operand
-                f32x4 acc[4][2];
+
+            // result: voxel j = j0 + 16 tt + row, output channels 4 kq + e
+            float gb[COUT == COUT_DUAL ? 4 : 1][2][2];
+            if constexpr (COUT == COUT_DUAL) {
+                // base of output row r: held by lane (row, r); every lane takes part
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
-                    for (int tt = 0; tt < 2; ++tt) acc[r][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                const uint4 *slab[G];
+                    for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-                for (int gi = 0; gi < G; ++gi) slab[gi] = ring + ((s + cdk[gi]) & (kRing - 1)) * SLAB;
-                // (staged row u, group gi) in sequence; the operands of the
-                // entry two ahead are read while the current one's MFMAs run
-                constexpr int NP = (kRowsPerWave + 2) * G;
-                bf16x8 X[3][2];
-                auto rd = [&](int p, bf16x8(&b)[2]) {
-                    const int u = p / G, gi = p % G;
+                        for (int c = 0; c < 2; ++c)
+                            gb[r][tt][c] = __int_as_float(
+                                __builtin_amdgcn_ds_bpermute(4 * (row + 16 * r), __float_as_int(eb[tt][c])));
+            }
 #pragma unroll
-                    for (int tt = 0; tt < 2; ++tt) b[tt] = __builtin_bit_cast(bf16x8, slab[gi][coff[gi][tt] + u * CPT * kSJ]);
-                };
-                rd(0, X[0]);
-                rd(1, X[1]);
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + kRowsPerWave * wv + r;
+                if (i >= nx) break; // uniform per wavefront
+                const size_t vrow = ((size_t)k * nx + i) * ny;
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    if (p + 2 < NP) rd(p + 2, X[(p + 2) % 3]);
-                    const int u = p / G, gi = p % G;
+                for (int tt = 0; tt < 2; ++tt) {
+                    const int j = j0 + 16 * tt + row;
+                    if (j >= ny) continue;
+                    const size_t v = vrow + j;
+                    float y[4];
 #pragma unroll
-                    for (int di = 0; di < 3; ++di) {
-                        const int r = u - di;
-                        if (r < 0 || r >= kRowsPerWave) continue;
-#pragma unroll
-                        for (int tt = 0; tt < 2; ++tt)
-                            acc[r][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[di][gi], X[p % 3][tt], acc[r][tt], 0, 0, 0);
-                    }
-                }
-
-                // result: voxel j = j0 + 16 tt + row, output channels 4 kq + e
-                float gb[COUT == COUT_DUAL ? 4 : 1][2][2];
-                if constexpr (COUT == COUT_DUAL) {
-                    // base of output row r: held by lane (row, r); every lane takes part
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-                            for (int c = 0; c < 2; ++c)
-                                gb[r][tt][c] = __int_as_float(
-                                    __builtin_amdgcn_ds_bpermute(4 * (row + 16 * r), __float_as_int(eb[tt][c])));
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + kRowsPerWave * wv + r;
-                    if (i >= nx) break; // uniform per wavefront
-                    const size_t vrow = ((size_t)k * nx + i) * ny;
-#pragma unroll
-                    for (int tt = 0; tt < 2; ++tt) {
-                        const int j = j0 + 16 * tt + row;
-                        if (j >= ny) continue;
-                        const size_t v = vrow + j;
-                        float y[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) y[e] = acc[r][tt][e] + bn[e];
-                        if constexpr (COUT == COUT_DUAL) {
-                            if (kq == 0) {
-                                // (base +) output, entries with no difference 0, projected
-                                float h = j < ny - 1 ? y[0] + gb[r][tt][0] : 0.0f;
-                                float w = i < nx - 1 ? y[1] + gb[r][tt][1] : 0.0f;
-                                if (a.tv == 0) {
-                                    h = fminf(fmaxf(h, -1.0f), 1.0f);
-                                    w = fminf(fmaxf(w, -1.0f), 1.0f);
-                                } else {
-                                    const float sc = fminf(1.0f, __builtin_amdgcn_rsqf(fmaf(w, w, h * h)));
-                                    h *= sc;
-                                    w *= sc;
-                                }
-                                a.out32[v] = h;
-                                a.out32[(size_t)V + v] = w;
+                    for (int e = 0; e < 4; ++e) y[e] = acc[r][tt][e] + bn[e];
+                    if constexpr (COUT == COUT_DUAL) {
+                        if (kq == 0) {
+                            // (base +) output, entries with no difference 0, projected
+                            float h = j < ny - 1 ? y[0] + gb[r][tt][0] : 0.0f;
+                            float w = i < nx - 1 ? y[1] + gb[r][tt][1] : 0.0f;
+                            if (a.tv == 0) {
+                                h = fminf(fmaxf(h, -1.0f), 1.0f);
+                                w = fminf(fmaxf(w, -1.0f), 1.0f);
+                            } else {
+                                const float sc = fminf(1.0f, __builtin_amdgcn_rsqf(fmaf(w, w, h * h)));
+                                h *= sc;
+                                w *= sc;
                             }
-                        } else if constexpr (COUT == COUT_F32) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                if (4 * kq + e < a.cout) a.out32[(size_t)(4 * kq + e) * V + v] = y[e];
-                        } else {
-                            if (RELU)
-#pragma unroll
-                                for (int e = 0; e < 4; ++e) y[e] = fmaxf(y[e], 0.0f);
-                            if constexpr (GATE) {
-                                const uint2 gv = eg[r][tt];
-                                if (!(__uint_as_float(gv.x << 16) > 0.0f)) y[0] = 0.0f;
-                                if (!(__uint_as_float(gv.x & 0xffff0000u) > 0.0f)) y[1] = 0.0f;
-                                if (!(__uint_as_float(gv.y << 16) > 0.0f)) y[2] = 0.0f;
-                                if (!(__uint_as_float(gv.y & 0xffff0000u) > 0.0f)) y[3] = 0.0f;
-                            }
-                            *(uint2 *)(a.out16 + v * 16 + 4 * kq) = make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
+                            a.out32[v] = h;
+                            a.out32[(size_t)V + v] = w;
                         }
+                    } else if constexpr (COUT == COUT_F32) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (4 * kq + e < a.cout) a.out32[(size_t)(4 * kq + e) * V + v] = y[e];
+                    } else {
+                        if (RELU)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) y[e] = fmaxf(y[e], 0.0f);
+                        if constexpr (GATE) {
+                            const uint2 gv = eg[r][tt];
+                            if (!(__uint_as_float(gv.x << 16) > 0.0f)) y[0] = 0.0f;
+                            if (!(__uint_as_float(gv.x & 0xffff0000u) > 0.0f)) y[1] = 0.0f;
+                            if (!(__uint_as_float(gv.y << 16) > 0.0f)) y[2] = 0.0f;
+                            if (!(__uint_as_float(gv.y & 0xffff0000u) > 0.0f)) y[3] = 0.0f;
+                        }
+                        *(uint2 *)(a.out16 + v * 16 + 4 * kq) = make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
                     }
                 }
             }
-            if constexpr (GATE) load_slab(setc, k0, s + 4);
-        };
-        // frames in pairs (both register sets on every trip, so the compiler
-        // can count the loads in flight), then an odd last frame
-        int s = 0;
-        for (; s + 1 < nf; s += 2) {
-            step(std::integral_constant<int, 0>{}, s);
-            step(std::integral_constant<int, 1>{}, s + 1);
         }
-        if (s < nf) step(std::integral_constant<int, 0>{}, s);
-    }
+        prefetch();
+    }, [](int, int, int) {});
 }
 
 // x [B][nx][ny] fp32 -> channels-last bf16 with x in channel 0 and, when
@@ -396,12 +446,11 @@ __global__ __launch_bounds__(256) void k_pack_input(uint32_t V, const float *__r
 {
     const uint32_t v = blockIdx.x * 256u + threadIdx.x;
     if (v >= V) return;
-    uint16_t *o = a + (size_t)v * 16;
-    o[0] = to_bf16(x[v]);
-    o[1] = dual ? to_bf16(dual[v]) : (uint16_t)0;
-    o[2] = dual ? to_bf16(dual[V + v]) : (uint16_t)0;
-#pragma unroll
-    for (int c = 3; c < 16; ++c) o[c] = 0;
+    const uint32_t c0 = to_bf16(x[v]);
+    const uint32_t c1 = dual ? to_bf16(dual[v]) : 0u, c2 = dual ? to_bf16(dual[V + v]) : 0u;
+    uint4 *o = (uint4 *)(a + (size_t)v * 16);
+    o[0] = make_uint4(c0 | (c1 << 16), c2, 0u, 0u);
+    o[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Loss 1/(cout V) sum (y + base - target)^2 over the first cout channels
@@ -417,17 +466,18 @@ __global__ __launch_bounds__(256) void k_loss(uint32_t V, int cout, const float 
     const double scale = 2.0 / ((double)cout * (double)V);
     double acc = 0.0;
     for (uint32_t v = blockIdx.x * 256u + threadIdx.x; v < V; v += kRedBlocks * 256u) {
-        uint16_t *o = dy + (size_t)v * 16;
+        uint32_t w[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
         for (int c = 0; c < 16; ++c) {
-            float gval = 0.0f;
-            if (c < cout) {
-                const double b = base ? (double)base[(size_t)c * V + v] : 0.0;
-                const double d = ((double)y[(size_t)c * V + v] + b) - (double)target[(size_t)c * V + v];
-                acc += d * d;
-                gval = (float)(scale * d);
-            }
-            o[c] = to_bf16(gval);
+            if (c >= cout) break;
+            const double b = base ? (double)base[(size_t)c * V + v] : 0.0;
+            const double d = ((double)y[(size_t)c * V + v] + b) - (double)target[(size_t)c * V + v];
+            acc += d * d;
+            w[c >> 1] |= (uint32_t)to_bf16((float)(scale * d)) << (16 * (c & 1));
         }
+        uint4 *o = (uint4 *)(dy + (size_t)v * 16);
+        o[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        o[1] = make_uint4(w[4], w[5], w[6], w[7]);
     }
     lds[threadIdx.x] = acc;
     __syncthreads();
@@ -503,11 +553,9 @@ __global__ __launch_bounds__(256) void k_loss_theta_dy(int nx, int ny, int B, co
                 const float gc = g[v];
                 const float dh = j < ny - 1 ? g[v + 1] - gc : 0.0f;
                 const float dv = i < nx - 1 ? g[v + ny] - gc : 0.0f;
-                uint16_t *o = dy + (size_t)v * 16;
-                o[0] = to_bf16(scale * dh);
-                o[1] = to_bf16(scale * dv);
-#pragma unroll
-                for (int c = 2; c < 16; ++c) o[c] = 0;
+                uint4 *o = (uint4 *)(dy + (size_t)v * 16);
+                o[0] = make_uint4((uint32_t)to_bf16(scale * dh) | ((uint32_t)to_bf16(scale * dv) << 16), 0u, 0u, 0u);
+                o[1] = make_uint4(0u, 0u, 0u, 0u);
             }
 }
 
@@ -526,95 +574,156 @@ __global__ __launch_bounds__(256) void k_sum_part(int n, const double *__restric
 }
 
 // Weight gradient dW[t][n][c] = sum_v dy[v][n] in[nb(v, t)][c] and
-// dbias[n] = sum_v dy[v][n], as MFMAs with the voxels as K, over LDS blocks
-// (the block shape of the convolution).
-// A workgroup walks a fixed strided set of blocks; per block it stages the
-// input with its halo and dy channel-major ([channel][voxel], bf16) so that
-// the MFMA operands, whose K dimension runs over voxels, are runs of voxels
-// of one channel. Wavefront w accumulates slots w, w+4, ... (27 taps and the
-// bias) over 16-voxel chunks along j:
-//   A[n][v'] = dy[v0 + v'][n]   (8-byte LDS read per lane)
-//   B[v'][c] = in[nb(v0 + v', t)][c]   (four 2-byte LDS reads: a tap shifts
-//   the run by dj, which breaks the 8-byte alignment)
-// and writes its partial sums for the fixed-order reduction.
+// dbias[n] = sum_v dy[v][n] (slot 27, column 0). The contraction runs over
+// voxels, so both MFMA operands must hold runs of voxels of one channel,
+// while the activations and dy are channels-last. A block of 16 voxels x 16
+// channels is made channel-major by v_mfma_f32_16x16x16bf16_1k against the
+// identity (D = A I = A, exact in FP32, read out in the result layout: lane
+// (c, kq) holds channel c of voxels 4kq .. 4kq+3), and two such blocks form
+// the K = 32 operand of v_mfma_f32_16x16x32_bf16 (K slot 8kq + e is voxel
+// 4kq + e of the first block for e < 4, of the second for e >= 4; dy and the
+// input use the same order). The input slabs are staged by the convolution's
+// frame walk; the shift of tap (dk, di, dj) is the staged position a block is
+// read from, and one transposed block of staged row u serves the output rows
+// u - di. Each wavefront accumulates the 27 taps and the bias for its four
+// output rows over all its items; the four wavefronts then add their sums in
+// LDS in a fixed order and the workgroup writes one partial [28][16][16] for
+// the fixed-order reduction.
 constexpr int kWgBlocks = 512;
-constexpr int kTK = 4, kTI = 8, kTJ = 32;           // block of output voxels
-constexpr int kHK = kTK + 2, kHI = kTI + 2, kHJ = kTJ + 2; // with its halo
 
-__global__ __launch_bounds__(256) void k_wgrad_tile(Geom g, int ntj, int nti, int nblocks,
-                                                    const uint16_t *__restrict__ dy, const uint16_t *__restrict__ in,
-                                                    float *__restrict__ part)
+struct WgradArgs {
+    WalkGeom w;
+    SlabSrc src;
+    const uint16_t *dy;
+    float *part;
+};
+
+__global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
 {
-    constexpr int NH = kHK * kHI * kHJ, NB = kTK * kTI * kTJ;
-    __shared__ uint16_t xT[16][NH];
-    __shared__ uint16_t dT[16][NB];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    using St = SlabStage<CIN_BF16>;
+    static_assert(28 * 256 * sizeof(float) <= kRing * St::SLAB * sizeof(uint4), "the wavefront sums fit in the ring");
+    __shared__ uint4 ring[kRing * St::SLAB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
-    constexpr int kSlotsPerWave = 7; // 28 slots over 4 wavefronts
-    f32x4 acc[kSlotsPerWave];
+    const int nx = a.w.g.nx, ny = a.w.g.ny;
+
+    // B operand of the transposing MFMA: the identity, B[4kq + e][n = row]
+    bf16x4 ident;
 #pragma unroll
-    for (int q = 0; q < kSlotsPerWave; ++q) acc[q] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    for (int blk = (int)blockIdx.x; blk < nblocks; blk += (int)gridDim.x) {
-        const int bj = blk % ntj, bi = (blk / ntj) % nti, bk = blk / (ntj * nti);
-        const int k0 = bk * kTK, i0 = bi * kTI, j0 = bj * kTJ;
-        __syncthreads(); // the previous block's operands have been read
-        for (int e = threadIdx.x; e < NH; e += 256) {
-            const int jj = e % kHJ, ii = (e / kHJ) % kHI, kk = e / (kHJ * kHI);
-            const int k = k0 + kk - 1, i = i0 + ii - 1, j = j0 + jj - 1;
-            const bool ok = k >= 0 && k < g.B && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-            const uint16_t *src = in + (ok ? (((size_t)k * g.nx + i) * g.ny + j) * 16 : 0);
+    for (int e = 0; e < 4; ++e) ident[e] = 4 * kq + e == row ? (short)0x3f80 : (short)0;
+    // B operand of the bias: ones in column 0
+    bf16x8 ones0;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) xT[c][e] = ok ? src[c] : (uint16_t)0;
-        }
-        for (int e = threadIdx.x; e < NB; e += 256) {
-            const int jl = e % kTJ, il = (e / kTJ) % kTI, kl = e / (kTJ * kTI);
-            const int k = k0 + kl, i = i0 + il, j = j0 + jl;
-            const bool ok = k < g.B && i < g.nx && j < g.ny; // voxels outside the volume add nothing
-            const uint16_t *src = dy + (ok ? (((size_t)k * g.nx + i) * g.ny + j) * 16 : 0);
+    for (int e = 0; e < 8; ++e) ones0[e] = row == 0 ? (__bf16)1.0f : (__bf16)0.0f;
+
+    f32x4 acc[27], accb = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int n = 0; n < 16; ++n) dT[n][e] = ok ? src[n] : (uint16_t)0;
-        }
-        __syncthreads();
-        for (int ch = 0; ch < NB / 16; ++ch) {
-            const int kl = ch / (kTI * kTJ / 16), il = (ch / (kTJ / 16)) % kTI, jc = (ch % (kTJ / 16)) * 16;
-            const int vb = (kl * kTI + il) * kTJ + jc; // first voxel of the chunk in the block
-            const bf16x4 a = *(const bf16x4 *)(&dT[row][vb + 4 * kq]);
+    for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // two transposed 16-voxel blocks as one K = 32 operand
+    auto pair = [](f32x4 t0, f32x4 t1) {
+        return __builtin_bit_cast(bf16x8, make_uint4(pack2_bf16(t0[0], t0[1]), pack2_bf16(t0[2], t0[3]),
+                                                     pack2_bf16(t1[0], t1[1]), pack2_bf16(t1[2], t1[3])));
+    };
+    auto transpose = [&](uint2 x) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, x), ident,
+                                                         f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+    };
+
+    // dy of the wavefront's rows in frame k: lane (voxel row, kq) reads
+    // channels 4kq .. 4kq+3; frame k + 1 is read while frame k is computed
+    uint2 dyr[2][4][2];
+    auto load_dy = [&](auto setc, int i0, int j0, int k) {
+        constexpr int S = decltype(setc)::value;
+        const int kc = min(k, a.w.g.B - 1); // past the last frame: read, never used
 #pragma unroll
-            for (int q = 0; q < kSlotsPerWave; ++q) {
-                const int t = wv + 4 * q; // 0..27
-                bf16x4 b;
-                if (t == 27) {
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) b[e] = row == 0 ? (short)0x3f80 : (short)0; // bias: 1 in column 0
-                } else {
-                    const int dk = t / 9, di = (t / 3) % 3, dj = t % 3; // offsets into the haloed block
-                    const int hb = ((kl + dk) * kHI + (il + di)) * kHJ + jc + dj + 4 * kq;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) b[e] = (short)xT[row][hb + e];
-                }
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
+            for (int sg = 0; sg < 2; ++sg) {
+                const int i = i0 + kRowsPerWave * wv + r, j = j0 + 16 * sg + row;
+                const size_t v = ((size_t)kc * nx + i) * ny + j;
+                dyr[S][r][sg] = i < nx && j < ny ? *(const uint2 *)(a.dy + v * 16 + 4 * kq) : make_uint2(0u, 0u);
             }
+    };
+
+    SlabStage<CIN_BF16> st;
+    st.init(tid);
+    frame_walk<CIN_BF16>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
+        constexpr int S = decltype(setc)::value;
+        prefetch();
+        load_dy(std::integral_constant<int, 1 - S>{}, i0, j0, k + 1);
+        if (i0 + kRowsPerWave * wv >= nx) return; // uniform per wavefront: no rows here
+        bf16x8 ady[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            ady[r] = pair(transpose(dyr[S][r][0]), transpose(dyr[S][r][1]));
+            accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ady[r], ones0, accb, 0, 0, 0);
+        }
+#pragma unroll
+        for (int dk = 0; dk < 3; ++dk) {
+            const uint2 *sl = (const uint2 *)(ring + ((s + dk) & (kRing - 1)) * St::SLAB);
+#pragma unroll
+            for (int u = 0; u < kRowsPerWave + 2; ++u)
+#pragma unroll
+                for (int dj = 0; dj < 3; ++dj) {
+                    f32x4 tb[2];
+#pragma unroll
+                    for (int sg = 0; sg < 2; ++sg) {
+                        const int col = 16 * sg + row + dj;
+                        const int slot = St::chunk_slot((kRowsPerWave * wv + u) * kSJ + col, col, kq >> 1);
+                        tb[sg] = transpose(sl[2 * slot + (kq & 1)]);
+                    }
+                    const bf16x8 bx = pair(tb[0], tb[1]);
+#pragma unroll
+                    for (int di = 0; di < 3; ++di) {
+                        const int r = u - di;
+                        if (r < 0 || r >= kRowsPerWave) continue;
+                        f32x4 &c = acc[(dk * 3 + di) * 3 + dj];
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ady[r], bx, c, 0, 0, 0);
+                    }
+                }
+        }
+    }, [&](int i0, int j0, int k0) { load_dy(std::integral_constant<int, 0>{}, i0, j0, k0); });
+
+    // acc[t]: lane (c = row, kq) holds dW[t][4kq + e][c]; sum the wavefronts in LDS
+    float *red = (float *)ring;
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wv == w) {
+#pragma unroll
+            for (int t = 0; t < 28; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int idx = t * 256 + (4 * kq + e) * 16 + row;
+                    const float val = t < 27 ? acc[t < 27 ? t : 0][e] : accb[e];
+                    red[idx] = w == 0 ? val : red[idx] + val;
+                }
         }
     }
-    // acc[q]: column c = row, rows n = 4 kq + e
-    float *p = part + (size_t)blockIdx.x * 28 * 256;
-#pragma unroll
-    for (int q = 0; q < kSlotsPerWave; ++q) {
-        const int t = wv + 4 * q;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) p[(size_t)t * 256 + (4 * kq + e) * 16 + row] = acc[q][e];
-    }
+    __syncthreads();
+    float *p = a.part + (size_t)blockIdx.x * 28 * 256;
+    for (int idx = tid; idx < 28 * 256; idx += 256) p[idx] = red[idx];
 }
 
-// grad[t][n][c] = sum over groups in fixed order.
+// grad[t][n][c] = sum over groups in a fixed order: thread (entry, chunk)
+// adds groups chunk, chunk + 8, ... of one of the block's 32 entries, and the
+// eight chunk sums are added in order.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(int ngroups, const float *__restrict__ part,
                                                       float *__restrict__ grad)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x; // 28 * 256 entries
-    if (idx >= 28 * 256) return;
+    __shared__ float lds[8][32];
+    const int e = (int)threadIdx.x & 31, ch = (int)threadIdx.x >> 5;
+    const int idx = blockIdx.x * 32 + e; // of 28 * 256 entries
     float s = 0.0f;
-    for (int b = 0; b < ngroups; ++b) s += part[(size_t)b * 28 * 256 + idx];
-    grad[idx] = s;
+    for (int b = ch; b < ngroups; b += 8) s += part[(size_t)b * 28 * 256 + idx];
+    lds[ch][e] = s;
+    __syncthreads();
+    if (ch == 0) {
+        float t = lds[0][e];
+#pragma unroll
+        for (int c = 1; c < 8; ++c) t += lds[c][e];
+        grad[idx] = t;
+    }
 }
 
 // Adam on the fp32 master parameters of one layer in the padded layout
@@ -713,26 +822,33 @@ int device_cus()
 }
 
 // Work split: tiles of kCI x kCJ, each walked through runs of F frames; the
-// frames are cut into runs only when there are fewer tiles than resident
-// workgroups (conv_wgs_per_cu per CU). Persistent grid of at most that many
+// frames are cut into runs only when there are fewer tiles than the
+// resident workgroups (`slots`). Persistent grid of at most that many
 // workgroups, each taking every gridDim-th item.
-template <int CIN, int COUT, bool RELU, bool GATE>
-void launch_conv(ConvArgs a, hipStream_t s)
+WalkGeom walk_geom(int nx, int ny, int B, int slots)
 {
-    const int nti = (a.g.nx + kCI - 1) / kCI;
-    a.ntj = (a.g.ny + kCJ - 1) / kCJ;
-    a.ntiles = nti * a.ntj;
-    const int slots = conv_wgs_per_cu<CIN>() * device_cus();
-    const int runs = std::max(1, std::min(a.g.B, (slots + a.ntiles - 1) / a.ntiles));
-    a.F = (a.g.B + runs - 1) / runs;
-    a.nitems = a.ntiles * ((a.g.B + a.F - 1) / a.F);
-    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE>), dim3(std::min(a.nitems, slots)), dim3(256), 0, s, a);
+    WalkGeom w{};
+    w.g = geom(nx, ny, B);
+    const int nti = (nx + kCI - 1) / kCI;
+    w.ntj = (ny + kCJ - 1) / kCJ;
+    w.ntiles = nti * w.ntj;
+    const int runs = std::max(1, std::min(B, (slots + w.ntiles - 1) / w.ntiles));
+    w.F = (B + runs - 1) / runs;
+    w.nitems = w.ntiles * ((B + w.F - 1) / w.F);
+    return w;
 }
 
-ConvArgs conv_args(int nx, int ny, int B, const uint16_t *Wk, const float *bias)
+template <int CIN, int COUT, bool RELU, bool GATE>
+void launch_conv(ConvArgs a, int nx, int ny, int B, hipStream_t s)
+{
+    const int slots = conv_wgs_per_cu<CIN>() * device_cus();
+    a.w = walk_geom(nx, ny, B, slots);
+    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE>), dim3(std::min(a.w.nitems, slots)), dim3(256), 0, s, a);
+}
+
+ConvArgs conv_args(const uint16_t *Wk, const float *bias)
 {
     ConvArgs a{};
-    a.g = geom(nx, ny, B);
     a.Wk = Wk;
     a.bias = bias;
     return a;
@@ -743,47 +859,47 @@ ConvArgs conv_args(int nx, int ny, int B, const uint16_t *Wk, const float *bias)
 void wsnet_conv_input(int nx, int ny, int B, const float *x, const float *base, const uint16_t *Wk, const float *bias,
                       uint16_t *out16, hipStream_t s)
 {
-    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
+    ConvArgs a = conv_args(Wk, bias);
     const size_t V = (size_t)nx * ny * B;
-    a.x = x;
-    a.xb0 = base ? base : x;
-    a.xb1 = base ? base + V : x;
-    a.xb_live = base != nullptr;
+    a.src.x = x;
+    a.src.xb0 = base ? base : x;
+    a.src.xb1 = base ? base + V : x;
+    a.src.xb_live = base != nullptr;
     a.out16 = out16;
-    launch_conv<CIN_F32, COUT_BF16, true, false>(a, s);
+    launch_conv<CIN_F32, COUT_BF16, true, false>(a, nx, ny, B, s);
 }
 
 void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
                 const uint16_t *gate, uint16_t *out16, hipStream_t s)
 {
-    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
-    a.in = in;
+    ConvArgs a = conv_args(Wk, bias);
+    a.src.in = in;
     a.gate = gate;
     a.out16 = out16;
-    if (gate) launch_conv<CIN_BF16, COUT_BF16, false, true>(a, s);
-    else if (relu) launch_conv<CIN_BF16, COUT_BF16, true, false>(a, s);
-    else launch_conv<CIN_BF16, COUT_BF16, false, false>(a, s);
+    if (gate) launch_conv<CIN_BF16, COUT_BF16, false, true>(a, nx, ny, B, s);
+    else if (relu) launch_conv<CIN_BF16, COUT_BF16, true, false>(a, nx, ny, B, s);
+    else launch_conv<CIN_BF16, COUT_BF16, false, false>(a, nx, ny, B, s);
 }
 
 void wsnet_conv_out(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int cout,
                     float *y, hipStream_t s)
 {
-    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
-    a.in = in;
+    ConvArgs a = conv_args(Wk, bias);
+    a.src.in = in;
     a.out32 = y;
     a.cout = cout;
-    launch_conv<CIN_BF16, COUT_F32, false, false>(a, s);
+    launch_conv<CIN_BF16, COUT_F32, false, false>(a, nx, ny, B, s);
 }
 
 void wsnet_conv_dual(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int tv,
                      const float *base, float *dual, hipStream_t s)
 {
-    ConvArgs a = conv_args(nx, ny, B, Wk, bias);
-    a.in = in;
+    ConvArgs a = conv_args(Wk, bias);
+    a.src.in = in;
     a.out32 = dual;
     a.obase = base;
     a.tv = tv;
-    launch_conv<CIN_BF16, COUT_DUAL, false, false>(a, s);
+    launch_conv<CIN_BF16, COUT_DUAL, false, false>(a, nx, ny, B, s);
 }
 
 int wsnet_reduce_blocks() { return kRedBlocks; }
@@ -821,12 +937,16 @@ int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, c
 void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,
                  hipStream_t s)
 {
-    const Geom g = geom(nx, ny, B);
-    const int ntj = (ny + kTJ - 1) / kTJ, nti = (nx + kTI - 1) / kTI, ntk = (B + kTK - 1) / kTK;
-    const int nblocks = ntj * nti * ntk;
-    const int groups = nblocks < kWgBlocks ? nblocks : kWgBlocks;
-    hipLaunchKernelGGL(k_wgrad_tile, dim3(groups), dim3(256), 0, s, g, ntj, nti, nblocks, dy, in, part);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28), dim3(256), 0, s, groups, (const float *)part, grad);
+    // one workgroup per CU: the 27 tap accumulators take the AGPRs as well
+    const int slots = std::min(device_cus(), kWgBlocks);
+    WgradArgs a{};
+    a.w = walk_geom(nx, ny, B, slots);
+    a.src.in = in;
+    a.dy = dy;
+    a.part = part;
+    const int groups = std::min(a.w.nitems, slots);
+    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 256 / 32), dim3(256), 0, s, groups, (const float *)part, grad);
 }
 
 void wsnet_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1, float c2, const float *grad,
