@@ -65,7 +65,10 @@ template <int M, int C> struct alignas(16) RowRing {
 // CH_STEP = 1 replaces the projection of q by Chambolle's (2004) semi-implicit step
 // p = (w + z/(8 lambda)) / (1 + |z/(8 lambda)|), |.| per component (ATV) or
 // per voxel (ITV2D), with the operations of the streaming pass.
-template <int TV, int M, int DT, int C, int MODE, int CH_STEP = 0>
+// MOM = 0 (no momentum: every beta of the pass is 0, MODE < 2, no p_prev
+// output) takes w = p at every level; the extrapolation and the previous
+// duals it would read drop out, with identical results.
+template <int TV, int M, int DT, int C, int MODE, int CH_STEP = 0, int MOM = 1>
 __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, int H, uint32_t fo, uint32_t V,
                                               const float *__restrict__ x,
                                               const typename Dual<DT>::T *__restrict__ pc,
@@ -245,8 +248,13 @@ __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, i
                             nv[c] = qv * sc;
                         }
                     }
-                    oh[c] = extrapolate(nh[c], cph[t][c], bnext);
-                    ov[c] = extrapolate(nv[c], cpv[t][c], bnext);
+                    if (MOM) {
+                        oh[c] = extrapolate(nh[c], cph[t][c], bnext);
+                        ov[c] = extrapolate(nv[c], cpv[t][c], bnext);
+                    } else {
+                        oh[c] = nh[c];
+                        ov[c] = nv[c];
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
@@ -288,7 +296,7 @@ __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, i
                         D::st(pn_out, o, jh[c]);
                         D::st(pn_out, V + o, jv[c]);
                     }
-                    if (pp_out) {
+                    if (MOM && pp_out) {
                         D::st(pp_out, o, qph[c]);
                         D::st(pp_out, V + o, qpv[c]);
                     }
@@ -302,7 +310,7 @@ __device__ __forceinline__ void fgp_rows_body(int nx, int ny, int sx, int seg, i
 
 // One pass over every frame: a one-wavefront workgroup per (frame, segment,
 // strip), numbered XCD-contiguously.
-template <int TV, int M, int DT, int C, int MODE, int CH_STEP>
+template <int TV, int M, int DT, int C, int MODE, int CH_STEP, int MOM>
 __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, int nseg, int H,
                                                     const float *__restrict__ x,
                                                     const typename Dual<DT>::T *__restrict__ pc,
@@ -316,13 +324,14 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
     const int per_frame = nstrip * nseg;
     const int frame = lin / per_frame, rem = lin % per_frame;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    fgp_rows_body<TV, M, DT, C, MODE, CH_STEP>(nx, ny, rem % nstrip, rem / nstrip, H, (uint32_t)frame * plane,
+    fgp_rows_body<TV, M, DT, C, MODE, CH_STEP, MOM>(nx, ny, rem % nstrip, rem / nstrip, H, (uint32_t)frame * plane,
                                       plane * (gridDim.x / (uint32_t)per_frame), x, pc, pp, bt, lam, step, pn_out,
                                       pp_out, theta_out, u_out, ring);
 }
 
 // Launch of one pass over every frame: strips of 64*C - 2M - 1 interior
-// columns, segments of H rows.
+// columns, segments of H rows. The Chambolle-2004 step without momentum
+// runs the MOM = 0 instantiation.
 template <int TV, int M, int DT, int C, int CH_STEP>
 void launch_rows_m(int H, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s)
 {
@@ -331,12 +340,18 @@ void launch_rows_m(int H, int nx, int ny, int B, const float *x, const TilePass 
     const int nstrip = (ny + TXO - 1) / TXO, nseg = (nx + H - 1) / H;
     const dim3 g(nstrip * nseg * B), b(64);
     const float step = 1.0f / (8.0f * lam);
-#define SCI_ROWS_MODE(md)                                                                                           \
-    hipLaunchKernelGGL((k_fgp_rows<TV, M, DT, C, md, CH_STEP>), g, b, 0, s, nx, ny, nstrip, nseg, H, x, (const T *)tp.pc,     \
-                       (const T *)tp.pp, tp.beta, lam, step, (T *)tp.pn_out, (T *)tp.pp_out, tp.theta, tp.u_out)
-    if (tp.mode == 0) SCI_ROWS_MODE(0);
-    else if (tp.mode == 1) SCI_ROWS_MODE(1);
-    else SCI_ROWS_MODE(2);
+    bool mom = tp.mode == 2 || tp.pp_out != nullptr;
+    for (int t = 1; t <= M; ++t) mom = mom || tp.beta.b[t] != 0.0f;
+#define SCI_ROWS_MODE(md, mo)                                                                                       \
+    hipLaunchKernelGGL((k_fgp_rows<TV, M, DT, C, md, CH_STEP, mo>), g, b, 0, s, nx, ny, nstrip, nseg, H, x,          \
+                       (const T *)tp.pc, (const T *)tp.pp, tp.beta, lam, step, (T *)tp.pn_out, (T *)tp.pp_out,      \
+                       tp.theta, tp.u_out)
+    if (CH_STEP && !mom) {
+        if (tp.mode == 0) SCI_ROWS_MODE(0, 0);
+        else SCI_ROWS_MODE(1, 0);
+    } else if (tp.mode == 0) SCI_ROWS_MODE(0, 1);
+    else if (tp.mode == 1) SCI_ROWS_MODE(1, 1);
+    else SCI_ROWS_MODE(2, 1);
 #undef SCI_ROWS_MODE
 }
 
