@@ -49,22 +49,23 @@ struct Geom {
 //
 // out[v][n] = sum_t sum_c Wk[t][n][c] in[nb(v, t)][c] + bias[n] over the
 // volume, zero outside it ("same" padding). A workgroup owns a tile of
-// kCI rows x kCJ columns and walks it through a run of frames; for output
-// frame k it needs the input slabs (tile plus one-voxel halo) of frames
-// k-1, k, k+1. Slabs sit in a ring of four in LDS: while frame k is computed
-// from three of them, the fourth is free, and the global loads of the slab
-// two frames ahead are in flight in registers. One barrier per frame.
+// 4 x (wavefronts) rows x kCJ columns and walks it through a run of frames;
+// for output frame k it needs the input slabs (tile plus one-voxel halo) of
+// frames k-1, k, k+1, held in a ring in LDS while the global loads of the
+// slab two frames ahead are in flight in registers (WalkShape).
 //
 // MFMA mapping (v_mfma_f32_16x16x32_bf16: A 16x32, B 32x16; lane l holds A
 // row l%16 and B column l%16 with K = 8 (l/16) .. +7, and the result column
-// l%16, rows 4 (l/16) .. +3). A row is an output voxel (16 consecutive
-// columns of one output row), a result column an output channel. The K = 32
-// of one instruction covers either two taps x 16 input channels or, for an
-// input with at most 8 channels, four taps x 8 channels; taps are grouped by
-// their (frame, column) offset (dk, dj), nine of them, so one operand read
-// from staged row s serves output rows s, s-1, s-2 (di = 0, 1, 2) with the
-// weights of (dk, di, dj): each wavefront computes four consecutive output
-// rows from six staged rows and reads every operand once.
+// l%16, rows 4 (l/16) .. +3). The weights are A (a row is an output
+// channel), the staged input B (a column is an output voxel, one of 16
+// consecutive columns of an output row), so a lane's result is four output
+// channels of one voxel. The K = 32 of one instruction covers either two
+// taps x 16 input channels or, for an input with at most 8 channels, four
+// taps x 8 channels; taps are grouped by their (frame, column) offset
+// (dk, dj), nine of them, so one operand read from staged row s serves output
+// rows s, s-1, s-2 (di = 0, 1, 2) with the weights of (dk, di, dj): each
+// wavefront computes four consecutive output rows from six staged rows and
+// reads every operand once.
 //
 // The nine (dk, dj) offsets fill 5 (or 3) MFMAs with one (or three) K slots
 // to spare; lanes of a spare slot read the last offset's data again and meet
@@ -78,14 +79,23 @@ struct Geom {
 // columns, or eight threads writing both chunks of four consecutive voxels,
 // touch 32 distinct banks. An input with at most 8 channels stages one chunk
 // per voxel, at slot v.
-constexpr int kCI = 16, kCJ = 32;                     // output tile
-constexpr int kSI = kCI + 2, kSJ = kCJ + 2;           // staged slab
-constexpr int kSlabVox = kSI * kSJ;                   // 612 voxels
-constexpr int kSlabChunks = 2 * kSlabVox;             // 1224 chunks, 19584 bytes
-constexpr int kRing = 4;
-constexpr int kChunkLoads = (kSlabChunks + 255) / 256; // per thread and slab, bf16 input
-constexpr int kVoxLoads = (kSlabVox + 255) / 256;      // per thread and slab, fp32 input
-constexpr int kRowsPerWave = kCI / 4;                  // 4 wavefronts
+constexpr int kRowsPerWave = 4, kCJ = 32;             // output rows per wavefront, tile columns
+constexpr int kSJ = kCJ + 2;                          // staged slab columns
+
+// Tile, slab and pipelining of a frame walk by workgroups of NW wavefronts:
+// NW * 4 output rows per tile. With several wavefronts the ring holds four
+// slabs (the one written at a step start was last read two steps before, and
+// the step's barrier orders that read before the write) and two register
+// sets of slabs are in flight; a lone wavefront reads and writes its LDS in
+// program order, so three slabs and one register set suffice.
+template <int NW> struct WalkShape {
+    static constexpr int NT = 64 * NW;
+    static constexpr int CI = kRowsPerWave * NW;
+    static constexpr int VOX = (CI + 2) * kSJ; // staged voxels per slab
+    static constexpr int RING = NW == 1 ? 3 : 4;
+    static constexpr int SETS = NW == 1 ? 1 : 2;
+    __device__ static int slot(int r) { return RING == 4 ? (r & 3) : (r % 3); }
+};
 
 static_assert(kCJ == 32 && kRowsPerWave == 4, "the compute loop is written for 4 rows x 2 tiles per wavefront");
 
@@ -130,11 +140,12 @@ __device__ inline uint32_t pack2_bf16(float lo, float hi)
 // Staging of input slabs (tile plus halo, one frame) through registers into
 // the LDS ring. Each thread owns NL fixed slots of a slab; two register sets
 // hold the slabs in flight.
-template <int CIN> struct SlabStage {
-    static constexpr int CPT = CIN == CIN_F32 ? 1 : 2;                  // 16-byte chunks per staged voxel
-    static constexpr int NL = CIN == CIN_F32 ? kVoxLoads : kChunkLoads; // slots per thread
-    static constexpr int SLAB = CPT == 1 ? kSlabVox : kSlabChunks;      // 16-byte slots per slab
-    static constexpr int NSLOT = CPT == 1 ? kSlabVox : kSlabChunks;     // live slots per slab
+template <int CIN, int NW> struct SlabStage {
+    using W = WalkShape<NW>;
+    static constexpr int CPT = CIN == CIN_F32 ? 1 : 2;  // 16-byte chunks per staged voxel
+    static constexpr int SLAB = CPT * W::VOX;           // 16-byte slots per slab
+    static constexpr int NL = (SLAB + W::NT - 1) / W::NT; // slots per thread
+    static constexpr int S = W::SETS;
 
     // LDS slot of chunk h of staged voxel v (slab column sj): one chunk per
     // voxel when only channels 0-7 are staged, else two, swizzled
@@ -143,11 +154,11 @@ template <int CIN> struct SlabStage {
     int pslot[NL];
     uint32_t poff[NL];
     uint32_t pok;
-    uint4 pre[2][CIN == CIN_F32 ? 1 : NL];
-    float px[2][CIN == CIN_F32 ? NL : 1], pb0[2][CIN == CIN_F32 ? NL : 1], pb1[2][CIN == CIN_F32 ? NL : 1];
-    bool fval[2];
+    uint4 pre[S][CIN == CIN_F32 ? 1 : NL];
+    float px[S][CIN == CIN_F32 ? NL : 1], pb0[S][CIN == CIN_F32 ? NL : 1], pb1[S][CIN == CIN_F32 ? NL : 1];
+    bool fval[S];
 
-    __device__ static bool live(int tid, int q) { return q < NL - 1 || tid + 256 * q < NSLOT; }
+    __device__ static bool live(int tid, int q) { return q < NL - 1 || tid + W::NT * q < SLAB; }
     __device__ static void split(int e, int &v, int &hh)
     {
         v = CIN == CIN_F32 ? e : (e >> 1);
@@ -159,10 +170,11 @@ template <int CIN> struct SlabStage {
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             int v, hh;
-            split(tid + 256 * q, v, hh);
+            split(tid + W::NT * q, v, hh);
             pslot[q] = chunk_slot(v, v % kSJ, hh);
         }
-        fval[0] = fval[1] = false;
+#pragma unroll
+        for (int k = 0; k < S; ++k) fval[k] = false;
     }
     // source offsets within a frame for the tile at (i0, j0); zero outside the frame
     __device__ void begin(int tid, int i0, int j0, int nx, int ny)
@@ -171,7 +183,7 @@ template <int CIN> struct SlabStage {
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             int v, hh;
-            split(tid + 256 * q, v, hh);
+            split(tid + W::NT * q, v, hh);
             const int i = i0 - 1 + v / kSJ, j = j0 - 1 + v % kSJ;
             const bool ok = live(tid, q) && i >= 0 && i < nx && j >= 0 && j < ny;
             poff[q] = ok ? (CIN == CIN_F32 ? (uint32_t)(i * ny + j) : (uint32_t)(i * ny + j) * 16u + 8u * hh) : 0u;
@@ -182,36 +194,36 @@ template <int CIN> struct SlabStage {
     // the nearest frame, dead slots read offset 0) and the zeros are applied
     // when the slab is stored: with a fixed count of loads per slab, the wait
     // for one slab's data lets the next slab's loads stay in flight.
-    template <int S> __device__ void load(const SlabSrc &src, const Geom &g, int f)
+    template <int K> __device__ void load(const SlabSrc &src, const Geom &g, int f)
     {
-        fval[S] = f >= 0 && f < g.B;
+        fval[K] = f >= 0 && f < g.B;
         const int fc = min(max(f, 0), g.B - 1);
         const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
         if constexpr (CIN == CIN_F32) {
             const size_t fb = (size_t)fc * plane;
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
-                px[S][q] = src.x[fb + poff[q]];
-                pb0[S][q] = src.xb0[fb + poff[q]];
-                pb1[S][q] = src.xb1[fb + poff[q]];
+                px[K][q] = src.x[fb + poff[q]];
+                pb0[K][q] = src.xb0[fb + poff[q]];
+                pb1[K][q] = src.xb1[fb + poff[q]];
             }
         } else {
             const uint16_t *p = src.in + (size_t)fc * plane * 16;
 #pragma unroll
-            for (int q = 0; q < NL; ++q) pre[S][q] = *(const uint4 *)(p + poff[q]);
+            for (int q = 0; q < NL; ++q) pre[K][q] = *(const uint4 *)(p + poff[q]);
         }
     }
-    template <int S> __device__ void store(const SlabSrc &src, uint4 *slab, int tid)
+    template <int K> __device__ void store(const SlabSrc &src, uint4 *slab, int tid)
     {
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             if (!live(tid, q)) continue;
-            const bool ok = fval[S] && ((pok >> q) & 1u);
+            const bool ok = fval[K] && ((pok >> q) & 1u);
             uint4 val;
             if constexpr (CIN == CIN_F32)
-                val = src.xb_live ? make_uint4(pack2_bf16(px[S][q], pb0[S][q]), pack2_bf16(pb1[S][q], 0.0f), 0u, 0u)
-                                  : make_uint4(pack2_bf16(px[S][q], 0.0f), 0u, 0u, 0u);
-            else val = pre[S][q];
+                val = src.xb_live ? make_uint4(pack2_bf16(px[K][q], pb0[K][q]), pack2_bf16(pb1[K][q], 0.0f), 0u, 0u)
+                                  : make_uint4(pack2_bf16(px[K][q], 0.0f), 0u, 0u, 0u);
+            else val = pre[K][q];
             slab[pslot[q]] = ok ? val : make_uint4(0u, 0u, 0u, 0u);
         }
     }
@@ -220,59 +232,80 @@ template <int CIN> struct SlabStage {
 // The frame walk: this workgroup's items (tile, run of frames), every
 // gridDim-th item after an XCD-contiguous renumbering. For output frame k0 + s
 // of an item, slabs r = s, s+1, s+2 (frames k0-1+r) are in LDS ring slots
-// r mod 4; step(setc, s, i0, j0, k, prefetch) computes it and must call
-// prefetch() exactly once (uniformly), which issues the loads of slab s + 4.
+// W::slot(r); step(setc, s, i0, j0, k, prefetch) computes it and must call
+// prefetch() exactly once (uniformly), which issues the loads of slab
+// s + 2 + SETS into the register set the step's store has just emptied.
 // begin(i0, j0, k0) runs once per item, after the first slabs are requested.
-template <int CIN, typename Step, typename Begin>
-__device__ __forceinline__ void frame_walk(const WalkGeom &w, const SlabSrc &src, uint4 *ring, SlabStage<CIN> &st,
-                                           Step &&step, Begin &&begin)
+template <int CIN, int NW, typename Step, typename Begin>
+__device__ __forceinline__ void frame_walk(const WalkGeom &w, const SlabSrc &src, uint4 *ring,
+                                           SlabStage<CIN, NW> &st, Step &&step, Begin &&begin)
 {
-    using St = SlabStage<CIN>;
+    using St = SlabStage<CIN, NW>;
+    using W = WalkShape<NW>;
     const int tid = threadIdx.x, nwg = (int)gridDim.x;
-    auto slab = [&](int r) { return ring + (r & (kRing - 1)) * St::SLAB; };
+    auto slab = [&](int r) { return ring + W::slot(r) * St::SLAB; };
     for (int it = xcd_contiguous((int)blockIdx.x, nwg); it < w.nitems; it += nwg) {
         const int run = it / w.ntiles, tile = it % w.ntiles;
-        const int i0 = (tile / w.ntj) * kCI, j0 = (tile % w.ntj) * kCJ, k0 = run * w.F;
+        const int i0 = (tile / w.ntj) * W::CI, j0 = (tile % w.ntj) * kCJ, k0 = run * w.F;
         const int nf = min(w.F, w.g.B - k0);
         st.begin(tid, i0, j0, w.g.nx, w.g.ny);
         __syncthreads(); // every wavefront is done with the previous item's slabs
-        st.template load<0>(src, w.g, k0 - 1);
-        st.template load<1>(src, w.g, k0);
-        st.template store<0>(src, slab(0), tid);
-        st.template store<1>(src, slab(1), tid);
-        st.template load<0>(src, w.g, k0 + 1);
-        st.template load<1>(src, w.g, k0 + 2);
+        if constexpr (W::SETS == 2) {
+            st.template load<0>(src, w.g, k0 - 1);
+            st.template load<1>(src, w.g, k0);
+            st.template store<0>(src, slab(0), tid);
+            st.template store<1>(src, slab(1), tid);
+            st.template load<0>(src, w.g, k0 + 1);
+            st.template load<1>(src, w.g, k0 + 2);
+        } else {
+            st.template load<0>(src, w.g, k0 - 1);
+            st.template store<0>(src, slab(0), tid);
+            st.template load<0>(src, w.g, k0);
+            st.template store<0>(src, slab(1), tid);
+            st.template load<0>(src, w.g, k0 + 1);
+        }
         begin(i0, j0, k0);
         auto one = [&](auto setc, int s) {
-            constexpr int S = decltype(setc)::value;
-            st.template store<S>(src, slab(s + 2), tid);
+            constexpr int K = decltype(setc)::value;
+            st.template store<K>(src, slab(s + 2), tid);
             __syncthreads();
             // past the run's last slab: loaded, never stored
-            auto prefetch = [&] { st.template load<S>(src, w.g, k0 + s + 3); };
+            auto prefetch = [&] { st.template load<K>(src, w.g, k0 + s + 1 + W::SETS); };
             step(setc, s, i0, j0, k0 + s, prefetch);
         };
-        // frames in pairs (both register sets on every trip, so the compiler
-        // can count the loads in flight), then an odd last frame
         int s = 0;
-        for (; s + 1 < nf; s += 2) {
-            one(std::integral_constant<int, 0>{}, s);
-            one(std::integral_constant<int, 1>{}, s + 1);
+        if constexpr (W::SETS == 2) {
+            // frames in pairs (both register sets on every trip, so the
+            // compiler can count the loads in flight), then an odd last frame
+            for (; s + 1 < nf; s += 2) {
+                one(std::integral_constant<int, 0>{}, s);
+                one(std::integral_constant<int, 1>{}, s + 1);
+            }
+            if (s < nf) one(std::integral_constant<int, 0>{}, s);
+        } else {
+            for (; s < nf; ++s) one(std::integral_constant<int, 0>{}, s);
         }
-        if (s < nf) one(std::integral_constant<int, 0>{}, s);
     }
 }
 
-// Workgroups per CU: LDS holds two rings of 16-channel slabs, three of 8-channel ones.
-template <int CIN> constexpr int conv_wgs_per_cu() { return CIN == CIN_F32 ? 3 : 2; }
+// The convolutions run 4-wavefront workgroups, two wavefronts per SIMD (the
+// LDS of two 16-channel rings per CU; registers), three for the 8-channel
+// first layer. (One-wavefront workgroups, eight per CU with a 3-slab ring
+// each and no barrier, measured no faster: 350-475 against 340-470 us for a
+// hidden layer at 1024x1024x24, and the first layer 15-25 % slower.)
+constexpr int kConvNW = 4;
+template <int CIN> constexpr int conv_waves_per_simd() { return CIN == CIN_F32 ? 3 : 2; }
+template <int CIN> constexpr int conv_wgs_per_cu() { return conv_waves_per_simd<CIN>() * 4 / kConvNW; }
 
 template <int CIN, int COUT, bool RELU, bool GATE>
-__global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const ConvArgs a)
+__global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_conv(const ConvArgs a)
 {
-    using St = SlabStage<CIN>;
+    using St = SlabStage<CIN, kConvNW>;
+    using W = WalkShape<kConvNW>;
     constexpr int CPT = St::CPT;                  // chunks of a tap in one MFMA operand
     constexpr int TPM = 4 / CPT;                  // (dk, dj) offsets per MFMA
     constexpr int G = (9 + TPM - 1) / TPM;        // MFMAs per (staged row, di)
-    __shared__ uint4 ring[kRing * St::SLAB];
+    __shared__ uint4 ring[W::RING * St::SLAB];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
@@ -303,11 +336,14 @@ __global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const Conv
 #pragma unroll
     for (int e = 0; e < 4; ++e) bn[e] = a.bias ? a.bias[4 * kq + e] : 0.0f;
 
-    SlabStage<CIN> st;
+    St st;
     st.init(tid);
-    frame_walk<CIN>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
+    frame_walk<CIN, kConvNW>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
         (void)setc;
         const bool rows_live = i0 + kRowsPerWave * wv < nx; // uniform per wavefront
+        // With one register set the loads of the slab two frames ahead go out
+        // first: they have this step's compute to arrive.
+        if constexpr (W::SETS == 1) prefetch();
         // Vector memory operations complete in issue order, and the
         // epilogue's stores are conditional, so the compiler cannot count
         // them: the prefetch is issued after the epilogue, and the wait for
@@ -347,7 +383,7 @@ __global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const Conv
                 for (int tt = 0; tt < 2; ++tt) acc[r][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
             const uint4 *slab[G];
 #pragma unroll
-            for (int gi = 0; gi < G; ++gi) slab[gi] = ring + ((s + cdk[gi]) & (kRing - 1)) * St::SLAB;
+            for (int gi = 0; gi < G; ++gi) slab[gi] = ring + W::slot(s + cdk[gi]) * St::SLAB;
             // (staged row u, group gi) in sequence; the operands of the
             // entry two ahead are read while the current one's MFMAs run
             constexpr int NP = (kRowsPerWave + 2) * G;
@@ -435,7 +471,7 @@ __global__ __launch_bounds__(256, conv_wgs_per_cu<CIN>()) void k_conv(const Conv
                 }
             }
         }
-        prefetch();
+        if constexpr (W::SETS == 2) prefetch();
     }, [](int, int, int) {});
 }
 
@@ -600,9 +636,10 @@ struct WgradArgs {
 
 __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
 {
-    using St = SlabStage<CIN_BF16>;
-    static_assert(28 * 256 * sizeof(float) <= kRing * St::SLAB * sizeof(uint4), "the wavefront sums fit in the ring");
-    __shared__ uint4 ring[kRing * St::SLAB];
+    using St = SlabStage<CIN_BF16, 4>;
+    using W = WalkShape<4>;
+    static_assert(28 * 256 * sizeof(float) <= W::RING * St::SLAB * sizeof(uint4), "the wavefront sums fit in the ring");
+    __shared__ uint4 ring[W::RING * St::SLAB];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int nx = a.w.g.nx, ny = a.w.g.ny;
@@ -646,9 +683,9 @@ __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
             }
     };
 
-    SlabStage<CIN_BF16> st;
+    St st;
     st.init(tid);
-    frame_walk<CIN_BF16>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
+    frame_walk<CIN_BF16, 4>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
         constexpr int S = decltype(setc)::value;
         prefetch();
         load_dy(std::integral_constant<int, 1 - S>{}, i0, j0, k + 1);
@@ -661,7 +698,7 @@ __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
         }
 #pragma unroll
         for (int dk = 0; dk < 3; ++dk) {
-            const uint2 *sl = (const uint2 *)(ring + ((s + dk) & (kRing - 1)) * St::SLAB);
+            const uint2 *sl = (const uint2 *)(ring + W::slot(s + dk) * St::SLAB);
 #pragma unroll
             for (int u = 0; u < kRowsPerWave + 2; ++u)
 #pragma unroll
@@ -821,15 +858,15 @@ int device_cus()
     return ncu;
 }
 
-// Work split: tiles of kCI x kCJ, each walked through runs of F frames; the
+// Work split: tiles of ci x kCJ, each walked through runs of F frames; the
 // frames are cut into runs only when there are fewer tiles than the
 // resident workgroups (`slots`). Persistent grid of at most that many
 // workgroups, each taking every gridDim-th item.
-WalkGeom walk_geom(int nx, int ny, int B, int slots)
+WalkGeom walk_geom(int nx, int ny, int B, int slots, int ci)
 {
     WalkGeom w{};
     w.g = geom(nx, ny, B);
-    const int nti = (nx + kCI - 1) / kCI;
+    const int nti = (nx + ci - 1) / ci;
     w.ntj = (ny + kCJ - 1) / kCJ;
     w.ntiles = nti * w.ntj;
     const int runs = std::max(1, std::min(B, (slots + w.ntiles - 1) / w.ntiles));
@@ -842,8 +879,9 @@ template <int CIN, int COUT, bool RELU, bool GATE>
 void launch_conv(ConvArgs a, int nx, int ny, int B, hipStream_t s)
 {
     const int slots = conv_wgs_per_cu<CIN>() * device_cus();
-    a.w = walk_geom(nx, ny, B, slots);
-    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE>), dim3(std::min(a.w.nitems, slots)), dim3(256), 0, s, a);
+    a.w = walk_geom(nx, ny, B, slots, WalkShape<kConvNW>::CI);
+    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE>), dim3(std::min(a.w.nitems, slots)), dim3(64 * kConvNW), 0, s,
+                       a);
 }
 
 ConvArgs conv_args(const uint16_t *Wk, const float *bias)
@@ -940,7 +978,7 @@ void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, 
     // one workgroup per CU: the 27 tap accumulators take the AGPRs as well
     const int slots = std::min(device_cus(), kWgBlocks);
     WgradArgs a{};
-    a.w = walk_geom(nx, ny, B, slots);
+    a.w = walk_geom(nx, ny, B, slots, WalkShape<4>::CI);
     a.src.in = in;
     a.dy = dy;
     a.part = part;
