@@ -59,6 +59,13 @@ template <int M, int C> struct alignas(16) RowRing {
     float v[2 * (M + kRowChunk)][64 * C];
 };
 
+// The ring padded to 1/8 of a CU's 160 KB of LDS.
+template <int M, int C> struct alignas(16) RowRingPadded {
+    static constexpr size_t kEighth = 160 * 1024 / 8;
+    RowRing<M, C> ring;
+    char pad[sizeof(RowRing<M, C>) < kEighth ? kEighth - sizeof(RowRing<M, C>) : 16];
+};
+
 // One wavefront's segment: strip sx, segment seg (rows [seg*H, seg*H + H)) of
 // the frame at element offset fo; V = elements per dual channel of the whole
 // video. MODE: 0 w = 0; 1 w = p^(s0); 2 w = p^(s0) + b[0] (p^(s0) - p^(s0-1)).
@@ -319,14 +326,30 @@ __global__ __launch_bounds__(64, 2) void k_fgp_rows(int nx, int ny, int nstrip, 
                                                     typename Dual<DT>::T *__restrict__ pp_out,
                                                     float *__restrict__ theta_out, float *__restrict__ u_out)
 {
-    __shared__ RowRing<M, C> ring;
     const int lin = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
     const int per_frame = nstrip * nseg;
     const int frame = lin / per_frame, rem = lin % per_frame;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    fgp_rows_body<TV, M, DT, C, MODE, CH_STEP, MOM>(nx, ny, rem % nstrip, rem / nstrip, H, (uint32_t)frame * plane,
-                                      plane * (gridDim.x / (uint32_t)per_frame), x, pc, pp, bt, lam, step, pn_out,
-                                      pp_out, theta_out, u_out, ring);
+    auto body = [&](RowRing<M, C> &ring) {
+        fgp_rows_body<TV, M, DT, C, MODE, CH_STEP, MOM>(nx, ny, rem % nstrip, rem / nstrip, H,
+                                                        (uint32_t)frame * plane,
+                                                        plane * (gridDim.x / (uint32_t)per_frame), x, pc, pp, bt, lam,
+                                                        step, pn_out, pp_out, theta_out, u_out, ring);
+    };
+    if constexpr (MOM) {
+        __shared__ RowRing<M, C> ring;
+        body(ring);
+    } else {
+        // The momentum-free kernel needs few enough registers for three
+        // wavefronts per SIMD; its one-wavefront workgroups then spread
+        // unevenly over the SIMDs (some run three: 309 against 238 us for a
+        // 10-iteration ITV2D pass at 1024x1024x24 inside GAP), so its LDS is
+        // padded to admit at most eight workgroups (two wavefronts per SIMD)
+        // per CU. The asm keeps the unused padding allocated.
+        __shared__ RowRingPadded<M, C> lds;
+        asm volatile("; lds padding %0" ::"v"((uint32_t)(size_t)&lds.pad[0]));
+        body(lds.ring);
+    }
 }
 
 // Launch of one pass over every frame: strips of 64*C - 2M - 1 interior
