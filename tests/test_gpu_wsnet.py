@@ -171,6 +171,36 @@ def test_gradients_frame_walk_match_oracle(sc, ctx, rnet):
         assert e <= 5e-3
 
 
+@pytest.mark.parametrize("c_out", [1, 5, 16])
+def test_wide_output_forward_and_gradients_match_oracle(sc, ctx, c_out):
+    """c_in = 1 networks with 1, 5 or 16 output channels: the raw output
+    planes (every output-channel group of the last layer's result) and all
+    gradients against the FP64 oracle."""
+    from paper_2005_08028_amd import warmstart
+    n = sc.sci_wsnet_create(ctx, c_in=1, c_out=c_out)
+    try:
+        P = warmstart.init_params(40 + c_out, c_out=c_out, last_scale=1.0)
+        sc.sci_wsnet_set_params(ctx, n, P)
+        r = np.random.default_rng(c_out)
+        B, nx, ny = 3, 21, 45
+        x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+        raw, _ = sc.sci_wsnet_forward(ctx, n, dev(x), want_raw=True, want_dual=False, c_out=c_out)
+        _, y = wo.forward(x, P, c_out=c_out)
+        e = rel(host(raw), y)
+        t = r.normal(scale=0.5, size=(c_out, B, nx, ny)).astype(np.float32)
+        loss, g = sc.sci_wsnet_grads(ctx, n, dev(x), dev(t))
+        lo, go = wo.loss_and_grads(x, t, P, c_out=c_out)
+        G, GO = g.reshape(4, 28, 16, 16), go.reshape(4, 28, 16, 16)
+        eg = [rel(G[l], GO[l]) for l in range(4)]
+        print(f"c_out {c_out}: forward rel-L2 {e:.2e}, loss {loss:.6e} (oracle {lo:.6e}), gradients "
+              + " ".join(f"{v:.2e}" for v in eg), flush=True)
+        assert e <= 1e-3
+        assert abs(loss - lo) <= 1e-4 * lo
+        assert max(eg) <= 5e-3
+    finally:
+        sc.sci_wsnet_destroy(n)
+
+
 def test_residual_zero_net_is_the_base(sc, ctx, rnet):
     """A freshly created network has zero weights: its projected prediction is
     the projected base dual, exactly."""
