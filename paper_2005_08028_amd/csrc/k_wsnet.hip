@@ -393,6 +393,9 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) b[tt] = __builtin_bit_cast(bf16x8, slab[gi][coff[gi][tt] + u * CPT * kSJ]);
             };
+            // interleave the LDS reads with the MFMAs (the compiler's
+            // small-GEMM schedule; the 8-channel first layer would spill)
+            if constexpr (CPT == 2) __builtin_amdgcn_iglp_opt(0);
             rd(0, X[0]);
             rd(1, X[1]);
 #pragma unroll
