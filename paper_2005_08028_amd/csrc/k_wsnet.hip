@@ -88,9 +88,9 @@ constexpr int kSJ = kCJ + 2;                          // staged slab columns
 // the step's barrier orders that read before the write) and two register
 // sets of slabs are in flight; a lone wavefront reads and writes its LDS in
 // program order, so three slabs and one register set suffice.
-template <int NW> struct WalkShape {
+template <int NW, int RG = NW> struct WalkShape { // RG groups of 4 rows
     static constexpr int NT = 64 * NW;
-    static constexpr int CI = kRowsPerWave * NW;
+    static constexpr int CI = kRowsPerWave * RG;
     static constexpr int VOX = (CI + 2) * kSJ; // staged voxels per slab
     static constexpr int RING = NW == 1 ? 3 : 4;
     static constexpr int SETS = NW == 1 ? 1 : 2;
@@ -126,8 +126,14 @@ struct ConvArgs {
     uint16_t *out16;             // COUT_BF16: [V][16]
     float *out32;                // COUT_F32: [cout][V] raw; COUT_DUAL: [2][V] projected dual
     const float *obase;          // COUT_DUAL: base dual added before the projection (nullable)
-    int cout, tv;                // COUT_F32 channels; COUT_DUAL: 0 ATV (clamp), 1 ITV2D (disc)
+    int cout, tv;                // output channels (2 for COUT_DUAL); COUT_DUAL: 0 ATV (clamp), 1 ITV2D (disc)
 };
+
+// per-lane choice without a branch: a where mask is all ones, b where it is 0
+__device__ inline float pick(uint32_t mask, float a, float b)
+{
+    return __uint_as_float((__float_as_uint(a) & mask) | (__float_as_uint(b) & ~mask));
+}
 
 // two floats to bf16 (round to nearest even; v_cvt_pk_bf16_f32), packed low | high << 16
 __device__ inline uint32_t pack2_bf16(float lo, float hi)
@@ -140,8 +146,8 @@ __device__ inline uint32_t pack2_bf16(float lo, float hi)
 // Staging of input slabs (tile plus halo, one frame) through registers into
 // the LDS ring. Each thread owns NL fixed slots of a slab; two register sets
 // hold the slabs in flight.
-template <int CIN, int NW> struct SlabStage {
-    using W = WalkShape<NW>;
+template <int CIN, int NW, int RG = NW> struct SlabStage {
+    using W = WalkShape<NW, RG>;
     static constexpr int CPT = CIN == CIN_F32 ? 1 : 2;  // 16-byte chunks per staged voxel
     static constexpr int SLAB = CPT * W::VOX;           // 16-byte slots per slab
     static constexpr int NL = (SLAB + W::NT - 1) / W::NT; // slots per thread
@@ -150,6 +156,8 @@ template <int CIN, int NW> struct SlabStage {
     // LDS slot of chunk h of staged voxel v (slab column sj): one chunk per
     // voxel when only channels 0-7 are staged, else two, swizzled
     __device__ static int chunk_slot(int v, int sj, int h) { return CPT == 1 ? v : 2 * v + (h ^ ((sj >> 2) & 1)); }
+    // 8-byte LDS index of quarter q (channels 4q .. 4q+3) of staged voxel v
+    __device__ static int quarter_slot(int v, int sj, int q) { return 2 * chunk_slot(v, sj, q >> 1) + (q & 1); }
 
     int pslot[NL];
     uint32_t poff[NL];
@@ -236,12 +244,11 @@ template <int CIN, int NW> struct SlabStage {
 // prefetch() exactly once (uniformly), which issues the loads of slab
 // s + 2 + SETS into the register set the step's store has just emptied.
 // begin(i0, j0, k0) runs once per item, after the first slabs are requested.
-template <int CIN, int NW, typename Step, typename Begin>
-__device__ __forceinline__ void frame_walk(const WalkGeom &w, const SlabSrc &src, uint4 *ring,
-                                           SlabStage<CIN, NW> &st, Step &&step, Begin &&begin)
+template <typename St, typename Step, typename Begin>
+__device__ __forceinline__ void frame_walk(const WalkGeom &w, const SlabSrc &src, uint4 *ring, St &st, Step &&step,
+                                           Begin &&begin)
 {
-    using St = SlabStage<CIN, NW>;
-    using W = WalkShape<NW>;
+    using W = typename St::W;
     const int tid = threadIdx.x, nwg = (int)gridDim.x;
     auto slab = [&](int r) { return ring + W::slot(r) * St::SLAB; };
     for (int it = xcd_contiguous((int)blockIdx.x, nwg); it < w.nitems; it += nwg) {
@@ -297,7 +304,15 @@ constexpr int kConvNW = 4;
 template <int CIN> constexpr int conv_waves_per_simd() { return CIN == CIN_F32 ? 3 : 2; }
 template <int CIN> constexpr int conv_wgs_per_cu() { return conv_waves_per_simd<CIN>() * 4 / kConvNW; }
 
-template <int CIN, int COUT, bool RELU, bool GATE>
+// PACK (an output of at most 4 channels): row m = 4 di + n of the weight
+// operand holds output channel n at row offset di, so one MFMA applies all
+// three row offsets to a staged row. Its result for staged row u, row m, is
+// then a partial sum of output row u - di, and output row r is the sum of the
+// partials of staged rows r, r+1, r+2 (lane groups kq = 0, 1, 2): a
+// reduce-scatter across the lane groups (ds_bpermute) leaves lane (column, kq)
+// with output row kq. Half the MFMAs of the 16-channel mapping, and the
+// epilogue runs on all 64 lanes.
+template <int CIN, int COUT, bool RELU, bool GATE, bool PACK = false>
 __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_conv(const ConvArgs a)
 {
     using St = SlabStage<CIN, kConvNW>;
@@ -305,6 +320,8 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
     constexpr int CPT = St::CPT;                  // chunks of a tap in one MFMA operand
     constexpr int TPM = 4 / CPT;                  // (dk, dj) offsets per MFMA
     constexpr int G = (9 + TPM - 1) / TPM;        // MFMAs per (staged row, di)
+    static_assert(!PACK || (CIN == CIN_BF16 && COUT != COUT_BF16), "packed rows: a 16-channel input, fp32 output");
+    static_assert(COUT != COUT_DUAL || PACK, "the dual output is packed");
     __shared__ uint4 ring[W::RING * St::SLAB];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -314,16 +331,24 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
     const uint32_t V = a.w.g.V;
 
     // A operands: weights of tap (dk, di, dj) for the lane's (dk, dj) in group gi
-    bf16x8 wb[3][G];
+    // (PACK: di and the output channel from the row)
+    bf16x8 wb[PACK ? 1 : 3][G];
     int coff[G][2], cdk[G];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
         const int c = TPM * gi + kq / CPT;
         const int cc = c < 9 ? c : 8, dk = cc / 3, dj = cc % 3;
+        if constexpr (PACK) {
+            const int di = row >> 2, n = row & 3;
+            wb[0][gi] = c < 9 && di < 3 && n < a.cout
+                            ? *(const bf16x8 *)(a.Wk + ((size_t)(dk * 9 + di * 3 + dj) * 16 + n) * 16 + 8 * hsel)
+                            : bf16x8{};
+        } else {
 #pragma unroll
-        for (int di = 0; di < 3; ++di) {
-            if (c < 9) wb[di][gi] = *(const bf16x8 *)(a.Wk + ((size_t)(dk * 9 + di * 3 + dj) * 16 + row) * 16 + 8 * hsel);
-            else wb[di][gi] = bf16x8{};
+            for (int di = 0; di < 3; ++di) {
+                if (c < 9) wb[di][gi] = *(const bf16x8 *)(a.Wk + ((size_t)(dk * 9 + di * 3 + dj) * 16 + row) * 16 + 8 * hsel);
+                else wb[di][gi] = bf16x8{};
+            }
         }
         cdk[gi] = dk;
 #pragma unroll
@@ -332,14 +357,32 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
             coff[gi][tt] = St::chunk_slot(kRowsPerWave * wv * kSJ + col, col, hsel);
         }
     }
-    float bn[4];
+    float bn[4]; // PACK: bias of channel e; else of channel 4 kq + e
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bn[e] = a.bias ? a.bias[4 * kq + e] : 0.0f;
+    for (int e = 0; e < 4; ++e) bn[e] = a.bias ? a.bias[PACK ? e : 4 * kq + e] : 0.0f;
+
+    // COUT_DUAL: the base dual at the lane's own output voxel (row kq), set
+    // S of frame k. With two register sets it is read a frame ahead, before
+    // the slab prefetch, so that the wait for it does not wait for a slab.
+    float eb[2][2][2];
+    auto load_eb = [&](auto setc, int i0, int j0, int k) {
+        constexpr int S = decltype(setc)::value;
+        const int kc = min(k, a.w.g.B - 1); // past the last frame: read, never used
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int i = i0 + kRowsPerWave * wv + kq, j = j0 + 16 * tt + row;
+            const size_t v = ((size_t)kc * nx + i) * ny + j;
+            const bool in = a.obase && i < nx && j < ny;
+            eb[S][tt][0] = in ? a.obase[v] : 0.0f;
+            eb[S][tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
+        }
+    };
+    constexpr bool EB_AHEAD = COUT == COUT_DUAL && W::SETS == 2;
 
     St st;
     st.init(tid);
-    frame_walk<CIN, kConvNW>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
-        (void)setc;
+    frame_walk(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
+        constexpr int S = EB_AHEAD ? decltype(setc)::value : 0;
         const bool rows_live = i0 + kRowsPerWave * wv < nx; // uniform per wavefront
         // With one register set the loads of the slab two frames ahead go out
         // first: they have this step's compute to arrive.
@@ -348,11 +391,8 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
         // epilogue's stores are conditional, so the compiler cannot count
         // them: the prefetch is issued after the epilogue, and the wait for
         // a slab (two steps later) then leaves the next slab's loads in
-        // flight. The epilogue's operands (the gate; the base dual, which
-        // lane (row, kq) reads for its own voxel of output row kq and the
-        // epilogue gathers across lanes) are read before the compute.
+        // flight. The gate is read before the compute.
         uint2 eg[GATE ? 4 : 1][2];
-        float eb[COUT == COUT_DUAL ? 2 : 1][2];
         if constexpr (GATE) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -363,33 +403,33 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
                     eg[r][tt] = i < nx && j < ny ? *(const uint2 *)(a.gate + v * 16 + 4 * kq) : make_uint2(0u, 0u);
                 }
         }
-        if constexpr (COUT == COUT_DUAL) {
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                const int i = i0 + kRowsPerWave * wv + kq, j = j0 + 16 * tt + row;
-                const size_t v = ((size_t)k * nx + i) * ny + j;
-                const bool in = a.obase && i < nx && j < ny;
-                eb[tt][0] = in ? a.obase[v] : 0.0f;
-                eb[tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
-            }
-        }
+        if constexpr (COUT == COUT_DUAL && !EB_AHEAD) load_eb(std::integral_constant<int, 0>{}, i0, j0, k);
         if (rows_live) {
             // D[n][voxel] = sum_K W[n][K] X[K][voxel]: the weights are the
-            // A operand, the staged voxels the B operand
-            f32x4 acc[4][2];
+            // A operand, the staged voxels the B operand. acc[q][tt]: output
+            // row q, or (PACK) the partials of staged row q.
+            constexpr int NQ = PACK ? kRowsPerWave + 2 : kRowsPerWave;
+            f32x4 acc[NQ][2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int q = 0; q < NQ; ++q)
 #pragma unroll
-                for (int tt = 0; tt < 2; ++tt) acc[r][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int tt = 0; tt < 2; ++tt) acc[q][tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
             const uint4 *slab[G];
 #pragma unroll
             for (int gi = 0; gi < G; ++gi) slab[gi] = ring + W::slot(s + cdk[gi]) * St::SLAB;
-            // (staged row u, group gi) in sequence; the operands of the
-            // entry two ahead are read while the current one's MFMAs run
-            constexpr int NP = (kRowsPerWave + 2) * G;
+            // (staged row u, group gi) in sequence, u inner for PACK (so
+            // that consecutive MFMAs feed different accumulators); the
+            // operands of the entry two ahead are read while the current
+            // one's MFMAs run
+            constexpr int NU = kRowsPerWave + 2, NP = NU * G;
+            auto entry = [](int p, int &u, int &gi) {
+                u = PACK ? p % NU : p / G;
+                gi = PACK ? p / NU : p % G;
+            };
             bf16x8 X[3][2];
             auto rd = [&](int p, bf16x8(&b)[2]) {
-                const int u = p / G, gi = p % G;
+                int u, gi;
+                entry(p, u, gi);
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) b[tt] = __builtin_bit_cast(bf16x8, slab[gi][coff[gi][tt] + u * CPT * kSJ]);
             };
@@ -401,81 +441,121 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 if (p + 2 < NP) rd(p + 2, X[(p + 2) % 3]);
-                const int u = p / G, gi = p % G;
-#pragma unroll
-                for (int di = 0; di < 3; ++di) {
-                    const int r = u - di;
-                    if (r < 0 || r >= kRowsPerWave) continue;
+                int u, gi;
+                entry(p, u, gi);
+                if constexpr (PACK) {
 #pragma unroll
                     for (int tt = 0; tt < 2; ++tt)
-                        acc[r][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[di][gi], X[p % 3][tt], acc[r][tt], 0, 0, 0);
+                        acc[u][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[0][gi], X[p % 3][tt], acc[u][tt], 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int di = 0; di < 3; ++di) {
+                        const int r = u - di;
+                        if (r < 0 || r >= kRowsPerWave) continue;
+#pragma unroll
+                        for (int tt = 0; tt < 2; ++tt)
+                            acc[r][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[di][gi], X[p % 3][tt], acc[r][tt], 0, 0, 0);
+                    }
                 }
             }
 
-            // result: voxel j = j0 + 16 tt + row, output channels 4 kq + e
-            float gb[COUT == COUT_DUAL ? 4 : 1][2][2];
-            if constexpr (COUT == COUT_DUAL) {
-                // base of output row r: held by lane (row, r); every lane takes part
+            if constexpr (PACK) {
+                // lane (row, kq) holds partial (di = kq, channel e) of staged
+                // row q in acc[q][tt][e]; t[r] = its share of output row r
+                // (group 3 holds none). Reduce-scatter: lane groups kq and
+                // kq ^ 2 add the rows of their half (rows 2h, 2h+1, h = kq>>1),
+                // then kq and kq ^ 1 add row kq.
+                constexpr int NE = COUT == COUT_DUAL ? 2 : 4; // channels reduced
+                const uint32_t g0 = 0u - (uint32_t)(kq == 0), g1 = 0u - (uint32_t)(kq == 1),
+                               g2 = 0u - (uint32_t)(kq == 2);
+                const uint32_t mh = 0u - (uint32_t)(kq >> 1), mb = 0u - (uint32_t)(kq & 1);
+                const int up = 4 * (lane ^ 32), side = 4 * (lane ^ 16);
+                float y[NE][2];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-                    for (int tt = 0; tt < 2; ++tt)
+                    for (int e = 0; e < NE; ++e) {
+                        float t[4];
 #pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            gb[r][tt][c] = __int_as_float(
-                                __builtin_amdgcn_ds_bpermute(4 * (row + 16 * r), __float_as_int(eb[tt][c])));
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + kRowsPerWave * wv + r;
-                if (i >= nx) break; // uniform per wavefront
-                const size_t vrow = ((size_t)k * nx + i) * ny;
+                        for (int r = 0; r < 4; ++r)
+                            t[r] = pick(g0, acc[r][tt][e], pick(g1, acc[r + 1][tt][e], pick(g2, acc[r + 2][tt][e], 0.0f)));
+                        const float s0 = pick(mh, t[0], t[2]), s1 = pick(mh, t[1], t[3]);
+                        const float a0 = pick(mh, t[2], t[0]) + __int_as_float(__builtin_amdgcn_ds_bpermute(up, __float_as_int(s0)));
+                        const float a1 = pick(mh, t[3], t[1]) + __int_as_float(__builtin_amdgcn_ds_bpermute(up, __float_as_int(s1)));
+                        const float snd = pick(mb, a0, a1);
+                        y[e][tt] = pick(mb, a1, a0) + __int_as_float(__builtin_amdgcn_ds_bpermute(side, __float_as_int(snd)));
+                    }
+                // lane (row, kq): output row kq, column j0 + 16 tt + row
+                const int i = i0 + kRowsPerWave * wv + kq;
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) {
                     const int j = j0 + 16 * tt + row;
-                    if (j >= ny) continue;
-                    const size_t v = vrow + j;
-                    float y[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) y[e] = acc[r][tt][e] + bn[e];
+                    if (i >= nx || j >= ny) continue;
+                    const size_t v = ((size_t)k * nx + i) * ny + j;
                     if constexpr (COUT == COUT_DUAL) {
-                        if (kq == 0) {
-                            // (base +) output, entries with no difference 0, projected
-                            float h = j < ny - 1 ? y[0] + gb[r][tt][0] : 0.0f;
-                            float w = i < nx - 1 ? y[1] + gb[r][tt][1] : 0.0f;
-                            if (a.tv == 0) {
-                                h = fminf(fmaxf(h, -1.0f), 1.0f);
-                                w = fminf(fmaxf(w, -1.0f), 1.0f);
-                            } else {
-                                const float sc = fminf(1.0f, __builtin_amdgcn_rsqf(fmaf(w, w, h * h)));
-                                h *= sc;
-                                w *= sc;
-                            }
-                            a.out32[v] = h;
-                            a.out32[(size_t)V + v] = w;
+                        // (base +) output, entries with no difference 0, projected
+                        float hh = j < ny - 1 ? (y[0][tt] + bn[0]) + eb[S][tt][0] : 0.0f;
+                        float ww = i < nx - 1 ? (y[1][tt] + bn[1]) + eb[S][tt][1] : 0.0f;
+                        if (a.tv == 0) {
+                            hh = fminf(fmaxf(hh, -1.0f), 1.0f);
+                            ww = fminf(fmaxf(ww, -1.0f), 1.0f);
+                        } else {
+                            const float sc = fminf(1.0f, __builtin_amdgcn_rsqf(fmaf(ww, ww, hh * hh)));
+                            hh *= sc;
+                            ww *= sc;
                         }
-                    } else if constexpr (COUT == COUT_F32) {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (4 * kq + e < a.cout) a.out32[(size_t)(4 * kq + e) * V + v] = y[e];
+                        a.out32[v] = hh;
+                        a.out32[(size_t)V + v] = ww;
                     } else {
-                        if (RELU)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) y[e] = fmaxf(y[e], 0.0f);
-                        if constexpr (GATE) {
-                            const uint2 gv = eg[r][tt];
-                            if (!(__uint_as_float(gv.x << 16) > 0.0f)) y[0] = 0.0f;
-                            if (!(__uint_as_float(gv.x & 0xffff0000u) > 0.0f)) y[1] = 0.0f;
-                            if (!(__uint_as_float(gv.y << 16) > 0.0f)) y[2] = 0.0f;
-                            if (!(__uint_as_float(gv.y & 0xffff0000u) > 0.0f)) y[3] = 0.0f;
+                        for (int e = 0; e < NE; ++e)
+                            if (e < a.cout) a.out32[(size_t)e * V + v] = y[e][tt] + bn[e];
+                    }
+                }
+            } else {
+                // result: voxel j = j0 + 16 tt + row, output channels 4 kq + e
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + kRowsPerWave * wv + r;
+                    if (i >= nx) break; // uniform per wavefront
+                    const size_t vrow = ((size_t)k * nx + i) * ny;
+#pragma unroll
+                    for (int tt = 0; tt < 2; ++tt) {
+                        const int j = j0 + 16 * tt + row;
+                        if (j >= ny) continue;
+                        const size_t v = vrow + j;
+                        float y[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) y[e] = acc[r][tt][e] + bn[e];
+                        if constexpr (COUT == COUT_F32) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (4 * kq + e < a.cout) a.out32[(size_t)(4 * kq + e) * V + v] = y[e];
+                        } else {
+                            if (RELU)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) y[e] = fmaxf(y[e], 0.0f);
+                            if constexpr (GATE) {
+                                const uint2 gv = eg[r][tt];
+                                if (!(__uint_as_float(gv.x << 16) > 0.0f)) y[0] = 0.0f;
+                                if (!(__uint_as_float(gv.x & 0xffff0000u) > 0.0f)) y[1] = 0.0f;
+                                if (!(__uint_as_float(gv.y << 16) > 0.0f)) y[2] = 0.0f;
+                                if (!(__uint_as_float(gv.y & 0xffff0000u) > 0.0f)) y[3] = 0.0f;
+                            }
+                            *(uint2 *)(a.out16 + v * 16 + 4 * kq) =
+                                make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
                         }
-                        *(uint2 *)(a.out16 + v * 16 + 4 * kq) = make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
                     }
                 }
             }
         }
-        if constexpr (W::SETS == 2) prefetch();
-    }, [](int, int, int) {});
+        if constexpr (W::SETS == 2) {
+            if constexpr (EB_AHEAD) load_eb(std::integral_constant<int, 1 - S>{}, i0, j0, k + 1);
+            prefetch();
+        }
+    }, [&](int i0, int j0, int k0) {
+        if constexpr (EB_AHEAD) load_eb(std::integral_constant<int, 0>{}, i0, j0, k0);
+    });
 }
 
 // x [B][nx][ny] fp32 -> channels-last bf16 with x in channel 0 and, when
@@ -624,10 +704,10 @@ __global__ __launch_bounds__(256) void k_sum_part(int n, const double *__restric
 // input use the same order). The input slabs are staged by the convolution's
 // frame walk; the shift of tap (dk, di, dj) is the staged position a block is
 // read from, and one transposed block of staged row u serves the output rows
-// u - di. Each wavefront accumulates the 27 taps and the bias for its four
-// output rows over all its items; the four wavefronts then add their sums in
-// LDS in a fixed order and the workgroup writes one partial [28][16][16] for
-// the fixed-order reduction.
+// u - di. A workgroup walks tiles of 16 output rows; each wavefront
+// accumulates its share of the taps for four of those rows over all its
+// items, the wavefronts then add their sums in LDS in a fixed order and the
+// workgroup writes one partial [28][16][16] for the fixed-order reduction.
 constexpr int kWgBlocks = 512;
 
 struct WgradArgs {
@@ -637,13 +717,19 @@ struct WgradArgs {
     float *part;
 };
 
-__global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
+// Eight wavefronts: four row groups of the tile times two halves of the nine
+// (dk, dj) offsets (5 and 4, the bias with the second half), so that each
+// holds 15 tap accumulators and two wavefronts fit a SIMD.
+constexpr int kWgNW = 8;
+
+__global__ __launch_bounds__(64 * kWgNW, 2) void k_wgrad(const WgradArgs a)
 {
-    using St = SlabStage<CIN_BF16, 4>;
-    using W = WalkShape<4>;
+    using St = SlabStage<CIN_BF16, kWgNW, 4>;
+    using W = WalkShape<kWgNW, 4>;
     static_assert(28 * 256 * sizeof(float) <= W::RING * St::SLAB * sizeof(uint4), "the wavefront sums fit in the ring");
     __shared__ uint4 ring[W::RING * St::SLAB];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int rg = wv & 3, th = wv >> 2; // row group, half of the (dk, dj) offsets
     const int row = lane & 15, kq = lane >> 4;
     const int nx = a.w.g.nx, ny = a.w.g.ny;
 
@@ -656,9 +742,12 @@ __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
 #pragma unroll
     for (int e = 0; e < 8; ++e) ones0[e] = row == 0 ? (__bf16)1.0f : (__bf16)0.0f;
 
-    f32x4 acc[27], accb = {0.0f, 0.0f, 0.0f, 0.0f};
+    // acc[ci][di]: tap (dk, di, dj) of the offset c = 5 th + ci = 3 dk + dj
+    f32x4 acc[5][3], accb = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ci = 0; ci < 5; ++ci)
+#pragma unroll
+        for (int di = 0; di < 3; ++di) acc[ci][di] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
     // two transposed 16-voxel blocks as one K = 32 operand
     auto pair = [](f32x4 t0, f32x4 t1) {
@@ -670,7 +759,7 @@ __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
                                                          f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
     };
 
-    // dy of the wavefront's rows in frame k: lane (voxel row, kq) reads
+    // dy of the row group's rows in frame k: lane (voxel row, kq) reads
     // channels 4kq .. 4kq+3; frame k + 1 is read while frame k is computed
     uint2 dyr[2][4][2];
     auto load_dy = [&](auto setc, int i0, int j0, int k) {
@@ -680,7 +769,7 @@ __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int sg = 0; sg < 2; ++sg) {
-                const int i = i0 + kRowsPerWave * wv + r, j = j0 + 16 * sg + row;
+                const int i = i0 + kRowsPerWave * rg + r, j = j0 + 16 * sg + row;
                 const size_t v = ((size_t)kc * nx + i) * ny + j;
                 dyr[S][r][sg] = i < nx && j < ny ? *(const uint2 *)(a.dy + v * 16 + 4 * kq) : make_uint2(0u, 0u);
             }
@@ -688,61 +777,72 @@ __global__ __launch_bounds__(256, 1) void k_wgrad(const WgradArgs a)
 
     St st;
     st.init(tid);
-    frame_walk<CIN_BF16, 4>(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
+    frame_walk(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
         constexpr int S = decltype(setc)::value;
         prefetch();
         load_dy(std::integral_constant<int, 1 - S>{}, i0, j0, k + 1);
-        if (i0 + kRowsPerWave * wv >= nx) return; // uniform per wavefront: no rows here
+        if (i0 + kRowsPerWave * rg >= nx) return; // uniform per wavefront: no rows here
         bf16x8 ady[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             ady[r] = pair(transpose(dyr[S][r][0]), transpose(dyr[S][r][1]));
-            accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ady[r], ones0, accb, 0, 0, 0);
+            if (th == 1) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ady[r], ones0, accb, 0, 0, 0);
         }
 #pragma unroll
-        for (int dk = 0; dk < 3; ++dk) {
+        for (int ci = 0; ci < 5; ++ci) {
+            const int c = 5 * th + ci;
+            if (c >= 9) break; // uniform per wavefront
+            const int dk = c / 3, dj = c % 3;
             const uint2 *sl = (const uint2 *)(ring + W::slot(s + dk) * St::SLAB);
 #pragma unroll
-            for (int u = 0; u < kRowsPerWave + 2; ++u)
+            for (int u = 0; u < kRowsPerWave + 2; ++u) {
+                f32x4 tb[2];
 #pragma unroll
-                for (int dj = 0; dj < 3; ++dj) {
-                    f32x4 tb[2];
-#pragma unroll
-                    for (int sg = 0; sg < 2; ++sg) {
-                        const int col = 16 * sg + row + dj;
-                        const int slot = St::chunk_slot((kRowsPerWave * wv + u) * kSJ + col, col, kq >> 1);
-                        tb[sg] = transpose(sl[2 * slot + (kq & 1)]);
-                    }
-                    const bf16x8 bx = pair(tb[0], tb[1]);
-#pragma unroll
-                    for (int di = 0; di < 3; ++di) {
-                        const int r = u - di;
-                        if (r < 0 || r >= kRowsPerWave) continue;
-                        f32x4 &c = acc[(dk * 3 + di) * 3 + dj];
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ady[r], bx, c, 0, 0, 0);
-                    }
+                for (int sg = 0; sg < 2; ++sg) {
+                    const int col = 16 * sg + row + dj;
+                    tb[sg] = transpose(sl[St::quarter_slot((kRowsPerWave * rg + u) * kSJ + col, col, kq)]);
                 }
+                const bf16x8 bx = pair(tb[0], tb[1]);
+#pragma unroll
+                for (int di = 0; di < 3; ++di) {
+                    const int r = u - di;
+                    if (r < 0 || r >= kRowsPerWave) continue;
+                    acc[ci][di] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ady[r], bx, acc[ci][di], 0, 0, 0);
+                }
+            }
         }
     }, [&](int i0, int j0, int k0) { load_dy(std::integral_constant<int, 0>{}, i0, j0, k0); });
 
-    // acc[t]: lane (c = row, kq) holds dW[t][4kq + e][c]; sum the wavefronts in LDS
+    // acc: lane (c = row, kq) holds dW[t][4kq + e][c]. The row groups' sums
+    // are added in LDS in a fixed order (row group 0 first).
     float *red = (float *)ring;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < kWgNW; ++w) {
         __syncthreads();
         if (wv == w) {
 #pragma unroll
-            for (int t = 0; t < 28; ++t)
+            for (int ci = 0; ci < 5; ++ci) {
+                const int c = 5 * th + ci;
+                if (c >= 9) break;
+#pragma unroll
+                for (int di = 0; di < 3; ++di)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int t = (c / 3) * 9 + di * 3 + c % 3;
+                        const int idx = t * 256 + (4 * kq + e) * 16 + row;
+                        red[idx] = rg == 0 ? acc[ci][di][e] : red[idx] + acc[ci][di][e];
+                    }
+            }
+            if (th == 1)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int idx = t * 256 + (4 * kq + e) * 16 + row;
-                    const float val = t < 27 ? acc[t < 27 ? t : 0][e] : accb[e];
-                    red[idx] = w == 0 ? val : red[idx] + val;
+                    const int idx = 27 * 256 + (4 * kq + e) * 16 + row;
+                    red[idx] = rg == 0 ? accb[e] : red[idx] + accb[e];
                 }
         }
     }
     __syncthreads();
     float *p = a.part + (size_t)blockIdx.x * 28 * 256;
-    for (int idx = tid; idx < 28 * 256; idx += 256) p[idx] = red[idx];
+    for (int idx = tid; idx < 28 * 256; idx += 64 * kWgNW) p[idx] = red[idx];
 }
 
 // grad[t][n][c] = sum over groups in a fixed order: thread (entry, chunk)
@@ -878,13 +978,13 @@ WalkGeom walk_geom(int nx, int ny, int B, int slots, int ci)
     return w;
 }
 
-template <int CIN, int COUT, bool RELU, bool GATE>
+template <int CIN, int COUT, bool RELU, bool GATE, bool PACK = false>
 void launch_conv(ConvArgs a, int nx, int ny, int B, hipStream_t s)
 {
     const int slots = conv_wgs_per_cu<CIN>() * device_cus();
     a.w = walk_geom(nx, ny, B, slots, WalkShape<kConvNW>::CI);
-    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE>), dim3(std::min(a.w.nitems, slots)), dim3(64 * kConvNW), 0, s,
-                       a);
+    hipLaunchKernelGGL((k_conv<CIN, COUT, RELU, GATE, PACK>), dim3(std::min(a.w.nitems, slots)), dim3(64 * kConvNW),
+                       0, s, a);
 }
 
 ConvArgs conv_args(const uint16_t *Wk, const float *bias)
@@ -929,7 +1029,8 @@ void wsnet_conv_out(int nx, int ny, int B, const uint16_t *in, const uint16_t *W
     a.src.in = in;
     a.out32 = y;
     a.cout = cout;
-    launch_conv<CIN_BF16, COUT_F32, false, false>(a, nx, ny, B, s);
+    if (cout <= 4) launch_conv<CIN_BF16, COUT_F32, false, false, true>(a, nx, ny, B, s);
+    else launch_conv<CIN_BF16, COUT_F32, false, false>(a, nx, ny, B, s);
 }
 
 void wsnet_conv_dual(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int tv,
@@ -940,7 +1041,8 @@ void wsnet_conv_dual(int nx, int ny, int B, const uint16_t *in, const uint16_t *
     a.out32 = dual;
     a.obase = base;
     a.tv = tv;
-    launch_conv<CIN_BF16, COUT_DUAL, false, false>(a, nx, ny, B, s);
+    a.cout = 2;
+    launch_conv<CIN_BF16, COUT_DUAL, false, false, true>(a, nx, ny, B, s);
 }
 
 int wsnet_reduce_blocks() { return kRedBlocks; }
@@ -978,15 +1080,15 @@ int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, c
 void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,
                  hipStream_t s)
 {
-    // one workgroup per CU: the 27 tap accumulators take the AGPRs as well
+    // one workgroup (two wavefronts per SIMD) per CU
     const int slots = std::min(device_cus(), kWgBlocks);
     WgradArgs a{};
-    a.w = walk_geom(nx, ny, B, slots, WalkShape<4>::CI);
+    a.w = walk_geom(nx, ny, B, slots, WalkShape<kWgNW, 4>::CI);
     a.src.in = in;
     a.dy = dy;
     a.part = part;
     const int groups = std::min(a.w.nitems, slots);
-    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(64 * kWgNW), 0, s, a);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 256 / 32), dim3(256), 0, s, groups, (const float *)part, grad);
 }
 

@@ -171,11 +171,12 @@ def test_gradients_frame_walk_match_oracle(sc, ctx, rnet):
         assert e <= 5e-3
 
 
-@pytest.mark.parametrize("c_out", [1, 5, 16])
+@pytest.mark.parametrize("c_out", [1, 4, 5, 16])
 def test_wide_output_forward_and_gradients_match_oracle(sc, ctx, c_out):
-    """c_in = 1 networks with 1, 5 or 16 output channels: the raw output
-    planes (every output-channel group of the last layer's result) and all
-    gradients against the FP64 oracle."""
+    """c_in = 1 networks with 1, 4, 5 or 16 output channels: the raw output
+    planes and all gradients against the FP64 oracle. Up to 4 channels the
+    last layer runs the row-packed mapping (all three row offsets in one
+    MFMA, partial rows summed across lanes); 5 and 16 the 16-channel one."""
     from paper_2005_08028_amd import warmstart
     n = sc.sci_wsnet_create(ctx, c_in=1, c_out=c_out)
     try:
