@@ -122,8 +122,9 @@ struct ConvArgs {
     SlabSrc src;
     const uint16_t *Wk;
     const float *bias;           // nullable
-    const uint16_t *gate;        // GATE: output zeroed where gate[v][n] <= 0
+    const uint8_t *gate;         // GATE: sign bytes [V][4] (bit e of byte q: channel 4q+e > 0); output zeroed where clear
     uint16_t *out16;             // COUT_BF16: [V][16]
+    uint8_t *sign;               // COUT_BF16 (nullable): sign bytes of the bf16 output, layout as gate
     float *out32;                // COUT_F32: [cout][V] raw; COUT_DUAL: [2][V] projected dual
     const float *obase;          // COUT_DUAL: base dual added before the projection (nullable)
     int cout, tv;                // output channels (2 for COUT_DUAL); COUT_DUAL: 0 ATV (clamp), 1 ITV2D (disc)
@@ -361,28 +362,35 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
 #pragma unroll
     for (int e = 0; e < 4; ++e) bn[e] = a.bias ? a.bias[PACK ? e : 4 * kq + e] : 0.0f;
 
-    // COUT_DUAL: the base dual at the lane's own output voxel (row kq), set
-    // S of frame k. With two register sets it is read a frame ahead, before
-    // the slab prefetch, so that the wait for it does not wait for a slab.
+    // The epilogue's operands at the lane's own voxel of output row kq, set
+    // S of frame k: the base dual (COUT_DUAL), the four sign bytes (GATE;
+    // the epilogue takes row r's from lane (row, r)). With two register sets
+    // they are read a frame ahead, before the slab prefetch, so that the wait
+    // for them does not wait for a slab.
     float eb[2][2][2];
-    auto load_eb = [&](auto setc, int i0, int j0, int k) {
+    uint32_t egw[2][2];
+    auto load_epi = [&](auto setc, int i0, int j0, int k) {
         constexpr int S = decltype(setc)::value;
         const int kc = min(k, a.w.g.B - 1); // past the last frame: read, never used
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt) {
             const int i = i0 + kRowsPerWave * wv + kq, j = j0 + 16 * tt + row;
             const size_t v = ((size_t)kc * nx + i) * ny + j;
-            const bool in = a.obase && i < nx && j < ny;
-            eb[S][tt][0] = in ? a.obase[v] : 0.0f;
-            eb[S][tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
+            if constexpr (COUT == COUT_DUAL) {
+                const bool in = a.obase && i < nx && j < ny;
+                eb[S][tt][0] = in ? a.obase[v] : 0.0f;
+                eb[S][tt][1] = in ? a.obase[(size_t)V + v] : 0.0f;
+            }
+            if constexpr (GATE) egw[S][tt] = i < nx && j < ny ? *(const uint32_t *)(a.gate + v * 4) : 0u;
         }
     };
-    constexpr bool EB_AHEAD = COUT == COUT_DUAL && W::SETS == 2;
+    constexpr bool EPI = COUT == COUT_DUAL || GATE;
+    constexpr bool AHEAD = EPI && W::SETS == 2;
 
     St st;
     st.init(tid);
     frame_walk(a.w, a.src, ring, st, [&](auto setc, int s, int i0, int j0, int k, auto &&prefetch) {
-        constexpr int S = EB_AHEAD ? decltype(setc)::value : 0;
+        constexpr int S = AHEAD ? decltype(setc)::value : 0;
         const bool rows_live = i0 + kRowsPerWave * wv < nx; // uniform per wavefront
         // With one register set the loads of the slab two frames ahead go out
         // first: they have this step's compute to arrive.
@@ -391,19 +399,8 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
         // epilogue's stores are conditional, so the compiler cannot count
         // them: the prefetch is issued after the epilogue, and the wait for
         // a slab (two steps later) then leaves the next slab's loads in
-        // flight. The gate is read before the compute.
-        uint2 eg[GATE ? 4 : 1][2];
-        if constexpr (GATE) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int tt = 0; tt < 2; ++tt) {
-                    const int i = i0 + kRowsPerWave * wv + r, j = j0 + 16 * tt + row;
-                    const size_t v = ((size_t)k * nx + i) * ny + j;
-                    eg[r][tt] = i < nx && j < ny ? *(const uint2 *)(a.gate + v * 16 + 4 * kq) : make_uint2(0u, 0u);
-                }
-        }
-        if constexpr (COUT == COUT_DUAL && !EB_AHEAD) load_eb(std::integral_constant<int, 0>{}, i0, j0, k);
+        // flight.
+        if constexpr (EPI && !AHEAD) load_epi(std::integral_constant<int, 0>{}, i0, j0, k);
         if (rows_live) {
             // D[n][voxel] = sum_K W[n][K] X[K][voxel]: the weights are the
             // A operand, the staged voxels the B operand. acc[q][tt]: output
@@ -536,25 +533,31 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
 #pragma unroll
                                 for (int e = 0; e < 4; ++e) y[e] = fmaxf(y[e], 0.0f);
                             if constexpr (GATE) {
-                                const uint2 gv = eg[r][tt];
-                                if (!(__uint_as_float(gv.x << 16) > 0.0f)) y[0] = 0.0f;
-                                if (!(__uint_as_float(gv.x & 0xffff0000u) > 0.0f)) y[1] = 0.0f;
-                                if (!(__uint_as_float(gv.y << 16) > 0.0f)) y[2] = 0.0f;
-                                if (!(__uint_as_float(gv.y & 0xffff0000u) > 0.0f)) y[3] = 0.0f;
+                                const uint32_t gw =
+                                    (uint32_t)__builtin_amdgcn_ds_bpermute(4 * (row + 16 * r), (int)egw[S][tt]);
+                                const uint32_t gb = gw >> (8 * kq);
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    if (!((gb >> e) & 1u)) y[e] = 0.0f;
                             }
-                            *(uint2 *)(a.out16 + v * 16 + 4 * kq) =
-                                make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
+                            const uint2 o = make_uint2(pack2_bf16(y[0], y[1]), pack2_bf16(y[2], y[3]));
+                            *(uint2 *)(a.out16 + v * 16 + 4 * kq) = o;
+                            if (a.sign) // uniform
+                                a.sign[v * 4 + kq] = (uint8_t)((__uint_as_float(o.x << 16) > 0.0f) |
+                                                               (__uint_as_float(o.x & 0xffff0000u) > 0.0f) << 1 |
+                                                               (__uint_as_float(o.y << 16) > 0.0f) << 2 |
+                                                               (__uint_as_float(o.y & 0xffff0000u) > 0.0f) << 3);
                         }
                     }
                 }
             }
         }
         if constexpr (W::SETS == 2) {
-            if constexpr (EB_AHEAD) load_eb(std::integral_constant<int, 1 - S>{}, i0, j0, k + 1);
+            if constexpr (AHEAD) load_epi(std::integral_constant<int, 1 - S>{}, i0, j0, k + 1);
             prefetch();
         }
     }, [&](int i0, int j0, int k0) {
-        if constexpr (EB_AHEAD) load_eb(std::integral_constant<int, 0>{}, i0, j0, k0);
+        if constexpr (AHEAD) load_epi(std::integral_constant<int, 0>{}, i0, j0, k0);
     });
 }
 
@@ -998,7 +1001,7 @@ ConvArgs conv_args(const uint16_t *Wk, const float *bias)
 } // namespace
 
 void wsnet_conv_input(int nx, int ny, int B, const float *x, const float *base, const uint16_t *Wk, const float *bias,
-                      uint16_t *out16, hipStream_t s)
+                      uint16_t *out16, uint8_t *sign, hipStream_t s)
 {
     ConvArgs a = conv_args(Wk, bias);
     const size_t V = (size_t)nx * ny * B;
@@ -1007,16 +1010,18 @@ void wsnet_conv_input(int nx, int ny, int B, const float *x, const float *base, 
     a.src.xb1 = base ? base + V : x;
     a.src.xb_live = base != nullptr;
     a.out16 = out16;
+    a.sign = sign;
     launch_conv<CIN_F32, COUT_BF16, true, false>(a, nx, ny, B, s);
 }
 
 void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
-                const uint16_t *gate, uint16_t *out16, hipStream_t s)
+                const uint8_t *gate, uint16_t *out16, uint8_t *sign, hipStream_t s)
 {
     ConvArgs a = conv_args(Wk, bias);
     a.src.in = in;
     a.gate = gate;
     a.out16 = out16;
+    a.sign = sign;
     if (gate) launch_conv<CIN_BF16, COUT_BF16, false, true>(a, nx, ny, B, s);
     else if (relu) launch_conv<CIN_BF16, COUT_BF16, true, false>(a, nx, ny, B, s);
     else launch_conv<CIN_BF16, COUT_BF16, false, false>(a, nx, ny, B, s);

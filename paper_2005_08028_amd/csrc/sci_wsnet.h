@@ -12,12 +12,15 @@ constexpr int kNetSlots = 28 * 256; // per layer: [27 taps + bias][16 out][16 in
 
 void wsnet_pack_input(int nx, int ny, int B, const float *x, const float *dual, uint16_t *a, hipStream_t s);
 // 3x3x3 convolutions (Wk[27][16 out][16 in] bf16, bias nullable):
-// first layer from fp32 planes x [V] and base [2][V] (nullable) with ReLU, to bf16 [V][16];
+// sign bytes [V][4]: bit e of byte q set where channel 4q+e of a bf16 [V][16] field is > 0;
+// first layer from fp32 planes x [V] and base [2][V] (nullable) with ReLU, to bf16 [V][16]
+// (and its sign bytes, when sign is non-null);
 void wsnet_conv_input(int nx, int ny, int B, const float *x, const float *base, const uint16_t *Wk, const float *bias,
-                      uint16_t *out16, hipStream_t s);
-// bf16 [V][16] to bf16 [V][16], with ReLU, or masked by gate > 0 (gate non-null, no ReLU);
+                      uint16_t *out16, uint8_t *sign, hipStream_t s);
+// bf16 [V][16] to bf16 [V][16], with ReLU, or zeroed where the gate's sign bit
+// is clear (gate non-null, no ReLU); sign (nullable) as above;
 void wsnet_conv(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, bool relu,
-                const uint16_t *gate, uint16_t *out16, hipStream_t s);
+                const uint8_t *gate, uint16_t *out16, uint8_t *sign, hipStream_t s);
 // bf16 [V][16] to the raw output planes y [cout][V] fp32;
 void wsnet_conv_out(int nx, int ny, int B, const uint16_t *in, const uint16_t *Wk, const float *bias, int cout,
                     float *y, hipStream_t s);

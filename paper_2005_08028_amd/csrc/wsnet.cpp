@@ -27,6 +27,7 @@ struct sci_wsnet {
     // activations for the largest volume seen
     size_t vcap = 0;
     uint16_t *act[kNetLayers] = {nullptr, nullptr, nullptr, nullptr}; // layer inputs a0..a3
+    uint8_t *sgn[kNetLayers] = {nullptr, nullptr, nullptr, nullptr};  // sign bytes [V][4] of a1..a3 (training)
     uint16_t *dA = nullptr, *dB = nullptr;                            // gradient ping-pong
     float *y = nullptr;                                               // last layer output [c_out][V]
     float *gth = nullptr;                                             // theta-loss D^T r [V]
@@ -44,6 +45,10 @@ int net_fail(sci_ctx *ctx, hipError_t e, const char *what) { return fail_hip(ctx
 void free_acts(sci_wsnet *n)
 {
     for (auto &a : n->act) {
+        if (a) (void)hipFree(a);
+        a = nullptr;
+    }
+    for (auto &a : n->sgn) {
         if (a) (void)hipFree(a);
         a = nullptr;
     }
@@ -66,6 +71,8 @@ int ensure_acts(sci_ctx *ctx, sci_wsnet *n, size_t V, hipStream_t s)
     const size_t ab = V * 16 * sizeof(uint16_t);
     for (auto &a : n->act)
         if ((e = hipMalloc(&a, ab)) != hipSuccess) return net_fail(ctx, e, "hipMalloc(activations)");
+    for (int l = 1; l < kNetLayers; ++l)
+        if ((e = hipMalloc(&n->sgn[l], V * 4)) != hipSuccess) return net_fail(ctx, e, "hipMalloc(activations)");
     if ((e = hipMalloc(&n->dA, ab)) != hipSuccess || (e = hipMalloc(&n->dB, ab)) != hipSuccess ||
         (e = hipMalloc(&n->y, V * (size_t)n->c_out * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&n->gth, V * sizeof(float))) != hipSuccess)
@@ -91,17 +98,18 @@ int check_net_args(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *X
 // a1 = relu(conv_0(X [, base])), read from the fp32 planes; a_{l+1} =
 // relu(conv_l(a_l)); the last layer writes the raw output planes y or, when
 // `dual` is given (a pointwise projection: ATV, ITV2D), the projected
-// (base +) output straight into it. The packed input a0 (bf16 [V][16]) is
-// written only for the gradients, whose first weight gradient reads it.
+// (base +) output straight into it. The packed input a0 (bf16 [V][16]) and
+// the sign bytes of a1..a3 (the ReLU masks of the data gradients) are written
+// only for the gradients, whose first weight gradient reads a0.
 void forward(sci_wsnet *n, const sci_dims &d, const float *X, const float *P_base, bool for_grads, float *dual,
              int tv, hipStream_t s)
 {
     const float *base = n->c_in == 3 ? P_base : nullptr;
     if (for_grads) wsnet_pack_input(d.nx, d.ny, d.B, X, base, n->act[0], s);
-    wsnet_conv_input(d.nx, d.ny, d.B, X, base, n->Wk, n->bias, n->act[1], s);
+    wsnet_conv_input(d.nx, d.ny, d.B, X, base, n->Wk, n->bias, n->act[1], for_grads ? n->sgn[1] : nullptr, s);
     for (int l = 1; l < kNetLayers - 1; ++l)
         wsnet_conv(d.nx, d.ny, d.B, n->act[l], n->Wk + (size_t)l * 27 * 256, n->bias + l * 16, true, nullptr,
-                   n->act[l + 1], s);
+                   n->act[l + 1], for_grads ? n->sgn[l + 1] : nullptr, s);
     const int l = kNetLayers - 1;
     const uint16_t *Wk = n->Wk + (size_t)l * 27 * 256;
     if (dual) wsnet_conv_dual(d.nx, d.ny, d.B, n->act[l], Wk, n->bias + l * 16, tv, base, dual, s);
@@ -121,8 +129,9 @@ void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, 
     for (int l = kNetLayers - 1; l >= 0; --l) {
         wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], n->wpart, n->g + (size_t)l * kNetSlots, s);
         if (l > 0) {
-            // d a_l = conv^T(d y_l), masked by the ReLU of a_l
-            wsnet_conv(d.nx, d.ny, d.B, dcur, n->WkT + (size_t)l * 27 * 256, nullptr, false, n->act[l], dnext, s);
+            // d a_l = conv^T(d y_l), masked by the ReLU of a_l (its sign bytes)
+            wsnet_conv(d.nx, d.ny, d.B, dcur, n->WkT + (size_t)l * 27 * 256, nullptr, false, n->sgn[l], dnext,
+                       nullptr, s);
             std::swap(dcur, dnext);
         }
     }
