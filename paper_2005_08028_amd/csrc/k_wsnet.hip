@@ -720,6 +720,13 @@ struct WgradArgs {
     float *part;
 };
 
+// LDS transpose read (ds_read_b64_tr_b16): within each 16-lane group, lane i
+// receives element e = 0..3 from component i & 3 of the 4 x 16-bit values that
+// lane 4e + (i >> 2) points at.
+typedef short v4s_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s_t lds_v4s_t;
+typedef __attribute__((address_space(3))) const uint2 lds_u2_t;
+
 // Eight wavefronts: four row groups of the tile times two halves of the nine
 // (dk, dj) offsets (5 and 4, the bias with the second half), so that each
 // holds 15 tap accumulators and two wavefronts fit a SIMD.
@@ -734,6 +741,7 @@ __global__ __launch_bounds__(64 * kWgNW, 2) void k_wgrad(const WgradArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int rg = wv & 3, th = wv >> 2; // row group, half of the (dk, dj) offsets
     const int row = lane & 15, kq = lane >> 4;
+    const int te = row >> 2, tq = row & 3;
     const int nx = a.w.g.nx, ny = a.w.g.ny;
 
     // B operand of the transposing MFMA: the identity, B[4kq + e][n = row]
@@ -796,16 +804,19 @@ __global__ __launch_bounds__(64 * kWgNW, 2) void k_wgrad(const WgradArgs a)
             const int c = 5 * th + ci;
             if (c >= 9) break; // uniform per wavefront
             const int dk = c / 3, dj = c % 3;
-            const uint2 *sl = (const uint2 *)(ring + W::slot(s + dk) * St::SLAB);
+            const lds_u2_t *sl = (const lds_u2_t *)(ring + W::slot(s + dk) * St::SLAB);
 #pragma unroll
             for (int u = 0; u < kRowsPerWave + 2; ++u) {
-                f32x4 tb[2];
+                // lane (row = 4 te + tq, kq) points the transposing read at
+                // channels 4 tq .. 4 tq+3 of voxel 4 kq + te of block sg
+                v4s_t tb[2];
 #pragma unroll
                 for (int sg = 0; sg < 2; ++sg) {
-                    const int col = 16 * sg + row + dj;
-                    tb[sg] = transpose(sl[St::quarter_slot((kRowsPerWave * rg + u) * kSJ + col, col, kq)]);
+                    const int col = 16 * sg + 4 * kq + te + dj;
+                    tb[sg] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                        (lds_v4s_t *)(sl + St::quarter_slot((kRowsPerWave * rg + u) * kSJ + col, col, tq)));
                 }
-                const bf16x8 bx = pair(tb[0], tb[1]);
+                const bf16x8 bx = __builtin_bit_cast(bf16x8, __builtin_shufflevector(tb[0], tb[1], 0, 1, 2, 3, 4, 5, 6, 7));
 #pragma unroll
                 for (int di = 0; di < 3; ++di) {
                     const int r = u - di;
