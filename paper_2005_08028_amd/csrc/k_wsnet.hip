@@ -862,12 +862,16 @@ __global__ __launch_bounds__(64 * kWgNW, 2) void k_wgrad(const WgradArgs a)
 // grad[t][n][c] = sum over groups in a fixed order: thread (entry, chunk)
 // adds groups chunk, chunk + 8, ... of one of the block's 32 entries, and the
 // eight chunk sums are added in order.
+// (blockIdx.y: the layer, whose partials start kWgBlocks x 28 x 256 floats
+// after the previous layer's)
 __global__ __launch_bounds__(256) void k_wgrad_reduce(int ngroups, const float *__restrict__ part,
                                                       float *__restrict__ grad)
 {
     __shared__ float lds[8][32];
     const int e = (int)threadIdx.x & 31, ch = (int)threadIdx.x >> 5;
     const int idx = blockIdx.x * 32 + e; // of 28 * 256 entries
+    part += (size_t)blockIdx.y * kWgBlocks * 28 * 256;
+    grad += (size_t)blockIdx.y * 28 * 256;
     float s = 0.0f;
     for (int b = ch; b < ngroups; b += 8) s += part[(size_t)b * 28 * 256 + idx];
     lds[ch][e] = s;
@@ -880,11 +884,13 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(int ngroups, const float *
     }
 }
 
-// Adam on the fp32 master parameters of one layer in the padded layout
-// [28][16][16] (slot 27 column 0 = bias); entries outside the layer's real
+// Adam on the fp32 master parameters of the layers in the padded layout
+// [28][16][16] (slot 27 column 0 = bias); entries outside a layer's real
 // channels stay zero. Then repack bf16 weights for the forward (Wk[t][n][c])
-// and transposed (WkT[t'][c][n], t' = mirrored tap) convolutions.
-__global__ __launch_bounds__(256) void k_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1,
+// and transposed (WkT[t'][c][n], t' = mirrored tap) convolutions. blockIdx.y:
+// the layer (input channels cin0 for the first, output channels coutL for the
+// last, 16 otherwise); every array advances by one layer's size.
+__global__ __launch_bounds__(256) void k_adam(int cin0, int coutL, float lr, float b1, float b2, float eps, float c1,
                                               float c2, const float *__restrict__ grad, float *__restrict__ w,
                                               float *__restrict__ m, float *__restrict__ v,
                                               uint16_t *__restrict__ Wk, uint16_t *__restrict__ WkT,
@@ -892,6 +898,16 @@ __global__ __launch_bounds__(256) void k_adam(int cin, int cout, float lr, float
 {
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= 28 * 256) return;
+    const int l = blockIdx.y;
+    const int cin = l == 0 ? cin0 : kNetHidden, cout = l == (int)gridDim.y - 1 ? coutL : kNetHidden;
+    const size_t o = (size_t)l * 28 * 256;
+    grad += o;
+    w += o;
+    m += o;
+    v += o;
+    Wk += (size_t)l * 27 * 256;
+    WkT += (size_t)l * 27 * 256;
+    bias += l * 16;
     const int t = idx / 256, n = (idx / 16) % 16, c = idx % 16;
     const bool live = (t < 27) ? (n < cout && c < cin) : (n < cout && c == 0);
     if (live && lr != 0.0f) {
@@ -1093,8 +1109,7 @@ int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, c
     return SCI_OK;
 }
 
-void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,
-                 hipStream_t s)
+int wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, hipStream_t s)
 {
     // one workgroup (two wavefronts per SIMD) per CU
     const int slots = std::min(device_cus(), kWgBlocks);
@@ -1105,14 +1120,20 @@ void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, 
     a.part = part;
     const int groups = std::min(a.w.nitems, slots);
     hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(64 * kWgNW), 0, s, a);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 256 / 32), dim3(256), 0, s, groups, (const float *)part, grad);
+    return groups;
 }
 
-void wsnet_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1, float c2, const float *grad,
-                float *w, float *m, float *v, uint16_t *Wk, uint16_t *WkT, float *bias, hipStream_t s)
+void wsnet_wgrad_reduce(int layers, int groups, const float *part, float *grad, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adam, dim3(28), dim3(256), 0, s, cin, cout, lr, b1, b2, eps, c1, c2, grad, w, m, v, Wk, WkT,
-                       bias);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(28 * 256 / 32, layers), dim3(256), 0, s, groups, part, grad);
+}
+
+void wsnet_adam(int layers, int cin0, int coutL, float lr, float b1, float b2, float eps, float c1, float c2,
+                const float *grad, float *w, float *m, float *v, uint16_t *Wk, uint16_t *WkT, float *bias,
+                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3(28, layers), dim3(256), 0, s, cin0, coutL, lr, b1, b2, eps, c1, c2, grad, w, m, v,
+                       Wk, WkT, bias);
 }
 
 void wsnet_dual_from_net(int nx, int ny, int B, int tv, const float *y, const float *base, float *dual, hipStream_t s)

@@ -36,10 +36,16 @@ void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *ba
 // into out[0] (part: wsnet_reduce_blocks() doubles).
 int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, const float *target, float *g,
                      uint16_t *dy, double *part, double *out, hipStream_t s);
-void wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, float *grad,
-                 hipStream_t s);
-void wsnet_adam(int cin, int cout, float lr, float b1, float b2, float eps, float c1, float c2, const float *grad,
-                float *w, float *m, float *v, uint16_t *Wk, uint16_t *WkT, float *bias, hipStream_t s);
+// weight-gradient partials of one layer into part (wsnet_wgrad_groups() x 28 x 256 floats); returns the
+// number of partials written
+int wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, hipStream_t s);
+// sums `groups` partials of each of `layers` consecutive layer regions of part into grad [layers][28][256]
+void wsnet_wgrad_reduce(int layers, int groups, const float *part, float *grad, hipStream_t s);
+// Adam and the bf16 repack of `layers` consecutive layers (cin0: the first layer's input channels, coutL:
+// the last layer's output channels)
+void wsnet_adam(int layers, int cin0, int coutL, float lr, float b1, float b2, float eps, float c1, float c2,
+                const float *grad, float *w, float *m, float *v, uint16_t *Wk, uint16_t *WkT, float *bias,
+                hipStream_t s);
 void wsnet_dual_from_net(int nx, int ny, int B, int tv, const float *y, const float *base, float *dual, hipStream_t s);
 
 // input channels of a network (1: x; 3: x and a base dual)

@@ -31,14 +31,11 @@ struct sci_wsnet {
     uint16_t *dA = nullptr, *dB = nullptr;                            // gradient ping-pong
     float *y = nullptr;                                               // last layer output [c_out][V]
     float *gth = nullptr;                                             // theta-loss D^T r [V]
-    float *wpart = nullptr;                                           // wgrad partials
+    float *wpart = nullptr;                                           // wgrad partials, per layer
     double *lpart = nullptr;                                          // loss partials (+ result)
 };
 
 namespace {
-
-int layer_cin(const sci_wsnet *n, int l) { return l == 0 ? n->c_in : kNetHidden; }
-int layer_cout(const sci_wsnet *n, int l) { return l == kNetLayers - 1 ? n->c_out : kNetHidden; }
 
 int net_fail(sci_ctx *ctx, hipError_t e, const char *what) { return fail_hip(ctx, e, what); }
 
@@ -126,8 +123,10 @@ void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, 
     else
         wsnet_loss(d.nx, d.ny, d.B, n->c_out, n->y, b, target, n->dA, n->lpart, n->lpart + nb, s);
     uint16_t *dcur = n->dA, *dnext = n->dB;
+    int groups = 0;
     for (int l = kNetLayers - 1; l >= 0; --l) {
-        wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], n->wpart, n->g + (size_t)l * kNetSlots, s);
+        groups = wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], n->wpart + (size_t)l * wsnet_wgrad_groups() * kNetSlots,
+                             s);
         if (l > 0) {
             // d a_l = conv^T(d y_l), masked by the ReLU of a_l (its sign bytes)
             wsnet_conv(d.nx, d.ny, d.B, dcur, n->WkT + (size_t)l * 27 * 256, nullptr, false, n->sgn[l], dnext,
@@ -135,6 +134,7 @@ void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, 
             std::swap(dcur, dnext);
         }
     }
+    wsnet_wgrad_reduce(kNetLayers, groups, n->wpart, n->g, s);
     (void)ctx;
 }
 
@@ -151,11 +151,8 @@ void adam(sci_wsnet *n, float lr, hipStream_t s)
     const int64_t t = n->step;
     const float c1 = lr != 0.0f ? (float)(1.0 - std::pow(0.9, (double)t)) : 1.0f;
     const float c2 = lr != 0.0f ? (float)(1.0 - std::pow(0.999, (double)t)) : 1.0f;
-    for (int l = 0; l < kNetLayers; ++l) {
-        const size_t o = (size_t)l * kNetSlots;
-        wsnet_adam(layer_cin(n, l), layer_cout(n, l), lr, b1, b2, eps, c1, c2, n->g + o, n->w + o, n->m + o, n->v + o,
-                   n->Wk + (size_t)l * 27 * 256, n->WkT + (size_t)l * 27 * 256, n->bias + l * 16, s);
-    }
+    wsnet_adam(kNetLayers, n->c_in, n->c_out, lr, b1, b2, eps, c1, c2, n->g, n->w, n->m, n->v, n->Wk, n->WkT, n->bias,
+               s);
 }
 
 } // namespace
@@ -183,7 +180,8 @@ int sci_wsnet_create(sci_ctx *ctx, int32_t c_in, int32_t c_out, sci_wsnet **out)
         (e = hipMalloc(&n->Wk, (size_t)kNetLayers * 27 * 256 * 2)) != hipSuccess ||
         (e = hipMalloc(&n->WkT, (size_t)kNetLayers * 27 * 256 * 2)) != hipSuccess ||
         (e = hipMalloc(&n->bias, (size_t)kNetLayers * 16 * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&n->wpart, (size_t)wsnet_wgrad_groups() * kNetSlots * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&n->wpart, (size_t)kNetLayers * wsnet_wgrad_groups() * kNetSlots * sizeof(float))) !=
+            hipSuccess ||
         (e = hipMalloc(&n->lpart, ((size_t)wsnet_reduce_blocks() + 8) * sizeof(double))) != hipSuccess) {
         sci_wsnet_destroy(n);
         return fail_hip(ctx, e, "hipMalloc(wsnet)");
