@@ -561,20 +561,6 @@ __global__ __launch_bounds__(64 * kConvNW, conv_waves_per_simd<CIN>()) void k_co
     });
 }
 
-// x [B][nx][ny] fp32 -> channels-last bf16 with x in channel 0 and, when
-// given, a dual field [2][V] in channels 1 and 2.
-__global__ __launch_bounds__(256) void k_pack_input(uint32_t V, const float *__restrict__ x,
-                                                    const float *__restrict__ dual, uint16_t *__restrict__ a)
-{
-    const uint32_t v = blockIdx.x * 256u + threadIdx.x;
-    if (v >= V) return;
-    const uint32_t c0 = to_bf16(x[v]);
-    const uint32_t c1 = dual ? to_bf16(dual[v]) : 0u, c2 = dual ? to_bf16(dual[V + v]) : 0u;
-    uint4 *o = (uint4 *)(a + (size_t)v * 16);
-    o[0] = make_uint4(c0 | (c1 << 16), c2, 0u, 0u);
-    o[1] = make_uint4(0u, 0u, 0u, 0u);
-}
-
 // Loss 1/(cout V) sum (y + base - target)^2 over the first cout channels
 // (base: an optional [cout][V] field the output is added to), its gradient
 // 2 (y + base - target) / (cout V) as bf16 [V][16] (other channels 0), and
@@ -732,9 +718,10 @@ typedef __attribute__((address_space(3))) const uint2 lds_u2_t;
 // holds 15 tap accumulators and two wavefronts fit a SIMD.
 constexpr int kWgNW = 8;
 
+template <int CIN>
 __global__ __launch_bounds__(64 * kWgNW, 2) void k_wgrad(const WgradArgs a)
 {
-    using St = SlabStage<CIN_BF16, kWgNW, 4>;
+    using St = SlabStage<CIN, kWgNW, 4>;
     using W = WalkShape<kWgNW, 4>;
     static_assert(28 * 256 * sizeof(float) <= W::RING * St::SLAB * sizeof(uint4), "the wavefront sums fit in the ring");
     __shared__ uint4 ring[W::RING * St::SLAB];
@@ -816,7 +803,9 @@ __global__ __launch_bounds__(64 * kWgNW, 2) void k_wgrad(const WgradArgs a)
                     tb[sg] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
                         (lds_v4s_t *)(sl + St::quarter_slot((kRowsPerWave * rg + u) * kSJ + col, col, tq)));
                 }
-                const bf16x8 bx = __builtin_bit_cast(bf16x8, __builtin_shufflevector(tb[0], tb[1], 0, 1, 2, 3, 4, 5, 6, 7));
+                bf16x8 bx = __builtin_bit_cast(bf16x8, __builtin_shufflevector(tb[0], tb[1], 0, 1, 2, 3, 4, 5, 6, 7));
+                // fp32 planes: channels 0-7 staged, quarters 2, 3 read 0, 1 again
+                if (CIN == CIN_F32 && row >= 8) bx = bf16x8{};
 #pragma unroll
                 for (int di = 0; di < 3; ++di) {
                     const int r = u - di;
@@ -969,12 +958,6 @@ inline Geom geom(int nx, int ny, int B) { return Geom{nx, ny, B, (uint32_t)nx * 
 
 } // namespace
 
-void wsnet_pack_input(int nx, int ny, int B, const float *x, const float *dual, uint16_t *a, hipStream_t s)
-{
-    const uint32_t V = (uint32_t)nx * ny * B;
-    hipLaunchKernelGGL(k_pack_input, dim3((V + 255) / 256), dim3(256), 0, s, V, x, dual, a);
-}
-
 namespace {
 
 int device_cus()
@@ -1109,17 +1092,27 @@ int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, c
     return SCI_OK;
 }
 
-int wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, hipStream_t s)
+int wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, const float *x, const float *base,
+                float *part, hipStream_t s)
 {
     // one workgroup (two wavefronts per SIMD) per CU
     const int slots = std::min(device_cus(), kWgBlocks);
     WgradArgs a{};
     a.w = walk_geom(nx, ny, B, slots, WalkShape<kWgNW, 4>::CI);
-    a.src.in = in;
     a.dy = dy;
     a.part = part;
     const int groups = std::min(a.w.nitems, slots);
-    hipLaunchKernelGGL(k_wgrad, dim3(groups), dim3(64 * kWgNW), 0, s, a);
+    if (in) {
+        a.src.in = in;
+        hipLaunchKernelGGL(k_wgrad<CIN_BF16>, dim3(groups), dim3(64 * kWgNW), 0, s, a);
+    } else {
+        const size_t V = (size_t)nx * ny * B;
+        a.src.x = x;
+        a.src.xb0 = base ? base : x;
+        a.src.xb1 = base ? base + V : x;
+        a.src.xb_live = base != nullptr;
+        hipLaunchKernelGGL(k_wgrad<CIN_F32>, dim3(groups), dim3(64 * kWgNW), 0, s, a);
+    }
     return groups;
 }
 

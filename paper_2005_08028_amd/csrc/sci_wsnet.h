@@ -10,7 +10,6 @@ constexpr int kNetLayers = 4;
 constexpr int kNetHidden = 16;
 constexpr int kNetSlots = 28 * 256; // per layer: [27 taps + bias][16 out][16 in] fp32 master layout
 
-void wsnet_pack_input(int nx, int ny, int B, const float *x, const float *dual, uint16_t *a, hipStream_t s);
 // 3x3x3 convolutions (Wk[27][16 out][16 in] bf16, bias nullable):
 // sign bytes [V][4]: bit e of byte q set where channel 4q+e of a bf16 [V][16] field is > 0;
 // first layer from fp32 planes x [V] and base [2][V] (nullable) with ReLU, to bf16 [V][16]
@@ -36,9 +35,11 @@ void wsnet_loss(int nx, int ny, int B, int cout, const float *y, const float *ba
 // into out[0] (part: wsnet_reduce_blocks() doubles).
 int wsnet_loss_theta(int nx, int ny, int B, const float *y, const float *base, const float *target, float *g,
                      uint16_t *dy, double *part, double *out, hipStream_t s);
-// weight-gradient partials of one layer into part (wsnet_wgrad_groups() x 28 x 256 floats); returns the
+// weight-gradient partials of one layer into part (wsnet_wgrad_groups() x 28 x 256 floats): input bf16
+// [V][16] `in`, or (in null) the first layer's fp32 planes x [V] and base [2][V] (nullable); returns the
 // number of partials written
-int wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, float *part, hipStream_t s);
+int wsnet_wgrad(int nx, int ny, int B, const uint16_t *dy, const uint16_t *in, const float *x, const float *base,
+                float *part, hipStream_t s);
 // sums `groups` partials of each of `layers` consecutive layer regions of part into grad [layers][28][256]
 void wsnet_wgrad_reduce(int layers, int groups, const float *part, float *grad, hipStream_t s);
 // Adam and the bf16 repack of `layers` consecutive layers (cin0: the first layer's input channels, coutL:

@@ -26,7 +26,7 @@ struct sci_wsnet {
     float *bias = nullptr;
     // activations for the largest volume seen
     size_t vcap = 0;
-    uint16_t *act[kNetLayers] = {nullptr, nullptr, nullptr, nullptr}; // layer inputs a0..a3
+    uint16_t *act[kNetLayers] = {nullptr, nullptr, nullptr, nullptr}; // layer inputs a1..a3 (a0: the fp32 planes)
     uint8_t *sgn[kNetLayers] = {nullptr, nullptr, nullptr, nullptr};  // sign bytes [V][4] of a1..a3 (training)
     uint16_t *dA = nullptr, *dB = nullptr;                            // gradient ping-pong
     float *y = nullptr;                                               // last layer output [c_out][V]
@@ -66,10 +66,9 @@ int ensure_acts(sci_ctx *ctx, sci_wsnet *n, size_t V, hipStream_t s)
     if (e != hipSuccess) return net_fail(ctx, e, "hipStreamSynchronize");
     free_acts(n);
     const size_t ab = V * 16 * sizeof(uint16_t);
-    for (auto &a : n->act)
-        if ((e = hipMalloc(&a, ab)) != hipSuccess) return net_fail(ctx, e, "hipMalloc(activations)");
     for (int l = 1; l < kNetLayers; ++l)
-        if ((e = hipMalloc(&n->sgn[l], V * 4)) != hipSuccess) return net_fail(ctx, e, "hipMalloc(activations)");
+        if ((e = hipMalloc(&n->act[l], ab)) != hipSuccess || (e = hipMalloc(&n->sgn[l], V * 4)) != hipSuccess)
+            return net_fail(ctx, e, "hipMalloc(activations)");
     if ((e = hipMalloc(&n->dA, ab)) != hipSuccess || (e = hipMalloc(&n->dB, ab)) != hipSuccess ||
         (e = hipMalloc(&n->y, V * (size_t)n->c_out * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&n->gth, V * sizeof(float))) != hipSuccess)
@@ -95,14 +94,12 @@ int check_net_args(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *X
 // a1 = relu(conv_0(X [, base])), read from the fp32 planes; a_{l+1} =
 // relu(conv_l(a_l)); the last layer writes the raw output planes y or, when
 // `dual` is given (a pointwise projection: ATV, ITV2D), the projected
-// (base +) output straight into it. The packed input a0 (bf16 [V][16]) and
-// the sign bytes of a1..a3 (the ReLU masks of the data gradients) are written
-// only for the gradients, whose first weight gradient reads a0.
+// (base +) output straight into it. The sign bytes of a1..a3 (the ReLU masks
+// of the data gradients) are written only for the gradients.
 void forward(sci_wsnet *n, const sci_dims &d, const float *X, const float *P_base, bool for_grads, float *dual,
              int tv, hipStream_t s)
 {
     const float *base = n->c_in == 3 ? P_base : nullptr;
-    if (for_grads) wsnet_pack_input(d.nx, d.ny, d.B, X, base, n->act[0], s);
     wsnet_conv_input(d.nx, d.ny, d.B, X, base, n->Wk, n->bias, n->act[1], for_grads ? n->sgn[1] : nullptr, s);
     for (int l = 1; l < kNetLayers - 1; ++l)
         wsnet_conv(d.nx, d.ny, d.B, n->act[l], n->Wk + (size_t)l * 27 * 256, n->bias + l * 16, true, nullptr,
@@ -114,7 +111,8 @@ void forward(sci_wsnet *n, const sci_dims &d, const float *X, const float *P_bas
 }
 
 // loss and gradients of every layer into n->g
-void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, const float *target, hipStream_t s)
+void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *X, const float *base, const float *target,
+              hipStream_t s)
 {
     const int nb = wsnet_reduce_blocks();
     const float *b = n->c_in == 3 ? base : nullptr;
@@ -125,8 +123,10 @@ void backward(sci_ctx *ctx, sci_wsnet *n, const sci_dims &d, const float *base, 
     uint16_t *dcur = n->dA, *dnext = n->dB;
     int groups = 0;
     for (int l = kNetLayers - 1; l >= 0; --l) {
-        groups = wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], n->wpart + (size_t)l * wsnet_wgrad_groups() * kNetSlots,
-                             s);
+        // the first layer's input straight from the fp32 planes, as its forward reads it
+        float *part = n->wpart + (size_t)l * wsnet_wgrad_groups() * kNetSlots;
+        groups = l == 0 ? wsnet_wgrad(d.nx, d.ny, d.B, dcur, nullptr, X, b, part, s)
+                        : wsnet_wgrad(d.nx, d.ny, d.B, dcur, n->act[l], nullptr, nullptr, part, s);
         if (l > 0) {
             // d a_l = conv^T(d y_l), masked by the ReLU of a_l (its sign bytes)
             wsnet_conv(d.nx, d.ny, d.B, dcur, n->WkT + (size_t)l * 27 * 256, nullptr, false, n->sgn[l], dnext,
@@ -276,7 +276,7 @@ int sci_wsnet_grads(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X, cons
     const size_t V = (size_t)d.nx * d.ny * d.B;
     if ((st = ensure_acts(ctx, n, V, stream)) != SCI_OK) return st;
     forward(n, d, X, P_base, true, nullptr, 0, stream);
-    backward(ctx, n, d, P_base, target, stream);
+    backward(ctx, n, d, X, P_base, target, stream);
     if ((st = check_launch(ctx, "wsnet grads")) != SCI_OK) return st;
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamSynchronize");
@@ -302,7 +302,7 @@ int sci_wsnet_train_step(sci_ctx *ctx, sci_wsnet *n, sci_dims d, const float *X,
     const size_t V = (size_t)d.nx * d.ny * d.B;
     if ((st = ensure_acts(ctx, n, V, stream)) != SCI_OK) return st;
     forward(n, d, X, P_base, true, nullptr, 0, stream);
-    backward(ctx, n, d, P_base, target, stream);
+    backward(ctx, n, d, X, P_base, target, stream);
     ++n->step;
     adam(n, lr, stream);
     if ((st = check_launch(ctx, "wsnet train step")) != SCI_OK) return st;
