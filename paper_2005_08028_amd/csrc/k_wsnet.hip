@@ -9,8 +9,10 @@
 // channels and the last layer's output channels. The convolutions are
 // implicit GEMMs on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the
 // weights as the A operand, the staged input voxels as B; the mapping is
-// described at the convolution kernel). The weight gradient runs on
-// v_mfma_f32_16x16x16bf16_1k with the voxels as K.
+// described at the convolution kernel). The weight gradient contracts over
+// voxels on the same MFMA, its voxel-major operands taken from the LDS slab by
+// transposing reads (ds_read_b64_tr_b16) and, for dy, made by
+// v_mfma_f32_16x16x16bf16_1k against the identity.
 //
 // MFMA operand layouts (checked on the hardware): 16x16x16 - lane l holds A
 // row l%16 and B column l%16 with K = 4*(l/16) .. +3; 16x16x32 - the same
@@ -38,7 +40,6 @@ __device__ inline uint16_t to_bf16(float v)
     if ((u & 0x7fffffffu) > 0x7f800000u) r = (u >> 16) | 0x40u;
     return (uint16_t)r;
 }
-__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 struct Geom {
     int nx, ny, B;
