@@ -96,6 +96,12 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
 #pragma unroll
     for (int kk = 0; kk < KF; ++kk) cpm[kk] = 0.0f;
     int par = 0; // LDS buffer of the next exchange
+    // Every exchange reads all kVtvMaxWaves slots (one fixed run of LDS reads,
+    // no loop over ng); the slots of absent wavefronts hold +0, which leaves
+    // the non-negative sum unchanged. The first exchange's barrier orders
+    // these writes before any read.
+    for (int e = (int)threadIdx.x; e < 2 * kVtvMaxWaves * 64; e += (int)blockDim.x)
+        if ((e >> 6) % kVtvMaxWaves >= ng) (&n2s[0][0][0])[e] = 0.0f;
 
     // Chunk loads of CH rows for every frame slot, from in-bounds addresses,
     // masked where consumed.
@@ -202,7 +208,8 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                 n2s[par][g][lane] = n2;
                 lds_barrier();
                 float tot = 0.0f;
-                for (int gg = 0; gg < ng; ++gg) tot += n2s[par][gg][lane];
+#pragma unroll
+                for (int gg = 0; gg < kVtvMaxWaves; ++gg) tot += n2s[par][gg][lane];
                 par ^= 1;
                 const float sc = CH_STEP ? semi_implicit_scale(tot) : iso_scale(tot);
                 const float bnext = bt.b[t + 1];
