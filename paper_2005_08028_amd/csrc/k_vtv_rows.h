@@ -58,7 +58,8 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
     constexpr int CH = kRowChunk;
     constexpr int TXO = 64 - 2 * M - 1; // interior columns per strip
     static_assert(TXO > 0, "strip too narrow for the pass length");
-    __shared__ float n2s[2][kVtvMaxWaves][64];
+    static_assert(CH == 2, "steps run in pairs, one pair per chunk");
+    __shared__ float2 n2s[2][kVtvMaxWaves][64]; // (step k, step k+1) partials
 
     const int ng = (int)(blockDim.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -83,13 +84,16 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
 
     // level t's state on its current row r, per frame slot
     float cth[M][KF], cwh[M][KF], cwv[M][KF], cph[M][KF], cpv[M][KF];
-    float xl[M + 1][KF]; // x of row k+1-t, the row level t reads in step k (t = M: the theta row)
+    // x of the rows the levels read: after the pair (k, k+1) starts, xl[t + 1]
+    // is the row level t reads in step k and xl[t] the row it reads in step
+    // k+1 (row k+2-t); xl[M+1] and xl[M] are the two theta rows
+    float xl[M + 2][KF];
 #pragma unroll
     for (int t = 0; t < M; ++t)
 #pragma unroll
         for (int kk = 0; kk < KF; ++kk) cth[t][kk] = cwh[t][kk] = cwv[t][kk] = cph[t][kk] = cpv[t][kk] = 0.0f;
 #pragma unroll
-    for (int t = 0; t <= M; ++t)
+    for (int t = 0; t <= M + 1; ++t)
 #pragma unroll
         for (int kk = 0; kk < KF; ++kk) xl[t][kk] = 0.0f;
     float cpm[KF]; // p_v^(s0+M) of the row above the theta row
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
     // the non-negative sum unchanged. The first exchange's barrier orders
     // these writes before any read.
     for (int e = (int)threadIdx.x; e < 2 * kVtvMaxWaves * 64; e += (int)blockDim.x)
-        if ((e >> 6) % kVtvMaxWaves >= ng) (&n2s[0][0][0])[e] = 0.0f;
+        if ((e >> 6) % kVtvMaxWaves >= ng) (&n2s[0][0][0])[e] = make_float2(0.0f, 0.0f);
 
     // Chunk loads of CH rows for every frame slot, from in-bounds addresses,
     // masked where consumed.
@@ -162,85 +166,111 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
             }
         }
         load_chunk(k0 + CH + 1);
+        // The two steps of the chunk run skewed: in round tau, step k0 runs
+        // level tau and step k0+1 level tau-1. (Step k, level t) needs only
+        // (k, t-1) and (k-1, t), both finished in the round before, so the
+        // two levels' partial norms share one exchange; each level's
+        // arithmetic and each sum's order are those of one step at a time.
 #pragma unroll
-        for (int s = 0; s < CH; ++s) {
-            const int k = k0 + s;
+        for (int t = M + 1; t > 1; --t)
 #pragma unroll
-            for (int t = M; t > 0; --t)
+            for (int kk = 0; kk < KF; ++kk) xl[t][kk] = xl[t - 2][kk];
 #pragma unroll
-                for (int kk = 0; kk < KF; ++kk) xl[t][kk] = xl[t - 1][kk];
+        for (int kk = 0; kk < KF; ++kk) {
+            xl[1][kk] = x0[0][kk];
+            xl[0][kk] = x0[1][kk];
+        }
+        // a step's chain: w and p handed from level t to level t+1, and
+        // p^(s0+M-1) of its output row
+        float ih[2][KF], iv[2][KF], jh[2][KF], jv[2][KF], qph[2][KF], qpv[2][KF];
 #pragma unroll
-            for (int kk = 0; kk < KF; ++kk) xl[0][kk] = x0[s][kk];
-            float ih[KF], iv[KF], jh[KF], jv[KF];
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int kk = 0; kk < KF; ++kk) {
-                ih[kk] = i0h[s][kk];
-                iv[kk] = i0v[s][kk];
-                jh[kk] = j0h[s][kk];
-                jv[kk] = j0v[s][kk];
+                ih[s][kk] = i0h[s][kk];
+                iv[s][kk] = i0v[s][kk];
+                jh[s][kk] = j0h[s][kk];
+                jv[s][kk] = j0v[s][kk];
             }
-            float qph[KF], qpv[KF]; // p^(s0+M-1) of the output row
 #pragma unroll
-            for (int t = 0; t < M; ++t) {
-                if (PB >= 0 && PB * CH + s < 2 * t) break; // this level and the later ones are idle
-                const int r = k - t;
+        for (int tau = 0; tau <= M; ++tau) {
+            // levels the pipeline fill has not reached stay idle (a level
+            // idle in step k0+1 is idle in step k0 too)
+            const bool runA = tau < M && !(PB >= 0 && PB * CH < 2 * tau);
+            const bool runB = tau >= 1 && !(PB >= 0 && PB * CH + 1 < 2 * (tau - 1));
+            if (!runA && !runB) break;
+            float thn[2][KF], qh[2][KF], qv[2][KF], n2[2] = {0.0f, 0.0f};
+            auto pre = [&](int sidx, int t) {
+                const int r = k0 + sidx - t;
                 const float step_v = (r >= 0 && r < nx - 1) ? step : 0.0f; // uniform per row
-                float thn[KF], qh[KF], qv[KF];
-                float n2 = 0.0f;
 #pragma unroll
                 for (int kk = 0; kk < KF; ++kk) {
-                    thn[kk] = theta_of(xl[t][kk], from_left(ih[kk]), ih[kk], cwv[t][kk], iv[kk], lam);
+                    thn[sidx][kk] = theta_of(xl[t + 1 - sidx][kk], from_left(ih[sidx][kk]), ih[sidx][kk], cwv[t][kk],
+                                             iv[sidx][kk], lam);
                     const float zh = from_right(cth[t][kk]) - cth[t][kk];
-                    const float zv = thn[kk] - cth[t][kk];
+                    const float zv = thn[sidx][kk] - cth[t][kk];
                     float n2a;
                     if (CH_STEP) {
                         const float sh = step_h * zh, sv = step_v * zv;
-                        qh[kk] = cwh[t][kk] + sh;
-                        qv[kk] = cwv[t][kk] + sv;
-                        n2a = norm2_add(n2, sh, sv);
+                        qh[sidx][kk] = cwh[t][kk] + sh;
+                        qv[sidx][kk] = cwv[t][kk] + sv;
+                        n2a = norm2_add(n2[sidx], sh, sv);
                     } else {
-                        qh[kk] = ascend(cwh[t][kk], zh, step_h);
-                        qv[kk] = ascend(cwv[t][kk], zv, step_v);
-                        n2a = norm2_add(n2, qh[kk], qv[kk]);
+                        qh[sidx][kk] = ascend(cwh[t][kk], zh, step_h);
+                        qv[sidx][kk] = ascend(cwv[t][kk], zv, step_v);
+                        n2a = norm2_add(n2[sidx], qh[sidx][kk], qv[sidx][kk]);
                     }
-                    n2 = kk < nk ? n2a : n2;
+                    n2[sidx] = kk < nk ? n2a : n2[sidx];
                 }
-                n2s[par][g][lane] = n2;
-                lds_barrier();
-                float tot = 0.0f;
-#pragma unroll
-                for (int gg = 0; gg < kVtvMaxWaves; ++gg) tot += n2s[par][gg][lane];
-                par ^= 1;
+            };
+            auto post = [&](int sidx, int t, float tot) {
                 const float sc = CH_STEP ? semi_implicit_scale(tot) : iso_scale(tot);
                 const float bnext = bt.b[t + 1];
 #pragma unroll
                 for (int kk = 0; kk < KF; ++kk) {
-                    const float nh = qh[kk] * sc, nv = qv[kk] * sc;
+                    const float nh = qh[sidx][kk] * sc, nv = qv[sidx][kk] * sc;
                     const float oh = extrapolate(nh, cph[t][kk], bnext);
                     const float ov = extrapolate(nv, cpv[t][kk], bnext);
                     if (t == M - 1) {
-                        qph[kk] = cph[t][kk];
-                        qpv[kk] = cpv[t][kk];
+                        qph[sidx][kk] = cph[t][kk];
+                        qpv[sidx][kk] = cpv[t][kk];
                     }
-                    cth[t][kk] = thn[kk];
-                    cwh[t][kk] = ih[kk];
-                    cwv[t][kk] = iv[kk];
-                    cph[t][kk] = jh[kk];
-                    cpv[t][kk] = jv[kk];
-                    ih[kk] = oh;
-                    iv[kk] = ov;
-                    jh[kk] = nh;
-                    jv[kk] = nv;
+                    cth[t][kk] = thn[sidx][kk];
+                    cwh[t][kk] = ih[sidx][kk];
+                    cwv[t][kk] = iv[sidx][kk];
+                    cph[t][kk] = jh[sidx][kk];
+                    cpv[t][kk] = jv[sidx][kk];
+                    ih[sidx][kk] = oh;
+                    iv[sidx][kk] = ov;
+                    jh[sidx][kk] = nh;
+                    jv[sidx][kk] = nv;
                 }
+            };
+            if (runA) pre(0, tau);
+            if (runB) pre(1, tau - 1);
+            n2s[par][g][lane] = make_float2(n2[0], n2[1]);
+            lds_barrier();
+            float totA = 0.0f, totB = 0.0f;
+#pragma unroll
+            for (int gg = 0; gg < kVtvMaxWaves; ++gg) {
+                const float2 v2 = n2s[par][gg][lane];
+                totA += v2.x;
+                totB += v2.y;
             }
-            if (PB >= 0) continue; // the theta row is above the segment
+            par ^= 1;
+            if (runA) post(0, tau, totA);
+            if (runB) post(1, tau - 1, totB);
+        }
+        if (PB >= 0) return; // the theta rows are above the segment
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
             // row r = k - M + 1 now has p^(s0+M) in jh, jv: theta = x - lambda D^T p
-            const int r = k - M + 1;
+            const int r = k0 + s - M + 1;
             float th[KF];
 #pragma unroll
             for (int kk = 0; kk < KF; ++kk) {
-                th[kk] = theta_of(xl[M][kk], from_left(jh[kk]), jh[kk], cpm[kk], jv[kk], lam);
-                cpm[kk] = jv[kk];
+                th[kk] = theta_of(xl[M + 1 - s][kk], from_left(jh[s][kk]), jh[s][kk], cpm[kk], jv[s][kk], lam);
+                cpm[kk] = jv[s][kk];
             }
             if (r >= a && r < hi && outc) {
                 const uint32_t rowo = (uint32_t)r * (uint32_t)ny;
@@ -249,14 +279,14 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                     if (kk >= nk) continue;
                     const uint32_t o = fo[kk] + rowo;
                     if (theta_out) theta_out[o] = th[kk];
-                    if (u_out) u_out[o] = xl[M][kk] - th[kk];
+                    if (u_out) u_out[o] = xl[M + 1 - s][kk] - th[kk];
                     if (pn_out) {
-                        D::st(pn_out, o, jh[kk]);
-                        D::st(pn_out, V + o, jv[kk]);
+                        D::st(pn_out, o, jh[s][kk]);
+                        D::st(pn_out, V + o, jv[s][kk]);
                     }
                     if (pp_out) {
-                        D::st(pp_out, o, qph[kk]);
-                        D::st(pp_out, V + o, qpv[kk]);
+                        D::st(pp_out, o, qph[s][kk]);
+                        D::st(pp_out, V + o, qpv[s][kk]);
                     }
                 }
             }
