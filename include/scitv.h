@@ -76,7 +76,7 @@ typedef enum { SCI_DUAL_F32 = 0, SCI_DUAL_BF16 = 1, SCI_DUAL_F16 = 2 } sci_dual_
  *   STREAM: one pass over HBM per inner iteration (dual fields in memory);
  *   FUSED : up to 10 inner iterations per on-chip pass, the dual fields
  *           written back only between passes (ATV and ITV2D with any dual
- *           type; VTV with any dual type, passes of at most 10 / 8 / 5 / 4
+ *           type; VTV with any dual type, passes of at most 10 / 10 / 7 / 4
  *           iterations for B <= 8 / 16 / 24 / 32; the Chambolle-2004 step
  *           with float32 duals on the row-pipelined kernels; ATV-Clip with
  *           float32 duals);
@@ -199,7 +199,7 @@ int sci_gap_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float
  * the same parameters and tile_passes = 1, except: Theta_out is required (it
  * holds theta between iterations); use_graph and warm_dual must be 0
  * (SCI_ERR_UNSUPPORTED); every denoiser call runs as one cold on-chip pass
- * that stores no dual, so n_inner <= 10 (VTV: 10 / 8 / 5 / 4 for
+ * that stores no dual, so n_inner <= 10 (VTV: 10 / 10 / 7 / 4 for
  * B <= 8 / 16 / 24 / 32; SCI_ERR_UNSUPPORTED beyond), schedule and
  * tile_passes are ignored and dual_dtype does not change the result. Every
  * part of the scratch is written before it is read in each call. All calls on

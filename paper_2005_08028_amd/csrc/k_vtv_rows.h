@@ -302,7 +302,7 @@ namespace sci {
 
 // Longest pass (inner iterations) the kernel runs without spilling
 // registers, by frames per wavefront; 0 where it does not run.
-constexpr int vtv_rows_max_m(int kf) { return kf == 1 ? 10 : kf == 2 ? 8 : kf == 3 ? 5 : kf == 4 ? 4 : 0; }
+constexpr int vtv_rows_max_m(int kf) { return kf == 1 ? 10 : kf == 2 ? 10 : kf == 3 ? 7 : kf == 4 ? 4 : 0; }
 
 // Segment height. A step of the kernel is bound by the latency of its chain
 // of norm exchanges, which a second workgroup on the same CU hides well and a

@@ -36,6 +36,19 @@ static int vtv_fpw(int B) { return (B + kVtvMaxWaves - 1) / kVtvMaxWaves; }
 
 int vtv_rows_max_pass(int B) { return B >= 1 ? vtv_rows_max_m(vtv_fpw(B)) : 0; }
 
+// With 2 frames per wavefront and fewer than 7 wavefronts, passes longer than
+// 8 need registers that leave one workgroup per CU instead of two, and two
+// passes of 5 beat one of 10 (measured at 1024x1024, 10 iterations: B = 9,
+// 10, 12 one pass 252, 252, 257 us against two 218, 219, 248; B = 14, 16 one
+// pass 272, 276 against two 284, 310; 3 frames per wavefront, 7 iterations:
+// one pass 211-225 against two 298-374 us for B = 17-24).
+int vtv_rows_auto_pass(int B)
+{
+    if (B < 1) return 0;
+    const int fpw = vtv_fpw(B), ng = (B + fpw - 1) / fpw;
+    return fpw == 2 && ng < 7 ? std::min(8, vtv_rows_max_m(fpw)) : vtv_rows_max_m(fpw);
+}
+
 int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,
                     bool chambolle04, int dual_dtype)
 {

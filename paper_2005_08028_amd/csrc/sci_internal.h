@@ -198,6 +198,10 @@ bool tile_shape_pipelined(int shape);
 // does not run them), and one pass of m iterations with the duals read and
 // written between passes in dual_dtype (16-bit: projection step only).
 int vtv_rows_max_pass(int B);
+// The pass length the fused schedule splits a VTV call by when it is not told
+// otherwise: the kernel's longest, except where that costs a co-resident
+// workgroup (see k_vtv_rows_kf1.hip).
+int vtv_rows_auto_pass(int B);
 int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,
                     bool chambolle04 = false, int dual_dtype = 0);
 // shape: index into the shape table (0 = default); 16-bit dual storage runs

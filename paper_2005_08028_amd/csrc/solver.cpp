@@ -244,8 +244,8 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
         const int rs = default_row_shape(ctx, d, std::min(n, kTileMaxM));
         shape = rs >= 0 ? rs : kTileShapes + 1;
     }
-    if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes the VTV kernel runs, unless more are asked for
-        const int mm = vtv_rows_max_pass(d.B);
+    if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes of the automatic length, unless more are asked for
+        const int mm = vtv_rows_auto_pass(d.B);
         if (mm < 1) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
         npass = std::min(n, std::max((n + mm - 1) / mm, p.tile_passes));
     }
@@ -928,7 +928,7 @@ int sci_gap_tv_noalloc(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, con
         if (t.n_inner > max_m || !fused_supported(t, d))
             return fail(ctx, SCI_ERR_UNSUPPORTED,
                         "the allocation-free GAP runs each denoiser call in one on-chip pass (n_inner <= 10; "
-                        "VTV: 10 / 8 / 5 / 4 for B <= 8 / 16 / 24 / 32)");
+                        "VTV: 10 / 10 / 7 / 4 for B <= 8 / 16 / 24 / 32)");
     }
     // no context event may be created here: the profiler is off for this call
     struct ProfOff {
