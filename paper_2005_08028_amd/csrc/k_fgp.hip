@@ -93,6 +93,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t V = plane * (uint32_t)B;
     const int nk = max(0, min(fpw, B - kbase)); // real frames of this wavefront
+    // VTV: every exchange reads all kMaxWaves slots in one fixed run (no loop
+    // over ng); absent wavefronts' slots hold +0, which leaves the
+    // non-negative sum unchanged. The first exchange's barrier orders these
+    // writes before any read.
+    if (TV == TV_VTV)
+        for (int e = (int)threadIdx.x; e < 2 * kMaxWaves * R * 64; e += (int)blockDim.x)
+            if ((e / (R * 64)) % kMaxWaves >= ng) (&n2s[0][0][0][0])[e] = 0.0f;
     uint32_t fo[KF];
 #pragma unroll
     for (int kk = 0; kk < KF; ++kk)
@@ -205,7 +212,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_fgp_groups(int nx, int ny, i
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 float tot = 0.0f;
-                for (int gg = 0; gg < ng; ++gg) tot += n2s[par][gg][rr][lane];
+#pragma unroll
+                for (int gg = 0; gg < kMaxWaves; ++gg) tot += n2s[par][gg][rr][lane];
                 sc[rr] = CH ? semi_implicit_scale(tot) : iso_scale(tot);
             }
             par ^= 1;
