@@ -130,6 +130,11 @@ __global__ __launch_bounds__(64 * kGapMaxWaves) void k_gap_rows(int nx, int ny, 
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t V = plane * (uint32_t)B;
     const int kbase = (fgrp * ng + g) * fpw; // fgrp = 0 for VTV
+    // VTV: the sums read all kGapMaxWaves slots in one fixed run; absent
+    // wavefronts' slots hold +0 (the first barrier orders these writes)
+    if (TV == TV_VTV)
+        for (int e = (int)threadIdx.x; e < 2 * kGapMaxWaves * 64; e += (int)blockDim.x)
+            if ((e >> 6) % kGapMaxWaves >= ng) (&s2s[0][0][0])[e] = 0.0;
     const int nk = max(0, min(fpw, B - kbase));
     uint32_t fo[KF];
 #pragma unroll
@@ -219,7 +224,8 @@ __global__ __launch_bounds__(64 * kGapMaxWaves) void k_gap_rows(int nx, int ny, 
                 lds_barrier();
                 if (g == 0 && acc) {
                     double tot = 0.0;
-                    for (int gg = 0; gg < ng; ++gg) tot += s2s[par][gg][lane];
+#pragma unroll
+                    for (int gg = 0; gg < kGapMaxWaves; ++gg) tot += s2s[par][gg][lane];
                     tv += sqrt(tot);
                 }
                 par ^= 1;
