@@ -233,9 +233,10 @@ def test_row_pipelined_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
 
 
 # 1..4 frames per wavefront (B = 8, 10, 24, 32 and splits with spare slots:
-# 3, 17, 29), several row segments, ragged strips, tiny images
-VTV_FUSED_CASES = [(1, 1, 1), (3, 2, 5), (8, 70, 33), (10, 130, 150), (17, 45, 100), (24, 64, 64), (29, 9, 130),
-                   (32, 40, 70)]
+# 3, 17, 29; B = 16 takes 10-level passes at 2 frames per wavefront), several
+# row segments, ragged strips, tiny images
+VTV_FUSED_CASES = [(1, 1, 1), (3, 2, 5), (8, 70, 33), (10, 130, 150), (16, 40, 70), (17, 45, 100), (24, 64, 64),
+                   (29, 9, 130), (32, 40, 70)]
 
 
 @pytest.mark.parametrize("B,nx,ny", VTV_FUSED_CASES)
@@ -567,7 +568,7 @@ def test_chambolle04_fused_bitwise_equals_streaming(sc, ctx, tv, B, nx, ny):
             np.testing.assert_array_equal(host(d), dref, err_msg="dual " + msg)
 
 
-@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (3, 2, 5), (10, 130, 150), (24, 64, 64), (29, 9, 130)])
+@pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (3, 2, 5), (10, 130, 150), (16, 40, 70), (24, 64, 64), (29, 9, 130)])
 def test_chambolle04_vtv_fused_bitwise_equals_streaming(sc, ctx, B, nx, ny):
     """VTV with the Chambolle-2004 step: the fused (row-pipelined) kernel
     against the streaming pass, one pass and several, cold and warm starts:
