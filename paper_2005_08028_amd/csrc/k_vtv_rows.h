@@ -44,7 +44,11 @@ constexpr int kVtvMaxWaves = 8; // wavefronts (frame groups) per workgroup, at m
 // operations of the streaming pass. DT: storage type of the duals read and
 // written between passes (arithmetic stays float32; 16-bit values are
 // rounded to nearest even where they are stored).
-template <int M, int KF, int MODE, int CH_STEP, int DT = DT_F32>
+// QIO: bit 0, p^(s0) and p^(s0-1) come as one record per voxel in pc; bit 1,
+// p^(s0+m) and p^(s0+m-1) leave as one record in pn_out (float32, projection
+// step; the records of a call's intermediate passes, one load and one store
+// instead of four).
+template <int M, int KF, int MODE, int CH_STEP, int DT = DT_F32, int QIO = 0>
 __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, int B, int fpw, int nstrip, int H,
                                                               const float *__restrict__ x,
                                                               const typename Dual<DT>::T *__restrict__ pc,
@@ -55,6 +59,9 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                                                               float *__restrict__ theta_out, float *__restrict__ u_out)
 {
     using D = Dual<DT>;
+    constexpr bool QIN = (QIO & 1) != 0, QOUT = (QIO & 2) != 0;
+    static_assert(QIO == 0 || (DT == DT_F32 && !CH_STEP), "dual records: float32 projection passes");
+    static_assert(!QIN || MODE >= 1, "a record input needs a dual start");
     constexpr int CH = kRowChunk;
     constexpr int TXO = 64 - 2 * M - 1; // interior columns per strip
     static_assert(TXO > 0, "strip too narrow for the pass length");
@@ -119,13 +126,21 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
             for (int kk = 0; kk < KF; ++kk) {
                 const uint32_t o = fo[kk] + rowo;
                 xn[s][kk] = x[o];
-                if (MODE >= 1) {
-                    lh[s][kk] = D::ld(pc, o);
-                    lv[s][kk] = D::ld(pc, V + o);
-                }
-                if (MODE == 2) {
-                    mh[s][kk] = D::ld(pp, o);
-                    mv[s][kk] = D::ld(pp, V + o);
+                if constexpr (QIN) {
+                    const float4 rec = ((const float4 *)pc)[o];
+                    lh[s][kk] = rec.x;
+                    lv[s][kk] = rec.y;
+                    mh[s][kk] = rec.z;
+                    mv[s][kk] = rec.w;
+                } else {
+                    if (MODE >= 1) {
+                        lh[s][kk] = D::ld(pc, o);
+                        lv[s][kk] = D::ld(pc, V + o);
+                    }
+                    if (MODE == 2) {
+                        mh[s][kk] = D::ld(pp, o);
+                        mv[s][kk] = D::ld(pp, V + o);
+                    }
                 }
             }
         }
@@ -280,13 +295,17 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                     const uint32_t o = fo[kk] + rowo;
                     if (theta_out) theta_out[o] = th[kk];
                     if (u_out) u_out[o] = xl[M + 1 - s][kk] - th[kk];
-                    if (pn_out) {
-                        D::st(pn_out, o, jh[s][kk]);
-                        D::st(pn_out, V + o, jv[s][kk]);
-                    }
-                    if (pp_out) {
-                        D::st(pp_out, o, qph[s][kk]);
-                        D::st(pp_out, V + o, qpv[s][kk]);
+                    if constexpr (QOUT) {
+                        ((float4 *)pn_out)[o] = make_float4(jh[s][kk], jv[s][kk], qph[s][kk], qpv[s][kk]);
+                    } else {
+                        if (pn_out) {
+                            D::st(pn_out, o, jh[s][kk]);
+                            D::st(pn_out, V + o, jv[s][kk]);
+                        }
+                        if (pp_out) {
+                            D::st(pp_out, o, qph[s][kk]);
+                            D::st(pp_out, V + o, qpv[s][kk]);
+                        }
                     }
                 }
             }
@@ -339,27 +358,55 @@ int vtv_segment_rows(K kernel, int ng, int nx, int nstrip)
     return (nx + nseg - 1) / nseg;
 }
 
-template <int M, int KF, int MODE, int CH_STEP, int DT>
+template <int M, int KF, int MODE, int CH_STEP, int DT, int QIO = 0>
 void launch_vtv_mode(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
                      hipStream_t s)
 {
     using T = typename Dual<DT>::T;
     constexpr int TXO = 64 - 2 * M - 1;
     const int nstrip = (ny + TXO - 1) / TXO;
-    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE, CH_STEP, DT>, ng, nx, nstrip);
+    const int H = vtv_segment_rows(k_vtv_rows<M, KF, MODE, CH_STEP, DT, QIO>, ng, nx, nstrip);
     const int nseg = (nx + H - 1) / H;
-    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE, CH_STEP, DT>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny, B, fpw,
-                       nstrip, H, x, (const T *)tp.pc, (const T *)tp.pp, tp.beta, lam, 1.0f / (8.0f * lam),
+    hipLaunchKernelGGL((k_vtv_rows<M, KF, MODE, CH_STEP, DT, QIO>), dim3(nstrip * nseg), dim3(64 * ng), 0, s, nx, ny,
+                       B, fpw, nstrip, H, x, (const T *)tp.pc, (const T *)tp.pp, tp.beta, lam, 1.0f / (8.0f * lam),
                        (T *)tp.pn_out, (T *)tp.pp_out, tp.theta, tp.u_out);
 }
 
-template <int M, int KF, int CH_STEP, int DT>
-void launch_vtv_m(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
-                  hipStream_t s)
+// Pass lengths with dual-record variants: float32 projection passes of at
+// least 3 iterations at 2 to 4 frames per wavefront (multi-pass calls at one
+// frame per wavefront need more than 10 iterations), at 2 frames up to 8.
+constexpr bool vtv_quad_inst(int kf, int m, int ch_step, int dt)
 {
-    if (tp.mode == 0) launch_vtv_mode<M, KF, 0, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
-    else if (tp.mode == 1) launch_vtv_mode<M, KF, 1, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
-    else launch_vtv_mode<M, KF, 2, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
+    return dt == DT_F32 && !ch_step && kf >= 2 && kf <= 4 && m >= 3 && m <= (kf == 2 ? 8 : vtv_rows_max_m(kf));
+}
+
+template <int M, int KF, int CH_STEP, int DT>
+int launch_vtv_m(int nx, int ny, int B, int fpw, int ng, const float *x, const TilePass &tp, float lam,
+                 hipStream_t s)
+{
+    const int qio = (tp.quad_in ? 1 : 0) | (tp.quad_out ? 2 : 0);
+    if (qio == 0) {
+        if (tp.mode == 0) launch_vtv_mode<M, KF, 0, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
+        else if (tp.mode == 1) launch_vtv_mode<M, KF, 1, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
+        else launch_vtv_mode<M, KF, 2, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);
+        return SCI_OK;
+    }
+    if constexpr (vtv_quad_inst(KF, M, CH_STEP, DT)) {
+        if (tp.mode == 0) {
+            if (qio != 2) return SCI_ERR_INVALID_ARG; // a cold start reads no dual
+            launch_vtv_mode<M, KF, 0, CH_STEP, DT, 2>(nx, ny, B, fpw, ng, x, tp, lam, s);
+            return SCI_OK;
+        }
+#define SCI_VTV_Q(md)                                                                                                   if (qio == 1) launch_vtv_mode<M, KF, md, CH_STEP, DT, 1>(nx, ny, B, fpw, ng, x, tp, lam, s);                        else if (qio == 2) launch_vtv_mode<M, KF, md, CH_STEP, DT, 2>(nx, ny, B, fpw, ng, x, tp, lam, s);                   else launch_vtv_mode<M, KF, md, CH_STEP, DT, 3>(nx, ny, B, fpw, ng, x, tp, lam, s);
+        if (tp.mode == 1) {
+            SCI_VTV_Q(1)
+        } else {
+            SCI_VTV_Q(2)
+        }
+#undef SCI_VTV_Q
+        return SCI_OK;
+    }
+    return SCI_ERR_UNSUPPORTED;
 }
 
 // Dispatch on the pass length m = 1..vtv_rows_max_m(KF).
@@ -372,7 +419,7 @@ int launch_vtv_kf(int m, int nx, int ny, int B, int fpw, int ng, const float *x,
     switch (m) {
 #define SCI_VTV_M(mm)                                                                                               \
     case mm:                                                                                                        \
-        if constexpr (mm <= MM) launch_vtv_m<mm, KF, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);                        \
+        if constexpr (mm <= MM) return launch_vtv_m<mm, KF, CH_STEP, DT>(nx, ny, B, fpw, ng, x, tp, lam, s);        \
         return SCI_OK;
         SCI_VTV_M(1) SCI_VTV_M(2) SCI_VTV_M(3) SCI_VTV_M(4) SCI_VTV_M(5) SCI_VTV_M(6) SCI_VTV_M(7) SCI_VTV_M(8)
         SCI_VTV_M(9) SCI_VTV_M(10)

@@ -36,17 +36,22 @@ static int vtv_fpw(int B) { return (B + kVtvMaxWaves - 1) / kVtvMaxWaves; }
 
 int vtv_rows_max_pass(int B) { return B >= 1 ? vtv_rows_max_m(vtv_fpw(B)) : 0; }
 
-// With 2 frames per wavefront and fewer than 7 wavefronts, passes longer than
-// 8 need registers that leave one workgroup per CU instead of two, and two
-// passes of 5 beat one of 10 (measured at 1024x1024, 10 iterations: B = 9,
-// 10, 12 one pass 252, 252, 257 us against two 218, 219, 248; B = 14, 16 one
-// pass 272, 276 against two 284, 310; 3 frames per wavefront, 7 iterations:
-// one pass 211-225 against two 298-374 us for B = 17-24).
-int vtv_rows_auto_pass(int B)
+bool vtv_rows_quad(int B, int m) { return B >= 1 && vtv_quad_inst(vtv_fpw(B), m, 0, DT_F32); }
+
+// With 2 frames per wavefront, passes longer than 8 need registers that cost
+// co-resident workgroups. With the dual records between passes two passes of
+// 5 beat one of 10 for every B (measured at 1024x1024, 10 iterations: B = 9,
+// 10, 12, 14, 16 one pass 214, 212, 242, 271, 276 us against two 198, 207,
+// 231, 235, 261); without them only below 7 wavefronts (B = 9, 10, 12: one
+// pass 252, 252, 257 against two 218, 219, 248; B = 14, 16: 272, 276 against
+// 284, 310). At 3 frames per wavefront one pass of 7 beats two (7 iterations,
+// B = 17-24: 213-226 against 268-319 us with records).
+int vtv_rows_auto_pass(int B, bool records)
 {
     if (B < 1) return 0;
     const int fpw = vtv_fpw(B), ng = (B + fpw - 1) / fpw;
-    return fpw == 2 && ng < 7 ? std::min(8, vtv_rows_max_m(fpw)) : vtv_rows_max_m(fpw);
+    if (fpw == 2 && (records || ng < 7)) return std::min(8, vtv_rows_max_m(fpw));
+    return vtv_rows_max_m(fpw);
 }
 
 int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,

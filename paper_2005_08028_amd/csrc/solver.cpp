@@ -97,6 +97,7 @@ bool gap_met(double rel, double tol) { return std::isfinite(rel) && rel <= tol; 
 // reads: p^(s-1) and p^(s) in, up to two new fields out.
 struct FgpRun {
     void *buf[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *quad[2] = {nullptr, nullptr}; // VTV: dual records between the passes of one call (when bound)
     const void *cur = nullptr;  // p^(s) (nullptr = zero)
     const void *prev = nullptr; // p^(s-1)
     int iters = 0;
@@ -244,11 +245,17 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
         const int rs = default_row_shape(ctx, d, std::min(n, kTileMaxM));
         shape = rs >= 0 ? rs : kTileShapes + 1;
     }
+    // VTV float32 projection passes hand their duals to the next pass of the
+    // call as one record per voxel (one load and one store instead of four),
+    // when every pass length of the split has that variant
+    const bool records = p.tv == SCI_TV_VTV && p.dual_dtype == SCI_DUAL_F32 && !p.chambolle04 && r.quad[0] && r.quad[1];
     if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes of the automatic length, unless more are asked for
-        const int mm = vtv_rows_auto_pass(d.B);
+        const int mm = vtv_rows_auto_pass(d.B, records);
         if (mm < 1) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
         npass = std::min(n, std::max((n + mm - 1) / mm, p.tile_passes));
     }
+    const bool quads = records && npass > 1 && vtv_rows_quad(d.B, n / npass) &&
+                       vtv_rows_quad(d.B, n / npass + (n % npass ? 1 : 0));
     for (int q = 0; q < npass; ++q) {
         const int m = n / npass + (q < n % npass ? 1 : 0);
         const bool last = q == npass - 1;
@@ -256,6 +263,8 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
         tp.mode = r.mode(p);
         tp.pc = r.cur;
         tp.pp = r.prev ? r.prev : r.cur;
+        tp.quad_in = quads && q > 0;
+        tp.quad_out = quads && !last;
         tp.beta.b[0] = (float)r.beta_prev;
         double bl = r.beta_prev;
         for (int t = 0; t < m; ++t) {
@@ -263,9 +272,9 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
             bl = p.accel ? b : 0.0;
             tp.beta.b[t + 1] = (float)bl;
         }
-        void *pn = (!last || keep_dual) ? r.free_buffer() : nullptr;
+        void *pn = tp.quad_out ? r.quad[q & 1] : (!last || keep_dual) ? r.free_buffer() : nullptr;
         // a one-iteration pass hands p^(s0) on as the next pass's p^(s-1)
-        void *ppn = ((!last || keep_dual) && m > 1) ? r.free_buffer(pn) : nullptr;
+        void *ppn = (!tp.quad_out && (!last || keep_dual) && m > 1) ? r.free_buffer(pn) : nullptr;
         tp.pn_out = pn;
         tp.pp_out = ppn;
         tp.theta = last ? theta : nullptr;
@@ -276,26 +285,41 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
         st = check_launch(ctx, "k_fgp_tile");
         if (st != SCI_OK) return st;
         r.beta_prev = bl;
-        r.prev = (m == 1) ? r.cur : ppn;
+        r.prev = tp.quad_out ? pn : (m == 1) ? r.cur : ppn; // a record holds both
         r.cur = pn;
         r.iters += m;
     }
     return SCI_OK;
 }
 
-int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s)
+// The four dual fields, and for VTV float32 projection passes at more than 8
+// frames (2 or more frames per wavefront) the two record buffers of
+// multi-pass calls.
+int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s, const sci_tv_params *tv = nullptr)
 {
     const size_t bytes = 2 * vol_elems(d) * dual_elem_bytes(dual_dtype);
     for (int k = 0; k < 4; ++k) {
         int st = ensure_ws(ctx, (BufSlot)(WS_DUAL0 + k), bytes, s);
         if (st != SCI_OK) return st;
     }
+    if (tv && tv->tv == SCI_TV_VTV && dual_dtype == SCI_DUAL_F32 && !tv->chambolle04 && d.B > 8)
+        for (int k = 0; k < 2; ++k) {
+            int st = ensure_ws(ctx, (BufSlot)(WS_VTVQ0 + k), 4 * vol_elems(d) * sizeof(float), s);
+            if (st != SCI_OK) return st;
+        }
     return SCI_OK;
 }
 
-void bind_duals(sci_ctx *ctx, FgpRun &r)
+// Binds the dual buffers (the record buffers only when they are large enough
+// for these dims, so a smaller earlier allocation is never used).
+void bind_duals(sci_ctx *ctx, FgpRun &r, const sci_dims &d)
 {
     for (int k = 0; k < 4; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
+    const size_t qb = 4 * vol_elems(d) * sizeof(float);
+    for (int k = 0; k < 2; ++k) {
+        const Buf &b = ctx->ws[WS_VTVQ0 + k];
+        r.quad[k] = b.bytes >= qb ? b.ptr : nullptr;
+    }
 }
 
 // VTV on the fused schedule: the row-pipelined kernel (16-bit dual storage
@@ -558,7 +582,7 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
     if (!Theta_out && (st = ensure_ws(ctx, WS_THETA, vb, s)) != SCI_OK) return st;
     if (admm && ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK || (st = ensure_ws(ctx, WS_UVOL, vb, s)) != SCI_OK))
         return st;
-    if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s, &p->tv)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), s)) != SCI_OK) return st;
 
     OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm,
@@ -652,7 +676,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     if ((st = ensure_ws(ctx, WS_SVOL, vb, s)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_XTMP, vb, s)) != SCI_OK) return st;
     if (twist && (st = ensure_ws(ctx, WS_XNEXT, vb, s)) != SCI_OK) return st;
-    if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, p->tv.dual_dtype, s, &p->tv)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_CBITS, cbits_bytes(d), s)) != SCI_OK) return st;
     double L = 0.0;
     if ((st = lipschitz(ctx, d, C, &L, s)) != SCI_OK) return st;
@@ -681,7 +705,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     }
     if ((st = check_launch(ctx, "setup")) != SCI_OK) return st;
     FgpRun r;
-    bind_duals(ctx, r);
+    bind_duals(ctx, r, d);
     double tau = 1.0;
     float ex = 0.0f; // FISTA: theta = xa + ex (xa - xb), formed by the projection as it loads
     const float a0 = (float)(1.0 - alpha), a1 = (float)(alpha - beta), a2 = (float)beta;
@@ -829,12 +853,12 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
         overlaps(dual_out, db, Theta_out, vb))
         return fail(ctx, SCI_ERR_ALIAS, "outputs must not overlap the inputs or each other");
     if ((st = use_device(ctx)) != SCI_OK) return st;
-    if ((st = ensure_duals(ctx, d, p->dual_dtype, stream)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, p->dual_dtype, stream, p)) != SCI_OK) return st;
 
     sci_tv_params q = *p;
     const bool want_dual = dual_out || rel_gap_out || adaptive;
     FgpRun r;
-    bind_duals(ctx, r);
+    bind_duals(ctx, r, d);
 
     if (q.lambda == 0.0f) {
         launch_copy(X_in, Theta_out, vb, stream);
@@ -978,7 +1002,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     if ((st = use_device(ctx)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_SINV, ib, stream)) != SCI_OK) return st;
     if (!Theta_out && (st = ensure_ws(ctx, WS_THETA, vb, stream)) != SCI_OK) return st;
-    if ((st = ensure_duals(ctx, d, SCI_DUAL_F32, stream)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, SCI_DUAL_F32, stream, &p->tv)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_XTMP, 2 * vb, stream)) != SCI_OK) return st; // predicted dual
     float *theta = Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr;
     float *Sinv = (float *)ctx->ws[WS_SINV].ptr;
@@ -992,7 +1016,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     if (p->outer_iters == 0) launch_copy(theta, X_out, vb, stream);
     if ((st = check_launch(ctx, "adaptive setup")) != SCI_OK) return st;
     FgpRun r;
-    bind_duals(ctx, r);
+    bind_duals(ctx, r, d);
     int inner = 0, fallbacks = 0, net_starts = 0;
     const void *keep = nullptr;
     for (int t = 0; t < p->outer_iters; ++t) {
@@ -1074,7 +1098,7 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     if (p->lambda == 0.0f || p->n_inner == 0) return fail(ctx, SCI_ERR_INVALID_ARG, "nothing to tune: lambda or n_inner is 0");
     if ((st = use_device(ctx)) != SCI_OK) return st;
     const size_t vb = vol_elems(d) * sizeof(float);
-    if ((st = ensure_duals(ctx, d, p->dual_dtype, stream)) != SCI_OK) return st;
+    if ((st = ensure_duals(ctx, d, p->dual_dtype, stream, p)) != SCI_OK) return st;
     if ((st = ensure_ws(ctx, WS_THETA, vb, stream)) != SCI_OK) return st;
     float *theta = (float *)ctx->ws[WS_THETA].ptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1090,7 +1114,7 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     sci_tv_params q = *p;
     q.schedule = one_per_pass ? SCI_SCHED_STREAM : SCI_SCHED_FUSED;
     FgpRun r;
-    bind_duals(ctx, r);
+    bind_duals(ctx, r, d);
     for (int sh = 0; sh < nshape && st == SCI_OK; ++sh) {
         for (int k = 0; k < kTuneSplits && st == SCI_OK; ++k) {
             const int np = one_per_pass ? n : pmin + k;
