@@ -477,6 +477,7 @@ struct OuterArgs {
     int *cflag;                // 1 when the packed masks apply
     float *svol, *u;           // ADMM only
     void *duals[4];            // dual fields (nullptr: none needed)
+    void *quads[2];            // VTV dual records between passes (nullptr: not used)
 };
 
 int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
@@ -506,6 +507,8 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
     }
     FgpRun r;
     for (int k = 0; k < 4; ++k) r.buf[k] = a.duals[k];
+    r.quad[0] = a.quads[0];
+    r.quad[1] = a.quads[1];
     const void *warm = nullptr;
     for (int t = 0; t < a.p.outer_iters; ++t) {
         if (!a.admm) {
@@ -588,8 +591,14 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
     OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm,
                 (float *)ctx->ws[WS_SINV].ptr, cbits_ptr(ctx), cflag_ptr(ctx, d),
                 admm ? (float *)ctx->ws[WS_SVOL].ptr : nullptr, admm ? (float *)ctx->ws[WS_UVOL].ptr : nullptr,
-                {nullptr, nullptr, nullptr, nullptr}};
+                {nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr}};
     for (int k = 0; k < 4; ++k) a.duals[k] = ctx->ws[WS_DUAL0 + k].ptr;
+    {
+        FgpRun rb;
+        bind_duals(ctx, rb, d); // the record buffers, when large enough for d
+        a.quads[0] = rb.quad[0];
+        a.quads[1] = rb.quad[1];
+    }
     if (!p->use_graph) return enqueue_outer(ctx, a, s);
 
     const std::string key = graph_key(a);
