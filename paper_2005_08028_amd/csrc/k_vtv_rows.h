@@ -9,9 +9,11 @@
 // slots; a slot past the last frame reads frame B-1, stays out of the norm and
 // stores nothing). All wavefronts walk the segment together, level t one row
 // behind level t-1. At every level and step each wavefront forms q for its
-// frames and their partial squared norm; the partials meet in LDS (one
-// LDS-only barrier, double-buffered) and are summed in wavefront order, so
-// every wavefront scales its frames by the same per-pixel factor. Frame split
+// frames and their partial squared norm; the two steps of a 2-row chunk run
+// one level apart, so that the partials of both travel in one exchange: they
+// meet in LDS (one LDS-only barrier per round, double-buffered, all slots
+// read in one fixed run) and are summed in wavefront order, so every
+// wavefront scales its frames by the same per-pixel factor. Frame split
 // and summation order are those of the streaming VTV pass, and the per-voxel
 // arithmetic uses the same helpers in the same order: with float32 duals the
 // results are bit-identical to streaming one iteration per pass.
