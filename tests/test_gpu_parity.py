@@ -605,6 +605,31 @@ def test_chambolle04_fused_solvers_bitwise(sc, ctx, solver):
         np.testing.assert_array_equal(tf, ts, err_msg=f"{solver} warm={warm}")
 
 
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+@pytest.mark.parametrize("B", [10, 24])
+def test_vtv_multipass_fused_solvers_bitwise(sc, ctx, solver, B):
+    """GAP / ADMM with VTV and 10 inner iterations per call, which the fused
+    schedule runs as two passes handing the duals over as one record per
+    voxel (B = 10: 2 frames per wavefront, B = 24: 3), with and without the
+    warm dual: the bits of the streaming schedule, and the oracle's result
+    within the usual tolerance."""
+    pr = synth.make_problem(70, 90, B, seed=43 + B, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (False, True):
+        kw = dict(outer_iters=3, rho=0.01, tv="vtv", lam=0.1, n_inner=10, warm_dual=warm)
+        xs, ts = run_solver(sc, ctx, solver, Y, pr.masks, schedule="stream", **kw)
+        xf, tf = run_solver(sc, ctx, solver, Y, pr.masks, schedule="fused", **kw)
+        np.testing.assert_array_equal(xf, xs, err_msg=f"{solver} B={B} warm={warm}")
+        np.testing.assert_array_equal(tf, ts, err_msg=f"{solver} B={B} warm={warm}")
+        if solver == "gap":
+            xr, _ = orc.gap_tv(Y, pr.masks, f32(0.1), 3, 10, tv="vtv", warm_dual=warm)
+        else:
+            xr, _ = orc.admm_tv(Y, pr.masks, f32(0.1), f32(0.01), 3, 10, tv="vtv", warm_dual=warm)
+        e = rel_l2(xf, xr)
+        say(f"{solver}-VTV B={B} 3 x 10 warm={warm}, fused (two passes, records) vs oracle: rel-L2 {e:.2e}")
+        assert e <= REL_TOL
+
+
 @pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (1, 2, 2), (2, 5, 3), (3, 17, 63), (4, 130, 64), (24, 16, 64)])
 def test_clip_matches_oracle(sc, ctx, B, nx, ny):
     """ATV-Clip: per-direction iterative clipping, threshold 2 lambda."""
