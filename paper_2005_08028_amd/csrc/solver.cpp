@@ -273,8 +273,9 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
             tp.beta.b[t + 1] = (float)bl;
         }
         void *pn = tp.quad_out ? r.quad[q & 1] : (!last || keep_dual) ? r.free_buffer() : nullptr;
-        // a one-iteration pass hands p^(s0) on as the next pass's p^(s-1)
-        void *ppn = (!tp.quad_out && (!last || keep_dual) && m > 1) ? r.free_buffer(pn) : nullptr;
+        // a one-iteration pass hands p^(s0) on as the next pass's p^(s-1);
+        // without acceleration no pass extrapolates, and p^(s-1) is not kept
+        void *ppn = (!tp.quad_out && (!last || keep_dual) && m > 1 && p.accel) ? r.free_buffer(pn) : nullptr;
         tp.pn_out = pn;
         tp.pp_out = ppn;
         tp.theta = last ? theta : nullptr;
