@@ -47,9 +47,38 @@ constexpr int kVtvMaxWaves = 8; // wavefronts (frame groups) per workgroup, at m
 // written between passes (arithmetic stays float32; 16-bit values are
 // rounded to nearest even where they are stored).
 // QIO: bit 0, p^(s0) and p^(s0-1) come as one record per voxel in pc; bit 1,
-// p^(s0+m) and p^(s0+m-1) leave as one record in pn_out (float32, projection
-// step; the records of a call's intermediate passes, one load and one store
-// instead of four).
+// p^(s0+m) and p^(s0+m-1) leave as one record in pn_out (projection step;
+// the records of a call's intermediate passes, one load and one store instead
+// of four; a 16-bit record holds the same rounded values as the four planar
+// stores would).
+// One voxel's dual record between passes: p_h, p_v, p_prev_h, p_prev_v in the
+// storage type (8 or 16 bytes, moved by one load or store).
+template <int DT> struct alignas(4 * sizeof(typename Dual<DT>::T)) DualRec {
+    typename Dual<DT>::T v[4];
+};
+
+// Stores of this kernel in a 16-bit type: the hardware conversions (round to
+// nearest even). For bfloat16 they give the bits of Dual<DT_BF16>::st on every
+// non-NaN input, denormals included (checked over all 2^32 float patterns on
+// the device), and a NaN stays a NaN; for binary16 they are Dual<DT_F16>::st.
+typedef float vtv_f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 vtv_b2 __attribute__((ext_vector_type(2)));
+typedef _Float16 vtv_h2 __attribute__((ext_vector_type(2)));
+
+template <int DT> __device__ inline typename Dual<DT>::T vtv_to16(float v)
+{
+    if constexpr (DT == DT_BF16) return __builtin_bit_cast(uint16_t, (__bf16)v);
+    else return (_Float16)v;
+}
+
+// two values packed into one word, the first in the low half
+template <int DT> __device__ inline uint32_t vtv_pack16(float a, float b)
+{
+    const vtv_f2 f = {a, b};
+    if constexpr (DT == DT_BF16) return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, vtv_b2));
+    else return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, vtv_h2));
+}
+
 template <int M, int KF, int MODE, int CH_STEP, int DT = DT_F32, int QIO = 0>
 __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, int B, int fpw, int nstrip, int H,
                                                               const float *__restrict__ x,
@@ -62,7 +91,7 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
 {
     using D = Dual<DT>;
     constexpr bool QIN = (QIO & 1) != 0, QOUT = (QIO & 2) != 0;
-    static_assert(QIO == 0 || (DT == DT_F32 && !CH_STEP), "dual records: float32 projection passes");
+    static_assert(QIO == 0 || !CH_STEP, "dual records: projection passes");
     static_assert(!QIN || MODE >= 1, "a record input needs a dual start");
     constexpr int CH = kRowChunk;
     constexpr int TXO = 64 - 2 * M - 1; // interior columns per strip
@@ -128,12 +157,18 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
             for (int kk = 0; kk < KF; ++kk) {
                 const uint32_t o = fo[kk] + rowo;
                 xn[s][kk] = x[o];
-                if constexpr (QIN) {
+                if constexpr (QIN && DT == DT_F32) {
                     const float4 rec = ((const float4 *)pc)[o];
                     lh[s][kk] = rec.x;
                     lv[s][kk] = rec.y;
                     mh[s][kk] = rec.z;
                     mv[s][kk] = rec.w;
+                } else if constexpr (QIN) {
+                    const DualRec<DT> rec = ((const DualRec<DT> *)pc)[o];
+                    lh[s][kk] = D::cvt(rec.v[0]);
+                    lv[s][kk] = D::cvt(rec.v[1]);
+                    mh[s][kk] = D::cvt(rec.v[2]);
+                    mv[s][kk] = D::cvt(rec.v[3]);
                 } else {
                     if (MODE >= 1) {
                         lh[s][kk] = D::ld(pc, o);
@@ -297,9 +332,12 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                     const uint32_t o = fo[kk] + rowo;
                     if (theta_out) theta_out[o] = th[kk];
                     if (u_out) u_out[o] = xl[M + 1 - s][kk] - th[kk];
-                    if constexpr (QOUT) {
+                    if constexpr (QOUT && DT == DT_F32) {
                         ((float4 *)pn_out)[o] = make_float4(jh[s][kk], jv[s][kk], qph[s][kk], qpv[s][kk]);
-                    } else {
+                    } else if constexpr (QOUT) {
+                        ((uint2 *)pn_out)[o] = make_uint2(vtv_pack16<DT>(jh[s][kk], jv[s][kk]),
+                                                          vtv_pack16<DT>(qph[s][kk], qpv[s][kk]));
+                    } else if constexpr (DT == DT_F32) {
                         if (pn_out) {
                             D::st(pn_out, o, jh[s][kk]);
                             D::st(pn_out, V + o, jv[s][kk]);
@@ -307,6 +345,15 @@ __global__ __launch_bounds__(64 * kVtvMaxWaves) void k_vtv_rows(int nx, int ny, 
                         if (pp_out) {
                             D::st(pp_out, o, qph[s][kk]);
                             D::st(pp_out, V + o, qpv[s][kk]);
+                        }
+                    } else {
+                        if (pn_out) {
+                            pn_out[o] = vtv_to16<DT>(jh[s][kk]);
+                            pn_out[V + o] = vtv_to16<DT>(jv[s][kk]);
+                        }
+                        if (pp_out) {
+                            pp_out[o] = vtv_to16<DT>(qph[s][kk]);
+                            pp_out[V + o] = vtv_to16<DT>(qpv[s][kk]);
                         }
                     }
                 }
@@ -374,12 +421,13 @@ void launch_vtv_mode(int nx, int ny, int B, int fpw, int ng, const float *x, con
                        (T *)tp.pn_out, (T *)tp.pp_out, tp.theta, tp.u_out);
 }
 
-// Pass lengths with dual-record variants: float32 projection passes of at
-// least 3 iterations at 2 to 4 frames per wavefront (multi-pass calls at one
-// frame per wavefront need more than 10 iterations), at 2 frames up to 8.
-constexpr bool vtv_quad_inst(int kf, int m, int ch_step, int dt)
+// Pass lengths with dual-record variants: projection passes of at least 3
+// iterations at 2 to 4 frames per wavefront (multi-pass calls at one frame per
+// wavefront need more than 10 iterations), at 2 frames up to 8; every storage
+// type.
+constexpr bool vtv_quad_inst(int kf, int m, int ch_step, int /*dt*/)
 {
-    return dt == DT_F32 && !ch_step && kf >= 2 && kf <= 4 && m >= 3 && m <= (kf == 2 ? 8 : vtv_rows_max_m(kf));
+    return !ch_step && kf >= 2 && kf <= 4 && m >= 3 && m <= (kf == 2 ? 8 : vtv_rows_max_m(kf));
 }
 
 template <int M, int KF, int CH_STEP, int DT>

@@ -36,7 +36,7 @@ static int vtv_fpw(int B) { return (B + kVtvMaxWaves - 1) / kVtvMaxWaves; }
 
 int vtv_rows_max_pass(int B) { return B >= 1 ? vtv_rows_max_m(vtv_fpw(B)) : 0; }
 
-bool vtv_rows_quad(int B, int m) { return B >= 1 && vtv_quad_inst(vtv_fpw(B), m, 0, DT_F32); }
+bool vtv_rows_quad(int B, int m) { return B >= 1 && vtv_quad_inst(vtv_fpw(B), m, 0, DT_F32); } // same for every type
 
 // With 2 frames per wavefront, passes longer than 8 need registers that cost
 // co-resident workgroups. With the dual records between passes two passes of

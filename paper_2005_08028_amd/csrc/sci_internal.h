@@ -189,9 +189,9 @@ struct TilePass {
     void *pp_out = nullptr;    // p^(s0+m-1)    (nullable)
     float *theta = nullptr;    // x - lambda D^T p^(s0+m) (nullable)
     float *u_out = nullptr;    // x - theta     (nullable)
-    // VTV float32 projection passes: pc (quad_in) or pn_out (quad_out) is one
-    // record (p_h, p_v, p_prev_h, p_prev_v) per voxel instead of the planar
-    // fields (pp / pp_out unused then); see vtv_rows_quad
+    // VTV projection passes: pc (quad_in) or pn_out (quad_out) is one record
+    // (p_h, p_v, p_prev_h, p_prev_v) per voxel in the storage type instead of
+    // the planar fields (pp / pp_out unused then); see vtv_rows_quad
     int quad_in = 0, quad_out = 0;
 };
 bool tile_supported(int tv);
@@ -207,8 +207,8 @@ int vtv_rows_max_pass(int B);
 // otherwise, with or without the dual records between passes: the kernel's
 // longest, except where a shorter one measured faster (k_vtv_rows_kf1.hip).
 int vtv_rows_auto_pass(int B, bool records);
-// Whether a fused VTV pass of m iterations over B frames (float32 duals,
-// projection step) reads and writes the per-voxel dual records of TilePass.
+// Whether a fused VTV pass of m iterations over B frames (projection step,
+// any storage type) reads and writes the per-voxel dual records of TilePass.
 bool vtv_rows_quad(int B, int m);
 int launch_vtv_rows(int m, int nx, int ny, int B, const float *x, const TilePass &tp, float lam, hipStream_t s,
                     bool chambolle04 = false, int dual_dtype = 0);

@@ -98,6 +98,7 @@ bool gap_met(double rel, double tol) { return std::isfinite(rel) && rel <= tol; 
 struct FgpRun {
     void *buf[4] = {nullptr, nullptr, nullptr, nullptr};
     void *quad[2] = {nullptr, nullptr}; // VTV: dual records between the passes of one call (when bound)
+    size_t quad_bytes = 0;              // size of each record buffer
     const void *cur = nullptr;  // p^(s) (nullptr = zero)
     const void *prev = nullptr; // p^(s-1)
     int iters = 0;
@@ -245,10 +246,11 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
         const int rs = default_row_shape(ctx, d, std::min(n, kTileMaxM));
         shape = rs >= 0 ? rs : kTileShapes + 1;
     }
-    // VTV float32 projection passes hand their duals to the next pass of the
-    // call as one record per voxel (one load and one store instead of four),
-    // when every pass length of the split has that variant
-    const bool records = p.tv == SCI_TV_VTV && p.dual_dtype == SCI_DUAL_F32 && !p.chambolle04 && r.quad[0] && r.quad[1];
+    // VTV projection passes hand their duals to the next pass of the call as
+    // one record per voxel in the storage type (one load and one store instead
+    // of four), when every pass length of the split has that variant
+    const bool records = p.tv == SCI_TV_VTV && !p.chambolle04 && r.quad[0] && r.quad[1] &&
+                         r.quad_bytes >= 4 * vol_elems(d) * dual_elem_bytes(p.dual_dtype);
     if (p.tv == SCI_TV_VTV) { // untuned: the fewest passes of the automatic length, unless more are asked for
         const int mm = vtv_rows_auto_pass(d.B, records);
         if (mm < 1) return fail(ctx, SCI_ERR_UNSUPPORTED, kFusedScope);
@@ -293,9 +295,9 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
     return SCI_OK;
 }
 
-// The four dual fields, and for VTV float32 projection passes at more than 8
-// frames (2 or more frames per wavefront) the two record buffers of
-// multi-pass calls.
+// The four dual fields, and for VTV projection passes at more than 8 frames
+// (2 or more frames per wavefront) the two record buffers of multi-pass calls
+// (four values of the storage type per voxel).
 int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s, const sci_tv_params *tv = nullptr)
 {
     const size_t bytes = 2 * vol_elems(d) * dual_elem_bytes(dual_dtype);
@@ -303,24 +305,21 @@ int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s,
         int st = ensure_ws(ctx, (BufSlot)(WS_DUAL0 + k), bytes, s);
         if (st != SCI_OK) return st;
     }
-    if (tv && tv->tv == SCI_TV_VTV && dual_dtype == SCI_DUAL_F32 && !tv->chambolle04 && d.B > 8)
+    if (tv && tv->tv == SCI_TV_VTV && !tv->chambolle04 && d.B > 8)
         for (int k = 0; k < 2; ++k) {
-            int st = ensure_ws(ctx, (BufSlot)(WS_VTVQ0 + k), 4 * vol_elems(d) * sizeof(float), s);
+            int st = ensure_ws(ctx, (BufSlot)(WS_VTVQ0 + k), 4 * vol_elems(d) * dual_elem_bytes(dual_dtype), s);
             if (st != SCI_OK) return st;
         }
     return SCI_OK;
 }
 
-// Binds the dual buffers (the record buffers only when they are large enough
-// for these dims, so a smaller earlier allocation is never used).
-void bind_duals(sci_ctx *ctx, FgpRun &r, const sci_dims &d)
+// Binds the dual buffers; the record buffers with their size, which a pass
+// checks against the records of its storage type and dims.
+void bind_duals(sci_ctx *ctx, FgpRun &r)
 {
     for (int k = 0; k < 4; ++k) r.buf[k] = ctx->ws[WS_DUAL0 + k].ptr;
-    const size_t qb = 4 * vol_elems(d) * sizeof(float);
-    for (int k = 0; k < 2; ++k) {
-        const Buf &b = ctx->ws[WS_VTVQ0 + k];
-        r.quad[k] = b.bytes >= qb ? b.ptr : nullptr;
-    }
+    for (int k = 0; k < 2; ++k) r.quad[k] = ctx->ws[WS_VTVQ0 + k].ptr;
+    r.quad_bytes = std::min(ctx->ws[WS_VTVQ0].bytes, ctx->ws[WS_VTVQ1].bytes);
 }
 
 // VTV on the fused schedule: the row-pipelined kernel (16-bit dual storage
@@ -479,6 +478,7 @@ struct OuterArgs {
     float *svol, *u;           // ADMM only
     void *duals[4];            // dual fields (nullptr: none needed)
     void *quads[2];            // VTV dual records between passes (nullptr: not used)
+    size_t quad_bytes;         // size of each record buffer
 };
 
 int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
@@ -510,6 +510,7 @@ int enqueue_outer(sci_ctx *ctx, const OuterArgs &a, hipStream_t s)
     for (int k = 0; k < 4; ++k) r.buf[k] = a.duals[k];
     r.quad[0] = a.quads[0];
     r.quad[1] = a.quads[1];
+    r.quad_bytes = a.quad_bytes;
     const void *warm = nullptr;
     for (int t = 0; t < a.p.outer_iters; ++t) {
         if (!a.admm) {
@@ -592,13 +593,14 @@ int run_outer(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, const
     OuterArgs a{d, *p, Y, C, X_init, X_out, Theta_out ? Theta_out : (float *)ctx->ws[WS_THETA].ptr, admm,
                 (float *)ctx->ws[WS_SINV].ptr, cbits_ptr(ctx), cflag_ptr(ctx, d),
                 admm ? (float *)ctx->ws[WS_SVOL].ptr : nullptr, admm ? (float *)ctx->ws[WS_UVOL].ptr : nullptr,
-                {nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr}};
+                {nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr}, 0};
     for (int k = 0; k < 4; ++k) a.duals[k] = ctx->ws[WS_DUAL0 + k].ptr;
     {
         FgpRun rb;
-        bind_duals(ctx, rb, d); // the record buffers, when large enough for d
+        bind_duals(ctx, rb);
         a.quads[0] = rb.quad[0];
         a.quads[1] = rb.quad[1];
+        a.quad_bytes = rb.quad_bytes;
     }
     if (!p->use_graph) return enqueue_outer(ctx, a, s);
 
@@ -715,7 +717,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     }
     if ((st = check_launch(ctx, "setup")) != SCI_OK) return st;
     FgpRun r;
-    bind_duals(ctx, r, d);
+    bind_duals(ctx, r);
     double tau = 1.0;
     float ex = 0.0f; // FISTA: theta = xa + ex (xa - xb), formed by the projection as it loads
     const float a0 = (float)(1.0 - alpha), a1 = (float)(alpha - beta), a2 = (float)beta;
@@ -868,7 +870,7 @@ int sci_tv_denoise(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float
     sci_tv_params q = *p;
     const bool want_dual = dual_out || rel_gap_out || adaptive;
     FgpRun r;
-    bind_duals(ctx, r, d);
+    bind_duals(ctx, r);
 
     if (q.lambda == 0.0f) {
         launch_copy(X_in, Theta_out, vb, stream);
@@ -1026,7 +1028,7 @@ int sci_gap_tv_adaptive(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, co
     if (p->outer_iters == 0) launch_copy(theta, X_out, vb, stream);
     if ((st = check_launch(ctx, "adaptive setup")) != SCI_OK) return st;
     FgpRun r;
-    bind_duals(ctx, r, d);
+    bind_duals(ctx, r);
     int inner = 0, fallbacks = 0, net_starts = 0;
     const void *keep = nullptr;
     for (int t = 0; t < p->outer_iters; ++t) {
@@ -1124,7 +1126,7 @@ int sci_autotune(sci_ctx *ctx, sci_dims d, const sci_tv_params *p, const float *
     sci_tv_params q = *p;
     q.schedule = one_per_pass ? SCI_SCHED_STREAM : SCI_SCHED_FUSED;
     FgpRun r;
-    bind_duals(ctx, r, d);
+    bind_duals(ctx, r);
     for (int sh = 0; sh < nshape && st == SCI_OK; ++sh) {
         for (int k = 0; k < kTuneSplits && st == SCI_OK; ++k) {
             const int np = one_per_pass ? n : pmin + k;

@@ -768,6 +768,36 @@ def test_vtv_fused_16bit_duals_between_passes(sc, ctx, B, maxpass, dt, bound):
         assert errs["fused"] <= bound and errs["stream"] <= bound
 
 
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("B,m", [(16, 8), (24, 7), (32, 4)])
+def test_vtv_16bit_records_equal_chained_calls(sc, ctx, B, m, dt):
+    """A fused VTV call of three passes with 16-bit dual storage hands the
+    dual from pass to pass as one record per voxel, rounded to the storage
+    type. Without acceleration each pass depends only on the dual it starts
+    from, so the call equals three calls of one pass each chained through a
+    16-bit dual_out / dual_init, bit for bit (theta and the returned dual),
+    cold and from a starting dual."""
+    r = np.random.default_rng(900 + B)
+    nx, ny = 37, 70
+    x = dev(r.uniform(size=(B, nx, ny)).astype(np.float32))
+    ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
+    p0 = dev(orc.project_dual(0.3 * r.normal(size=(2, B, nx, ny)), "vtv").astype(np.float32), ddt)
+    for init in (None, p0):
+        prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=3 * m, accel=False, dual_dtype=dt)
+        d_one = torch.empty((2, B, nx, ny), device="cuda", dtype=ddt)
+        th_one, _, its, _ = sc.sci_tv_denoise(ctx, x, prm, dual_init=init, dual_out=d_one)
+        assert its == 3 * m
+        prm1 = sc.tv_params(tv="vtv", lam=0.1, n_inner=m, accel=False, dual_dtype=dt)
+        d = init
+        for _ in range(3):
+            d_next = torch.empty((2, B, nx, ny), device="cuda", dtype=ddt)
+            th, _, its, _ = sc.sci_tv_denoise(ctx, x, prm1, dual_init=d, dual_out=d_next)
+            assert its == m
+            d = d_next
+        np.testing.assert_array_equal(host(th_one), host(th))
+        np.testing.assert_array_equal(d_one.view(torch.int16).cpu().numpy(), d.view(torch.int16).cpu().numpy())
+
+
 # ---------------------------------------------------------------------------
 # GAP / ADMM.
 # ---------------------------------------------------------------------------
