@@ -252,14 +252,18 @@ typedef struct {
 
 /* GAP (Eq. (21)-(22)) for n independent measurements of different sizes in
  * one go: each outer iteration is one projection launch and one fused
- * denoise launch that cover every problem still iterating, and with
- * p->use_graph the whole loop is one HIP graph launch. Results are
- * bit-identical to sci_gap_tv on each problem with the fused schedule.
- * Requirements: ATV or ITV2D, lambda > 0, 1 <= n_inner <= 10, cold start
+ * denoise launch that cover every problem still iterating (VTV, Eq. (31)-(32):
+ * one row-pipelined denoise pass per such problem), and with p->use_graph the
+ * whole loop is one HIP graph launch. Results are bit-identical to
+ * sci_gap_tv on each problem with the fused schedule.
+ * Requirements: ATV, ITV2D or VTV, lambda > 0, 1 <= n_inner <= 10 (VTV: at
+ * most 10 / 8 / 7 / 4 for B <= 8 / 16 / 24 / 32 frames, the longest single
+ * pass sci_gap_tv runs unsplit, for every problem), cold start
  * (warm_dual = 0), B <= 32 per problem; dual_dtype and schedule are
- * ignored (the dual never leaves the chip). Outputs of different problems
- * must not overlap. The tile shape is p->tv.tile_shape, else the one
- * sci_autotune_batched chose for this batch, else the default. */
+ * ignored (the dual never leaves the chip); otherwise SCI_ERR_UNSUPPORTED.
+ * Outputs of different problems must not overlap. The tile shape (ATV,
+ * ITV2D) is p->tv.tile_shape, else the one sci_autotune_batched chose for
+ * this batch, else the default. */
 int sci_gap_tv_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const sci_solver_params *p,
                        hipStream_t stream);
 
@@ -268,7 +272,8 @@ int sci_gap_tv_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const 
  * same sizes, TV kind and n_inner. Uses the problems' X_out / Theta_out as
  * scratch. best_shape_out (nullable, HOST): 1-based winner; times_ms_out
  * (nullable, HOST array of sci_tile_shape_count() doubles): mean time of one
- * batched denoise launch per shape. Synchronises `stream`. */
+ * batched denoise launch per shape. Synchronises `stream`. VTV batches have
+ * no tile shape: SCI_ERR_UNSUPPORTED. */
 int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, const sci_solver_params *p,
                          int32_t *best_shape_out, double *times_ms_out, hipStream_t stream);
 

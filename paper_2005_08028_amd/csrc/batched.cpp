@@ -1,7 +1,8 @@
 // Host driver of the batched GAP-TV solve: many independent measurements of
 // different sizes reconstructed together, one batched projection and one
-// batched fused-denoise launch per outer iteration, the whole loop captured
-// once in a HIP graph.
+// batched fused-denoise launch per outer iteration (VTV: one row-pipelined
+// pass per problem still iterating), the whole loop captured once in a HIP
+// graph.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -41,8 +42,8 @@ int validate(sci_ctx *ctx, int n, const sci_problem *probs, const sci_solver_par
 {
     if (n < 1 || !probs || !p) return fail(ctx, SCI_ERR_INVALID_ARG, "batched: n >= 1, probs and params required");
     const sci_tv_params &t = p->tv;
-    if (t.tv != SCI_TV_ATV && t.tv != SCI_TV_ITV2D)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "batched solve covers ATV and ITV2D (fused schedule)");
+    if (t.tv != SCI_TV_ATV && t.tv != SCI_TV_ITV2D && t.tv != SCI_TV_VTV)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "batched solve covers ATV, ITV2D and VTV (fused schedule)");
     if (!std::isfinite(t.lambda) || t.lambda <= 0.0f) return fail(ctx, SCI_ERR_INVALID_ARG, "batched: lambda must be > 0");
     if (t.n_inner < 1 || t.n_inner > kTileMaxM)
         return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: n_inner must be in 1..10 (one on-chip pass)");
@@ -58,6 +59,12 @@ int validate(sci_ctx *ctx, int n, const sci_problem *probs, const sci_solver_par
         if (q.d.nx < 1 || q.d.ny < 1 || q.d.B < 1 || (int64_t)q.d.nx * q.d.ny * q.d.B >= ((int64_t)1 << 31))
             return fail(ctx, SCI_ERR_INVALID_ARG, "batched: bad dims of problem " + std::to_string(i));
         if (q.d.B > 32) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched: B <= 32 per problem");
+        // VTV: the denoise is one cold pass of the length a lone solve would
+        // also run unsplit, so the dual never leaves the chip
+        if (t.tv == SCI_TV_VTV && t.n_inner > vtv_rows_auto_pass(q.d.B, true))
+            return fail(ctx, SCI_ERR_UNSUPPORTED,
+                        "batched VTV: n_inner must fit one pass (10 / 8 / 7 / 4 for B <= 8 / 16 / 24 / 32), problem " +
+                            std::to_string(i));
         if (!q.Y || !q.C || !q.X_out) return fail(ctx, SCI_ERR_INVALID_ARG, "batched: null pointer in problem " + std::to_string(i));
         if (q.outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "batched: outer_iters must be >= 0");
         const size_t vb = (size_t)q.d.nx * q.d.ny * q.d.B * 4, ib = (size_t)q.d.nx * q.d.ny * 4;
@@ -170,7 +177,17 @@ int enqueue_batch(sci_ctx *ctx, const BatchPlan &pl, const BatchProb *tab_dev, c
         }
         if (st != SCI_OK) return fail(ctx, st, "batched projection");
         if ((st = check_launch(ctx, "k_batch_project")) != SCI_OK) return st;
-        {
+        if (p.tv.tv == SCI_TV_VTV) {
+            ProfScope prof(ctx, PF_FGP_FUSED, s);
+            for (int k = 0; k < na && st == SCI_OK; ++k) {
+                const BatchProb &b = pl.tab[k];
+                TilePass tp; // cold start, theta out; the dual stays on chip
+                tp.mode = 0;
+                tp.beta = bt;
+                tp.theta = b.theta;
+                st = launch_vtv_rows(pl.m, b.nx, b.ny, b.B, b.x, tp, p.tv.lambda, s);
+            }
+        } else {
             ProfScope prof(ctx, PF_FGP_FUSED, s);
             st = launch_batch_denoise(p.tv.tv, pl.shape, pl.m, na, pl.wg_end[na], tab_dev, bt, p.tv.lambda, s);
         }
@@ -272,6 +289,7 @@ int sci_autotune_batched(sci_ctx *ctx, int32_t n, const sci_problem *probs, cons
     if (!ctx) return SCI_ERR_INVALID_ARG;
     int st = validate(ctx, n, probs, p);
     if (st != SCI_OK) return st;
+    if (p->tv.tv == SCI_TV_VTV) return fail(ctx, SCI_ERR_UNSUPPORTED, "batched VTV has no tile shape to tune");
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
         hipError_t e = hipSetDevice(ctx->device);

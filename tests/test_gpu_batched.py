@@ -1,6 +1,6 @@
-"""GPU: batched GAP-TV over measurements of different sizes equals the
-per-measurement solves bit for bit, and the per-measurement solves equal the
-FP64 oracle to the parity bar."""
+"""GPU: batched GAP-TV (ATV, ITV2D, VTV) over measurements of different sizes
+equals the per-measurement solves bit for bit, and the per-measurement solves
+equal the FP64 oracle to the parity bar."""
 import numpy as np
 import pytest
 
@@ -52,7 +52,7 @@ def make_batch(seed=0):
     return items, refs
 
 
-@pytest.mark.parametrize("tv", ["atv", "itv2d"])
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batched_equals_per_problem(sc, ctx, tv, use_graph):
     items, refs = make_batch(10)
@@ -91,6 +91,39 @@ def test_batched_every_shape_equals_per_problem(sc, ctx, tv):
             np.testing.assert_array_equal(host(it["X_out"]), r, err_msg=f"shape {k}, problem {i}")
 
 
+VTV_SIZES = [(40, 70, 20, 3), (64, 64, 24, 2), (1, 1, 1, 4), (33, 129, 32, 0), (70, 41, 9, 1), (16, 300, 17, 2)]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_vtv_many_frames(sc, ctx, use_graph):
+    """VTV batches up to 32 frames (3 and 4 frames per wavefront, one pass of
+    4 iterations): the bits of the per-problem fused solves, and the FP64
+    oracle within the parity bar."""
+    items, refs = [], []
+    for k, (nx, ny, B, T) in enumerate(VTV_SIZES):
+        pr = synth.make_problem(nx, ny, B, seed=500 + k, sigma=0.01, mask_p=0.4 + 0.05 * k,
+                                radius=(2.0, 0.2 * max(nx, ny) + 3))
+        Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+        items.append(dict(Y=dev(Y), C=dev(pr.masks), X_out=torch.empty((B, nx, ny), device="cuda"),
+                          Theta_out=torch.empty((B, nx, ny), device="cuda") if k % 2 else None, outer_iters=T))
+        refs.append((pr, Y))
+    prm = sc.solver_params(outer_iters=3, tv="vtv", lam=0.1, n_inner=4, use_graph=use_graph)
+    for it in items:
+        it["X_out"].fill_(float("nan"))
+    sc.sci_gap_tv_batched(ctx, items, prm)
+    for i, (it, (pr, Y)) in enumerate(zip(items, refs)):
+        T = it["outer_iters"] or 3
+        one = sc.solver_params(outer_iters=T, tv="vtv", lam=0.1, n_inner=4, schedule="fused")
+        th = torch.empty_like(it["C"])
+        x, _ = sc.sci_gap_tv(ctx, it["Y"], it["C"], one, Theta_out=th)
+        np.testing.assert_array_equal(host(it["X_out"]), host(x), err_msg=f"problem {i}")
+        if it["Theta_out"] is not None:
+            np.testing.assert_array_equal(host(it["Theta_out"]), host(th), err_msg=f"problem {i}")
+        ref, _ = orc.gap_tv(Y, pr.masks, float(np.float32(0.1)), T, 4, tv="vtv")
+        got = host(it["X_out"])
+        assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref), f"problem {i}"
+
+
 def test_batched_matches_oracle(sc, ctx):
     items, refs = make_batch(20)
     prm = sc.solver_params(outer_iters=3, tv="atv", lam=0.1, n_inner=4)
@@ -115,12 +148,21 @@ def test_batched_autotune_keeps_results(sc, ctx):
 
 
 def test_batched_rejects_unsupported(sc, ctx):
+    """Requests the batched solve does not run fail before any launch: a VTV
+    denoise longer than one pass for some problem (B = 16 takes at most 8),
+    n_inner above 10, lambda = 0, and tuning a VTV batch (no tile shapes)."""
     items, _ = make_batch(40)
-    for kw in (dict(tv="vtv"), dict(n_inner=11), dict(lam=0.0)):
+    for it in items:
+        it["X_out"].fill_(7.0)
+    for kw in (dict(tv="vtv", n_inner=9), dict(n_inner=11), dict(lam=0.0)):
         args = dict(outer_iters=2, tv="atv", lam=0.1, n_inner=5)
         args.update(kw)
         with pytest.raises(sc.SciError):
             sc.sci_gap_tv_batched(ctx, items, sc.solver_params(**args))
+    with pytest.raises(sc.SciError):
+        sc.sci_autotune_batched(ctx, items, sc.solver_params(outer_iters=2, tv="vtv", lam=0.1, n_inner=5))
+    for it in items:
+        assert bool((it["X_out"] == 7.0).all())
 
 
 def test_batched_workload_full_count_psnr_matches_oracle(sc, ctx):
