@@ -630,6 +630,36 @@ def test_vtv_multipass_fused_solvers_bitwise(sc, ctx, solver, B):
         assert e <= REL_TOL
 
 
+@pytest.mark.parametrize("dt,bound", [("f32", REL_TOL), ("bf16", 5e-5), ("f16", 5e-6)])
+@pytest.mark.parametrize("solver", ["gap", "admm"])
+def test_vtv_multipass_graph_replays(sc, ctx, solver, dt, bound):
+    """The same two-pass VTV solves (B = 24, records between the passes in the
+    storage type) captured in a HIP graph: every replay, with eager solves
+    between them, gives the bits of the eager solve; the result is within
+    about ten times the measured error of the oracle (rounding to 16 bits at
+    each pass boundary: 3-4e-6 bf16, 4-6e-7 fp16)."""
+    B = 24
+    pr = synth.make_problem(66, 75, B, seed=77, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    for warm in (False, True):
+        kw = dict(outer_iters=3, rho=0.01, tv="vtv", lam=0.1, n_inner=10, warm_dual=warm, dual_dtype=dt,
+                  schedule="fused")
+        xe, te = run_solver(sc, ctx, solver, Y, pr.masks, **kw)
+        for rep in range(3):
+            xg, tg = run_solver(sc, ctx, solver, Y, pr.masks, use_graph=True, **kw)
+            np.testing.assert_array_equal(xg, xe, err_msg=f"{solver} {dt} warm={warm} replay {rep}")
+            np.testing.assert_array_equal(tg, te, err_msg=f"{solver} {dt} warm={warm} replay {rep}")
+            xe2, _ = run_solver(sc, ctx, solver, Y, pr.masks, **kw)  # eager work between replays
+            np.testing.assert_array_equal(xe2, xe)
+        if solver == "gap":
+            xr, _ = orc.gap_tv(Y, pr.masks, f32(0.1), 3, 10, tv="vtv", warm_dual=warm)
+        else:
+            xr, _ = orc.admm_tv(Y, pr.masks, f32(0.1), f32(0.01), 3, 10, tv="vtv", warm_dual=warm)
+        e = rel_l2(xe, xr)
+        say(f"{solver}-VTV B={B} {dt} 3 x 10 warm={warm}, graph = eager; vs oracle rel-L2 {e:.2e}")
+        assert e <= bound
+
+
 @pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (1, 2, 2), (2, 5, 3), (3, 17, 63), (4, 130, 64), (24, 16, 64)])
 def test_clip_matches_oracle(sc, ctx, B, nx, ny):
     """ATV-Clip: per-direction iterative clipping, threshold 2 lambda."""
