@@ -114,9 +114,10 @@ typedef struct {
     int32_t chambolle04;     /* 1 = Chambolle's (2004) semi-implicit step (Sec. 2.3):
                                 p = (w + z/(8 lambda)) / (1 + |z|/(8 lambda)), z = D theta, |z| per
                                 the TV kind, in place of the projection of w + z/(8 lambda);
-                                float32 duals; fused schedule: row-pipelined passes (for ATV and
-                                ITV2D tile_shape is then a row-pipelined shape or 0). 0 =
-                                projection */
+                                fused schedule (float32 duals): row-pipelined passes (for ATV
+                                and ITV2D tile_shape is then a row-pipelined shape or 0);
+                                16-bit duals run on the streaming schedule (AUTO picks it;
+                                FUSED is SCI_ERR_UNSUPPORTED). 0 = projection */
     int32_t clip;            /* 1 = ATV-Clip (Sec. 2.3, Algorithm 1 Clip box): one dual per
                                 direction, w_d <- clip(w_d + D_d (x - D_d^T w_d) / clip_alpha,
                                 2 lambda), output x - D_h^T w_h - D_v^T w_v; tv must be ATV,

@@ -349,14 +349,15 @@ int launch_stream_dt(int tv, int nx, int ny, int B, const float *x, const void *
     return SCI_ERR_UNSUPPORTED;
 }
 
-// Chambolle-2004 step, float32 duals, every TV kind
+// Chambolle-2004 step, every TV kind and storage type
+template <int DT>
 int launch_stream_ch(int tv, int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn,
                      int mode, float beta, float lam, hipStream_t s)
 {
     switch (tv) {
-    case TV_ATV: return launch_groups<TV_ATV, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    case TV_ITV2D: return launch_groups<TV_ITV2D, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
-    case TV_VTV: return launch_groups<TV_VTV, DT_F32, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    case TV_ATV: return launch_groups<TV_ATV, DT, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    case TV_ITV2D: return launch_groups<TV_ITV2D, DT, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
+    case TV_VTV: return launch_groups<TV_VTV, DT, 1>(nx, ny, B, x, pc, pp, pn, mode, beta, lam, s);
     }
     return SCI_ERR_INVALID_ARG;
 }
@@ -366,8 +367,12 @@ int launch_stream_ch(int tv, int nx, int ny, int B, const float *x, const void *
 int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                                   const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s)
 {
-    if (dual_dtype != DT_F32) return SCI_ERR_UNSUPPORTED;
-    return launch_stream_ch(tv, nx, ny, B, x, p_cur, p_prev, p_next, mode, beta, lam, s);
+    switch (dual_dtype) {
+    case DT_F32: return launch_stream_ch<DT_F32>(tv, nx, ny, B, x, p_cur, p_prev, p_next, mode, beta, lam, s);
+    case DT_BF16: return launch_stream_ch<DT_BF16>(tv, nx, ny, B, x, p_cur, p_prev, p_next, mode, beta, lam, s);
+    case DT_F16: return launch_stream_ch<DT_F16>(tv, nx, ny, B, x, p_cur, p_prev, p_next, mode, beta, lam, s);
+    }
+    return SCI_ERR_UNSUPPORTED;
 }
 
 int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,

@@ -155,7 +155,7 @@ void launch_zero(void *dst, size_t bytes, hipStream_t s);
 int launch_fgp_stream(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                       const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
 // The same iteration with Chambolle's (2004) semi-implicit step in place of
-// the projection (float32 duals; every TV kind).
+// the projection (every storage type and TV kind).
 int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B, const float *x, const void *p_cur,
                                   const void *p_prev, void *p_next, int mode, float beta, float lam, hipStream_t s);
 // One ATV-Clip iteration: w_next = per-direction clip(w + D theta_d / alpha,

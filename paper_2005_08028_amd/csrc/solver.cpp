@@ -54,8 +54,9 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p.tile_passes < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "tile_passes must be >= 0");
     if (p.chambolle04 != 0 && p.chambolle04 != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "chambolle04 must be 0 or 1");
-    if (p.chambolle04 && p.dual_dtype != SCI_DUAL_F32)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "the Chambolle-2004 step runs with float32 duals");
+    if (p.chambolle04 && p.dual_dtype != SCI_DUAL_F32 && p.schedule == SCI_SCHED_FUSED)
+        return fail(ctx, SCI_ERR_UNSUPPORTED,
+                    "the Chambolle-2004 step with 16-bit duals runs on the streaming schedule only");
     if (p.clip != 0 && p.clip != 1) return fail(ctx, SCI_ERR_INVALID_ARG, "clip must be 0 or 1");
     if (p.clip) {
         if (p.tv != SCI_TV_ATV) return fail(ctx, SCI_ERR_INVALID_ARG, "ATV-Clip is defined for anisotropic TV");

@@ -92,7 +92,7 @@ def test_solver_validation(sc, ctx, bufs):
         (dict(tile_shape=99), sc.SCI_ERR_INVALID_ARG),
         (dict(rho=-0.5), sc.SCI_ERR_INVALID_ARG),
         (dict(outer_iters=-3), sc.SCI_ERR_INVALID_ARG),
-        (dict(chambolle04=True, dual_dtype="bf16"), sc.SCI_ERR_UNSUPPORTED),
+        (dict(chambolle04=True, dual_dtype="bf16", schedule="fused"), sc.SCI_ERR_UNSUPPORTED),
         (dict(clip=True, tv="itv2d"), sc.SCI_ERR_INVALID_ARG),  # ATV-Clip is defined for ATV only
     ]
     for kw, want in cases:

@@ -537,8 +537,56 @@ def test_chambolle04_matches_oracle(sc, ctx, tv, B, nx, ny):
         ep = np.abs(host(dual) - pref).max()
         say(f"chambolle04 {tv} B={B} {nx}x{ny} N={n} accel={accel} warm={warm}: rel-L2 {e:.2e}, dual {ep:.2e}")
         assert e <= REL_TOL and ep <= 1e-4
-    with pytest.raises(RuntimeError):
-        sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv=tv, n_inner=3, chambolle04=True, dual_dtype="bf16"))
+    with pytest.raises(RuntimeError):  # 16-bit storage: streaming only
+        sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv=tv, n_inner=3, chambolle04=True, dual_dtype="bf16",
+                                                    schedule="fused"))
+
+
+@pytest.mark.parametrize("dt,bound", [("bf16", 2e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
+def test_chambolle04_16bit_duals(sc, ctx, tv, dt, bound):
+    """The Chambolle-2004 step with 16-bit dual storage (streaming schedule,
+    which the automatic schedule picks for it): float32 arithmetic, rounding
+    at every store, so the error against the FP64 oracle is bounded as for
+    the projection step (4 lambda u per iteration); cold and warm, with and
+    without momentum; the automatic and streaming schedules agree bit for
+    bit."""
+    r = np.random.default_rng(31)
+    B, nx, ny = 5, 50, 130
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
+    p0 = dev(r.uniform(-0.5, 0.5, size=(2, B, nx, ny)).astype(np.float32), ddt)
+    u = 2.0 ** -8 if dt == "bf16" else 2.0 ** -11
+    for accel, warm in ((False, False), (True, False), (False, True)):
+        outs = []
+        for schedule in ("auto", "stream"):
+            prm = sc.tv_params(tv=tv, lam=0.1, n_inner=10, accel=accel, chambolle04=True, dual_dtype=dt,
+                               schedule=schedule)
+            th, _, its, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=p0 if warm else None)
+            assert its == 10
+            outs.append(host(th))
+        np.testing.assert_array_equal(outs[0], outs[1])
+        ref = orc.tv_denoise(x, f32(0.1), 10, tv, accel=accel, chambolle04=True,
+                             p_init=host(p0) if warm else None)
+        e = rel_l2(outs[0], ref)
+        amax = np.abs(outs[0] - ref).max()
+        say(f"chambolle04 {tv} {dt} accel={accel} warm={warm}: rel-L2 {e:.2e}, max-abs {amax:.2e}")
+        assert e <= bound
+        assert amax <= 10 * 4 * 0.1 * u
+
+
+@pytest.mark.parametrize("dt,bound", [("bf16", 5e-3), ("f16", 1e-3)])
+def test_chambolle04_16bit_gap_solve(sc, ctx, dt, bound):
+    """GAP-ITV2D with the Chambolle-2004 step, the warm dual kept in 16 bits
+    between outer iterations, against the FP64 oracle."""
+    pr = synth.make_problem(60, 90, 8, seed=61, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    x, _ = run_solver(sc, ctx, "gap", Y, pr.masks, outer_iters=4, tv="itv2d", lam=0.1, n_inner=7, warm_dual=True,
+                      chambolle04=True, dual_dtype=dt)
+    xr, _ = orc.gap_tv(Y, pr.masks, f32(0.1), 4, 7, tv="itv2d", warm_dual=True, chambolle04=True)
+    e = rel_l2(x, xr)
+    say(f"GAP-ITV2D chambolle04 {dt} 4 x 7 warm: rel-L2 {e:.2e}")
+    assert e <= bound
 
 
 @pytest.mark.parametrize("tv", ["atv", "itv2d"])
