@@ -121,9 +121,11 @@ typedef struct {
     int32_t clip;            /* 1 = ATV-Clip (Sec. 2.3, Algorithm 1 Clip box): one dual per
                                 direction, w_d <- clip(w_d + D_d (x - D_d^T w_d) / clip_alpha,
                                 2 lambda), output x - D_h^T w_h - D_v^T w_v; tv must be ATV,
-                                float32 duals, fixed n_inner (accel and chambolle04 do not
-                                apply); fused schedule: row-pipelined passes (tile_shape a
-                                row-pipelined shape or 0). 0 = FGP / projected gradient */
+                                fixed n_inner (accel and chambolle04 do not apply); fused
+                                schedule (float32 duals): row-pipelined passes (tile_shape a
+                                row-pipelined shape or 0); 16-bit duals run on the streaming
+                                schedule (AUTO picks it; FUSED is SCI_ERR_UNSUPPORTED).
+                                0 = FGP / projected gradient */
     float clip_alpha;        /* ATV-Clip step 1/clip_alpha; 0 = 4 (the largest eigenvalue of
                                 D_d D_d^T is below 4; the iteration converges for alpha > 2) */
 } sci_tv_params;

@@ -165,8 +165,9 @@ int launch_fgp_stream_chambolle04(int tv, int dual_dtype, int nx, int ny, int B,
 // w_out (nullable), theta = x - D^T w and u = x - theta (nullable).
 int launch_clip_rows(int H, int m, int nx, int ny, int B, const float *x, const float *w_in, float *w_out,
                      float alpha, float lambda, float *theta, float *u_out, hipStream_t s);
-void launch_clip(int nx, int ny, int B, const float *x, const float *w, float *w_next, float alpha, float lambda,
-                 hipStream_t s);
+// One streaming ATV-Clip iteration, duals of any storage type.
+int launch_clip(int dual_dtype, int nx, int ny, int B, const float *x, const void *w, void *w_next, float alpha,
+                float lambda, hipStream_t s);
 // theta = x - lambda D^T p; when u_out is non-null also u_out = x - theta.
 int launch_tv_theta(int dual_dtype, int nx, int ny, int B, const float *x, const void *p, float lam,
                     float *theta, float *u_out, hipStream_t s);

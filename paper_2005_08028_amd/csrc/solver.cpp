@@ -62,8 +62,10 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         if (p.tv != SCI_TV_ATV) return fail(ctx, SCI_ERR_INVALID_ARG, "ATV-Clip is defined for anisotropic TV");
         if (!(p.clip_alpha >= 0.0f) || !std::isfinite(p.clip_alpha))
             return fail(ctx, SCI_ERR_INVALID_ARG, "clip_alpha must be finite and >= 0 (0 = 4)");
-        if (p.chambolle04 || p.dual_dtype != SCI_DUAL_F32 || p.gap_tol > 0.0)
-            return fail(ctx, SCI_ERR_UNSUPPORTED, "ATV-Clip runs a fixed iteration count with float32 duals");
+        if (p.chambolle04 || p.gap_tol > 0.0)
+            return fail(ctx, SCI_ERR_UNSUPPORTED, "ATV-Clip runs a fixed iteration count");
+        if (p.dual_dtype != SCI_DUAL_F32 && p.schedule == SCI_SCHED_FUSED)
+            return fail(ctx, SCI_ERR_UNSUPPORTED, "ATV-Clip with 16-bit duals runs on the streaming schedule only");
     }
     return SCI_OK;
 }
@@ -395,9 +397,10 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
             return SCI_OK;
         }
         for (int it = 0; it < p.n_inner; ++it) {
-            float *out = (float *)r.free_buffer();
+            void *out = r.free_buffer();
             ProfScope prof(ctx, PF_FGP_STREAM, s);
-            launch_clip(d.nx, d.ny, d.B, x, (const float *)r.cur, out, alpha, p.lambda, s);
+            int st = launch_clip(p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, out, alpha, p.lambda, s);
+            if (st != SCI_OK) return fail(ctx, st, "ATV-Clip pass");
             r.prev = r.cur;
             r.cur = out;
             ++r.iters;
@@ -405,7 +408,7 @@ int denoise_fixed(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, const
         int st = check_launch(ctx, "k_clip");
         if (st != SCI_OK) return st;
         ProfScope prof(ctx, PF_TV_THETA, s);
-        st = launch_tv_theta(SCI_DUAL_F32, d.nx, d.ny, d.B, x, r.cur, 1.0f, theta, u_out, s);
+        st = launch_tv_theta(p.dual_dtype, d.nx, d.ny, d.B, x, r.cur, 1.0f, theta, u_out, s);
         if (st != SCI_OK) return fail(ctx, st, "theta pass");
         return check_launch(ctx, "k_tv_theta");
     }

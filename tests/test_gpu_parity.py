@@ -724,9 +724,44 @@ def test_clip_matches_oracle(sc, ctx, B, nx, ny):
         ew = np.abs(host(dual) - wref).max()
         say(f"clip B={B} {nx}x{ny} N={n} alpha={alpha} warm={warm}: rel-L2 {e:.2e}, dual {ew:.2e}")
         assert e <= REL_TOL and ew <= 1e-6
-    for bad in (dict(tv="itv2d"), dict(tv="atv", dual_dtype="bf16"), dict(tv="atv", gap_tol=1e-3, n_inner_max=10)):
+    for bad in (dict(tv="itv2d"), dict(tv="atv", dual_dtype="bf16", schedule="fused"),
+                dict(tv="atv", gap_tol=1e-3, n_inner_max=10)):
         with pytest.raises(RuntimeError):
             sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(lam=0.05, n_inner=3, clip=True, **bad))
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_clip_16bit_duals(sc, ctx, dt):
+    """ATV-Clip with 16-bit dual storage (streaming schedule, which the
+    automatic schedule picks for it), cold and warm: the automatic and
+    streaming schedules agree bit for bit; against the FP64 oracle the
+    error stays within the rounding of the stores (each |w| <= 2 lambda is
+    stored with relative error u, and theta = x - D^T w takes four of them:
+    at most n * 8 lambda u after n non-expansive iterations), and the
+    returned dual is the oracle's to within one rounding per iteration."""
+    r = np.random.default_rng(41)
+    B, nx, ny, lam, n = 3, 50, 130, 0.05, 8
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
+    w0 = dev(r.uniform(-0.1, 0.1, size=(2, B, nx, ny)).astype(np.float32), ddt)
+    u = 2.0 ** -8 if dt == "bf16" else 2.0 ** -11
+    for warm in (False, True):
+        outs, duals = [], []
+        for schedule in ("auto", "stream"):
+            prm = sc.tv_params(tv="atv", lam=lam, n_inner=n, clip=True, dual_dtype=dt, schedule=schedule)
+            dual = torch.empty((2, B, nx, ny), device="cuda", dtype=ddt)
+            th, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=w0 if warm else None, dual_out=dual)
+            outs.append(host(th))
+            duals.append(host(dual))
+        np.testing.assert_array_equal(outs[0], outs[1])
+        np.testing.assert_array_equal(duals[0], duals[1])
+        ref, wref = orc.clip_denoise(x, f32(lam), n, 4.0, w_init=host(w0) if warm else None, return_dual=True)
+        amax = np.abs(outs[0] - ref).max()
+        ew = np.abs(duals[0] - wref).max()
+        say(f"clip {dt} warm={warm}: rel-L2 {rel_l2(outs[0], ref):.2e}, max-abs {amax:.2e} "
+            f"(bound {n * 8 * lam * u:.2e}), dual {ew:.2e}")
+        assert amax <= n * 8 * lam * u
+        assert ew <= n * 2 * lam * u
 
 
 @pytest.mark.parametrize("B,nx,ny", [(1, 1, 1), (2, 5, 3), (3, 130, 64), (2, 300, 130), (1, 97, 214)])
