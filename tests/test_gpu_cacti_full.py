@@ -99,19 +99,29 @@ def test_cacti_200x10_matches_oracle_reference(sc, ctx, cacti, ref, dual):
     assert abs(sumsq_x - ref["sumsq_x"]) <= 2 * rel_bar * ref["sumsq_x"]
 
 
-def test_cacti_vtv_two_outer_iterations_match_oracle(sc, ctx, cacti):
-    """VTV at 1024x1024x24 (two fused row-pipelined passes of 5 per denoiser
-    call at B = 24), two outer iterations of 10, element by element against
-    the oracle."""
+@pytest.fixture(scope="module")
+def vtv_ref(cacti):
     pr, Y = cacti
-    prm = sc.solver_params(outer_iters=2, tv="vtv", lam=0.1, n_inner=10)
+    return orc.gap_tv(Y, pr.masks, float(np.float32(0.1)), 2, 10, tv="vtv")
+
+
+@pytest.mark.parametrize("dual,bound", [("f32", 1e-4), ("bf16", 2e-4), ("f16", 2.5e-5)])
+def test_cacti_vtv_two_outer_iterations_match_oracle(sc, ctx, cacti, vtv_ref, dual, bound):
+    """VTV at 1024x1024x24 (two fused row-pipelined passes of 5 per denoiser
+    call at B = 24, the dual handed from the first to the second as one
+    record per voxel in the storage type), two outer iterations of 10,
+    element by element against the oracle. 16-bit storage rounds the dual
+    once per call: measured rel-L2 of x / theta 2.3e-5 / 3.3e-5 (bf16) and
+    2.9e-6 / 4.1e-6 (fp16); the bounds are about six times those."""
+    pr, Y = cacti
+    prm = sc.solver_params(outer_iters=2, tv="vtv", lam=0.1, n_inner=10, dual_dtype=dual)
     Cd = torch.from_numpy(pr.masks).cuda()
     th = torch.empty_like(Cd)
     x, _ = sc.sci_gap_tv(ctx, torch.from_numpy(Y).cuda(), Cd, prm, Theta_out=th)
-    xr, thr = orc.gap_tv(Y, pr.masks, float(np.float32(0.1)), 2, 10, tv="vtv")
+    xr, thr = vtv_ref
     xh = x.cpu().numpy().astype(np.float64)
     e = np.linalg.norm(xh - xr) / np.linalg.norm(xr)
     et = np.linalg.norm(th.cpu().numpy().astype(np.float64) - thr) / np.linalg.norm(thr)
     dp = orc.psnr(xh, pr.truth) - orc.psnr(xr, pr.truth)
-    print(f"1024x1024x24 GAP-VTV 2x10: rel-L2 x {e:.2e} theta {et:.2e}, dPSNR {dp:+.1e} dB", flush=True)
-    assert e <= 1e-4 and et <= 1e-4 and abs(dp) <= 0.01
+    print(f"1024x1024x24 GAP-VTV 2x10 {dual}: rel-L2 x {e:.2e} theta {et:.2e}, dPSNR {dp:+.1e} dB", flush=True)
+    assert e <= bound and et <= bound and abs(dp) <= 0.01
