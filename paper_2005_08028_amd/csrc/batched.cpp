@@ -63,8 +63,9 @@ int validate(sci_ctx *ctx, int n, const sci_problem *probs, const sci_solver_par
         // also run unsplit, so the dual never leaves the chip
         if (t.tv == SCI_TV_VTV && t.n_inner > vtv_rows_auto_pass(q.d.B, true))
             return fail(ctx, SCI_ERR_UNSUPPORTED,
-                        "batched VTV: n_inner must fit one pass (10 / 8 / 7 / 4 for B <= 8 / 16 / 24 / 32), problem " +
-                            std::to_string(i));
+                        "batched VTV: n_inner must fit one pass, at most " +
+                            std::to_string(vtv_rows_auto_pass(q.d.B, true)) + " iterations for B = " +
+                            std::to_string(q.d.B) + " (problem " + std::to_string(i) + ")");
         if (!q.Y || !q.C || !q.X_out) return fail(ctx, SCI_ERR_INVALID_ARG, "batched: null pointer in problem " + std::to_string(i));
         if (q.outer_iters < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "batched: outer_iters must be >= 0");
         const size_t vb = (size_t)q.d.nx * q.d.ny * q.d.B * 4, ib = (size_t)q.d.nx * q.d.ny * 4;
