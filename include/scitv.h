@@ -99,7 +99,11 @@ typedef struct {
                                 gap <= gap_tol (checked every gap_check_every iterations,
                                 at most n_inner_max iterations; on the fused schedule the
                                 iterations between two checks run in on-chip passes of up to
-                                10); <= 0 runs exactly n_inner */
+                                10); <= 0 runs exactly n_inner. With 16-bit dual storage the
+                                gap is that of the stored dual, which rounding may move out of
+                                the unit ball by half an ulp: its gap can then come out at or
+                                slightly below zero and meet any tolerance, so tolerances
+                                below what the storage type resolves certify nothing more */
     int32_t n_inner_max;
     int32_t gap_check_every;
     int32_t tile_shape;      /* fused schedule: 0 = autotuned for this problem (sci_autotune) or the

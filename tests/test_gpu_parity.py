@@ -500,6 +500,51 @@ def test_gap_controlled_denoise(sc, ctx, tv):
     assert st == sc.SCI_NOT_CONVERGED and its == 6
 
 
+@pytest.mark.parametrize("dt,bound", [("f32", REL_TOL), ("bf16", 2e-2), ("f16", 3e-3)])
+def test_gap_controlled_vtv_records(sc, ctx, dt, bound):
+    """Gap-controlled VTV at B = 24: every 10 iterations between two gap
+    checks run as two on-chip passes that hand the dual over as one record
+    per voxel. float32: the streaming schedule's iterates bit for bit, to
+    convergence. 16-bit: at most 30 iterations towards a tolerance of 1e-12
+    (below what a 16-bit dual can certify: rounded to 16 bits it may leave the
+    unit ball by half an ulp, and its gap can then come out at or below zero,
+    which meets any tolerance), against the oracle within the storage type's
+    bound, and the reported gap is the FP64 gap of the returned dual."""
+    r = np.random.default_rng(24)
+    B, nx, ny = 24, 40, 70
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    ddt = sc.DUAL_TORCH[sc.DUAL[dt]]
+    p0 = dev(orc.project_dual(0.3 * r.normal(size=(2, B, nx, ny)), "vtv").astype(np.float32), ddt)
+    if dt == "f32":
+        out = {}
+        for schedule in ("stream", "auto"):
+            prm = sc.tv_params(tv="vtv", lam=0.1, gap_tol=1e-4, n_inner_max=3000, gap_check_every=10,
+                               schedule=schedule)
+            dual = torch.empty((2, B, nx, ny), device="cuda")
+            th, g, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=p0, dual_out=dual, want_gap=True)
+            assert st == sc.SCI_OK and g <= 1e-4
+            out[schedule] = (host(th), host(dual), its)
+        say(f"vtv B=24 gap-controlled: {out['auto'][2]} iterations on both schedules")
+        assert out["stream"][2] == out["auto"][2]
+        np.testing.assert_array_equal(out["stream"][0], out["auto"][0])
+        np.testing.assert_array_equal(out["stream"][1], out["auto"][1])
+        its, th = out["auto"][2], out["auto"][0]
+    else:
+        prm = sc.tv_params(tv="vtv", lam=0.1, gap_tol=1e-12, n_inner_max=30, gap_check_every=10, dual_dtype=dt)
+        dual = torch.empty((2, B, nx, ny), device="cuda", dtype=ddt)
+        tht, g, its, st = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=p0, dual_out=dual, want_gap=True)
+        say(f"vtv B=24 {dt} gap-controlled: status {st}, {its} iterations, rel gap {g:.3e}")
+        assert its % 10 == 0 and 10 <= its <= 30
+        assert (st == sc.SCI_NOT_CONVERGED and its == 30 and g > 1e-12) or (st == sc.SCI_OK and g <= 1e-12)
+        th = host(tht)
+        g64, prim = orc.dual_gap(x, host(dual), f32(0.1), "vtv")
+        assert abs(g - g64 / prim) <= 1e-3 * abs(g64 / prim) + 1e-9
+    ref = orc.tv_denoise(x, f32(0.1), its, "vtv", p_init=host(p0))
+    e = rel_l2(th, ref)
+    say(f"vtv B=24 {dt} gap-controlled, {its} iterations: rel-L2 {e:.2e}")
+    assert e <= bound
+
+
 @pytest.mark.parametrize("tv", ["atv", "itv2d", "vtv"])
 def test_gap_controlled_schedules_agree(sc, ctx, tv):
     """Gap-controlled denoising: iterations between gap checks run as on-chip
