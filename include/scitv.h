@@ -65,7 +65,9 @@ typedef struct {
 /* TV regulariser (Sec. 2.1). ITV2D and ITV3D are per-pixel isotropic norms:
  * ITV2D over (h, v) of one voxel (Eq. (9), dual projection Eq. (29)-(30));
  * SCI_TV_VTV is the paper's ITV3D, a norm over (h, v) of all B frames at one
- * pixel (Eq. (10), dual projection Eq. (31)-(32)). */
+ * pixel (Eq. (10), dual projection Eq. (31)-(32)); all frames of a pixel are
+ * held by one workgroup, so VTV takes B <= 48 (B <= 32 on the fused
+ * schedule, more on the streaming one; otherwise SCI_ERR_UNSUPPORTED). */
 typedef enum { SCI_TV_ATV = 0, SCI_TV_ITV2D = 1, SCI_TV_VTV = 2 } sci_tv_kind;
 
 /* Storage type of the dual fields kept in device memory between denoiser
@@ -418,7 +420,7 @@ int sci_residual_sq(sci_ctx *ctx, sci_dims d, const float *C, const float *X, co
  * P(theta) = 1/2 ||theta - x||^2 + lambda TV(theta) with
  * theta = x - lambda D^T p, all in FP64, summed in a fixed order
  * (repeated calls return identical values). Either host output may be
- * NULL. VTV with B > 32: SCI_ERR_UNSUPPORTED (as for the VTV denoiser). */
+ * NULL. VTV with B > 48: SCI_ERR_UNSUPPORTED (as for the VTV denoiser). */
 int sci_dual_gap(sci_ctx *ctx, sci_dims d, int32_t tv, int32_t dual_dtype, float lambda, const float *X,
                  const void *p, double *gap_host, double *primal_host, hipStream_t stream);
 

@@ -318,7 +318,7 @@ void launch_groups_mode(int nx, int ny, int B, int fpw, int ng, int gy, const fl
 }
 
 // VTV: B split over at most kMaxWaves wavefronts of one workgroup (at most
-// 4 frames each). Per-voxel TVs: one frame per wavefront, kMaxWaves
+// 6 frames each). Per-voxel TVs: one frame per wavefront, kMaxWaves
 // wavefronts per workgroup, frame groups along blockIdx.y.
 template <int TV, int DT, int CH>
 int launch_groups(int nx, int ny, int B, const float *x, const void *pc, const void *pp, void *pn, int mode,
@@ -336,8 +336,20 @@ int launch_groups(int nx, int ny, int B, const float *x, const void *pc, const v
     case 2: launch_groups_mode<TV, 2, DT, CH>(nx, ny, B, fpw, ng, 1, x, pc, pp, pn, mode, beta, lam, s); return SCI_OK;
     case 3: launch_groups_mode<TV, 3, DT, CH>(nx, ny, B, fpw, ng, 1, x, pc, pp, pn, mode, beta, lam, s); return SCI_OK;
     case 4: launch_groups_mode<TV, 4, DT, CH>(nx, ny, B, fpw, ng, 1, x, pc, pp, pn, mode, beta, lam, s); return SCI_OK;
+    case 5:
+        if constexpr (TV == TV_VTV) {
+            launch_groups_mode<TV, 5, DT, CH>(nx, ny, B, fpw, ng, 1, x, pc, pp, pn, mode, beta, lam, s);
+            return SCI_OK;
+        }
+        break;
+    case 6:
+        if constexpr (TV == TV_VTV) {
+            launch_groups_mode<TV, 6, DT, CH>(nx, ny, B, fpw, ng, 1, x, pc, pp, pn, mode, beta, lam, s);
+            return SCI_OK;
+        }
+        break;
     }
-    return SCI_ERR_UNSUPPORTED; // more than 32 frames
+    return SCI_ERR_UNSUPPORTED; // more than 48 frames
 }
 
 template <int DT>

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(64 * kGapMaxWaves) void k_gap_rows(int nx, int ny, 
 
 // Launch shape of k_gap_rows: frames per wavefront, wavefronts per
 // workgroup, frame groups (grid y), rows per segment, grid x. VTV keeps
-// all frames of a pixel in one workgroup (at most 8 x 4 frames); the
+// all frames of a pixel in one workgroup (at most 8 x 6 frames); the
 // per-voxel TVs take one frame per wavefront.
 struct GapShape {
     int fpw, ng, gy, rows, gx, nstrips;
@@ -312,8 +312,20 @@ int launch_gap_kf(const GapShape &sh, int nx, int ny, int B, double lam, const f
     case 2: launch_gap_rows<TV, 2, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
     case 3: launch_gap_rows<TV, 3, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
     case 4: launch_gap_rows<TV, 4, DT>(sh, nx, ny, B, lam, x, p, part, s); return SCI_OK;
+    case 5:
+        if constexpr (TV == TV_VTV) {
+            launch_gap_rows<TV, 5, DT>(sh, nx, ny, B, lam, x, p, part, s);
+            return SCI_OK;
+        }
+        break;
+    case 6:
+        if constexpr (TV == TV_VTV) {
+            launch_gap_rows<TV, 6, DT>(sh, nx, ny, B, lam, x, p, part, s);
+            return SCI_OK;
+        }
+        break;
     }
-    return SCI_ERR_UNSUPPORTED; // VTV with more than 32 frames
+    return SCI_ERR_UNSUPPORTED; // VTV with more than 48 frames
 }
 
 template <int TV>

@@ -231,7 +231,7 @@ void launch_residual_sq(int nx, int ny, int B, const float *C, const float *X, c
                         double *out_dev, hipStream_t s);
 // out_dev[0] = TV(theta), out_dev[1] = <D theta, p>, out_dev[2] = ||theta - x||^2;
 // `partials` holds gap_partial_doubles(nx, ny, B, tv) doubles. VTV with
-// B > 32: SCI_ERR_UNSUPPORTED, nothing launched.
+// B > 48: SCI_ERR_UNSUPPORTED, nothing launched.
 int launch_gap_terms(int tv, int dual_dtype, int nx, int ny, int B, float lam, const float *x, const void *p,
                      double *partials, double *out_dev, hipStream_t s);
 

@@ -48,8 +48,10 @@ int check_tv(sci_ctx *ctx, const sci_tv_params &p, const sci_dims &d)
         return fail(ctx, SCI_ERR_INVALID_ARG, "unknown dual dtype");
     if (p.schedule < SCI_SCHED_AUTO || p.schedule > SCI_SCHED_FUSED)
         return fail(ctx, SCI_ERR_INVALID_ARG, "unknown schedule");
-    if (p.tv == SCI_TV_VTV && d.B > 32)
-        return fail(ctx, SCI_ERR_UNSUPPORTED, "VTV denoiser supports B <= 32 frames");
+    if (p.tv == SCI_TV_VTV && d.B > 48)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "VTV denoiser supports B <= 48 frames");
+    if (p.tv == SCI_TV_VTV && d.B > 32 && p.schedule == SCI_SCHED_FUSED)
+        return fail(ctx, SCI_ERR_UNSUPPORTED, "VTV with more than 32 frames runs on the streaming schedule only");
     if (p.tile_shape < 0 || p.tile_shape > tile_shape_count())
         return fail(ctx, SCI_ERR_INVALID_ARG, "tile_shape out of range");
     if (p.tile_passes < 0) return fail(ctx, SCI_ERR_INVALID_ARG, "tile_passes must be >= 0");
@@ -298,8 +300,8 @@ int fgp_tile_iterate(sci_ctx *ctx, const sci_dims &d, const sci_tv_params &p, co
     return SCI_OK;
 }
 
-// The four dual fields, and for VTV projection passes at more than 8 frames
-// (2 or more frames per wavefront) the two record buffers of multi-pass calls
+// The four dual fields, and for fused VTV projection passes at 9 to 32 frames
+// (2 to 4 frames per wavefront) the two record buffers of multi-pass calls
 // (four values of the storage type per voxel).
 int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s, const sci_tv_params *tv = nullptr)
 {
@@ -308,7 +310,7 @@ int ensure_duals(sci_ctx *ctx, const sci_dims &d, int dual_dtype, hipStream_t s,
         int st = ensure_ws(ctx, (BufSlot)(WS_DUAL0 + k), bytes, s);
         if (st != SCI_OK) return st;
     }
-    if (tv && tv->tv == SCI_TV_VTV && !tv->chambolle04 && d.B > 8)
+    if (tv && tv->tv == SCI_TV_VTV && !tv->chambolle04 && d.B > 8 && d.B <= 32)
         for (int k = 0; k < 2; ++k) {
             int st = ensure_ws(ctx, (BufSlot)(WS_VTVQ0 + k), 4 * vol_elems(d) * dual_elem_bytes(dual_dtype), s);
             if (st != SCI_OK) return st;
@@ -444,7 +446,7 @@ int rel_gap(sci_ctx *ctx, const sci_dims &d, int tv, int dual_dtype, float lam, 
         p = ctx->ws[WS_DUAL2].ptr;
     }
     st = launch_gap_terms(tv, dual_dtype, d.nx, d.ny, d.B, lam, x, p, part, outd, s);
-    if (st != SCI_OK) return fail(ctx, st, "duality gap: VTV supports B <= 32 frames");
+    if (st != SCI_OK) return fail(ctx, st, "duality gap: VTV supports B <= 48 frames");
     st = check_launch(ctx, "k_gap_rows");
     if (st != SCI_OK) return st;
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, outd, 3 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -100,12 +100,12 @@ def test_solver_validation(sc, ctx, bufs):
         msg = sc.lib.sci_last_error(ctx).decode()
         assert st == want, (kw, st, msg)
         assert msg, kw
-    # VTV couples all frames of a pixel: at most 32
-    B2 = 33
-    C2 = torch.ones((B2, 4, 5), device="cuda")
-    Y2 = torch.ones((4, 5), device="cuda")
-    o2 = torch.empty((B2, 4, 5), device="cuda")
-    assert gap_call(sc, ctx, D(4, 5, B2), prm(tv="vtv"), Y2, C2, o2) == sc.SCI_ERR_UNSUPPORTED
+    # VTV couples all frames of a pixel: at most 48, and at most 32 on the fused schedule
+    for B2, kw in ((49, dict()), (33, dict(schedule="fused"))):
+        C2 = torch.ones((B2, 4, 5), device="cuda")
+        Y2 = torch.ones((4, 5), device="cuda")
+        o2 = torch.empty((B2, 4, 5), device="cuda")
+        assert gap_call(sc, ctx, D(4, 5, B2), prm(tv="vtv", **kw), Y2, C2, o2) == sc.SCI_ERR_UNSUPPORTED
     # outputs overlapping inputs
     assert gap_call(sc, ctx, d, prm(), Y, C, C) == sc.SCI_ERR_ALIAS
     assert gap_call(sc, ctx, d, prm(), Y, C, out, theta=out) != sc.SCI_OK

@@ -464,9 +464,50 @@ def test_dual_gap_shapes(sc, ctx, tv, shape):
 
 
 def test_dual_gap_vtv_frame_limit(sc, ctx):
-    x = torch.zeros((33, 8, 8), device="cuda")
+    x = torch.zeros((49, 8, 8), device="cuda")
     with pytest.raises(sc.SciError):
-        sc.sci_dual_gap(ctx, x, torch.zeros((2, 33, 8, 8), device="cuda"), "vtv", 0.1)
+        sc.sci_dual_gap(ctx, x, torch.zeros((2, 49, 8, 8), device="cuda"), "vtv", 0.1)
+
+
+@pytest.mark.parametrize("B,nx,ny", [(33, 17, 70), (40, 30, 66), (48, 9, 130)])
+def test_vtv_many_frames_streaming(sc, ctx, B, nx, ny):
+    """VTV at 33 to 48 frames (5 or 6 frames in each of 8 wavefronts, the
+    streaming schedule, which the automatic schedule picks beyond 32 frames):
+    the denoiser (cold, warm, with and without momentum; theta and dual), its
+    16-bit storage, the FP64 duality gap and a GAP solve, each against the
+    oracle; the automatic and streaming schedules agree bit for bit."""
+    r = np.random.default_rng(B + nx)
+    x = r.uniform(size=(B, nx, ny)).astype(np.float32)
+    p0 = orc.project_dual(0.3 * r.normal(size=(2, B, nx, ny)), "vtv").astype(np.float32)
+    for n, accel, warm in ((1, True, False), (7, True, False), (6, False, True), (5, True, True)):
+        outs = []
+        for schedule in ("auto", "stream"):
+            prm = sc.tv_params(tv="vtv", lam=0.1, n_inner=n, accel=accel, schedule=schedule)
+            dual = torch.empty((2, B, nx, ny), device="cuda")
+            th, _, its, _ = sc.sci_tv_denoise(ctx, dev(x), prm, dual_init=dev(p0) if warm else None, dual_out=dual)
+            assert its == n
+            outs.append((host(th), host(dual)))
+        np.testing.assert_array_equal(outs[0][0], outs[1][0])
+        np.testing.assert_array_equal(outs[0][1], outs[1][1])
+        ref, pref = orc.tv_denoise(x, f32(0.1), n, "vtv", accel=accel, p_init=p0 if warm else None,
+                                   return_dual=True)
+        e, ep = rel_l2(outs[0][0], ref), np.abs(outs[0][1] - pref).max()
+        say(f"vtv B={B} {nx}x{ny} N={n} accel={accel} warm={warm}: rel-L2 {e:.2e}, dual {ep:.2e}")
+        assert e <= REL_TOL and ep <= 1e-4
+        g, prim = sc.sci_dual_gap(ctx, dev(x), dev(outs[0][1]), "vtv", 0.1)
+        g_or, prim_or = orc.dual_gap(x, outs[0][1], f32(0.1), "vtv")
+        assert abs(g - g_or) <= 1e-9 * prim_or and abs(prim - prim_or) <= 1e-10 * prim_or
+    th16, _, _, _ = sc.sci_tv_denoise(ctx, dev(x), sc.tv_params(tv="vtv", lam=0.1, n_inner=10, dual_dtype="bf16"))
+    e16 = rel_l2(host(th16), orc.tv_denoise(x, f32(0.1), 10, "vtv"))
+    say(f"vtv B={B} bf16 duals, 10 iterations: rel-L2 {e16:.2e}")
+    assert e16 <= 2e-2
+    pr = synth.make_problem(nx, ny, B, seed=B, sigma=0.01)
+    Y = orc.measurement(pr.masks, pr.truth, pr.noise)
+    xg, _ = run_solver(sc, ctx, "gap", Y, pr.masks, outer_iters=3, tv="vtv", lam=0.1, n_inner=5, warm_dual=True)
+    xr, _ = orc.gap_tv(Y, pr.masks, f32(0.1), 3, 5, tv="vtv", warm_dual=True)
+    eg = rel_l2(xg, xr)
+    say(f"GAP-VTV B={B} 3 x 5 warm: rel-L2 {eg:.2e}")
+    assert eg <= REL_TOL
 
 
 @pytest.mark.parametrize("tv", ["itv2d", "vtv"])
@@ -1204,8 +1245,12 @@ def test_errors_are_reported(sc, ctx):
         sc.sci_gap_tv(ctx, Y, C, sc.solver_params(outer_iters=2), X_out=C)
     assert e.value.status == sc.SCI_ERR_ALIAS
     with pytest.raises(sc.SciError) as e:
-        big = torch.zeros((33, 4, 4), device="cuda")
+        big = torch.zeros((49, 4, 4), device="cuda")
         sc.sci_tv_denoise(ctx, big, sc.tv_params(tv="vtv"))
+    assert e.value.status == sc.SCI_ERR_UNSUPPORTED
+    with pytest.raises(sc.SciError) as e:
+        big = torch.zeros((33, 4, 4), device="cuda")
+        sc.sci_tv_denoise(ctx, big, sc.tv_params(tv="vtv", schedule="fused"))
     assert e.value.status == sc.SCI_ERR_UNSUPPORTED
 
 
