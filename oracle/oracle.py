@@ -62,8 +62,8 @@ def _load():
         "orc_admm_tv": (i, [i, i, i, i, d, d, i, i, i, i, i, d, P, P, P, P, P]),
         "orc_clip_denoise": (i, [i, i, i, d, d, i, P, P, P, P, P]),
         "orc_lipschitz": (d, [i, i, i, P]),
-        "orc_fista_tv": (i, [i, i, i, i, d, i, i, i, P, P, P, P, P]),
-        "orc_twist_tv": (i, [i, i, i, i, d, d, d, i, i, i, P, P, P, P, P]),
+        "orc_fista_tv": (i, [i, i, i, i, d, i, i, i, i, P, P, P, P, P]),
+        "orc_twist_tv": (i, [i, i, i, i, d, d, d, i, i, i, i, P, P, P, P, P]),
         "orc_psnr": (d, [ctypes.c_long, P, P, d]),
         "orc_residual_sq": (d, [i, i, i, P, P, P]),
         "orc_set_threads": (i, [i]),
@@ -257,22 +257,24 @@ def twist_default_ab(xi1=0.1, xim=1.0):
     return alpha, 2.0 * alpha / (xi1 + xim)
 
 
-def fista_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None):
-    """FISTA with the TV prox (Sec. 2.2). Returns (x^(T), theta^(T+1))."""
+def fista_tv(Y, C, lam, T, N, tv="atv", accel=True, x_init=None, warm_dual=False):
+    """FISTA with the TV prox (Sec. 2.2). Returns (x^(T), theta^(T+1)).
+    warm_dual: each prox call starts from the previous call's final dual."""
     Y, C = _d(Y), _d(C)
     B, nx, ny = _dims(C)
     x = np.empty((B, nx, ny))
     th = np.empty((B, nx, ny))
     xi = None if x_init is None else _d(x_init)
-    rc = _load().orc_fista_tv(_kind(tv), B, nx, ny, float(lam), int(T), int(N), int(bool(accel)), _p(Y), _p(C),
-                              _p(xi), _p(x), _p(th))
+    rc = _load().orc_fista_tv(_kind(tv), B, nx, ny, float(lam), int(T), int(N), int(bool(accel)),
+                              int(bool(warm_dual)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
     if rc != 0:
         raise ValueError("FISTA needs a nonzero mask (L(f) > 0)")
     return x, th
 
 
-def twist_tv(Y, C, lam, T, N, tv="atv", alpha=None, beta=None, accel=True, x_init=None):
-    """TwIST with the TV denoiser (Sec. 2.2). Returns (x^(T), theta^(T-1))."""
+def twist_tv(Y, C, lam, T, N, tv="atv", alpha=None, beta=None, accel=True, x_init=None, warm_dual=False):
+    """TwIST with the TV denoiser (Sec. 2.2). Returns (x^(T), theta^(T-1)).
+    warm_dual: each denoiser call starts from the previous call's final dual."""
     if alpha is None or beta is None:
         alpha, beta = twist_default_ab()
     Y, C = _d(Y), _d(C)
@@ -281,7 +283,7 @@ def twist_tv(Y, C, lam, T, N, tv="atv", alpha=None, beta=None, accel=True, x_ini
     th = np.empty((B, nx, ny))
     xi = None if x_init is None else _d(x_init)
     rc = _load().orc_twist_tv(_kind(tv), B, nx, ny, float(lam), float(alpha), float(beta), int(T), int(N),
-                              int(bool(accel)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
+                              int(bool(accel)), int(bool(warm_dual)), _p(Y), _p(C), _p(xi), _p(x), _p(th))
     if rc != 0:
         raise ValueError("TwIST needs a nonzero mask (L(f) > 0)")
     return x, th

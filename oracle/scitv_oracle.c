@@ -568,13 +568,17 @@ static void grad_step(int B, int nx, int ny, const double *C, const double *Y, d
  *   theta^(t+1) = x^(t) + (tau^(t) - 1) / tau^(t+1) (x^(t) - x^(t-1))
  * (the printed extrapolation uses x^(t+1) - x^(t), which is not yet known at
  * that point; Beck and Teboulle's method extrapolates along x^(t) - x^(t-1)).
+ * warm = 1: each denoiser call starts from the previous call's final dual (the
+ * warm-dual reading of the GAP and ADMM loops; the paper starts every call at
+ * zero); warm = 0: every call starts at zero.
  * Returns x^(T) and theta^(T+1); -1 if every mask entry is zero (L = 0). */
-int orc_fista_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel, const double *Y,
-                 const double *C, const double *x_init, double *x_out, double *theta_out)
+int orc_fista_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, int accel, int warm,
+                 const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
 {
     size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
     const double L = orc_lipschitz(B, nx, ny, C);
     if (!(L > 0.0)) return -1;
+    double *P = (double *)calloc(2 * V, sizeof(double)); /* carried dual [2][V] (warm) */
     double *r = (double *)malloc(n * sizeof(double));
     double *cr = (double *)malloc(V * sizeof(double));
     double *th = (double *)malloc(V * sizeof(double));
@@ -588,7 +592,7 @@ int orc_fista_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, i
     for (int t = 1; t <= T; ++t) {
         memcpy(xp, x, V * sizeof(double));
         grad_step(B, nx, ny, C, Y, 1.0 / L, th, r, cr, z);
-        orc_tv_denoise(kind, B, nx, ny, lambda / L, N, accel, 0, 0, z, NULL, x, NULL, NULL);
+        orc_tv_denoise(kind, B, nx, ny, lambda / L, N, accel, 0, 0, z, warm ? P : NULL, x, P, P + V);
         const double tau1 = (1.0 + sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
         const double c = (tau - 1.0) / tau1;
         for (size_t k = 0; k < V; ++k) th[k] = x[k] + c * (x[k] - xp[k]);
@@ -596,7 +600,7 @@ int orc_fista_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, i
     }
     memcpy(x_out, x, V * sizeof(double));
     if (theta_out) memcpy(theta_out, th, V * sizeof(double));
-    free(r); free(cr); free(th); free(z); free(x); free(xp);
+    free(P); free(r); free(cr); free(th); free(z); free(x); free(xp);
     return 0;
 }
 
@@ -608,14 +612,16 @@ int orc_fista_tv(int kind, int B, int nx, int ny, double lambda, int T, int N, i
  *   x^(1)     = theta^(0)  (one plain iterative-shrinkage step starts the
  *               two-step recursion, which needs x^(t-1))
  *   x^(t+1)   = (1 - alpha) x^(t-1) + (alpha - beta) x^(t) + beta theta^(t),  t >= 1
+ * warm as for FISTA.
  * Returns x^(T) and theta^(T-1) (the last denoiser output; x^(0) when T = 0);
  * -1 if L = 0. */
 int orc_twist_tv(int kind, int B, int nx, int ny, double lambda, double alpha, double beta, int T, int N, int accel,
-                 const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
+                 int warm, const double *Y, const double *C, const double *x_init, double *x_out, double *theta_out)
 {
     size_t V = (size_t)B * nx * ny, n = (size_t)nx * ny;
     const double L = orc_lipschitz(B, nx, ny, C);
     if (!(L > 0.0)) return -1;
+    double *P = (double *)calloc(2 * V, sizeof(double)); /* carried dual [2][V] (warm) */
     double *r = (double *)malloc(n * sizeof(double));
     double *cr = (double *)malloc(V * sizeof(double));
     double *th = (double *)malloc(V * sizeof(double));
@@ -627,7 +633,7 @@ int orc_twist_tv(int kind, int B, int nx, int ny, double lambda, double alpha, d
     memcpy(th, x, V * sizeof(double));
     for (int t = 0; t < T; ++t) {
         grad_step(B, nx, ny, C, Y, 1.0 / L, x, r, cr, z);
-        orc_tv_denoise(kind, B, nx, ny, lambda / L, N, accel, 0, 0, z, NULL, th, NULL, NULL);
+        orc_tv_denoise(kind, B, nx, ny, lambda / L, N, accel, 0, 0, z, warm ? P : NULL, th, P, P + V);
         if (t == 0) {
             memcpy(xp, x, V * sizeof(double));
             memcpy(x, th, V * sizeof(double));
@@ -641,7 +647,7 @@ int orc_twist_tv(int kind, int B, int nx, int ny, double lambda, double alpha, d
     }
     memcpy(x_out, x, V * sizeof(double));
     if (theta_out) memcpy(theta_out, th, V * sizeof(double));
-    free(r); free(cr); free(th); free(z); free(x); free(xp);
+    free(P); free(r); free(cr); free(th); free(z); free(x); free(xp);
     return 0;
 }
 

@@ -570,6 +570,58 @@ def test_warm_dual_admm_and_chambolle04_outer():
     assert np.abs(xs - xh).max() < 1e-4
 
 
+def explicit_prox_grad(Y, C, lam, T, N, tv, warm, twist, alpha=None, beta=None):
+    """FISTA (twist = False) or TwIST written out from the primitives, the
+    prox dual carried by hand when warm."""
+    L = orc.lipschitz(C)
+    x = orc.adjoint(C, Y)
+    th = x.copy()
+    xp = None
+    tau, p = 1.0, None
+    for t in range(T):
+        base = x if twist else th
+        z = base + orc.adjoint(C, Y - orc.forward(C, base)) / L
+        d, pn = orc.tv_denoise(z, lam / L, N, tv, p_init=p if warm else None, return_dual=True)
+        p = pn
+        if twist:
+            th = d
+            if t == 0:
+                xp, x = x, d
+            else:
+                xp, x = x, (1.0 - alpha) * xp + (alpha - beta) * x + beta * d
+        else:
+            xp, x = x, d
+            tau1 = (1.0 + math.sqrt(1.0 + 4.0 * tau * tau)) / 2.0
+            th = x + (tau - 1.0) / tau1 * (x - xp)
+            tau = tau1
+    return x, th
+
+
+@pytest.mark.parametrize("twist", [False, True])
+def test_warm_dual_fista_twist(twist):
+    """Warm duals in FISTA / TwIST (each prox call starts from the previous
+    call's final dual): the drivers equal the loops written out with the
+    dual carried by hand; one outer iteration equals the cold start; with few
+    inner iterations the start matters, with converged inner solves it does
+    not (the prox is unique)."""
+    C, X, Y = small_problem(43, B=3, nx=9, ny=8)
+    a, b = orc.twist_default_ab()
+
+    def run(T, N, warm):
+        if twist:
+            return orc.twist_tv(Y, C, 0.1, T, N, tv="itv2d", alpha=a, beta=b, warm_dual=warm)
+        return orc.fista_tv(Y, C, 0.1, T, N, tv="itv2d", warm_dual=warm)
+
+    for warm in (False, True):
+        xw, tw = run(4, 3, warm)
+        xe, te = explicit_prox_grad(Y, C, 0.1, 4, 3, "itv2d", warm, twist, a, b)
+        np.testing.assert_allclose(xw, xe, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(tw, te, rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(run(1, 3, True)[0], run(1, 3, False)[0])
+    assert np.abs(run(4, 3, True)[0] - run(4, 3, False)[0]).max() > 1e-6
+    assert np.abs(run(3, 3000, True)[0] - run(3, 3000, False)[0]).max() < 1e-7
+
+
 # ---------------------------------------------------------------------------
 # FISTA and TwIST (Sec. 2.2) for 1/2 ||y - Phi x||^2 + lambda TV(x).
 # ---------------------------------------------------------------------------
