@@ -231,9 +231,10 @@ int sci_admm_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const floa
  *   z = theta^(t) + (1/L) Phi^T (y - Phi theta^(t)),
  *   x^(t) = TVdenoise(z) with weight lambda / L (p->tv otherwise),
  *   theta^(t+1) = x^(t) + (tau^(t) - 1) / tau^(t+1) (x^(t) - x^(t-1)).
- * X_out = x^(T); Theta_out (nullable) = theta^(T+1). Runs eagerly (L is read
- * back, which synchronises `stream` once): p->use_graph and p->warm_dual
- * must be 0. SCI_ERR_INVALID_ARG when every mask entry is 0. */
+ * X_out = x^(T); Theta_out (nullable) = theta^(T+1). p->warm_dual = 1 starts
+ * each prox call from the previous call's final dual. Runs eagerly (L is read
+ * back, which synchronises `stream` once): p->use_graph must be 0.
+ * SCI_ERR_INVALID_ARG when every mask entry is 0. */
 int sci_fista_tv(sci_ctx *ctx, sci_dims d, const sci_solver_params *p, const float *Y, const float *C, float *X_out,
                  float *Theta_out, const float *X_init, hipStream_t stream);
 

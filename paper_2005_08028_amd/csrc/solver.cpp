@@ -681,7 +681,6 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     int st = check_outer_args(ctx, d, p, Y, C, X_out, Theta_out, X_init);
     if (st != SCI_OK) return st;
     if (p->use_graph) return fail(ctx, SCI_ERR_UNSUPPORTED, "FISTA / TwIST run eagerly (L(f) is read back)");
-    if (p->warm_dual) return fail(ctx, SCI_ERR_UNSUPPORTED, "FISTA / TwIST start every denoiser call cold");
     double alpha = p->twist_alpha, beta = p->twist_beta;
     if (twist) {
         if (alpha == 0.0 && beta == 0.0) twist_defaults(&alpha, &beta);
@@ -724,6 +723,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
     if ((st = check_launch(ctx, "setup")) != SCI_OK) return st;
     FgpRun r;
     bind_duals(ctx, r);
+    const void *warm = nullptr; // warm_dual: the previous prox call's final dual
     double tau = 1.0;
     float ex = 0.0f; // FISTA: theta = xa + ex (xa - xb), formed by the projection as it loads
     const float a0 = (float)(1.0 - alpha), a1 = (float)(alpha - beta), a2 = (float)beta;
@@ -747,12 +747,12 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
         if ((st = check_launch(ctx, "k_project")) != SCI_OK) return st;
         if (!twist) {
             // x^(t) into the other buffer; x^(t-1) stays in xa
-            if ((st = denoise_fixed(ctx, d, q, z, xb, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
+            if ((st = denoise_fixed(ctx, d, q, z, xb, nullptr, warm, p->warm_dual != 0, r, s)) != SCI_OK) return st;
             const double tau1 = (1.0 + std::sqrt(1.0 + 4.0 * tau * tau)) / 2.0;
             ex = (float)((tau - 1.0) / tau1);
             tau = tau1;
         } else {
-            if ((st = denoise_fixed(ctx, d, q, z, theta, nullptr, nullptr, false, r, s)) != SCI_OK) return st;
+            if ((st = denoise_fixed(ctx, d, q, z, theta, nullptr, warm, p->warm_dual != 0, r, s)) != SCI_OK) return st;
             if (t == 0) {
                 launch_copy(theta, xb, vb, s); // x^(1) = theta^(0)
                 std::swap(xa, xb);
@@ -761,6 +761,7 @@ int run_prox_grad(sci_ctx *ctx, const sci_dims &d, const sci_solver_params *p, c
             }
         }
         if ((st = check_launch(ctx, "update")) != SCI_OK) return st;
+        if (p->warm_dual) warm = r.cur;
         if (!twist) std::swap(xa, xb); // xa = newest iterate, xb = the one before
     }
     if (pend) {
